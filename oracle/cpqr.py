@@ -34,14 +34,17 @@ def householder_nonneg(x: np.ndarray, norm2: float):
         return v, 0.0, 0.0
     alpha = float(x[0])
     rest2 = float(np.dot(x[1:], x[1:]))
+    # d = alpha - beta and tau = (beta - alpha)/beta, both evaluated without
+    # cancellation when alpha > 0 (beta^2 - alpha^2 = rest2)
     if alpha <= 0.0:
         d = alpha - beta
+        tau = (beta - alpha) / beta
     else:
         d = -rest2 / (alpha + beta)
+        tau = rest2 / (beta * (beta + alpha))
     if d == 0.0:
         return v, 0.0, beta
     v[1:] = x[1:] / d
-    tau = (beta - alpha) / beta
     return v, tau, beta
 
 
