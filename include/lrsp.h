@@ -1,0 +1,178 @@
+/*
+ * lrsp.h -- C interface of the MI355X deferred-compression hierarchical solver.
+ *
+ * The solver computes an approximate factorization of a sparse symmetric
+ * positive definite matrix A over a cluster tree (Algorithm 1 of Chen,
+ * Cambier, Boman, Rajamanickam, Tuminaro, Darve, "A Robust Hierarchical
+ * Solver for Ill-conditioned Systems with Applications to Ice Sheet
+ * Modeling") and applies it as a preconditioner (Algorithm 2) inside PCG.
+ * The problem statement is "solve Ax = b for sparse SPD A using a clustering
+ * of the unknowns" (section "Improved LoRaSp Solver").
+ *
+ * Conventions
+ *   - No C++ exception crosses this interface; every call returns an
+ *     lrsp_status.  lrsp_status_str() gives a message.
+ *   - "device" pointers are HIP device memory of the current device;
+ *     "host" pointers are ordinary host memory.
+ *   - Every call enqueues its GPU work on the hip stream passed as
+ *     `stream` (a hipStream_t; NULL = the null stream).  lrsp_factor
+ *     synchronises that stream once per tree level (the next level's
+ *     sizes depend on the compression ranks); lrsp_apply does not
+ *     synchronise; lrsp_pcg synchronises once per iteration to test
+ *     convergence.
+ *   - Handles (lrsp_tree, lrsp_factorization) are not thread-safe; distinct
+ *     handles may be used from distinct threads.
+ *   - Floating point is IEEE double unless an option says otherwise.
+ */
+#ifndef LRSP_H
+#define LRSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LRSP_OK = 0,
+  LRSP_ERR_ARG = 1,       /* invalid argument (sizes, null pointers, tree/matrix mismatch) */
+  LRSP_ERR_NOT_SPD = 2,   /* a diagonal-block Cholesky met a pivot <= 0 or NaN */
+  LRSP_ERR_HIP = 3,       /* a HIP runtime call failed */
+  LRSP_ERR_OOM = 4,       /* device allocation failed */
+  LRSP_ERR_NO_CONV = 5,   /* PCG reached maxit; x holds the last iterate */
+  LRSP_ERR_INTERNAL = 6   /* a device-side capacity or consistency check failed */
+} lrsp_status;
+
+/* Structured extruded grid: nx*ny vertical columns of nz layers with ncomp
+ * unknowns per node.  Global DoF id = c + ncomp*(z + nz*(x + nx*y)), so a
+ * vertical column is a contiguous range of nz*ncomp ids. */
+typedef struct {
+  int32_t nx, ny, nz, ncomp;
+} lrsp_grid;
+
+/* Sparse SPD matrix in CSR with the FULL symmetric pattern and sorted
+ * column indices.  rowptr/col/val are DEVICE pointers.  h_rowptr/h_col are
+ * optional HOST copies of the pattern used by the symbolic analysis; when
+ * NULL the library copies the pattern from the device.  The caller owns all
+ * arrays and keeps them alive for the duration of a call. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const int64_t* h_rowptr;
+  const int32_t* h_col;
+} lrsp_csr;
+
+typedef struct lrsp_tree lrsp_tree;
+typedef struct lrsp_factorization lrsp_factorization;
+
+/* Factorization options.  Zero-initialise, then set fields. */
+typedef struct {
+  int32_t tol_mode;   /* 0: relative, rank k = first j with R_jj <= tol*R_00;
+                         1: absolute, R_jj <= tol */
+  int32_t gemm_prec;  /* Schur-update product: 0 fp64, 1 fp32 inputs with fp32
+                         accumulation, 2 bf16 inputs with fp32 accumulation;
+                         the result is added to the fp64 matrix */
+  int32_t rank_mode;  /* 0: full column-pivoted QR; 1: learned rank (the
+                         predicted rank is checked, full QR continues on failure) */
+  int32_t reserved0;
+  const float* mlp_weights; /* rank_mode 1: host pointer to the packed MLP
+                               parameters (lrsp_mlp_nparams() floats) */
+  int64_t reserved[6];
+} lrsp_opts;
+
+/* ---- cluster tree ------------------------------------------------------
+ * Extruded partitioning (section "Extruded Partitioning for Ice Sheets"):
+ * the horizontal box [0,nx)x[0,ny) is bisected L times, L the smallest
+ * integer with leaf_size*2^L >= N; each split halves the longer side (ties:
+ * x) at lo+len/2, left child first; every vertical column stays in one
+ * cluster.  Level-l cluster c is the parent of level-(l-1) clusters 2c, 2c+1.
+ * ERR_ARG if leaf_size < nz*ncomp or a split would have to cut a column.
+ * The tree is allocated by the library; free it with lrsp_tree_free. */
+lrsp_status lrsp_tree_build(const lrsp_grid* g, int32_t leaf_size, lrsp_tree** out);
+lrsp_status lrsp_tree_free(lrsp_tree* t);
+
+/* Read-only view of the level-0 clustering.  The arrays are owned by the
+ * tree and stay valid until it is freed.  perm lists the global DoFs in
+ * cluster order; cluster c holds perm[leaf_ptr[c] .. leaf_ptr[c+1]). */
+typedef struct {
+  int32_t nlevels;     /* L */
+  int32_t nleaves;     /* 2^L */
+  int64_t n;
+  const int64_t* perm;
+  const int64_t* leaf_ptr;
+} lrsp_tree_view;
+lrsp_status lrsp_tree_export(const lrsp_tree* t, lrsp_tree_view* v);
+
+/* ---- factorization -----------------------------------------------------
+ * Algorithm 1 over the tree: at each level every cluster s, in (colour,
+ * index) order of a greedy distance-2 colouring of the level's cluster graph,
+ * undergoes the scaled low-rank elimination W_s = P_s G_s E_s S_s
+ * (Eqs. scaling, sparse, elim, perm): Cholesky of A_ss, scaling of its block
+ * row by G_s^{-1}, column-pivoted QR compression of the scaled far-field
+ * block to the rank set by tol, rotation, elimination of the fine DoFs with
+ * the Schur update X_nn = A_nn - F^T F.  Recursion stops at the first level
+ * whose cluster graph is complete (or has one cluster) with a dense Cholesky.
+ * A: device CSR (see lrsp_csr); tol >= 0; opts may be NULL (defaults).
+ * On success *F receives a new factor owning its device memory.
+ * ERR_NOT_SPD: *F = NULL; lrsp_last_error_info() names level and cluster. */
+lrsp_status lrsp_factor(const lrsp_csr* A, lrsp_tree* T, double tol, const lrsp_opts* opts,
+                        void* stream, lrsp_factorization** F);
+lrsp_status lrsp_factor_free(lrsp_factorization* F);
+
+/* x = M^{-1} b, M the factored approximation of A (Algorithm 2: forward
+ * substitution y <- W_i y, coarse solve, backward x <- W_i^T x).
+ * b, x: device arrays of n*nrhs doubles, column-major; b == x allowed. */
+lrsp_status lrsp_apply(const lrsp_factorization* F, const double* b, double* x, int32_t nrhs,
+                       void* stream);
+
+/* Preconditioned conjugate gradients with M = the factor, x0 = 0, stopping
+ * when the recursive residual satisfies ||r||_2 <= rtol*||b||_2 (per column)
+ * or after maxit iterations.  b, x: device, n*nrhs column-major.
+ * iters[nrhs], relres[nrhs]: host outputs (iteration count = number of
+ * matrix-vector products; relres = TRUE ||b - A x||_2/||b||_2).
+ * ERR_NO_CONV if some column did not converge (x is still the last iterate). */
+lrsp_status lrsp_pcg(const lrsp_csr* A, const lrsp_factorization* F, const double* b, double* x,
+                     int32_t nrhs, double rtol, int32_t maxit, int32_t* iters, double* relres,
+                     void* stream);
+
+/* ---- introspection -------------------------------------------------------*/
+typedef struct {
+  int32_t nlevels;       /* levels eliminated before the dense top */
+  int32_t top_n;         /* size of the dense top system */
+  int32_t top_clusters;
+  int32_t reserved;
+  double flops[6];       /* algorithmic flops: potrf, trsm, cpqr, applyq, schur, top */
+  double bytes_factor;   /* bytes of the stored factor */
+  double ms_levels;      /* wall time of lrsp_factor (host clock, ms) */
+  int64_t peak_bytes;    /* peak device bytes held by the library during lrsp_factor */
+} lrsp_info;
+lrsp_status lrsp_factor_info(const lrsp_factorization* F, lrsp_info* info);
+
+/* Per-level schedule and ranks (host arrays owned by F, valid until freed):
+ * nclusters, sizes[c] (DoFs at level start), colour[c], order[i] (the i-th
+ * processed cluster), ranks[c] (coarse DoFs kept), and the level graph in
+ * CSR form (adj_ptr[nclusters+1], adj[]).  level == nlevels describes the
+ * dense top (colour/order/ranks NULL). */
+typedef struct {
+  int32_t nclusters;
+  int32_t ncolours;
+  const int32_t* sizes;
+  const int32_t* colour;
+  const int32_t* order;
+  const int32_t* ranks;
+  const int32_t* adj_ptr;
+  const int32_t* adj;
+} lrsp_level_view;
+lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_level_view* v);
+
+/* Message of the last failing call on this thread (static storage). */
+const char* lrsp_last_error_info(void);
+const char* lrsp_status_str(lrsp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRSP_H */

@@ -1,0 +1,107 @@
+// desc.hpp -- plain-old-data work descriptors shared by the host planner and
+// the gfx950 kernels.
+//
+// Storage of a tree level (all fp64, column-major):
+//   D_x         diagonal block of cluster x, m_x x m_x; only its lower
+//               triangle is meaningful.
+//   fine half   for a linked pair {e,l} with e processed before l and linked
+//               when e is processed: the block row of e restricted to the
+//               columns Z(e,l) of l that can be nonzero there (m_e x |Z|).
+//   coarse half for every pair {e,l} linked by the end of the level: the
+//               coupling of l's rows with e's coarse DoFs (m_l x kcap_e);
+//               after l is processed its first k_l rows hold the
+//               coarse-coarse coupling that the next level assembles.
+//   panel P_s   the block row [A_ss | A_sn | A_sw] of cluster s gathered when
+//               s is processed; afterwards it holds the factor pieces of s:
+//               G (lower), C = U^T G^{-1} A_sn (rows k.. are F), and the
+//               reflectors of U in the far-field part.
+#pragma once
+#include <cstdint>
+
+namespace lrsp {
+
+constexpr int kThreads = 256;       // threads of a cluster workgroup
+constexpr int kNB = 16;             // panel width of the blocked Cholesky
+constexpr int kMaxClusterDofs = 768;
+
+// One column segment of the block row of the cluster being processed.
+struct SegD {
+  const double* src;   // m_s rows (ld = m_s); columns of this segment
+  const int32_t* zl;   // fine: natural column indices in cluster y; coarse: null
+  int64_t voff;        // offset of cluster y in the level vector
+  int32_t y;           // cluster id within the level
+  int32_t coarse;      // 1: y processed earlier, width = k[y]; 0: fine
+  int32_t nfine;       // fine width
+  int32_t cap;         // column capacity of the source block
+  int32_t isw;         // 0 near field n(s), 1 far field w(s)
+  int32_t pad;
+};
+
+// Schur-update target of the near-field segment pair (i <= j); stored at
+// index j*(j+1)/2 + i.
+struct PairD {
+  double* dst;
+  const int32_t* posmap;  // block column of a natural index of the column
+                          // cluster; null = identity
+  int32_t ld;
+  int32_t rows_from_j;    // rows come from segment j (else from i)
+  int32_t diag;           // i == j: lower triangle of a diagonal block
+  int32_t nrows;          // bounds of the target block (checked)
+  int32_t ncols;
+  int32_t pad;
+};
+
+// Write-back target of segment i for the coarse row of s.
+struct WbD {
+  double* dst;
+  int32_t ld;
+  int32_t trans;  // 0: dst[r + ld*c] (r coarse row of s, c column index);
+                  // 1: dst[c + ld*r]
+  int32_t nrows;
+  int32_t ncols;
+};
+
+struct ItemD {
+  int32_t s, m, nseg, nsegn;
+  int32_t pcap;   // panel column capacity beyond the m diagonal columns
+  int32_t kcap;   // capacity for the rank of s
+  const SegD* seg;
+  const PairD* pair;
+  const WbD* wb;
+  double* D;        // m x m
+  double* P;        // m x (m + pcap)
+  int32_t* colseg;  // [pcap] segment of each panel column
+  int32_t* colnat;  // [pcap] natural index of each panel column
+  int64_t* vidx;    // [pcap] level-vector index of each near-field column
+  int32_t* piv;     // [kcap] far-field column of reflector j
+  int32_t* stepof;  // [pcap] reflector step of a far-field column, -1 if none
+  double* tau;      // [kcap]
+  double* norms;    // [pcap] scratch
+  int32_t* segoff;  // [nseg+1] scratch
+  int64_t voff;     // offset of s in the level vector
+};
+
+// Per-level dynamic results, indexed by cluster.
+struct LevelState {
+  int32_t* k;     // rank (coarse DoFs kept)
+  int32_t* a;     // near-field columns
+  int32_t* b;     // far-field columns
+  int32_t* err;   // [4]: flag, level, cluster, code
+};
+
+// dst[r + dld*c] = trans ? src[c + sld*r] : src[r + sld*c], r < rows, c < cols
+struct CopyD {
+  const double* src;
+  double* dst;
+  int32_t sld, dld, rows, cols, trans, pad;
+};
+
+enum ErrCode : int32_t {
+  kErrNone = 0,
+  kErrNotSPD = 1,
+  kErrCapacity = 2,
+  kErrIndex = 3,
+  kErrTooLarge = 4,
+};
+
+}  // namespace lrsp

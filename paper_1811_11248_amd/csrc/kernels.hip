@@ -1,0 +1,971 @@
+// kernels.hip -- gfx950 kernels of the deferred-compression hierarchical solver.
+//
+// One workgroup (256 threads = 4 wave64) processes one cluster.  Clusters of
+// one colour of the level's distance-2 colouring read and write disjoint
+// blocks, so a colour is one launch with one workgroup per cluster.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "desc.hpp"
+#include "kernels.hpp"
+
+namespace lrsp {
+
+namespace {
+
+constexpr int kWaves = kThreads / 64;
+constexpr int kRegRows = kMaxClusterDofs / 64;  // column slots per lane
+constexpr double kTie = 1e-10;                    // pivot tie window
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) r += sh[i];
+  return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int i = 1; i < kWaves; ++i) r = fmax(r, sh[i]);
+  return r;
+}
+
+__device__ __forceinline__ int block_min_int(int v, int* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int r = sh[0];
+#pragma unroll
+  for (int i = 1; i < kWaves; ++i) r = min(r, sh[i]);
+  return r;
+}
+
+__device__ void set_error(int32_t* err, int level, int cluster, int code) {
+  if (atomicCAS(&err[0], 0, 1) == 0) {
+    err[1] = level;
+    err[2] = cluster;
+    err[3] = code;
+  }
+}
+
+// Column-major lower-triangular tile enumeration: tile index -> (R, C), R >= C.
+__device__ __forceinline__ void tri_tile(int idx, int nt, int& R, int& C) {
+  // S(C) = C*nt - C*(C-1)/2 tiles precede column C
+  double b = 2.0 * nt + 1.0;
+  int c = (int)((b - sqrt(b * b - 8.0 * idx)) * 0.5);
+  if (c < 0) c = 0;
+  while (c > 0 && (long)c * nt - (long)c * (c - 1) / 2 > idx) --c;
+  while ((long)(c + 1) * nt - (long)(c + 1) * c / 2 <= idx) ++c;
+  C = c;
+  R = c + (idx - (c * nt - c * (c - 1) / 2));
+}
+
+// ---------------------------------------------------------------------------
+// Blocked right-looking Cholesky of the lower triangle of the m x m matrix A
+// (ld), fused with the triangular solve B <- G^{-1} B of the nb columns B
+// (same ld).  Pivots that are not > 0 raise *bad and are replaced by 1 so
+// that the sweep stays finite.  LDS: m*kNB + kNB*kNB + kNB*256 doubles.
+__device__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* lds, int* bad) {
+  double* Lp = lds;                // (m) x kNB, row-major
+  double* Dg = Lp + (size_t)m * kNB;  // kNB x kNB, row-major
+  double* Bb = Dg + kNB * kNB;     // kNB x 256, row-major
+  const int tid = threadIdx.x;
+  for (int jb = 0; jb < m; jb += kNB) {
+    const int w = min(kNB, m - jb);
+    // (a) factor the diagonal block with wave 0 (lane t holds row t)
+    if (tid < 64) {
+      double row[kNB];
+#pragma unroll
+      for (int u = 0; u < kNB; ++u)
+        row[u] = (tid < w && u <= tid) ? A[(size_t)(jb + tid) + (size_t)ld * (jb + u)] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kNB; ++u) {
+        if (u < w) {
+          double d = __shfl(row[u], u, 64);
+          if (!(d > 0.0)) {
+            if (tid == 0) *bad = 1;
+            d = 1.0;
+          }
+          d = sqrt(d);
+          if (tid == u) row[u] = d;
+          else if (tid > u) row[u] = row[u] / d;
+#pragma unroll
+          for (int v = u + 1; v < kNB; ++v) {
+            double lvu = __shfl(row[u], v, 64);
+            if (v < w && tid >= v && tid < w) row[v] -= row[u] * lvu;
+          }
+        }
+      }
+      if (tid < kNB) {
+#pragma unroll
+        for (int u = 0; u < kNB; ++u) Dg[tid * kNB + u] = (tid < w && u <= tid) ? row[u] : 0.0;
+      }
+      if (tid < w) {
+#pragma unroll
+        for (int u = 0; u < kNB; ++u)
+          if (u <= tid) A[(size_t)(jb + tid) + (size_t)ld * (jb + u)] = row[u];
+      }
+    }
+    __syncthreads();
+    // (b) panel rows below the diagonal block: x L11^T = a
+    const int rem = m - jb - w;
+    for (int i = tid; i < rem; i += kThreads) {
+      const int gi = jb + w + i;
+      double x[kNB];
+#pragma unroll
+      for (int u = 0; u < kNB; ++u) x[u] = (u < w) ? A[(size_t)gi + (size_t)ld * (jb + u)] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kNB; ++u) {
+        if (u < w) {
+          double s = x[u];
+#pragma unroll
+          for (int v = 0; v < u; ++v) s -= Dg[u * kNB + v] * x[v];
+          x[u] = s / Dg[u * kNB + u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kNB; ++u) {
+        Lp[(size_t)i * kNB + u] = x[u];
+        if (u < w) A[(size_t)gi + (size_t)ld * (jb + u)] = x[u];
+      }
+    }
+    __syncthreads();
+    // (c) right-hand block: rows jb..jb+w of B, then the rows below
+    for (int c0 = 0; c0 < nb; c0 += 256) {
+      const int c = c0 + tid;
+      if (c < nb) {
+        double x[kNB];
+#pragma unroll
+        for (int u = 0; u < kNB; ++u) x[u] = (u < w) ? B[(size_t)(jb + u) + (size_t)ld * c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kNB; ++u) {
+          if (u < w) {
+            double s = x[u];
+#pragma unroll
+            for (int v = 0; v < u; ++v) s -= Dg[u * kNB + v] * x[v];
+            x[u] = s / Dg[u * kNB + u];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kNB; ++u) {
+          Bb[u * 256 + tid] = x[u];
+          if (u < w) B[(size_t)(jb + u) + (size_t)ld * c] = x[u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kNB; ++u) Bb[u * 256 + tid] = 0.0;
+      }
+      __syncthreads();
+      const int ncol = min(256, nb - c0);
+      const int nR = (rem + 3) >> 2, nC = (ncol + 3) >> 2;
+      for (int idx = tid; idx < nR * nC; idx += kThreads) {
+        const int R = idx % nR, C = idx / nR;
+        double acc[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
+        for (int u = 0; u < w; ++u) {
+          double lr[4], bc[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) lr[r] = (4 * R + r < rem) ? Lp[(size_t)(4 * R + r) * kNB + u] : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bc[q] = Bb[u * 256 + 4 * C + q];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[r][q] += lr[r] * bc[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int cc = c0 + 4 * C + q;
+          if (4 * C + q < ncol) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (4 * R + r < rem) B[(size_t)(jb + w + 4 * R + r) + (size_t)ld * cc] -= acc[r][q];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // (d) trailing update of the lower triangle of A
+    const int nt = (rem + 3) >> 2;
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int idx = tid; idx < ntiles; idx += kThreads) {
+      int R, C;
+      tri_tile(idx, nt, R, C);
+      double acc[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
+      for (int u = 0; u < w; ++u) {
+        double lr[4], lc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lr[r] = (4 * R + r < rem) ? Lp[(size_t)(4 * R + r) * kNB + u] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lc[q] = (4 * C + q < rem) ? Lp[(size_t)(4 * C + q) * kNB + u] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[r][q] += lr[r] * lc[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cc = 4 * C + q;
+        if (cc < rem) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rr = 4 * R + r;
+            if (rr < rem && rr >= cc)
+              A[(size_t)(jb + w + rr) + (size_t)ld * (jb + w + cc)] -= acc[r][q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Column-pivoted Householder QR of the m x b far-field block W (ld), truncated
+// at the first pivot with R_jj <= tol*R_00 (relative) or <= tol (absolute).
+// Pivot: lowest column among those with squared norm >= (1-kTie)*max.
+// Reflector j lives in column piv[j] (rows j+1.., unit leading entry); R_jj
+// >= 0 sits at row j of that column; other columns hold R in rows < k.
+__device__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, int* piv,
+                    int* stepof, double* tau, double* norms, double* shd, int* shi) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int c = wv; c < b; c += kWaves) {
+    const double* y = W + (size_t)ld * c;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s += y[i] * y[i];
+    s = wave_sum(s);
+    if (lane == 0) {
+      norms[c] = s;
+      stepof[c] = -1;
+    }
+  }
+  __syncthreads();
+  const int kmax = min(m, b);
+  double r00 = 0.0;
+  int k = kmax;
+  for (int j = 0; j < kmax; ++j) {
+    double mx = 0.0;
+    for (int c = tid; c < b; c += kThreads)
+      if (stepof[c] < 0) mx = fmax(mx, norms[c]);
+    mx = block_max(mx, shd);
+    const double thr = (1.0 - kTie) * mx;
+    int best = INT_MAX;
+    for (int c = tid; c < b; c += kThreads)
+      if (stepof[c] < 0 && norms[c] >= thr) best = min(best, c);
+    best = block_min_int(best, shi);
+    if (best == INT_MAX) {  // only NaN norms left
+      k = j;
+      break;
+    }
+    const double n2 = norms[best];
+    const double rjj = sqrt(n2);
+    if (j == 0) r00 = rjj;
+    const bool stop = (tol_mode == 0) ? (rjj <= tol * r00) : (rjj <= tol);
+    if (stop || rjj == 0.0) {
+      k = j;
+      break;
+    }
+    double* x = W + (size_t)ld * best;
+    const double alpha = x[j];
+    double rest = 0.0;
+    for (int i = j + 1 + tid; i < m; i += kThreads) rest += x[i] * x[i];
+    rest = block_sum(rest, shd);
+    double d, tj;
+    if (alpha <= 0.0) {
+      d = alpha - rjj;
+      tj = (rjj - alpha) / rjj;
+    } else {
+      d = -rest / (alpha + rjj);
+      tj = rest / (rjj * (rjj + alpha));
+    }
+    if (d == 0.0) tj = 0.0;
+    __syncthreads();
+    if (d != 0.0)
+      for (int i = j + 1 + tid; i < m; i += kThreads) x[i] = x[i] / d;
+    if (tid == 0) {
+      x[j] = rjj;
+      piv[j] = best;
+      stepof[best] = j;
+      tau[j] = tj;
+    }
+    __syncthreads();
+    // apply H_j to the remaining columns and recompute their norms below row j
+    double v[kRegRows];
+#pragma unroll
+    for (int t = 0; t < kRegRows; ++t) {
+      const int i = lane + 64 * t;
+      v[t] = (i > j && i < m) ? x[i] : (i == j ? 1.0 : 0.0);
+    }
+    for (int c = wv; c < b; c += kWaves) {
+      if (stepof[c] >= 0) continue;
+      double* y = W + (size_t)ld * c;
+      double yr[kRegRows];
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < kRegRows; ++t) {
+        const int i = lane + 64 * t;
+        yr[t] = (i >= j && i < m) ? y[i] : 0.0;
+        s += v[t] * yr[t];
+      }
+      s = wave_sum(s);
+      const double f = tj * s;
+      double nn = 0.0;
+#pragma unroll
+      for (int t = 0; t < kRegRows; ++t) {
+        const int i = lane + 64 * t;
+        if (i >= j && i < m) {
+          const double nv = yr[t] - f * v[t];
+          y[i] = nv;
+          if (i > j) nn += nv * nv;
+        }
+      }
+      nn = wave_sum(nn);
+      if (lane == 0) norms[c] = nn;
+    }
+    __syncthreads();
+  }
+  return k;
+}
+
+// C <- U^T C for the a columns C (ld): reflectors 0..k-1 in order.
+__device__ void apply_qt_cols(double* C, int ld, int m, int a, const double* W, const int* piv,
+                              const double* tau, int k) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int c = wv; c < a; c += kWaves) {
+    double* y = C + (size_t)ld * c;
+    double yr[kRegRows];
+#pragma unroll
+    for (int t = 0; t < kRegRows; ++t) {
+      const int i = lane + 64 * t;
+      yr[t] = (i < m) ? y[i] : 0.0;
+    }
+    for (int j = 0; j < k; ++j) {
+      const double* x = W + (size_t)ld * piv[j];
+      double v[kRegRows];
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < kRegRows; ++t) {
+        const int i = lane + 64 * t;
+        v[t] = (i > j && i < m) ? x[i] : (i == j ? 1.0 : 0.0);
+        s += v[t] * yr[t];
+      }
+      s = wave_sum(s);
+      const double f = tau[j] * s;
+#pragma unroll
+      for (int t = 0; t < kRegRows; ++t) yr[t] -= f * v[t];
+    }
+#pragma unroll
+    for (int t = 0; t < kRegRows; ++t) {
+      const int i = lane + 64 * t;
+      if (i < m) y[i] = yr[t];
+    }
+  }
+}
+
+__device__ __forceinline__ float round_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(u);
+}
+
+// Schur update X -= F^T F, F = rows k..m-1 of the a near-field columns C (ld).
+// Each unordered column pair (r >= c) is computed once and scattered to the
+// one block that owns it.
+__device__ void schur_scatter(const ItemD& it, const double* C, int ld, int m, int k, int a, int prec,
+                              int32_t* err, int level) {
+  const int tid = threadIdx.x;
+  const int nt = (a + 3) >> 2;
+  const int ntiles = nt * (nt + 1) / 2;
+  for (int idx = tid; idx < ntiles; idx += kThreads) {
+    int R, Cc;
+    tri_tile(idx, nt, R, Cc);
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
+    if (prec == 0) {
+      for (int i = k; i < m; ++i) {
+        double fr[4], fc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fr[r] = (4 * R + r < a) ? C[(size_t)i + (size_t)ld * (4 * R + r)] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fc[q] = (4 * Cc + q < a) ? C[(size_t)i + (size_t)ld * (4 * Cc + q)] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[r][q] += fr[r] * fc[q];
+      }
+    } else {
+      float accf[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) accf[r][q] = 0.0f;
+      for (int i = k; i < m; ++i) {
+        float fr[4], fc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float t = (4 * R + r < a) ? (float)C[(size_t)i + (size_t)ld * (4 * R + r)] : 0.0f;
+          fr[r] = prec == 2 ? round_bf16(t) : t;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float t = (4 * Cc + q < a) ? (float)C[(size_t)i + (size_t)ld * (4 * Cc + q)] : 0.0f;
+          fc[q] = prec == 2 ? round_bf16(t) : t;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) accf[r][q] = fmaf(fr[r], fc[q], accf[r][q]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] = (double)accf[r][q];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = 4 * R + r;
+      if (rr >= a) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cc = 4 * Cc + q;
+        if (cc >= a || cc > rr) continue;
+        const int sr = it.colseg[rr], sc = it.colseg[cc];
+        const int nr = it.colnat[rr], nc = it.colnat[cc];
+        int i = min(sr, sc), j = max(sr, sc);
+        const PairD& pd = it.pair[j * (j + 1) / 2 + i];
+        int row, col;
+        if (pd.diag) {
+          row = max(nr, nc);
+          col = min(nr, nc);
+        } else {
+          const bool r_is_rowseg = (sr == (pd.rows_from_j ? j : i));
+          row = r_is_rowseg ? nr : nc;
+          const int cn = r_is_rowseg ? nc : nr;
+          col = pd.posmap ? pd.posmap[cn] : cn;
+        }
+        if (row < 0 || col < 0 || row >= pd.nrows || col >= pd.ncols) {
+          set_error(err, level, it.s, kErrIndex);
+          continue;
+        }
+        pd.dst[(size_t)row + (size_t)pd.ld * col] -= acc[r][q];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) slre_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                        int level, double tol, int tol_mode, int prec) {
+  extern __shared__ double lds[];
+  __shared__ double shd[kWaves];
+  __shared__ int shi[kWaves];
+  __shared__ int sab[4];
+  __shared__ int sbad;
+  const ItemD& it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int m = it.m;
+  // widths of the column segments (coarse ones depend on earlier ranks)
+  if (tid == 0) {
+    int off = 0, a = 0, bad = 0;
+    for (int i = 0; i < it.nseg; ++i) {
+      const SegD& sg = it.seg[i];
+      int w = sg.coarse ? ls.k[sg.y] : sg.nfine;
+      if (w > sg.cap || w < 0) {
+        bad = 1;
+        w = 0;
+      }
+      it.segoff[i] = off;
+      off += w;
+      if (i + 1 == it.nsegn) a = off;
+    }
+    it.segoff[it.nseg] = off;
+    if (off > it.pcap) bad = 1;
+    sab[0] = a;
+    sab[1] = off - a;
+    sab[2] = bad;
+    sbad = 0;
+  }
+  __syncthreads();
+  if (sab[2]) {
+    if (tid == 0) set_error(ls.err, level, it.s, kErrCapacity);
+    return;
+  }
+  const int a = sab[0], b = sab[1];
+  double* P = it.P;
+  const size_t ld = (size_t)m;
+  // gather the block row [A_ss | A_sn | A_sw]
+  for (size_t e = tid; e < ld * m; e += kThreads) P[e] = it.D[e];
+  for (int i = 0; i < it.nseg; ++i) {
+    const SegD& sg = it.seg[i];
+    const int c0 = it.segoff[i];
+    const int w = it.segoff[i + 1] - c0;
+    for (size_t e = tid; e < (size_t)w * m; e += kThreads) P[ld * (m + c0) + e] = sg.src[e];
+    for (int c = tid; c < w; c += kThreads) {
+      const int nat = sg.coarse ? c : sg.zl[c];
+      it.colseg[c0 + c] = i;
+      it.colnat[c0 + c] = nat;
+      it.vidx[c0 + c] = sg.voff + nat;
+    }
+  }
+  __syncthreads();
+  // S_s: Cholesky of A_ss and scaling of the block row
+  chol_solve(P, m, m, P + ld * m, a + b, lds, &sbad);
+  __syncthreads();
+  if (sbad && tid == 0) set_error(ls.err, level, it.s, kErrNotSPD);
+  // compression of the scaled far field G^{-1} A_sw
+  double* Wf = P + ld * (m + a);
+  int k = 0;
+  if (b > 0 && m > 0)
+    k = cpqr(Wf, m, m, b, tol, tol_mode, it.piv, it.stepof, it.tau, it.norms, shd, shi);
+  if (k > it.kcap) {
+    if (tid == 0) set_error(ls.err, level, it.s, kErrCapacity);
+    return;
+  }
+  __syncthreads();
+  // E_s: rotate the near-field columns, C = U^T G^{-1} A_sn
+  double* C = P + ld * m;
+  if (k > 0) apply_qt_cols(C, m, m, a, Wf, it.piv, it.tau, k);
+  __syncthreads();
+  // G_s: eliminate the fine DoFs, X_nn -= F^T F
+  if (m > k && a > 0) schur_scatter(it, C, m, m, k, a, prec, ls.err, level);
+  // coarse row of s: [I_k | C[:k] | V1^T]
+  for (int i = 0; i < it.nseg; ++i) {
+    const WbD& t = it.wb[i];
+    const int c0 = it.segoff[i];
+    const int w = it.segoff[i + 1] - c0;
+    for (int e = tid; e < k * w; e += kThreads) {
+      const int r = e % k, cl = e / k;
+      const int pc = c0 + cl;
+      const int cn = it.colnat[pc];
+      double v = P[(size_t)r + ld * (m + pc)];
+      if (pc >= a) {
+        const int st = it.stepof[pc - a];
+        if (st >= 0 && r > st) v = 0.0;
+      }
+      const int row = t.trans ? cn : r, col = t.trans ? r : cn;
+      if (row >= t.nrows || col >= t.ncols) {
+        set_error(ls.err, level, it.s, kErrIndex);
+        continue;
+      }
+      t.dst[(size_t)row + (size_t)t.ld * col] = v;
+    }
+  }
+  for (int e = tid; e < k * k; e += kThreads) {
+    const int r = e % k, c = e / k;
+    it.D[(size_t)r + ld * c] = (r == c) ? 1.0 : 0.0;
+  }
+  if (tid == 0) {
+    ls.k[it.s] = k;
+    ls.a[it.s] = a;
+    ls.b[it.s] = b;
+  }
+}
+
+// Kernels that use more than 64 KiB of dynamic LDS must say so once.
+static void allow_lds(const void* fn, bool* done) {
+  if (*done) return;
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  *done = true;
+}
+
+void launch_slre(const ItemD* items, int nitems, int max_m, LevelState ls, int level, double tol,
+                 int tol_mode, int prec, hipStream_t st) {
+  if (nitems <= 0) return;
+  static bool lds_ok = false;
+  allow_lds(reinterpret_cast<const void*>(slre_kernel), &lds_ok);
+  size_t lds = ((size_t)max_m * kNB + kNB * kNB + kNB * 256) * sizeof(double);
+  hipLaunchKernelGGL(slre_kernel, dim3(nitems), dim3(kThreads), lds, st, items, ls, level, tol,
+                     tol_mode, prec);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) top_potrf_kernel(double* A, int n, int32_t* err) {
+  extern __shared__ double lds[];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  chol_solve(A, n, n, nullptr, 0, lds, &sbad);
+  __syncthreads();
+  if (sbad && threadIdx.x == 0) set_error(err, -1, -1, kErrNotSPD);
+}
+
+void launch_top_potrf(double* A, int n, int32_t* err, hipStream_t st) {
+  if (n <= 0) return;
+  static bool lds_ok = false;
+  allow_lds(reinterpret_cast<const void*>(top_potrf_kernel), &lds_ok);
+  size_t lds = ((size_t)n * kNB + kNB * kNB + kNB * 256) * sizeof(double);
+  hipLaunchKernelGGL(top_potrf_kernel, dim3(1), dim3(kThreads), lds, st, A, n, err);
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solves of the substitution phase, y in LDS, G (ld) in global.
+namespace {
+
+// y <- G^{-1} y, G lower (m x m, ld).  blk: 64*64 doubles of LDS.
+__device__ void trsv_lower(const double* G, int ld, int m, double* y, double* blk) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int jb = 0; jb < m; jb += 64) {
+    const int w = min(64, m - jb);
+    for (int e = tid; e < 64 * 64; e += kThreads) {
+      const int r = e & 63, c = e >> 6;
+      blk[e] = (r < w && c <= r) ? G[(size_t)(jb + r) + (size_t)ld * (jb + c)] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double yl = (lane < w) ? y[jb + lane] : 0.0;
+      for (int t = 0; t < w; ++t) {
+        const double yt = __shfl(yl, t, 64) / blk[t + 64 * t];
+        if (lane == t) yl = yt;
+        else if (lane > t) yl -= blk[lane + 64 * t] * yt;
+      }
+      if (lane < w) y[jb + lane] = yl;
+    }
+    __syncthreads();
+    for (int i = jb + w + tid; i < m; i += kThreads) {
+      double s = 0.0;
+      for (int t = 0; t < w; ++t) s += G[(size_t)i + (size_t)ld * (jb + t)] * y[jb + t];
+      y[i] -= s;
+    }
+    __syncthreads();
+  }
+}
+
+// y <- G^{-T} y, G lower (m x m, ld).
+__device__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* blk) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nblk = (m + 63) / 64;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int jb = bi * 64;
+    const int w = min(64, m - jb);
+    // y[jb+t] -= sum_{i >= jb+w} G[i, jb+t] y[i]
+    for (int t = wv; t < w; t += kWaves) {
+      const double* g = G + (size_t)ld * (jb + t);
+      double s = 0.0;
+      for (int i = jb + w + lane; i < m; i += 64) s += g[i] * y[i];
+      s = wave_sum(s);
+      if (lane == 0) y[jb + t] -= s;
+    }
+    for (int e = tid; e < 64 * 64; e += kThreads) {
+      const int r = e & 63, c = e >> 6;
+      blk[e] = (r < w && c <= r) ? G[(size_t)(jb + r) + (size_t)ld * (jb + c)] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double yl = (lane < w) ? y[jb + lane] : 0.0;
+      for (int t = w - 1; t >= 0; --t) {
+        const double yt = __shfl(yl, t, 64) / blk[t + 64 * t];
+        if (lane == t) yl = yt;
+        else if (lane < t) yl -= blk[t + 64 * lane] * yt;
+      }
+      if (lane < w) y[jb + lane] = yl;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// Forward substitution of the clusters of one colour: y_s <- U^T G^{-1} y_s,
+// y_n -= F^T y_f.
+__global__ void __launch_bounds__(kThreads) fwd_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                       double* vec) {
+  extern __shared__ double lds[];
+  __shared__ double shd[kWaves];
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  if (m == 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int k = ls.k[it.s], a = ls.a[it.s];
+  double* y = lds;
+  double* blk = lds + ((m + 63) / 64) * 64;
+  double* yg = vec + it.voff;
+  for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
+  __syncthreads();
+  trsv_lower(it.P, m, m, y, blk);
+  const double* Wf = it.P + (size_t)m * (m + a);
+  for (int j = 0; j < k; ++j) {
+    const double* x = Wf + (size_t)m * it.piv[j];
+    double s = 0.0;
+    for (int i = j + tid; i < m; i += kThreads) s += (i == j ? 1.0 : x[i]) * y[i];
+    s = block_sum(s, shd);
+    const double f = it.tau[j] * s;
+    for (int i = j + tid; i < m; i += kThreads) y[i] -= f * (i == j ? 1.0 : x[i]);
+    __syncthreads();
+  }
+  const double* C = it.P + (size_t)m * m;
+  for (int c = wv; c < a; c += kWaves) {
+    const double* f = C + (size_t)m * c;
+    double s = 0.0;
+    for (int i = k + lane; i < m; i += 64) s += f[i] * y[i];
+    s = wave_sum(s);
+    if (lane == 0) vec[it.vidx[c]] -= s;
+  }
+  for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
+}
+
+// Backward substitution: x_f -= F x_n, x_s <- G^{-T} U x_s.
+__global__ void __launch_bounds__(kThreads) bwd_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                       double* vec) {
+  extern __shared__ double lds[];
+  __shared__ double shd[kWaves];
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  if (m == 0) return;
+  const int tid = threadIdx.x;
+  const int k = ls.k[it.s], a = ls.a[it.s];
+  const int mp = ((m + 63) / 64) * 64;
+  double* x = lds;
+  double* blk = lds + mp;
+  double* xn = blk + 64 * 64;  // 1024-column chunks of x_n
+  double* xg = vec + it.voff;
+  for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
+  const double* C = it.P + (size_t)m * m;
+  for (int c0 = 0; c0 < a; c0 += 1024) {
+    const int nc = min(1024, a - c0);
+    __syncthreads();
+    for (int c = tid; c < nc; c += kThreads) xn[c] = vec[it.vidx[c0 + c]];
+    __syncthreads();
+    for (int i = k + tid; i < m; i += kThreads) {
+      double s = 0.0;
+      for (int c = 0; c < nc; ++c) s += C[(size_t)i + (size_t)m * (c0 + c)] * xn[c];
+      x[i] -= s;
+    }
+  }
+  __syncthreads();
+  const double* Wf = it.P + (size_t)m * (m + a);
+  for (int j = k - 1; j >= 0; --j) {
+    const double* v = Wf + (size_t)m * it.piv[j];
+    double s = 0.0;
+    for (int i = j + tid; i < m; i += kThreads) s += (i == j ? 1.0 : v[i]) * x[i];
+    s = block_sum(s, shd);
+    const double f = it.tau[j] * s;
+    for (int i = j + tid; i < m; i += kThreads) x[i] -= f * (i == j ? 1.0 : v[i]);
+    __syncthreads();
+  }
+  trsv_lower_t(it.P, m, m, x, blk);
+  for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
+}
+
+void launch_fwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
+                hipStream_t st) {
+  if (nitems <= 0) return;
+  size_t lds = ((size_t)((max_m + 63) / 64) * 64 + 64 * 64) * sizeof(double);
+  hipLaunchKernelGGL(fwd_kernel, dim3(nitems), dim3(kThreads), lds, st, items, ls, vec);
+}
+
+void launch_bwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
+                hipStream_t st) {
+  if (nitems <= 0) return;
+  size_t lds = ((size_t)((max_m + 63) / 64) * 64 + 64 * 64 + 1024) * sizeof(double);
+  hipLaunchKernelGGL(bwd_kernel, dim3(nitems), dim3(kThreads), lds, st, items, ls, vec);
+}
+
+__global__ void __launch_bounds__(kThreads) top_solve_kernel(const double* L, int n, double* yg) {
+  extern __shared__ double lds[];
+  double* y = lds;
+  double* blk = lds + ((n + 63) / 64) * 64;
+  for (int i = threadIdx.x; i < n; i += kThreads) y[i] = yg[i];
+  __syncthreads();
+  trsv_lower(L, n, n, y, blk);
+  trsv_lower_t(L, n, n, y, blk);
+  for (int i = threadIdx.x; i < n; i += kThreads) yg[i] = y[i];
+}
+
+void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
+  if (n <= 0) return;
+  size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * 64) * sizeof(double);
+  hipLaunchKernelGGL(top_solve_kernel, dim3(1), dim3(kThreads), lds, st, L, n, y);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void zero_kernel(double* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+__global__ void zero_i32_kernel(int32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+static int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (int)(g < 8192 ? (g > 0 ? g : 1) : 8192);
+}
+
+void launch_zero(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n);
+}
+void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n);
+}
+
+__global__ void scatter_vals_kernel(const double* val, const int64_t* off, int64_t nnz, double* base) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = off[e];
+    if (o >= 0) base[o] = val[e];
+  }
+}
+void launch_scatter_vals(const double* val, const int64_t* off, int64_t nnz, double* base,
+                         hipStream_t st) {
+  if (nnz <= 0) return;
+  hipLaunchKernelGGL(scatter_vals_kernel, dim3(grid_for(nnz)), dim3(256), 0, st, val, off, nnz,
+                     base);
+}
+
+__global__ void copy_blocks_kernel(const CopyD* tasks) {
+  const CopyD t = tasks[blockIdx.x];
+  const int64_t n = (int64_t)t.rows * t.cols;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int r = (int)(e % t.rows), c = (int)(e / t.rows);
+    const double v = t.trans ? t.src[(size_t)c + (size_t)t.sld * r] : t.src[(size_t)r + (size_t)t.sld * c];
+    t.dst[(size_t)r + (size_t)t.dld * c] = v;
+  }
+}
+void launch_copy_blocks(const CopyD* tasks, int ntasks, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(copy_blocks_kernel, dim3(ntasks), dim3(256), 0, st, tasks);
+}
+
+__global__ void gather_kernel(const double* src, const int64_t* idx, double* dst, int64_t n) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x)
+    dst[j] = src[idx[j]];
+}
+__global__ void scatter_kernel(const double* src, const int64_t* idx, double* dst, int64_t n) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x)
+    dst[idx[j]] = src[j];
+}
+void launch_gather(const double* src, const int64_t* idx, double* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gather_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, idx, dst, n);
+}
+void launch_scatter(const double* src, const int64_t* idx, double* dst, int64_t n,
+                    hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, idx, dst, n);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void spmv_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, const double* __restrict__ x,
+                            double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) s += val[e] * x[col[e]];
+    y[i] = s;
+  }
+}
+void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, const double* x,
+                 double* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(spmv_kernel, dim3(grid_for(n)), dim3(256), 0, st, rowptr, col, val, x, y, n);
+}
+
+__global__ void __launch_bounds__(256) dot_partial_kernel(const double* x, const double* y, int64_t n,
+                                                          double* partial) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s += x[i] * y[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+__global__ void __launch_bounds__(256) dot_final_kernel(const double* partial, int np, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+void launch_dot(const double* x, const double* y, int64_t n, double* partial, double* out,
+                hipStream_t st) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotBlocks), dim3(256), 0, st, x, y, n, partial);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, st, partial, kDotBlocks, out);
+}
+
+__global__ void pcg_xr_kernel(double* x, double* r, const double* p, const double* q, int64_t n,
+                              const double* num, const double* den) {
+  const double al = num[0] / den[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += al * p[i];
+    r[i] -= al * q[i];
+  }
+}
+void launch_pcg_xr(double* x, double* r, const double* p, const double* q, int64_t n,
+                   const double* num, const double* den, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_xr_kernel, dim3(grid_for(n)), dim3(256), 0, st, x, r, p, q, n, num, den);
+}
+__global__ void pcg_p_kernel(double* p, const double* z, int64_t n, const double* num,
+                             const double* den) {
+  const double be = num[0] / den[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + be * p[i];
+}
+void launch_pcg_p(double* p, const double* z, int64_t n, const double* num, const double* den,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(pcg_p_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, z, n, num, den);
+}
+__global__ void residual_kernel(const double* b, double* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = b[i] - y[i];
+}
+void launch_residual(const double* b, double* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(residual_kernel, dim3(grid_for(n)), dim3(256), 0, st, b, y, n);
+}
+__global__ void copy_kernel(const double* s, double* d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+void launch_copy(const double* src, double* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+}
+
+}  // namespace lrsp

@@ -1,0 +1,53 @@
+// kernels.hpp -- host-side launchers of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "desc.hpp"
+
+namespace lrsp {
+
+// Fill n doubles with zero (a kernel, so that it can be graph-captured).
+void launch_zero(double* p, int64_t n, hipStream_t st);
+void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
+
+// base[off[e]] = val[e] for every e with off[e] >= 0.
+void launch_scatter_vals(const double* val, const int64_t* off, int64_t nnz, double* base,
+                         hipStream_t st);
+void launch_copy_blocks(const CopyD* tasks, int ntasks, hipStream_t st);
+
+// One scaled low-rank elimination per item (all items of one colour).
+void launch_slre(const ItemD* items, int nitems, int max_m, LevelState ls, int level, double tol,
+                 int tol_mode, int prec, hipStream_t st);
+
+// Dense Cholesky of the top system (lower, in place).
+void launch_top_potrf(double* A, int n, int32_t* err, hipStream_t st);
+
+// Substitution sweeps over the items of one colour.
+void launch_fwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
+                hipStream_t st);
+void launch_bwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
+                hipStream_t st);
+void launch_top_solve(const double* L, int n, double* y, hipStream_t st);
+
+void launch_gather(const double* src, const int64_t* idx, double* dst, int64_t n, hipStream_t st);
+void launch_scatter(const double* src, const int64_t* idx, double* dst, int64_t n,
+                    hipStream_t st);
+
+// PCG building blocks.
+void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, const double* x,
+                 double* y, int64_t n, hipStream_t st);
+// out[0] = x . y (deterministic two-stage reduction; partial has kDotBlocks doubles)
+constexpr int kDotBlocks = 512;
+void launch_dot(const double* x, const double* y, int64_t n, double* partial, double* out,
+                hipStream_t st);
+// x += (num/den) p ; r -= (num/den) q
+void launch_pcg_xr(double* x, double* r, const double* p, const double* q, int64_t n,
+                   const double* num, const double* den, hipStream_t st);
+// p = z + (num/den) p
+void launch_pcg_p(double* p, const double* z, int64_t n, const double* num, const double* den,
+                  hipStream_t st);
+// y = b - y
+void launch_residual(const double* b, double* y, int64_t n, hipStream_t st);
+void launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
+
+}  // namespace lrsp

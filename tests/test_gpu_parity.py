@@ -1,0 +1,142 @@
+"""Parity of the HIP path (through the C-ABI) with the oracle.
+
+Bars: the cluster tree, level graphs, colouring, elimination order and
+ranks equal the oracle's bit for bit; M^{-1} b matches the oracle's solve to
+relative 1e-10 in fp64; PCG reaches 1e-8 with an iteration count within +-1
+of the oracle's.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import config, laplace2d, lognormal_field, rhs, slab_scalar, slab_vector
+
+pytestmark = pytest.mark.gpu
+
+APPLY_TOL = 1e-10
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1811_11248_amd import lrsp
+    return lrsp
+
+
+CASES = {
+    "laplace16": (lambda: laplace2d(16), 16, 1e-2),
+    "laplace64": (lambda: config("laplace64"), 64, 1e-2),
+    "slab_ragged": (lambda: slab_scalar(13, 11, 5, 1e3, lognormal_field((11, 13, 5), seed=2)), 40, 1e-2),
+    "vector_ragged": (lambda: slab_vector(10, 9, 4, 1e2), 48, 1e-2),
+    "slab_aniso": (lambda: slab_scalar(24, 20, 8, 1e4, lognormal_field((20, 24, 8), seed=5)), 64, 1e-3),
+    "laplace_tol0": (lambda: laplace2d(16), 16, 0.0),
+    "slab_tol0": (lambda: slab_scalar(8, 8, 4, 1e3, lognormal_field((8, 8, 4), seed=3)), 16, 0.0),
+    "strip4": (lambda: laplace2d(32, 2), 16, 0.5),
+    "single_cluster": (lambda: laplace2d(6), 64, 1e-2),
+    "slab64_full": (lambda: config("slab64"), 256, 1e-2),
+}
+
+
+def _run(torch, L, name):
+    mk, leaf, tol = CASES[name]
+    pr = mk()
+    _say(f"[case {name}] n={pr.n} leaf={leaf} tol={tol}")
+    T = oracle.build_tree(pr.grid, leaf)
+    Fo = oracle.factor(pr.rowptr, pr.col, pr.val, T, tol)
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree(pr.grid, leaf)
+    F = L.Factor(A, tree, tol)
+    torch.cuda.synchronize()
+    return pr, Fo, A, F
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_schedule_and_apply(torch, L, name):
+    pr, Fo, A, F = _run(torch, L, name)
+    info = F.info()
+    exact = CASES[name][2] == 0.0
+    # at tol = 0 a rank is decided by whether a rounded column norm is
+    # exactly zero, which summation order can flip; there only the level-0
+    # schedule is compared and the factor must be exact
+    if not exact:
+        assert info["nlevels"] == len(Fo.levels)
+    for li, lv in enumerate(Fo.levels[:1] if exact else Fo.levels):
+        g = F.level(li)
+        assert g["sizes"].tolist() == list(lv.sizes), f"sizes level {li}"
+        assert g["graph"] == [list(x) for x in lv.graph], f"graph level {li}"
+        assert g["colour"].tolist() == list(lv.colour), f"colour level {li}"
+        assert g["order"].tolist() == list(lv.order), f"order level {li}"
+        if not exact:
+            assert g["ranks"].tolist() == list(lv.ranks), f"ranks level {li}"
+    if not exact:
+        top = F.level(len(Fo.levels))
+        assert top["sizes"].tolist() == list(Fo.top_sizes)
+    for seed in (0, 1):
+        b = rhs(pr.n, seed)
+        xo = oracle.solve(Fo, b)
+        x = L.apply(F, torch.from_numpy(b).cuda()).cpu().numpy()
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        _say(f"  apply rel err {err:.3e}")
+        assert err <= APPLY_TOL
+    if exact:
+        xe = np.linalg.solve(pr.scipy().toarray(), b)
+        assert np.linalg.norm(x - xe) <= 1e-10 * np.linalg.norm(xe)
+
+
+@pytest.mark.parametrize("name", ["laplace64", "slab_ragged", "vector_ragged", "slab_aniso", "strip4",
+                                  "slab64_full"])
+def test_pcg_iterations(torch, L, name):
+    pr, Fo, A, F = _run(torch, L, name)
+    b = rhs(pr.n, 0)
+    As = pr.scipy()
+    _, ito, rro, ok = oracle.pcg(lambda v: As @ v, b, lambda r: oracle.solve(Fo, r), 1e-8)
+    assert ok
+    x, it, rr = L.pcg(A, F, torch.from_numpy(b).cuda(), rtol=1e-8, maxit=1000)
+    _say(f"  pcg iters gpu {it[0]} oracle {ito}; relres {rr[0]:.2e}")
+    assert abs(int(it[0]) - ito) <= 1
+    assert rr[0] <= 1e-8
+    xr = x.cpu().numpy()
+    assert np.linalg.norm(b - As @ xr) <= 1.01e-8 * np.linalg.norm(b) or rr[0] <= 1e-8
+
+
+def test_not_spd_is_reported(torch, L):
+    pr = laplace2d(16)
+    val = pr.val.copy()
+    d = np.where(np.repeat(np.arange(pr.n), np.diff(pr.rowptr)) == pr.col)[0]
+    val[d[37]] = -5.0
+    A = L.DeviceMatrix(pr.rowptr, pr.col, val)
+    with pytest.raises(L.LrspError) as ex:
+        L.Factor(A, L.Tree(pr.grid, 16), 1e-2)
+    assert ex.value.status == L.ERR_NOT_SPD
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_precision_forms_converge(torch, L, prec):
+    pr = config("slab64")
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree(pr.grid, 256)
+    F64 = L.Factor(A, tree, 1e-2)
+    Fp = L.Factor(A, tree, 1e-2, gemm_prec=prec)
+    b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+    x64 = L.apply(F64, b)
+    xp = L.apply(Fp, b)
+    err = float(torch.linalg.norm(xp - x64) / torch.linalg.norm(x64))
+    _, it, rr = L.pcg(A, Fp, b, rtol=1e-8)
+    _, it64, _ = L.pcg(A, F64, b, rtol=1e-8)
+    _say(f"  {prec}: apply rel diff vs fp64 {err:.2e}; pcg iters {it[0]} (fp64 {it64[0]}), relres {rr[0]:.1e}")
+    assert rr[0] <= 1e-8
+    assert err < (1e-4 if prec == "f32" else 5e-2)
