@@ -1,0 +1,185 @@
+"""Benchmark: time to a 1e-8 PCG residual (factor + PCG) and factor GFLOP/s.
+
+One step = one pass of the whole hot path on one synthetic system already
+resident in HBM: the hierarchical factorization of A (every level: Cholesky,
+scaling, rank-revealing compression, Schur update) followed by PCG with the
+factor as preconditioner until ||r|| <= 1e-8 ||b||.
+
+Workload (default): 64x64x16 extruded slab, 65,536 DoF, 7-point anisotropic
+diffusion (vertical/horizontal 1e4 times a log-normal field, sigma 1,
+correlation 8 cells, seed 1), horizontal-only cluster tree with leaf 256,
+tolerance 1e-2, N(0,1) right-hand side from seed 0.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 residual (factor+PCG) & factor GFLOP/s, plain FP64 vs mixed"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+
+    from paper_1811_11248_amd import lrsp
+    from synth import config, rhs
+
+    pr = config(args.workload)
+    A = lrsp.DeviceMatrix.from_problem(pr)
+    tree = lrsp.Tree(pr.grid, pr.leaf)
+    b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+    torch.cuda.synchronize()
+
+    def step(prec):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        F = lrsp.Factor(A, tree, pr.tol, gemm_prec=prec)
+        e1.record()
+        _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8, maxit=1000)
+        e2.record()
+        return F, e0, e1, e2, int(it[0]), float(rr[0])
+
+    results = {}
+    timing = {}
+    for prec in ["f64"] + ([] if args.no_mixed else ["f32", "bf16"]):
+        nsteps = args.steps if prec == "f64" else max(1, min(args.steps, 3))
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        if prec == "f64":
+            lrsp.timing_reset()
+            lrsp.timing_enable(True)
+        t0 = time.perf_counter()
+        recs = [step(prec) for _ in range(nsteps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if prec == "f64":
+            lrsp.timing_enable(False)
+            timing = {f: lrsp.timing_read(f) for f in ("eliminate", "forward", "backward")}
+        F = recs[-1][0]
+        info = F.info()
+        fl = sum(info["flops"].values())
+        fms = [r[1].elapsed_time(r[2]) for r in recs]
+        pms = [r[2].elapsed_time(r[3]) for r in recs]
+        results[prec] = dict(
+            ms_per_step=(t1 - t0) * 1e3 / nsteps,
+            factor_ms=float(np.median(fms)), pcg_ms=float(np.median(pms)),
+            iters=recs[-1][4], relres=recs[-1][5], factor_gflops=fl / (np.median(fms) * 1e-3) / 1e9,
+            flops=info["flops"], levels=info["nlevels"], top_n=info["top_n"],
+            factor_bytes=info["bytes_factor"])
+        log(f"[{prec}] {results[prec]}")
+    log(f"[timing] {timing}")
+    return pr, results, timing
+
+
+def roofline(timing):
+    """Roofline of the kernel family with the most GPU time in the timed region."""
+    fam = max(timing, key=lambda f: timing[f]["total_ms"])
+    t = timing[fam]
+    sec = t["total_ms"] * 1e-3
+    if fam == "eliminate":
+        ach = t["flops"] / sec / 1e12 if sec > 0 else 0.0
+        return {"kernel": "slre_kernel (cluster elimination)", "bound": "alu",
+                "achieved": round(ach, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP64_PEAK_TFLOPS, 6), "traffic": None,
+                "launches": t["launches"], "avg_launch_us": round(t["total_ms"] * 1e3 / max(1, t["launches"]), 2),
+                "work_per_launch": round(t["flops"] / max(1, t["launches"])), "work_unit": "flop"}
+    ach = t["bytes"] / sec / 1e9 if sec > 0 else 0.0
+    return {"kernel": f"{fam} sweep", "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 6), "traffic": None,
+            "launches": t["launches"], "avg_launch_us": round(t["total_ms"] * 1e3 / max(1, t["launches"]), 2),
+            "work_per_launch": round(t["bytes"] / max(1, t["launches"])), "work_unit": "byte"}
+
+
+def run_cpu_baseline(workload):
+    """The oracle, as it stands, on one full step of the same workload."""
+    import numpy as np
+    import threadpoolctl
+
+    import oracle
+    from synth import config, rhs
+
+    pr = config(workload)
+    As = pr.scipy()
+    b = rhs(pr.n, 0)
+    T = oracle.build_tree(pr.grid, pr.leaf)
+    t0 = time.perf_counter()
+    Fo = oracle.factor(pr.rowptr, pr.col, pr.val, T, pr.tol)
+    t1 = time.perf_counter()
+    _, it, rr, ok = oracle.pcg(lambda v: As @ v, b, lambda r: oracle.solve(Fo, r), 1e-8)
+    t2 = time.perf_counter()
+    info = threadpoolctl.threadpool_info()
+    cores = max([d.get("num_threads", 1) for d in info if d.get("user_api") == "blas"] or [1])
+    return dict(value=(t2 - t0) * 1e3, unit="ms", cores=int(cores), kind="oracle",
+                sample=f"one full step of {workload}: factor {t1 - t0:.1f} s + PCG {t2 - t1:.1f} s "
+                       f"({it} iterations), numpy/OpenBLAS fp64",
+                factor_gflops=sum(Fo.flops.values()) / (t1 - t0) / 1e9)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="slab64")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the solver runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+    pr, res, timing = run_gpu(args)
+    f64 = res["f64"]
+    out = {
+        "metric": METRIC,
+        "value": round(f64["ms_per_step"], 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f64["ms_per_step"], 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {pr.grid[0]}x{pr.grid[1]}x{pr.grid[2]} slab, "
+                               f"{pr.n} DoF, leaf {pr.leaf}, tol {pr.tol}, PCG to 1e-8",
+                   "n": pr.n, "nnz": pr.nnz, "leaf": pr.leaf, "tol": pr.tol},
+        "factor_ms": round(f64["factor_ms"], 4),
+        "pcg_ms": round(f64["pcg_ms"], 4),
+        "pcg_iters": f64["iters"],
+        "relres": f64["relres"],
+        "roofline": roofline(timing),
+        "kernel_families": {f: {"launches": t["launches"], "total_ms": round(t["total_ms"], 4)}
+                            for f, t in timing.items()},
+        "factor_gflops": round(f64["factor_gflops"], 2),
+        "mixed": {p: {k: (round(v, 4) if isinstance(v, float) and k != "relres" else v)
+                      for k, v in res[p].items()
+                      if k in ("ms_per_step", "factor_ms", "pcg_ms", "iters", "relres", "factor_gflops")}
+                  for p in res if p != "f64"},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = run_cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,26 @@ typedef struct {
 } lrsp_level_view;
 lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_level_view* v);
 
+/* ---- measurement ---------------------------------------------------------
+ * When timing is on, the library records a pair of HIP events on the call's
+ * stream around every launch of the kernel families below and accumulates,
+ * per family, the launch count, the summed event durations and the
+ * algorithmic work of those launches (flops of the factorization model:
+ * POTRF m^3/3, TRSM m^2(a+b), CPQR and U^T rotation 4(m-j)(b-j), 4(m-j)a per
+ * reflector, Schur a(a+1)(m-k); bytes of the sweeps: every stored factor
+ * entry read once plus the vector entries read and written).
+ * Families: 0 = cluster elimination (factorization), 1 = forward sweep,
+ * 2 = backward sweep.  lrsp_timing_read synchronises the device. */
+typedef struct {
+  int64_t launches;
+  double total_ms;
+  double flops;
+  double bytes;
+} lrsp_timing;
+lrsp_status lrsp_timing_enable(int32_t on);
+lrsp_status lrsp_timing_reset(void);
+lrsp_status lrsp_timing_read(int32_t family, lrsp_timing* out);
+
 /* Message of the last failing call on this thread (static storage). */
 const char* lrsp_last_error_info(void);
 const char* lrsp_status_str(lrsp_status s);

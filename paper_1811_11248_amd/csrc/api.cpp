@@ -27,6 +27,61 @@ lrsp_status fail(lrsp_status s, const std::string& msg) {
   return s;
 }
 
+// Event timing of kernel families (lrsp_timing_*).
+struct TimingState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
+  int64_t launches[3] = {0, 0, 0};
+  double ms[3] = {0, 0, 0};
+  double flops[3] = {0, 0, 0};
+  double bytes[3] = {0, 0, 0};
+};
+TimingState g_tm;
+
+hipEvent_t tm_event() {
+  if (!g_tm.pool.empty()) {
+    hipEvent_t e = g_tm.pool.back();
+    g_tm.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Records the start event of a timed launch; returns the pending index.
+struct TimedLaunch {
+  int fam;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  TimedLaunch(int f, hipStream_t s) : fam(f), st(s) {
+    if (!g_tm.on) return;
+    a = tm_event();
+    (void)hipEventRecord(a, st);
+  }
+  ~TimedLaunch() {
+    if (!a) return;
+    hipEvent_t b = tm_event();
+    (void)hipEventRecord(b, st);
+    g_tm.pending[fam].push_back({a, b});
+    g_tm.launches[fam]++;
+  }
+};
+
+void tm_collect() {
+  for (int f = 0; f < 3; ++f) {
+    for (auto& pr : g_tm.pending[f]) {
+      float ms = 0.f;
+      (void)hipEventSynchronize(pr.second);
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) g_tm.ms[f] += ms;
+      g_tm.pool.push_back(pr.first);
+      g_tm.pool.push_back(pr.second);
+    }
+    g_tm.pending[f].clear();
+  }
+}
+
 #define HIPCHK(expr)                                                                        \
   do {                                                                                      \
     hipError_t e_ = (expr);                                                                 \
@@ -82,6 +137,7 @@ struct LevelDev {
   DevBuf gidx;             // level >= 1: indices into the previous level's vector
   // adjacency export
   std::vector<int> adj_ptr, adj, sizes_i, colour_i, order_i;
+  std::vector<double> sweep_bytes;  // per colour: bytes one sweep of it moves
 };
 
 }  // namespace
@@ -561,9 +617,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     }
     // eliminate the clusters colour by colour
     const LevelPlan& p = L->plan;
-    for (int c = 0; c < p.ncolours; ++c)
+    for (int c = 0; c < p.ncolours; ++c) {
+      TimedLaunch tl(0, st);
       launch_slre(L->d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L->max_m, L->ls, level,
                   tol, o.tol_mode, o.gemm_prec, st);
+    }
     HIPCHK(hipGetLastError());
     L->k.resize(M);
     L->a.resize(M);
@@ -582,16 +640,25 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
                                          ") at level " + std::to_string(herr[1]) + " cluster " +
                                          std::to_string(herr[2]));
     }
+    double lvl_flops = 0.0;
+    L->sweep_bytes.assign(p.ncolours, 0.0);
     for (int s = 0; s < M; ++s) {
       const double m = p.m[s], a = L->a[s], b = L->b[s], k = L->k[s];
-      flops[0] += m * m * m / 3.0;
-      flops[1] += m * m * (a + b);
+      double f[5] = {m * m * m / 3.0, m * m * (a + b), 0.0, 0.0, a * (a + 1.0) * (m - k)};
       for (int j = 0; j < k; ++j) {
-        flops[2] += 4.0 * (m - j) * (b - j);
-        flops[3] += 4.0 * (m - j) * a;
+        f[2] += 4.0 * (m - j) * (b - j);
+        f[3] += 4.0 * (m - j) * a;
       }
-      flops[4] += a * (a + 1.0) * (m - k);
+      for (int i = 0; i < 5; ++i) {
+        flops[i] += f[i];
+        lvl_flops += f[i];
+      }
+      // one sweep reads G (lower), the k reflectors and F once, and reads
+      // and writes the cluster's and its near field's vector entries
+      L->sweep_bytes[p.colour[s]] +=
+          8.0 * (m * (m + 1) / 2.0 + k * m + (m - k) * a) + 8.0 * (2.0 * m + 2.0 * a);
     }
+    if (g_tm.on) g_tm.flops[0] += lvl_flops;
     // next level
     std::vector<int> nsz(M / 2);
     for (int P = 0; P < M / 2; ++P) nsz[P] = L->k[2 * P] + L->k[2 * P + 1];
@@ -718,8 +785,11 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
   for (int l = 0; l < nl; ++l) {
     const LevelDev& L = *F->levels[l];
     const LevelPlan& p = L.plan;
-    for (int c = 0; c < p.ncolours; ++c)
+    for (int c = 0; c < p.ncolours; ++c) {
+      TimedLaunch tl(1, st);
       launch_fwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.ls, V, st);
+      if (g_tm.on) g_tm.bytes[1] += L.sweep_bytes[c];
+    }
     if (l + 1 < nl) {
       const LevelDev& N = *F->levels[l + 1];
       launch_gather(V, at<int64_t>(N.gidx, 0), V + N.vbase, N.nvec, st);
@@ -737,8 +807,11 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
     } else {
       launch_scatter(V + F->top_vbase, at<int64_t>(F->top_gidx, 0), V, F->top_n, st);
     }
-    for (int c = p.ncolours - 1; c >= 0; --c)
+    for (int c = p.ncolours - 1; c >= 0; --c) {
+      TimedLaunch tl(2, st);
       launch_bwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.ls, V, st);
+      if (g_tm.on) g_tm.bytes[2] += L.sweep_bytes[c];
+    }
   }
   launch_scatter(v0, at<int64_t>(F->perm, 0), x, n, st);
   HIPCHK(hipGetLastError());
@@ -822,6 +895,30 @@ lrsp_status lrsp_pcg(const lrsp_csr* A, const lrsp_factorization* F, const doubl
   }
   if (result != LRSP_OK) g_last_error = "PCG reached maxit";
   return result;
+}
+
+lrsp_status lrsp_timing_enable(int32_t on) {
+  g_tm.on = on != 0;
+  return LRSP_OK;
+}
+
+lrsp_status lrsp_timing_reset(void) {
+  tm_collect();
+  for (int f = 0; f < 3; ++f) {
+    g_tm.launches[f] = 0;
+    g_tm.ms[f] = g_tm.flops[f] = g_tm.bytes[f] = 0.0;
+  }
+  return LRSP_OK;
+}
+
+lrsp_status lrsp_timing_read(int32_t family, lrsp_timing* out) {
+  if (family < 0 || family > 2 || !out) return fail(LRSP_ERR_ARG, "invalid timing family");
+  tm_collect();
+  out->launches = g_tm.launches[family];
+  out->total_ms = g_tm.ms[family];
+  out->flops = g_tm.flops[family];
+  out->bytes = g_tm.bytes[family];
+  return LRSP_OK;
 }
 
 lrsp_status lrsp_factor_info(const lrsp_factorization* F, lrsp_info* info) {

@@ -59,6 +59,11 @@ class LevelView(C.Structure):
                 ("adj_ptr", C.POINTER(C.c_int32)), ("adj", C.POINTER(C.c_int32))]
 
 
+class Timing(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("flops", C.c_double),
+                ("bytes", C.c_double)]
+
+
 # (name, restype, argtypes) of every symbol declared in include/lrsp.h
 SIGNATURES = [
     ("lrsp_tree_build", C.c_int, [C.POINTER(Grid), C.c_int32, C.POINTER(C.c_void_p)]),
@@ -73,6 +78,9 @@ SIGNATURES = [
                            C.c_void_p]),
     ("lrsp_factor_info", C.c_int, [C.c_void_p, C.POINTER(Info)]),
     ("lrsp_factor_level", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(LevelView)]),
+    ("lrsp_timing_enable", C.c_int, [C.c_int32]),
+    ("lrsp_timing_reset", C.c_int, []),
+    ("lrsp_timing_read", C.c_int, [C.c_int32, C.POINTER(Timing)]),
     ("lrsp_last_error_info", C.c_char_p, []),
     ("lrsp_status_str", C.c_char_p, [C.c_int]),
 ]
@@ -233,3 +241,20 @@ def pcg(A: DeviceMatrix, F: Factor, b, rtol=1e-8, maxit=1000, stream=None, raise
         _check(st)
     xo = x if b.dim() == 1 else x.view(nrhs, -1).t()
     return xo, np.array(it[:], dtype=np.int64), np.array(rr[:])
+
+
+TIMING_FAMILIES = {"eliminate": 0, "forward": 1, "backward": 2}
+
+
+def timing_enable(on: bool = True):
+    _check(lib().lrsp_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(lib().lrsp_timing_reset())
+
+
+def timing_read(family: str) -> dict:
+    t = Timing()
+    _check(lib().lrsp_timing_read(TIMING_FAMILIES[family], C.byref(t)))
+    return {"launches": int(t.launches), "total_ms": t.total_ms, "flops": t.flops, "bytes": t.bytes}
