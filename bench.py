@@ -47,16 +47,28 @@ def run_gpu(args):
     torch.cuda.synchronize()
 
     def step(prec):
+        # one factorization + PCG solve; the factor is released at the end of
+        # the step, which hands its level workspaces back to the tree
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
         F = lrsp.Factor(A, tree, pr.tol, gemm_prec=prec)
         e1.record()
         _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8, maxit=1000)
         e2.record()
-        return F, e0, e1, e2, int(it[0]), float(rr[0])
+        info = F.info()
+        del F
+        return info, e0, e1, e2, int(it[0]), float(rr[0])
 
     results = {}
     timing = {}
+    analysis = {}
+    # one-time host analysis of the pattern (reported, not part of a step)
+    t0 = time.perf_counter()
+    F0 = lrsp.Factor(A, tree, pr.tol)
+    torch.cuda.synchronize()
+    analysis_ms = (time.perf_counter() - t0) * 1e3
+    analysis_info = F0.info()
+    del F0
     for prec in ["f64"] + ([] if args.no_mixed else ["f32", "bf16"]):
         nsteps = args.steps if prec == "f64" else max(1, min(args.steps, 3))
         for _ in range(args.warmup):
@@ -72,8 +84,7 @@ def run_gpu(args):
         if prec == "f64":
             lrsp.timing_enable(False)
             timing = {f: lrsp.timing_read(f) for f in ("eliminate", "forward", "backward")}
-        F = recs[-1][0]
-        info = F.info()
+        info = recs[-1][0]
         fl = sum(info["flops"].values())
         fms = [r[1].elapsed_time(r[2]) for r in recs]
         pms = [r[2].elapsed_time(r[3]) for r in recs]
@@ -82,9 +93,11 @@ def run_gpu(args):
             factor_ms=float(np.median(fms)), pcg_ms=float(np.median(pms)),
             iters=recs[-1][4], relres=recs[-1][5], factor_gflops=fl / (np.median(fms) * 1e-3) / 1e9,
             flops=info["flops"], levels=info["nlevels"], top_n=info["top_n"],
-            factor_bytes=info["bytes_factor"])
+            factor_bytes=info["bytes_factor"], levels_reused=info["levels_reused"],
+            ms_analysis_in_step=info["ms_analysis"])
         log(f"[{prec}] {results[prec]}")
     log(f"[timing] {timing}")
+    results["analysis"] = dict(first_factor_ms=analysis_ms, host_analysis_ms=analysis_info["ms_analysis"])
     return pr, results, timing
 
 
@@ -171,10 +184,13 @@ def main():
         "kernel_families": {f: {"launches": t["launches"], "total_ms": round(t["total_ms"], 4)}
                             for f, t in timing.items()},
         "factor_gflops": round(f64["factor_gflops"], 2),
+        "one_time_analysis_ms": round(res["analysis"]["host_analysis_ms"], 2),
+        "first_factor_ms": round(res["analysis"]["first_factor_ms"], 2),
+        "levels_reused": f64["levels_reused"],
         "mixed": {p: {k: (round(v, 4) if isinstance(v, float) and k != "relres" else v)
                       for k, v in res[p].items()
                       if k in ("ms_per_step", "factor_ms", "pcg_ms", "iters", "relres", "factor_gflops")}
-                  for p in res if p != "f64"},
+                  for p in res if p not in ("f64", "analysis")},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(args.workload)

@@ -77,7 +77,11 @@ typedef struct {
                          the result is added to the fp64 matrix */
   int32_t rank_mode;  /* 0: full column-pivoted QR; 1: learned rank (the
                          predicted rank is checked, full QR continues on failure) */
-  int32_t reserved0;
+  int32_t exec_mode;  /* kernel schedule (results agree to rounding): 0 auto;
+                         1 one workgroup per cluster, one launch per colour;
+                         2 one workgroup per cluster, one cooperative launch per
+                         level; 3 several workgroups per cluster for clusters of
+                         96..512 DoFs, else as 2 */
   const float* mlp_weights; /* rank_mode 1: host pointer to the packed MLP
                                parameters (lrsp_mlp_nparams() floats) */
   int64_t reserved[6];
@@ -105,6 +109,15 @@ typedef struct {
   const int64_t* leaf_ptr;
 } lrsp_tree_view;
 lrsp_status lrsp_tree_export(const lrsp_tree* t, lrsp_tree_view* v);
+
+/* ---- analysis reuse ------------------------------------------------------
+ * A tree caches the symbolic analysis of the last matrix pattern factored
+ * with it (level graphs, colouring, fill, block layout, descriptors) together
+ * with the device workspace of each level.  lrsp_factor reuses a level when
+ * the pattern and the sizes of its clusters (the ranks of the level below)
+ * are unchanged, and lrsp_factor_free returns the workspace to the tree.
+ * A factor alive at the same time as another one from the same tree simply
+ * allocates its own workspace.  Results do not depend on reuse. */
 
 /* ---- factorization -----------------------------------------------------
  * Algorithm 1 over the tree: at each level every cluster s, in (colour,
@@ -147,7 +160,12 @@ typedef struct {
   double flops[6];       /* algorithmic flops: potrf, trsm, cpqr, applyq, schur, top */
   double bytes_factor;   /* bytes of the stored factor */
   double ms_levels;      /* wall time of lrsp_factor (host clock, ms) */
-  int64_t peak_bytes;    /* peak device bytes held by the library during lrsp_factor */
+  int64_t peak_bytes;    /* device bytes held by the factor */
+  double ms_analysis;    /* host time spent on symbolic analysis and setup
+                            (zero for levels whose analysis was reused) */
+  int32_t levels_reused; /* levels whose analysis and workspace came from the
+                            tree's cache (same pattern, same ranks below) */
+  int32_t reserved2;
 } lrsp_info;
 lrsp_status lrsp_factor_info(const lrsp_factorization* F, lrsp_info* info);
 
@@ -176,8 +194,12 @@ lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_l
  * POTRF m^3/3, TRSM m^2(a+b), CPQR and U^T rotation 4(m-j)(b-j), 4(m-j)a per
  * reflector, Schur a(a+1)(m-k); bytes of the sweeps: every stored factor
  * entry read once plus the vector entries read and written).
- * Families: 0 = cluster elimination (factorization), 1 = forward sweep,
- * 2 = backward sweep.  lrsp_timing_read synchronises the device. */
+ * Families: 0 = all cluster-elimination launches, 1 = forward sweep,
+ * 2 = backward sweep, 3..9 = the split elimination kernels (3 segment
+ * offsets + gather [bytes], 4 Cholesky, 5 triangular scaling, 6 pivoted
+ * QR, 7 U^T rotation, 8 Schur update, 9 write-back [bytes]), 10 = the
+ * one-workgroup-per-cluster elimination kernel.  lrsp_timing_read
+ * synchronises the device. */
 typedef struct {
   int64_t launches;
   double total_ms;

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblrsp.so")
-SOURCES = ["kernels.hip", "plan.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "split.hip", "plan.cpp", "api.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -28,14 +28,15 @@ lrsp_status fail(lrsp_status s, const std::string& msg) {
 }
 
 // Event timing of kernel families (lrsp_timing_*).
+constexpr int kFamilies = 11;
 struct TimingState {
   bool on = false;
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
-  int64_t launches[3] = {0, 0, 0};
-  double ms[3] = {0, 0, 0};
-  double flops[3] = {0, 0, 0};
-  double bytes[3] = {0, 0, 0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kFamilies];
+  int64_t launches[kFamilies] = {};
+  double ms[kFamilies] = {};
+  double flops[kFamilies] = {};
+  double bytes[kFamilies] = {};
 };
 TimingState g_tm;
 
@@ -70,7 +71,7 @@ struct TimedLaunch {
 };
 
 void tm_collect() {
-  for (int f = 0; f < 3; ++f) {
+  for (int f = 0; f < kFamilies; ++f) {
     for (auto& pr : g_tm.pending[f]) {
       float ms = 0.f;
       (void)hipEventSynchronize(pr.second);
@@ -119,7 +120,10 @@ void dfree(DevBuf* b, hipStream_t st) {
   b->bytes = 0;
 }
 
+uint64_t g_level_ids = 0;
+
 struct LevelDev {
+  const uint64_t id = ++g_level_ids;  // unique per workspace
   LevelPlan plan;
   std::vector<int> k, a, b;
   int max_m = 0;
@@ -138,12 +142,50 @@ struct LevelDev {
   // adjacency export
   std::vector<int> adj_ptr, adj, sizes_i, colour_i, order_i;
   std::vector<double> sweep_bytes;  // per colour: bytes one sweep of it moves
+  std::vector<SplitDims> cdims;     // per colour capacities
+  int max_items = 0;                // largest colour
+  int max_nseg = 0;
+  bool split = false;               // several workgroups per cluster
+  const int32_t* d_cstart = nullptr;
+  DevBuf vals_off;                  // level 0: CSR entry -> work-arena offset
+  DevBuf tasks;                     // level >= 1: assembly copy tasks
+  int ntasks = 0;
+  uint64_t tasks_src = 0;           // id of the level the tasks read from
+  void free_all(hipStream_t st) {
+    dfree(&work, st); dfree(&wints, st); dfree(&fac, st); dfree(&fints, st); dfree(&fvidx, st);
+    dfree(&desc, st); dfree(&state, st); dfree(&gidx, st); dfree(&vals_off, st); dfree(&tasks, st);
+  }
 };
+
+// Analysis of the last pattern factored with a tree, and level workspaces
+// returned by freed factors.
+struct TreeCache {
+  bool have = false;
+  uint64_t hash = 0;
+  int64_t nnz = -1;
+  std::vector<std::vector<int>> adj0;
+  std::unordered_map<uint64_t, std::vector<uint64_t>> z0;
+  std::vector<std::unique_ptr<LevelDev>> levels;
+  hipStream_t stream = nullptr;
+  ~TreeCache() {
+    for (auto& L : levels)
+      if (L) L->free_all(stream);
+    (void)hipStreamSynchronize(stream);
+  }
+};
+
+uint64_t pattern_hash(const int64_t* rp, const int32_t* cl, int64_t n, int64_t nnz) {
+  uint64_t h = 1469598103934665603ull ^ (uint64_t)n ^ ((uint64_t)nnz << 32);
+  for (int64_t i = 0; i <= n; ++i) h = (h ^ (uint64_t)rp[i]) * 1099511628211ull;
+  for (int64_t e = 0; e < nnz; ++e) h = (h ^ (uint32_t)cl[e]) * 1099511628211ull;
+  return h;
+}
 
 }  // namespace
 
 struct lrsp_tree {
   TreeH t;
+  std::shared_ptr<TreeCache> cache = std::make_shared<TreeCache>();
 };
 
 struct lrsp_factorization {
@@ -163,11 +205,21 @@ struct lrsp_factorization {
   size_t scratch_n = 0;
   lrsp_info info{};
   hipStream_t stream = nullptr;
+  std::weak_ptr<TreeCache> cache;
+  uint64_t pattern = 0;
   ~lrsp_factorization() {
-    for (auto& L : levels) {
-      dfree(&L->work, stream); dfree(&L->wints, stream); dfree(&L->fac, stream);
-      dfree(&L->fints, stream); dfree(&L->fvidx, stream); dfree(&L->desc, stream);
-      dfree(&L->state, stream); dfree(&L->gidx, stream);
+    std::shared_ptr<TreeCache> c = cache.lock();
+    const bool give = c && c->have && c->hash == pattern;
+    for (size_t l = 0; l < levels.size(); ++l) {
+      if (!levels[l]) continue;
+      if (give) {
+        if (c->levels.size() <= l) c->levels.resize(l + 1);
+        if (c->levels[l]) c->levels[l]->free_all(stream);
+        c->levels[l] = std::move(levels[l]);
+        c->stream = stream;
+      } else {
+        levels[l]->free_all(stream);
+      }
     }
     dfree(&top, stream); dfree(&top_gidx, stream); dfree(&perm, stream); dfree(&vec, stream);
     dfree(&scratch, stream);
@@ -387,10 +439,11 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase) {
       }
   }
   const size_t bs = sizeof(SegD) * segs.size(), bp = sizeof(PairD) * pairs.size(),
-               bw = sizeof(WbD) * wbs.size(), bi = sizeof(ItemD) * M;
+               bw = sizeof(WbD) * wbs.size(), bi = sizeof(ItemD) * M,
+               bc = sizeof(int32_t) * (p.ncolours + 1);
   const size_t o1 = (bs + 255) & ~(size_t)255, o2 = o1 + ((bp + 255) & ~(size_t)255),
-               o3 = o2 + ((bw + 255) & ~(size_t)255);
-  HIPCHK(dalloc(&L->desc, o3 + bi, st));
+               o3 = o2 + ((bw + 255) & ~(size_t)255), o4 = o3 + ((bi + 255) & ~(size_t)255);
+  HIPCHK(dalloc(&L->desc, o4 + bc, st));
   char* db = reinterpret_cast<char*>(L->desc.p);
   double* F = at<double>(L->fac, 0);
   int32_t* FI = at<int32_t>(L->fints, 0);
@@ -419,13 +472,31 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase) {
     it.vidx = FV + vxoff[s];
     it.voff = L->voff[s];
   }
-  std::vector<char> blob(o3 + bi, 0);
+  std::vector<char> blob(o4 + bc, 0);
   if (bs) std::memcpy(blob.data(), segs.data(), bs);
   if (bp) std::memcpy(blob.data() + o1, pairs.data(), bp);
   if (bw) std::memcpy(blob.data() + o2, wbs.data(), bw);
   std::memcpy(blob.data() + o3, items.data(), bi);
+  std::memcpy(blob.data() + o4, p.cstart.data(), bc);
   HIPCHK(hipMemcpyAsync(db, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
   L->d_items = reinterpret_cast<ItemD*>(db + o3);
+  L->d_cstart = reinterpret_cast<const int32_t*>(db + o4);
+  // per-colour capacities
+  L->cdims.assign(p.ncolours, SplitDims{0, 0, 0, 0});
+  L->max_items = 0;
+  L->max_nseg = 0;
+  for (int c = 0; c < p.ncolours; ++c) {
+    L->max_items = std::max(L->max_items, p.cstart[c + 1] - p.cstart[c]);
+    SplitDims& d = L->cdims[c];
+    for (int idx = p.cstart[c]; idx < p.cstart[c + 1]; ++idx) {
+      const ItemD& it = items[idx];
+      d.max_m = std::max(d.max_m, it.m);
+      d.max_nseg = std::max(d.max_nseg, it.nseg);
+      d.max_pcap = std::max(d.max_pcap, it.pcap);
+      d.max_acap = std::max(d.max_acap, p.acap[it.s]);
+    }
+    L->max_nseg = std::max(L->max_nseg, d.max_nseg);
+  }
   // hipMemcpyAsync from pageable memory may return before the copy is done
   HIPCHK(hipStreamSynchronize(st));
   // export copies
@@ -506,7 +577,8 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   if (!A->rowptr || !A->col || !A->val) return fail(LRSP_ERR_ARG, "null CSR array");
   lrsp_opts o{};
   if (opts) o = *opts;
-  if (o.gemm_prec < 0 || o.gemm_prec > 2 || o.tol_mode < 0 || o.tol_mode > 1)
+  if (o.gemm_prec < 0 || o.gemm_prec > 2 || o.tol_mode < 0 || o.tol_mode > 1 || o.exec_mode < 0 ||
+      o.exec_mode > 3)
     return fail(LRSP_ERR_ARG, "invalid option");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
@@ -529,27 +601,48 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   auto F = std::make_unique<lrsp_factorization>();
   F->n = A->n;
   F->stream = st;
+  double ms_an = 0.0;
+  auto tick = [] { return std::chrono::steady_clock::now(); };
+  auto ms_since = [](std::chrono::steady_clock::time_point t) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+  };
+  std::shared_ptr<TreeCache> cache = T->cache;
+  F->cache = cache;
   // level 0 clusters and graph
   std::vector<int> sizes(tr.leaf_ptr.size() - 1);
   for (size_t c = 0; c + 1 < tr.leaf_ptr.size(); ++c)
     sizes[c] = (int)(tr.leaf_ptr[c + 1] - tr.leaf_ptr[c]);
-  std::vector<std::vector<int>> adj;
-  level0_graph(tr, rp, cl, &adj);
-  // initial fine column sets of level-0 blocks
-  std::unordered_map<uint64_t, std::vector<uint64_t>> z0;
-  for (int64_t i = 0; i < tr.n; ++i) {
-    const int p = tr.dof_cluster[i];
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-      const int j = cl[e];
-      if (j < 0 || j >= tr.n) return fail(LRSP_ERR_ARG, "column index out of range");
-      const int q = tr.dof_cluster[j];
-      if (q == p) continue;
-      std::vector<uint64_t>& b = z0[pkey(p, q)];
-      if (b.empty()) b.assign((sizes[q] + 63) / 64, 0);
-      const int lj = tr.dof_local[j];
-      b[lj >> 6] |= 1ull << (lj & 63);
+  const uint64_t ph = pattern_hash(rp, cl, A->n, A->nnz);
+  F->pattern = ph;
+  if (!(cache->have && cache->hash == ph && cache->nnz == A->nnz)) {
+    const auto ta = tick();
+    for (auto& Lc : cache->levels)
+      if (Lc) Lc->free_all(st);
+    cache->levels.clear();
+    cache->have = false;
+    level0_graph(tr, rp, cl, &cache->adj0);
+    // initial fine column sets of level-0 blocks
+    cache->z0.clear();
+    for (int64_t i = 0; i < tr.n; ++i) {
+      const int p = tr.dof_cluster[i];
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = cl[e];
+        if (j < 0 || j >= tr.n) return fail(LRSP_ERR_ARG, "column index out of range");
+        const int q = tr.dof_cluster[j];
+        if (q == p) continue;
+        std::vector<uint64_t>& b = cache->z0[pkey(p, q)];
+        if (b.empty()) b.assign((sizes[q] + 63) / 64, 0);
+        const int lj = tr.dof_local[j];
+        b[lj >> 6] |= 1ull << (lj & 63);
+      }
     }
+    cache->have = true;
+    cache->hash = ph;
+    cache->nnz = A->nnz;
+    ms_an += ms_since(ta);
   }
+  std::vector<std::vector<int>> adj = cache->adj0;
+  int reused = 0;
   HIPCHK(dalloc(&F->perm, sizeof(int64_t) * tr.n, st));
   HIPCHK(hipMemcpyAsync(F->perm.p, tr.perm.data(), sizeof(int64_t) * tr.n, hipMemcpyHostToDevice, st));
   double flops[6] = {0, 0, 0, 0, 0, 0};
@@ -560,16 +653,32 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   while (true) {
     const int M = (int)sizes.size();
     if (M == 1 || complete_graph(adj)) break;
-    auto Lp = std::make_unique<LevelDev>();
+    std::unique_ptr<LevelDev> Lp;
+    bool reuse = false;
+    if ((int)cache->levels.size() > level && cache->levels[level] &&
+        cache->levels[level]->plan.m == sizes && cache->levels[level]->vbase == vbase) {
+      Lp = std::move(cache->levels[level]);
+      reuse = true;
+      ++reused;
+    }
+    const auto ta = tick();
+    if (!reuse) {
+      Lp = std::make_unique<LevelDev>();
+      Lp->plan.M = M;
+      Lp->plan.m = sizes;
+      Lp->plan.adj = adj;
+      plan_level(&Lp->plan, level == 0 ? &cache->z0 : nullptr);
+      if (lrsp_status s = setup_level(Lp.get(), st, vbase)) return s;
+    } else {
+      launch_zero(at<double>(Lp->work, 0), Lp->plan.work_doubles, st);
+      launch_zero_i32(at<int32_t>(Lp->state, 0), 3 * (int64_t)M + 8, st);
+    }
     LevelDev* L = Lp.get();
-    L->plan.M = M;
-    L->plan.m = sizes;
-    L->plan.adj = adj;
-    plan_level(&L->plan, level == 0 ? &z0 : nullptr);
-    if (lrsp_status s = setup_level(L, st, vbase)) return s;
     vbase += L->nvec;
     // assemble the level's matrix
-    if (level == 0) {
+    if (level == 0 && L->vals_off.p) {
+      launch_scatter_vals(A->val, at<int64_t>(L->vals_off, 0), A->nnz, at<double>(L->work, 0), st);
+    } else if (level == 0) {
       std::vector<int64_t> off(A->nnz, -1);
       const LevelPlan& p = L->plan;
       for (int64_t i = 0; i < tr.n; ++i) {
@@ -589,38 +698,61 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
           }
         }
       }
-      DevBuf doff;
-      if (lrsp_status s = upload(&doff, off.data(), off.size() * 8, st)) return s;
-      launch_scatter_vals(A->val, at<int64_t>(doff, 0), A->nnz, at<double>(L->work, 0), st);
-      dfree(&doff, st);
+      if (lrsp_status s = upload(&L->vals_off, off.data(), off.size() * 8, st)) return s;
+      launch_scatter_vals(A->val, at<int64_t>(L->vals_off, 0), A->nnz, at<double>(L->work, 0), st);
     } else {
-      std::vector<CopyD> tasks;
-      if (!assembly_tasks(*prev, *L, &tasks))
-        return fail(LRSP_ERR_INTERNAL, "coarse fine-half block is not dense");
-      DevBuf dt;
-      if (!tasks.empty()) {
-        if (lrsp_status s = upload(&dt, tasks.data(), tasks.size() * sizeof(CopyD), st)) return s;
-        launch_copy_blocks(at<CopyD>(dt, 0), (int)tasks.size(), st);
-        dfree(&dt, st);
+      if (!(reuse && L->tasks_src == prev->id)) {
+        std::vector<CopyD> tasks;
+        if (!assembly_tasks(*prev, *L, &tasks))
+          return fail(LRSP_ERR_INTERNAL, "coarse fine-half block is not dense");
+        dfree(&L->tasks, st);
+        L->ntasks = (int)tasks.size();
+        if (!tasks.empty())
+          if (lrsp_status s = upload(&L->tasks, tasks.data(), tasks.size() * sizeof(CopyD), st)) return s;
+        L->tasks_src = prev->id;
+        // gather indices into the previous level's vector
+        std::vector<int64_t> g;
+        g.reserve(L->nvec);
+        for (int P = 0; P < M; ++P)
+          for (int c = 0; c < 2; ++c) {
+            const int x = 2 * P + c;
+            for (int i = 0; i < prev->k[x]; ++i) g.push_back(prev->voff[x] + i);
+          }
+        dfree(&L->gidx, st);
+        if (lrsp_status s = upload(&L->gidx, g.data(), g.size() * 8, st)) return s;
       }
-      dfree(&prev->work, st);
-      dfree(&prev->wints, st);
-      // gather indices into the previous level's vector
-      std::vector<int64_t> g;
-      g.reserve(L->nvec);
-      for (int P = 0; P < M; ++P)
-        for (int c = 0; c < 2; ++c) {
-          const int x = 2 * P + c;
-          for (int i = 0; i < prev->k[x]; ++i) g.push_back(prev->voff[x] + i);
-        }
-      if (lrsp_status s = upload(&L->gidx, g.data(), g.size() * 8, st)) return s;
+      if (L->ntasks > 0) launch_copy_blocks(at<CopyD>(L->tasks, 0), L->ntasks, st);
     }
+    if (!reuse) ms_an += ms_since(ta);
     // eliminate the clusters colour by colour
     const LevelPlan& p = L->plan;
-    for (int c = 0; c < p.ncolours; ++c) {
-      TimedLaunch tl(0, st);
-      launch_slre(L->d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L->max_m, L->ls, level,
-                  tol, o.tol_mode, o.gemm_prec, st);
+    const int mode = o.exec_mode == 0 ? 3 : o.exec_mode;
+    L->split = mode == 3 && L->max_m >= kSplitMinDofs && L->max_m <= kSplitMaxDofs;
+    bool done = false;
+    if (L->split) {
+      for (int c = 0; c < p.ncolours; ++c) {
+        TimedLaunch tall(0, st);
+        for (int step = 0; step < kSplitSteps; ++step) {
+          static const int fam[kSplitSteps] = {3, 3, 4, 5, 6, 7, 8, 9};
+          TimedLaunch ts(fam[step], st);
+          launch_split_step(step, L->d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L->cdims[c],
+                            L->ls, level, tol, o.tol_mode, o.gemm_prec, st);
+        }
+      }
+      done = true;
+    } else if (mode >= 2) {
+      TimedLaunch tall(0, st), tf(10, st);
+      done = launch_slre_level(L->d_items, L->d_cstart, p.ncolours, L->max_items, L->max_m,
+                               L->max_nseg, L->ls, level, tol, o.tol_mode, o.gemm_prec,
+                               st) == hipSuccess;
+      if (!done) (void)hipGetLastError();
+    }
+    if (!done) {
+      for (int c = 0; c < p.ncolours; ++c) {
+        TimedLaunch tall(0, st), tf(10, st);
+        launch_slre(L->d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L->max_m, L->max_nseg,
+                    L->ls, level, tol, o.tol_mode, o.gemm_prec, st);
+      }
     }
     HIPCHK(hipGetLastError());
     L->k.resize(M);
@@ -653,12 +785,20 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
         flops[i] += f[i];
         lvl_flops += f[i];
       }
+      if (g_tm.on && L->split) {
+        for (int i = 0; i < 5; ++i) g_tm.flops[4 + i] += f[i];
+        g_tm.bytes[3] += 16.0 * m * (m + a + b);  // panel gathered: read + write
+        g_tm.bytes[9] += 16.0 * k * (a + b);
+      }
       // one sweep reads G (lower), the k reflectors and F once, and reads
       // and writes the cluster's and its near field's vector entries
       L->sweep_bytes[p.colour[s]] +=
           8.0 * (m * (m + 1) / 2.0 + k * m + (m - k) * a) + 8.0 * (2.0 * m + 2.0 * a);
     }
-    if (g_tm.on) g_tm.flops[0] += lvl_flops;
+    if (g_tm.on) {
+      g_tm.flops[0] += lvl_flops;
+      if (!L->split) g_tm.flops[10] += lvl_flops;
+    }
     // next level
     std::vector<int> nsz(M / 2);
     for (int P = 0; P < M / 2; ++P) nsz[P] = L->k[2 * P] + L->k[2 * P + 1];
@@ -726,8 +866,6 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       launch_copy_blocks(at<CopyD>(dt, 0), (int)tasks.size(), st);
       dfree(&dt, st);
     }
-    dfree(&prev->work, st);
-    dfree(&prev->wints, st);
     std::vector<int64_t> g;
     for (int P = 0; P < M; ++P)
       for (int c = 0; c < 2; ++c) {
@@ -761,6 +899,13 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   for (auto& L : F->levels) fb += (double)L->fac.bytes;
   inf.bytes_factor = fb;
   inf.ms_levels = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  inf.ms_analysis = ms_an;
+  inf.levels_reused = reused;
+  int64_t held = 0;
+  for (auto& L : F->levels)
+    held += (int64_t)(L->work.bytes + L->wints.bytes + L->fac.bytes + L->fints.bytes + L->fvidx.bytes +
+                      L->desc.bytes + L->state.bytes + L->gidx.bytes + L->vals_off.bytes + L->tasks.bytes);
+  inf.peak_bytes = held + (int64_t)(F->top.bytes + F->vec.bytes + F->perm.bytes);
   *out = F.release();
   return LRSP_OK;
 }
@@ -785,10 +930,16 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
   for (int l = 0; l < nl; ++l) {
     const LevelDev& L = *F->levels[l];
     const LevelPlan& p = L.plan;
-    for (int c = 0; c < p.ncolours; ++c) {
+    {
       TimedLaunch tl(1, st);
-      launch_fwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.ls, V, st);
-      if (g_tm.on) g_tm.bytes[1] += L.sweep_bytes[c];
+      if (launch_sweep_level(true, L.d_items, L.d_cstart, p.ncolours, L.max_items, L.max_m, L.ls, V,
+                             st) != hipSuccess) {
+        (void)hipGetLastError();
+        for (int c = 0; c < p.ncolours; ++c)
+          launch_fwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.ls, V, st);
+      }
+      if (g_tm.on)
+        for (double by : L.sweep_bytes) g_tm.bytes[1] += by;
     }
     if (l + 1 < nl) {
       const LevelDev& N = *F->levels[l + 1];
@@ -807,10 +958,16 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
     } else {
       launch_scatter(V + F->top_vbase, at<int64_t>(F->top_gidx, 0), V, F->top_n, st);
     }
-    for (int c = p.ncolours - 1; c >= 0; --c) {
+    {
       TimedLaunch tl(2, st);
-      launch_bwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.ls, V, st);
-      if (g_tm.on) g_tm.bytes[2] += L.sweep_bytes[c];
+      if (launch_sweep_level(false, L.d_items, L.d_cstart, p.ncolours, L.max_items, L.max_m, L.ls, V,
+                             st) != hipSuccess) {
+        (void)hipGetLastError();
+        for (int c = p.ncolours - 1; c >= 0; --c)
+          launch_bwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.ls, V, st);
+      }
+      if (g_tm.on)
+        for (double by : L.sweep_bytes) g_tm.bytes[2] += by;
     }
   }
   launch_scatter(v0, at<int64_t>(F->perm, 0), x, n, st);
@@ -904,7 +1061,7 @@ lrsp_status lrsp_timing_enable(int32_t on) {
 
 lrsp_status lrsp_timing_reset(void) {
   tm_collect();
-  for (int f = 0; f < 3; ++f) {
+  for (int f = 0; f < kFamilies; ++f) {
     g_tm.launches[f] = 0;
     g_tm.ms[f] = g_tm.flops[f] = g_tm.bytes[f] = 0.0;
   }
@@ -912,7 +1069,7 @@ lrsp_status lrsp_timing_reset(void) {
 }
 
 lrsp_status lrsp_timing_read(int32_t family, lrsp_timing* out) {
-  if (family < 0 || family > 2 || !out) return fail(LRSP_ERR_ARG, "invalid timing family");
+  if (family < 0 || family >= kFamilies || !out) return fail(LRSP_ERR_ARG, "invalid timing family");
   tm_collect();
   out->launches = g_tm.launches[family];
   out->total_ms = g_tm.ms[family];

@@ -1,0 +1,134 @@
+// devutil.hpp -- device helpers shared by the gfx950 kernels: wave64 and
+// workgroup reductions, error reporting, MFMA operand types.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "desc.hpp"
+
+namespace lrsp {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+constexpr double kTie = 1e-10;  // pivot tie window of the column-pivoted QR
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup (nt threads, nt/64 <= 16 waves); every thread gets
+// the result.  sh: >= nt/64 doubles of LDS.
+template <int NT>
+__device__ __forceinline__ double group_sum(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) r += sh[i];
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ double group_max(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) r = fmax(r, sh[i]);
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ int group_min_int(int v, int* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int r = sh[0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) r = min(r, sh[i]);
+  return r;
+}
+
+__device__ __forceinline__ void set_error(int32_t* err, int level, int cluster, int code) {
+  if (atomicCAS(&err[0], 0, 1) == 0) {
+    err[1] = level;
+    err[2] = cluster;
+    err[3] = code;
+  }
+}
+
+// Column-major lower-triangular tile enumeration: index -> (R, C), R >= C.
+__device__ __forceinline__ void tri_tile(int idx, int nt, int& R, int& C) {
+  double b = 2.0 * nt + 1.0;
+  int c = (int)((b - sqrt(b * b - 8.0 * idx)) * 0.5);
+  if (c < 0) c = 0;
+  while (c > 0 && (long)c * nt - (long)c * (c - 1) / 2 > idx) --c;
+  while ((long)(c + 1) * nt - (long)(c + 1) * c / 2 <= idx) ++c;
+  C = c;
+  R = c + (idx - (c * nt - c * (c - 1) / 2));
+}
+
+__device__ __forceinline__ float round_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(u);
+}
+
+// MFMA tiles, lane l of a wave64 (layouts checked on gfx950):
+//   f64 16x16x4 : A[l%16][l/16], B[l/16][l%16], D[4i + l/16][l%16]
+//   f32 16x16x4 : A[l%16][l/16], B[l/16][l%16], D[4(l/16) + i][l%16]
+//   bf16 16x16x16: A[l%16][4(l/16)+j], B[4(l/16)+j][l%16], D as f32
+__device__ __forceinline__ int mfma64_row(int lane, int i) { return 4 * i + (lane >> 4); }
+__device__ __forceinline__ int mfma32_row(int lane, int i) { return 4 * (lane >> 4) + i; }
+
+// Copies a rows x cols column-major global block (leading dimension lds_src)
+// into LDS with row stride ldd (dst[r*ldd + c]), zero outside `valid`
+// (valid(r, c) decides), with NT threads and 8 loads in flight per thread.
+template <int NT, class Valid>
+__device__ __forceinline__ void load_block_rowmajor(double* dst, int ldd, const double* src, size_t ld_src,
+                                                    int rows, int cols, Valid valid) {
+  const int n = rows * cols;
+  for (int e0 = threadIdx.x; e0 < n; e0 += NT * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT;
+      const int c = e / rows, r = e - c * rows;
+      v[u] = (e < n && valid(r, c)) ? src[(size_t)r + ld_src * c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT;
+      if (e < n) {
+        const int c = e / rows, r = e - c * rows;
+        dst[r * ldd + c] = v[u];
+      }
+    }
+  }
+}
+
+// Stores an LDS block (row stride ldd) to a column-major global block.
+template <int NT>
+__device__ __forceinline__ void store_block_rowmajor(double* dst, size_t ld_dst, const double* src, int ldd,
+                                                     int rows, int cols) {
+  const int n = rows * cols;
+  for (int e = threadIdx.x; e < n; e += NT) {
+    const int c = e / rows, r = e - c * rows;
+    dst[(size_t)r + ld_dst * c] = src[r * ldd + c];
+  }
+}
+
+}  // namespace lrsp

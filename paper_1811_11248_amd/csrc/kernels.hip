@@ -5,10 +5,14 @@
 // blocks, so a colour is one launch with one workgroup per cluster.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "desc.hpp"
+#include "devutil.hpp"
 #include "kernels.hpp"
 
 namespace lrsp {
@@ -17,68 +21,10 @@ namespace {
 
 constexpr int kWaves = kThreads / 64;
 constexpr int kRegRows = kMaxClusterDofs / 64;  // column slots per lane
-constexpr double kTie = 1e-10;                    // pivot tie window
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = 0.0;
-#pragma unroll
-  for (int i = 0; i < kWaves; ++i) r += sh[i];
-  return r;
-}
-
-__device__ __forceinline__ double block_max(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = sh[0];
-#pragma unroll
-  for (int i = 1; i < kWaves; ++i) r = fmax(r, sh[i]);
-  return r;
-}
-
-__device__ __forceinline__ int block_min_int(int v, int* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int r = sh[0];
-#pragma unroll
-  for (int i = 1; i < kWaves; ++i) r = min(r, sh[i]);
-  return r;
-}
-
-__device__ void set_error(int32_t* err, int level, int cluster, int code) {
-  if (atomicCAS(&err[0], 0, 1) == 0) {
-    err[1] = level;
-    err[2] = cluster;
-    err[3] = code;
-  }
-}
-
-// Column-major lower-triangular tile enumeration: tile index -> (R, C), R >= C.
-__device__ __forceinline__ void tri_tile(int idx, int nt, int& R, int& C) {
-  // S(C) = C*nt - C*(C-1)/2 tiles precede column C
-  double b = 2.0 * nt + 1.0;
-  int c = (int)((b - sqrt(b * b - 8.0 * idx)) * 0.5);
-  if (c < 0) c = 0;
-  while (c > 0 && (long)c * nt - (long)c * (c - 1) / 2 > idx) --c;
-  while ((long)(c + 1) * nt - (long)(c + 1) * c / 2 <= idx) ++c;
-  C = c;
-  R = c + (idx - (c * nt - c * (c - 1) / 2));
-}
+__device__ __forceinline__ double block_sum(double v, double* sh) { return group_sum<kThreads>(v, sh); }
+__device__ __forceinline__ double block_max(double v, double* sh) { return group_max<kThreads>(v, sh); }
+__device__ __forceinline__ int block_min_int(int v, int* sh) { return group_min_int<kThreads>(v, sh); }
 
 // ---------------------------------------------------------------------------
 // Blocked right-looking Cholesky of the lower triangle of the m x m matrix A
@@ -388,12 +334,6 @@ __device__ void apply_qt_cols(double* C, int ld, int m, int a, const double* W, 
   }
 }
 
-__device__ __forceinline__ float round_bf16(float x) {
-  uint32_t u = __float_as_uint(x);
-  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
-  return __uint_as_float(u);
-}
-
 // Schur update X -= F^T F, F = rows k..m-1 of the a near-field columns C (ld).
 // Each unordered column pair (r >= c) is computed once and scattered to the
 // one block that owns it.
@@ -482,62 +422,115 @@ __device__ void schur_scatter(const ItemD& it, const double* C, int ld, int m, i
   }
 }
 
-}  // namespace
-
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) slre_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                        int level, double tol, int tol_mode, int prec) {
-  extern __shared__ double lds[];
-  __shared__ double shd[kWaves];
-  __shared__ int shi[kWaves];
-  __shared__ int sab[4];
-  __shared__ int sbad;
-  const ItemD& it = items[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int m = it.m;
-  // widths of the column segments (coarse ones depend on earlier ranks)
-  if (tid == 0) {
-    int off = 0, a = 0, bad = 0;
-    for (int i = 0; i < it.nseg; ++i) {
+// Widths of the column segments (coarse ones are earlier ranks), their
+// exclusive prefix sum into soff[0..nseg] (LDS) and it.segoff, and the near
+// and far widths.  Returns false (after recording the error) when a width
+// exceeds its capacity.
+__device__ bool seg_scan(const ItemD& it, LevelState ls, int level, int* soff, int* wsum, int* flag,
+                         int& a_out, int& b_out) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nseg = it.nseg;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  int carry = 0;
+  for (int base = 0; base < nseg; base += kThreads) {
+    const int i = base + tid;
+    int w = 0;
+    if (i < nseg) {
       const SegD& sg = it.seg[i];
-      int w = sg.coarse ? ls.k[sg.y] : sg.nfine;
-      if (w > sg.cap || w < 0) {
-        bad = 1;
+      w = sg.coarse ? ls.k[sg.y] : sg.nfine;
+      if (w < 0 || w > sg.cap) {
+        *flag = 1;
         w = 0;
       }
-      it.segoff[i] = off;
-      off += w;
-      if (i + 1 == it.nsegn) a = off;
     }
-    it.segoff[it.nseg] = off;
-    if (off > it.pcap) bad = 1;
-    sab[0] = a;
-    sab[1] = off - a;
-    sab[2] = bad;
-    sbad = 0;
+    int x = w;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int pre = 0;
+    for (int q = 0; q < wv; ++q) pre += wsum[q];
+    int tot = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) tot += wsum[q];
+    if (i < nseg) soff[i] = carry + pre + x - w;
+    carry += tot;
+    __syncthreads();
   }
+  if (tid == 0) soff[nseg] = carry;
   __syncthreads();
-  if (sab[2]) {
-    if (tid == 0) set_error(ls.err, level, it.s, kErrCapacity);
+  a_out = soff[it.nsegn];
+  b_out = soff[nseg] - a_out;
+  const bool bad = *flag || soff[nseg] > it.pcap;
+  for (int i = tid; i <= nseg; i += kThreads) it.segoff[i] = soff[i];
+  if (bad && tid == 0) set_error(ls.err, level, it.s, kErrCapacity);
+  __syncthreads();
+  return !bad;
+}
+
+// One scaled low-rank elimination W_s = P_s G_s E_s S_s by one workgroup.
+// lds: m*kNB + kNB*kNB + kNB*256 doubles, then nseg+1 ints.
+__device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol, int tol_mode,
+                          int prec, double* lds, int* soff) {
+  __shared__ double shd[kWaves];
+  __shared__ int shi[kWaves];
+  __shared__ int wsum[kWaves];
+  __shared__ int sflag, sbad;
+  const int tid = threadIdx.x;
+  const int m = it.m;
+  int a = 0, b = 0;
+  if (!seg_scan(it, ls, level, soff, wsum, &sflag, a, b)) {
+    if (tid == 0) {
+      ls.k[it.s] = 0;
+      ls.a[it.s] = 0;
+      ls.b[it.s] = 0;
+    }
     return;
   }
-  const int a = sab[0], b = sab[1];
   double* P = it.P;
   const size_t ld = (size_t)m;
-  // gather the block row [A_ss | A_sn | A_sw]
-  for (size_t e = tid; e < ld * m; e += kThreads) P[e] = it.D[e];
-  for (int i = 0; i < it.nseg; ++i) {
-    const SegD& sg = it.seg[i];
-    const int c0 = it.segoff[i];
-    const int w = it.segoff[i + 1] - c0;
-    for (size_t e = tid; e < (size_t)w * m; e += kThreads) P[ld * (m + c0) + e] = sg.src[e];
-    for (int c = tid; c < w; c += kThreads) {
-      const int nat = sg.coarse ? c : sg.zl[c];
-      it.colseg[c0 + c] = i;
-      it.colnat[c0 + c] = nat;
-      it.vidx[c0 + c] = sg.voff + nat;
+  const int lane = tid & 63, wv = tid >> 6;
+  // gather [A_ss | A_sn | A_sw]: one column per wave, rows in registers
+  const int ncols = m + a + b;
+  for (int c = wv; c < ncols; c += kWaves) {
+    const double* src;
+    if (c < m) {
+      src = it.D + ld * c;
+    } else {
+      const int pc = c - m;
+      int lo = 0, hi = it.nseg - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (soff[mid] <= pc) lo = mid;
+        else hi = mid - 1;
+      }
+      const SegD& sg = it.seg[lo];
+      const int loc = pc - soff[lo];
+      src = sg.src + ld * loc;
+      if (lane == 0) {
+        const int nat = sg.coarse ? loc : sg.zl[loc];
+        it.colseg[pc] = lo;
+        it.colnat[pc] = nat;
+        it.vidx[pc] = sg.voff + nat;
+      }
+    }
+    double v[kRegRows];
+#pragma unroll
+    for (int t = 0; t < kRegRows; ++t) {
+      const int r = lane + 64 * t;
+      v[t] = r < m ? src[r] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kRegRows; ++t) {
+      const int r = lane + 64 * t;
+      if (r < m) P[ld * c + r] = v[t];
     }
   }
+  if (tid == 0) sbad = 0;
   __syncthreads();
   // S_s: Cholesky of A_ss and scaling of the block row
   chol_solve(P, m, m, P + ld * m, a + b, lds, &sbad);
@@ -550,7 +543,7 @@ __global__ void __launch_bounds__(kThreads) slre_kernel(const ItemD* __restrict_
     k = cpqr(Wf, m, m, b, tol, tol_mode, it.piv, it.stepof, it.tau, it.norms, shd, shi);
   if (k > it.kcap) {
     if (tid == 0) set_error(ls.err, level, it.s, kErrCapacity);
-    return;
+    k = it.kcap;
   }
   __syncthreads();
   // E_s: rotate the near-field columns, C = U^T G^{-1} A_sn
@@ -560,26 +553,21 @@ __global__ void __launch_bounds__(kThreads) slre_kernel(const ItemD* __restrict_
   // G_s: eliminate the fine DoFs, X_nn -= F^T F
   if (m > k && a > 0) schur_scatter(it, C, m, m, k, a, prec, ls.err, level);
   // coarse row of s: [I_k | C[:k] | V1^T]
-  for (int i = 0; i < it.nseg; ++i) {
-    const WbD& t = it.wb[i];
-    const int c0 = it.segoff[i];
-    const int w = it.segoff[i + 1] - c0;
-    for (int e = tid; e < k * w; e += kThreads) {
-      const int r = e % k, cl = e / k;
-      const int pc = c0 + cl;
-      const int cn = it.colnat[pc];
-      double v = P[(size_t)r + ld * (m + pc)];
-      if (pc >= a) {
-        const int st = it.stepof[pc - a];
-        if (st >= 0 && r > st) v = 0.0;
-      }
-      const int row = t.trans ? cn : r, col = t.trans ? r : cn;
-      if (row >= t.nrows || col >= t.ncols) {
-        set_error(ls.err, level, it.s, kErrIndex);
-        continue;
-      }
-      t.dst[(size_t)row + (size_t)t.ld * col] = v;
+  for (int e = tid; e < k * (a + b); e += kThreads) {
+    const int r = e % k, pc = e / k;
+    const WbD& t = it.wb[it.colseg[pc]];
+    const int cn = it.colnat[pc];
+    double v = P[(size_t)r + ld * (m + pc)];
+    if (pc >= a) {
+      const int st = it.stepof[pc - a];
+      if (st >= 0 && r > st) v = 0.0;
     }
+    const int row = t.trans ? cn : r, col = t.trans ? r : cn;
+    if (row >= t.nrows || col >= t.ncols) {
+      set_error(ls.err, level, it.s, kErrIndex);
+      continue;
+    }
+    t.dst[(size_t)row + (size_t)t.ld * col] = v;
   }
   for (int e = tid; e < k * k; e += kThreads) {
     const int r = e % k, c = e / k;
@@ -590,6 +578,35 @@ __global__ void __launch_bounds__(kThreads) slre_kernel(const ItemD* __restrict_
     ls.a[it.s] = a;
     ls.b[it.s] = b;
   }
+  __syncthreads();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) slre_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                        int level, double tol, int tol_mode, int prec,
+                                                        int max_m) {
+  extern __shared__ double lds[];
+  int* soff = reinterpret_cast<int*>(lds + (size_t)max_m * kNB + kNB * kNB + kNB * 256);
+  slre_item(items[blockIdx.x], ls, level, tol, tol_mode, prec, lds, soff);
+}
+
+// All colours of a level in one cooperative launch: workgroups stride over
+// the clusters of a colour, then wait at a grid barrier before the next.
+__global__ void __launch_bounds__(kThreads) slre_level_kernel(const ItemD* __restrict__ items,
+                                                              const int32_t* __restrict__ cstart,
+                                                              int ncolours, LevelState ls, int level,
+                                                              double tol, int tol_mode, int prec,
+                                                              int max_m) {
+  extern __shared__ double lds[];
+  int* soff = reinterpret_cast<int*>(lds + (size_t)max_m * kNB + kNB * kNB + kNB * 256);
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int c = 0; c < ncolours; ++c) {
+    for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x)
+      slre_item(items[i], ls, level, tol, tol_mode, prec, lds, soff);
+    grid.sync();
+  }
 }
 
 // Kernels that use more than 64 KiB of dynamic LDS must say so once.
@@ -599,14 +616,44 @@ static void allow_lds(const void* fn, bool* done) {
   *done = true;
 }
 
-void launch_slre(const ItemD* items, int nitems, int max_m, LevelState ls, int level, double tol,
-                 int tol_mode, int prec, hipStream_t st) {
+static size_t slre_lds(int max_m, int max_nseg) {
+  return ((size_t)max_m * kNB + kNB * kNB + kNB * 256) * sizeof(double) + (size_t)(max_nseg + 1) * 4;
+}
+
+void launch_slre(const ItemD* items, int nitems, int max_m, int max_nseg, LevelState ls, int level,
+                 double tol, int tol_mode, int prec, hipStream_t st) {
   if (nitems <= 0) return;
   static bool lds_ok = false;
   allow_lds(reinterpret_cast<const void*>(slre_kernel), &lds_ok);
-  size_t lds = ((size_t)max_m * kNB + kNB * kNB + kNB * 256) * sizeof(double);
-  hipLaunchKernelGGL(slre_kernel, dim3(nitems), dim3(kThreads), lds, st, items, ls, level, tol,
-                     tol_mode, prec);
+  hipLaunchKernelGGL(slre_kernel, dim3(nitems), dim3(kThreads), slre_lds(max_m, max_nseg), st, items,
+                     ls, level, tol, tol_mode, prec, max_m);
+}
+
+static int coop_grid(const void* fn, size_t lds, int want) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 1;
+  }
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, lds) != hipSuccess || per < 1)
+    per = 1;
+  return std::max(1, std::min(want, per * cus));
+}
+
+hipError_t launch_slre_level(const ItemD* items, const int32_t* cstart, int ncolours, int max_items,
+                             int max_m, int max_nseg, LevelState ls, int level, double tol,
+                             int tol_mode, int prec, hipStream_t st) {
+  static bool lds_ok = false;
+  allow_lds(reinterpret_cast<const void*>(slre_level_kernel), &lds_ok);
+  const size_t lds = slre_lds(max_m, max_nseg);
+  const int g = coop_grid(reinterpret_cast<const void*>(slre_level_kernel), lds, max_items);
+  void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&level,
+                  (void*)&tol, (void*)&tol_mode, (void*)&prec, (void*)&max_m};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(slre_level_kernel), dim3(g),
+                                    dim3(kThreads), args, lds, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -696,13 +743,12 @@ __device__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* 
 
 }  // namespace
 
-// Forward substitution of the clusters of one colour: y_s <- U^T G^{-1} y_s,
-// y_n -= F^T y_f.
-__global__ void __launch_bounds__(kThreads) fwd_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                       double* vec) {
-  extern __shared__ double lds[];
+namespace {
+
+// Forward substitution of one cluster: y_s <- U^T G^{-1} y_s, y_n -= F^T y_f.
+// lds: mp + 64*64 doubles (mp = m rounded up to 64).
+__device__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
   __shared__ double shd[kWaves];
-  const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   if (m == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -732,14 +778,13 @@ __global__ void __launch_bounds__(kThreads) fwd_kernel(const ItemD* __restrict__
     if (lane == 0) vec[it.vidx[c]] -= s;
   }
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
+  __syncthreads();
 }
 
-// Backward substitution: x_f -= F x_n, x_s <- G^{-T} U x_s.
-__global__ void __launch_bounds__(kThreads) bwd_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                       double* vec) {
-  extern __shared__ double lds[];
+// Backward substitution of one cluster: x_f -= F x_n, x_s <- G^{-T} U x_s.
+// lds: mp + 64*64 + 1024 doubles.
+__device__ void bwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
   __shared__ double shd[kWaves];
-  const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   if (m == 0) return;
   const int tid = threadIdx.x;
@@ -775,20 +820,67 @@ __global__ void __launch_bounds__(kThreads) bwd_kernel(const ItemD* __restrict__
   }
   trsv_lower_t(it.P, m, m, x, blk);
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
+  __syncthreads();
+}
+
+size_t sweep_lds(int max_m) { return ((size_t)((max_m + 63) / 64) * 64 + 64 * 64 + 1024) * sizeof(double); }
+
+}  // namespace
+
+__global__ void __launch_bounds__(kThreads) fwd_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                       double* vec) {
+  extern __shared__ double lds[];
+  fwd_item(items[blockIdx.x], ls, vec, lds);
+}
+
+__global__ void __launch_bounds__(kThreads) bwd_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                       double* vec) {
+  extern __shared__ double lds[];
+  bwd_item(items[blockIdx.x], ls, vec, lds);
+}
+
+__global__ void __launch_bounds__(kThreads) fwd_level_kernel(const ItemD* __restrict__ items,
+                                                             const int32_t* __restrict__ cstart,
+                                                             int ncolours, LevelState ls, double* vec) {
+  extern __shared__ double lds[];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int c = 0; c < ncolours; ++c) {
+    for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) fwd_item(items[i], ls, vec, lds);
+    grid.sync();
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) bwd_level_kernel(const ItemD* __restrict__ items,
+                                                             const int32_t* __restrict__ cstart,
+                                                             int ncolours, LevelState ls, double* vec) {
+  extern __shared__ double lds[];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int c = ncolours - 1; c >= 0; --c) {
+    for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) bwd_item(items[i], ls, vec, lds);
+    grid.sync();
+  }
 }
 
 void launch_fwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
                 hipStream_t st) {
   if (nitems <= 0) return;
-  size_t lds = ((size_t)((max_m + 63) / 64) * 64 + 64 * 64) * sizeof(double);
-  hipLaunchKernelGGL(fwd_kernel, dim3(nitems), dim3(kThreads), lds, st, items, ls, vec);
+  hipLaunchKernelGGL(fwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, ls, vec);
 }
 
 void launch_bwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
                 hipStream_t st) {
   if (nitems <= 0) return;
-  size_t lds = ((size_t)((max_m + 63) / 64) * 64 + 64 * 64 + 1024) * sizeof(double);
-  hipLaunchKernelGGL(bwd_kernel, dim3(nitems), dim3(kThreads), lds, st, items, ls, vec);
+  hipLaunchKernelGGL(bwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, ls, vec);
+}
+
+hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
+                              int max_items, int max_m, LevelState ls, double* vec, hipStream_t st) {
+  const void* fn = forward ? reinterpret_cast<const void*>(fwd_level_kernel)
+                           : reinterpret_cast<const void*>(bwd_level_kernel);
+  const size_t lds = sweep_lds(max_m);
+  const int g = coop_grid(fn, lds, max_items);
+  void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&vec};
+  return hipLaunchCooperativeKernel(fn, dim3(g), dim3(kThreads), args, lds, st);
 }
 
 __global__ void __launch_bounds__(kThreads) top_solve_kernel(const double* L, int n, double* yg) {

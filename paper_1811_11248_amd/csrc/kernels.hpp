@@ -15,9 +15,28 @@ void launch_scatter_vals(const double* val, const int64_t* off, int64_t nnz, dou
                          hipStream_t st);
 void launch_copy_blocks(const CopyD* tasks, int ntasks, hipStream_t st);
 
-// One scaled low-rank elimination per item (all items of one colour).
-void launch_slre(const ItemD* items, int nitems, int max_m, LevelState ls, int level, double tol,
-                 int tol_mode, int prec, hipStream_t st);
+// One scaled low-rank elimination per item (all items of one colour), one
+// workgroup per cluster.
+void launch_slre(const ItemD* items, int nitems, int max_m, int max_nseg, LevelState ls, int level,
+                 double tol, int tol_mode, int prec, hipStream_t st);
+// All colours of a level in one cooperative launch (grid barrier between
+// colours); cstart is a device array of ncolours+1 item offsets.
+hipError_t launch_slre_level(const ItemD* items, const int32_t* cstart, int ncolours, int max_items,
+                             int max_m, int max_nseg, LevelState ls, int level, double tol,
+                             int tol_mode, int prec, hipStream_t st);
+
+// Capacities of one colour for the split (several workgroups per cluster) path.
+struct SplitDims {
+  int max_m, max_nseg, max_pcap, max_acap;
+};
+constexpr int kSplitMaxDofs = 512;   // LDS limit of the split kernels
+constexpr int kSplitMinDofs = 96;    // below this one workgroup per cluster wins
+enum SplitStep {
+  kSplitOffsets = 0, kSplitGather, kSplitPotrf, kSplitTrsm, kSplitCpqr, kSplitApplyq, kSplitSchur,
+  kSplitWriteback, kSplitSteps
+};
+void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims& d, LevelState ls,
+                       int level, double tol, int tol_mode, int prec, hipStream_t st);
 
 // Dense Cholesky of the top system (lower, in place).
 void launch_top_potrf(double* A, int n, int32_t* err, hipStream_t st);
@@ -27,6 +46,8 @@ void launch_fwd(const ItemD* items, int nitems, int max_m, LevelState ls, double
                 hipStream_t st);
 void launch_bwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
                 hipStream_t st);
+hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
+                              int max_items, int max_m, LevelState ls, double* vec, hipStream_t st);
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st);
 
 void launch_gather(const double* src, const int64_t* idx, double* dst, int64_t n, hipStream_t st);

@@ -1,0 +1,757 @@
+// split.hip -- elimination of the clusters of one colour when clusters are
+// large: each step of the scaled low-rank elimination is its own launch and
+// spreads a cluster over several workgroups where the step allows it.
+//
+//   seg_offsets  segment widths -> panel column offsets, column metadata
+//   gather       [A_ss | A_sn | A_sw] -> panel P (several wgs per cluster)
+//   potrf        A_ss = G G^T, one 512-thread wg per cluster
+//   trsm         G^{-1}[A_sn | A_sw] by column chunks, MFMA f64 updates;
+//                also the squared norms of the far-field columns
+//   cpqr         column-pivoted QR of the scaled far field (one wg)
+//   applyq       C = U^T G^{-1} A_sn by column chunks
+//   schur        X -= F^T F, 32x32 output tiles on MFMA (f64, f32 or bf16
+//                inputs), scattered to the owning blocks
+//   writeback    coarse row of s, identity diagonal block
+#include <hip/hip_runtime.h>
+
+#include "desc.hpp"
+#include "devutil.hpp"
+#include "kernels.hpp"
+
+namespace lrsp {
+
+namespace {
+constexpr int kRegRows = kMaxClusterDofs / 64;
+}
+
+__global__ void __launch_bounds__(256) seg_offsets_kernel(const ItemD* __restrict__ items,
+                                                          LevelState ls, int level) {
+  extern __shared__ int soff[];
+  __shared__ int wsum[4];
+  __shared__ int sbad;
+  const ItemD& it = items[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nseg = it.nseg;
+  if (tid == 0) sbad = 0;
+  __syncthreads();
+  int carry = 0;
+  for (int base = 0; base < nseg; base += 256) {
+    const int i = base + tid;
+    int w = 0;
+    if (i < nseg) {
+      const SegD& sg = it.seg[i];
+      w = sg.coarse ? ls.k[sg.y] : sg.nfine;
+      if (w < 0 || w > sg.cap) {
+        sbad = 1;
+        w = 0;
+      }
+    }
+    int x = w;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int pre = 0;
+    for (int q = 0; q < wv; ++q) pre += wsum[q];
+    const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (i < nseg) soff[i] = carry + pre + x - w;
+    carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) soff[nseg] = carry;
+  __syncthreads();
+  const int total = soff[nseg];
+  const int a = soff[it.nsegn];
+  if (tid == 0 && total > it.pcap) sbad = 1;
+  __syncthreads();
+  if (sbad) {
+    if (tid == 0) {
+      set_error(ls.err, level, it.s, kErrCapacity);
+      ls.a[it.s] = 0;
+      ls.b[it.s] = 0;
+    }
+    return;
+  }
+  for (int i = tid; i <= nseg; i += 256) it.segoff[i] = soff[i];
+  if (tid == 0) {
+    ls.a[it.s] = a;
+    ls.b[it.s] = total - a;
+  }
+  for (int c = tid; c < total; c += 256) {
+    int lo = 0, hi = nseg - 1;  // last segment starting at or before c
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (soff[mid] <= c) lo = mid;
+      else hi = mid - 1;
+    }
+    const SegD& sg = it.seg[lo];
+    const int loc = c - soff[lo];
+    const int nat = sg.coarse ? loc : sg.zl[loc];
+    it.colseg[c] = lo;
+    it.colnat[c] = nat;
+    it.vidx[c] = sg.voff + nat;
+  }
+}
+
+__global__ void __launch_bounds__(256) gather_panel_kernel(const ItemD* __restrict__ items,
+                                                           LevelState ls) {
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  if (m == 0) return;
+  const int ncols = m + ls.a[it.s] + ls.b[it.s];
+  const int c0 = blockIdx.y * 32;
+  if (c0 >= ncols) return;
+  const int c1 = min(ncols, c0 + 32);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c = c0 + wv; c < c1; c += 4) {
+    const double* src;
+    if (c < m) {
+      src = it.D + (size_t)m * c;
+    } else {
+      const int pc = c - m;
+      const int sg = it.colseg[pc];
+      src = it.seg[sg].src + (size_t)m * (pc - it.segoff[sg]);
+    }
+    double* dst = it.P + (size_t)m * c;
+    double v[kRegRows];
+#pragma unroll
+    for (int t = 0; t < kRegRows; ++t) {
+      const int r = lane + 64 * t;
+      v[t] = r < m ? src[r] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kRegRows; ++t) {
+      const int r = lane + 64 * t;
+      if (r < m) dst[r] = v[t];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blocked right-looking Cholesky (lower, in place) by one workgroup of NT
+// threads.  The 32-wide panel is staged in LDS (row stride 33); its diagonal
+// block is factored by wave 0 in registers, the rows below by one thread per
+// row; the trailing update runs on v_mfma_f64_16x16x4 in 16x16 lower tiles,
+// four tiles per wave loaded before they are updated.
+// LDS: m*33 doubles.
+template <int NT>
+__device__ void potrf_wg(double* A, int ld, int m, double* lds, int* bad) {
+  constexpr int NB = 32, LDL = 33, NWV = NT / 64, G = 4;
+  double* Lp = lds;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int jb = 0; jb < m; jb += NB) {
+    const int w = min(NB, m - jb);
+    const int rows = m - jb;
+    load_block_rowmajor<NT>(Lp, LDL, A + (size_t)jb * ld + jb, (size_t)ld, rows, NB,
+                            [&](int r, int c) { return c < w && c <= r; });
+    __syncthreads();
+    if (wv == 0) {
+      double row[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) row[u] = (lane < w) ? Lp[lane * LDL + u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        if (u < w) {
+          double d = __shfl(row[u], u, 64);
+          if (!(d > 0.0)) {
+            if (lane == 0) *bad = 1;
+            d = 1.0;
+          }
+          d = sqrt(d);
+          if (lane == u) row[u] = d;
+          else if (lane > u) row[u] = row[u] / d;
+#pragma unroll
+          for (int v = u + 1; v < NB; ++v) {
+            const double lvu = __shfl(row[u], v, 64);
+            if (v < w && lane >= v && lane < w) row[v] -= row[u] * lvu;
+          }
+        }
+      }
+      if (lane < w) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) Lp[lane * LDL + u] = (u <= lane) ? row[u] : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int r = w + tid; r < rows; r += NT) {
+      double x[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) x[u] = (u < w) ? Lp[r * LDL + u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        if (u < w) {
+          double s = x[u];
+#pragma unroll
+          for (int v = 0; v < u; ++v) s -= Lp[u * LDL + v] * x[v];
+          x[u] = s / Lp[u * LDL + u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) Lp[r * LDL + u] = x[u];
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * w; e += NT) {
+      const int c = e / rows, r = e - c * rows;
+      if (c <= r) A[(size_t)(jb + r) + (size_t)ld * (jb + c)] = Lp[r * LDL + c];
+    }
+    const int rb = rows - w;
+    const int nt = (rb + 15) >> 4;
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int t0 = wv; t0 < ntiles; t0 += NWV * G) {
+      int TR[G], TC[G];
+      double cur[G][4];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int t = t0 + g * NWV;
+        TR[g] = -1;
+        TC[g] = 0;
+        if (t < ntiles) tri_tile(t, nt, TR[g], TC[g]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = 16 * TC[g] + 4 * i + (lane >> 4), r = 16 * TR[g] + (lane & 15);
+          cur[g][i] = (TR[g] >= 0 && r < rb && c <= r)
+                          ? A[(size_t)(jb + w + r) + (size_t)ld * (jb + w + c)]
+                          : 0.0;
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (TR[g] < 0) continue;
+        const int cr = 16 * TC[g] + (lane & 15), rr = 16 * TR[g] + (lane & 15);
+        d4_t acc = {0.0, 0.0, 0.0, 0.0};
+        for (int u0 = 0; u0 < w; u0 += 4) {
+          const int u = u0 + (lane >> 4);
+          const double av = (cr < rb && u < w) ? Lp[(w + cr) * LDL + u] : 0.0;
+          const double bv = (rr < rb && u < w) ? Lp[(w + rr) * LDL + u] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = 16 * TC[g] + 4 * i + (lane >> 4), r = 16 * TR[g] + (lane & 15);
+          if (r < rb && c <= r) A[(size_t)(jb + w + r) + (size_t)ld * (jb + w + c)] = cur[g][i] - acc[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(512) potrf_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                    int level) {
+  extern __shared__ double lds[];
+  __shared__ int sbad;
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  if (m == 0) return;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  potrf_wg<512>(it.P, m, m, lds, &sbad);
+  __syncthreads();
+  if (sbad && threadIdx.x == 0) set_error(ls.err, level, it.s, kErrNotSPD);
+}
+
+// ---------------------------------------------------------------------------
+// B <- G^{-1} B for BW columns of [A_sn | A_sw] per workgroup.  B chunk and a
+// BW-wide panel of G are staged in LDS (rows padded to BW+1).  The diagonal
+// block is solved wave-locally (each wave owns BW/4 columns, each column
+// spread over 256/BW lanes); the rows below are updated with
+// v_mfma_f64_16x16x4.
+template <int BW>
+__global__ void __launch_bounds__(256) trsm_kernel(const ItemD* __restrict__ items, LevelState ls) {
+  extern __shared__ double lds[];
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  if (m == 0) return;
+  const int a = ls.a[it.s], nb = a + ls.b[it.s];
+  const int c0 = blockIdx.y * BW;
+  if (c0 >= nb) return;
+  const int w = min(BW, nb - c0);
+  constexpr int LDB = BW + 1;
+  constexpr int LPC = 256 / BW;       // lanes per column in the diagonal solve
+  constexpr int RPL = BW / LPC;       // rows of the diagonal block per lane
+  double* Bs = lds;
+  double* Gs = lds + (size_t)m * LDB;
+  const double* G = it.P;
+  double* B = it.P + (size_t)m * (m + c0);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  load_block_rowmajor<256>(Bs, LDB, B, (size_t)m, m, BW, [&](int, int c) { return c < w; });
+  __syncthreads();
+  const int col = wv * (BW / 4) + lane / LPC;  // diagonal-solve column of this lane
+  const int g = lane % LPC;                    // its row group
+  for (int jb = 0; jb < m; jb += BW) {
+    const int jw = min(BW, m - jb);
+    const int rows = m - jb;
+    load_block_rowmajor<256>(Gs, LDB, G + (size_t)jb * m + jb, (size_t)m, rows, BW,
+                             [&](int r, int c) { return c < jw && c <= r; });
+    __syncthreads();
+    {
+      double x[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = g + LPC * t;
+        x[t] = (r < jw) ? Bs[(jb + r) * LDB + col] : 0.0;
+      }
+      for (int u = 0; u < jw; ++u) {
+        const int tu = u / LPC, gu = u % LPC;
+        double own = x[0];
+#pragma unroll
+        for (int t = 1; t < RPL; ++t)
+          if (t == tu) own = x[t];
+        const double xu = __shfl(own, (lane / LPC) * LPC + gu, 64) / Gs[u * LDB + u];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int r = g + LPC * t;
+          if (r == u) x[t] = xu;
+          else if (r > u && r < jw) x[t] -= Gs[r * LDB + u] * xu;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = g + LPC * t;
+        if (r < jw) Bs[(jb + r) * LDB + col] = x[t];
+      }
+    }
+    __syncthreads();
+    const int rb = rows - jw;
+    const int nrt = (rb + 15) >> 4;
+    constexpr int nct = BW / 16;
+    for (int t = wv; t < nrt * nct; t += 4) {
+      const int R0 = (t % nrt) * 16, C0 = (t / nrt) * 16;
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+      const int ar = R0 + (lane & 15);
+      for (int u0 = 0; u0 < jw; u0 += 4) {
+        const int ka = u0 + (lane >> 4);
+        const double av = (ar < rb && ka < jw) ? Gs[(jw + ar) * LDB + ka] : 0.0;
+        const double bv = (ka < jw) ? Bs[(jb + ka) * LDB + C0 + (lane & 15)] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = R0 + mfma64_row(lane, i);
+        if (r < rb) Bs[(jb + jw + r) * LDB + C0 + (lane & 15)] -= acc[i];
+      }
+    }
+    __syncthreads();
+  }
+  store_block_rowmajor<256>(B, (size_t)m, Bs, LDB, m, w);
+  for (int c = wv; c < w; c += 4) {
+    const int pc = c0 + c;
+    if (pc < a) continue;
+    double s = 0.0;
+    for (int r = lane; r < m; r += 64) {
+      const double x = Bs[r * LDB + c];
+      s += x * x;
+    }
+    s = wave_sum(s);
+    if (lane == 0) it.norms[pc - a] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column-pivoted QR of the far-field block (same rule as the fused kernel).
+// 1024 threads; norms and pivot flags in LDS; each update pass streams the
+// remaining columns with CPW columns x R rows per lane in flight.
+template <int R>
+__global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                    double tol, int tol_mode, int level) {
+  constexpr int NT = 1024, NW = NT / 64, CPW = (R <= 4 ? 6 : (R <= 8 ? 3 : 2));
+  extern __shared__ double lds[];
+  __shared__ double shd[NW];
+  __shared__ int shi[NW];
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  const int a = ls.a[it.s], b = ls.b[it.s];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (m == 0 || b == 0) {
+    if (tid == 0) ls.k[it.s] = 0;
+    return;
+  }
+  double* nrm = lds;                          // b
+  double* vs = lds + b;                       // m
+  int* stp = reinterpret_cast<int*>(vs + m);  // b
+  double* W = it.P + (size_t)m * (m + a);
+  for (int c = tid; c < b; c += NT) {
+    nrm[c] = it.norms[c];
+    stp[c] = -1;
+  }
+  __syncthreads();
+  const int kmax = min(m, b);
+  double r00 = 0.0;
+  int k = kmax;
+  for (int j = 0; j < kmax; ++j) {
+    double mx = 0.0;
+    for (int c = tid; c < b; c += NT)
+      if (stp[c] < 0) mx = fmax(mx, nrm[c]);
+    mx = group_max<NT>(mx, shd);
+    const double thr = (1.0 - kTie) * mx;
+    int best = INT_MAX;
+    for (int c = tid; c < b; c += NT)
+      if (stp[c] < 0 && nrm[c] >= thr) best = min(best, c);
+    best = group_min_int<NT>(best, shi);
+    if (best == INT_MAX) {
+      k = j;
+      break;
+    }
+    const double rjj = sqrt(nrm[best]);
+    if (j == 0) r00 = rjj;
+    const bool stop = (tol_mode == 0) ? (rjj <= tol * r00) : (rjj <= tol);
+    if (stop || rjj == 0.0) {
+      k = j;
+      break;
+    }
+    double* x = W + (size_t)m * best;
+    double xv = 0.0, rest = 0.0;
+    for (int i = j + 1 + tid; i < m; i += NT) {
+      xv = x[i];
+      rest += xv * xv;
+    }
+    rest = group_sum<NT>(rest, shd);
+    const double alpha = x[j];
+    double d, tj;
+    if (alpha <= 0.0) {
+      d = alpha - rjj;
+      tj = (rjj - alpha) / rjj;
+    } else {
+      d = -rest / (alpha + rjj);
+      tj = rest / (rjj * (rjj + alpha));
+    }
+    if (d == 0.0) tj = 0.0;
+    for (int i = tid; i < m; i += NT) {
+      double v = 0.0;
+      if (i == j) v = 1.0;
+      else if (i > j) v = (d != 0.0) ? x[i] / d : 0.0;
+      vs[i] = v;
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < m; i += NT) x[i] = vs[i];
+    if (tid == 0) {
+      x[j] = rjj;
+      it.piv[j] = best;
+      stp[best] = j;
+      it.tau[j] = tj;
+    }
+    __syncthreads();
+    double vr[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = lane + 64 * t;
+      vr[t] = i < m ? vs[i] : 0.0;
+    }
+    for (int cb = wv * CPW; cb < b; cb += NW * CPW) {
+      double y[CPW][R];
+      bool act[CPW];
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) {
+        const int c = cb + q;
+        act[q] = c < b && stp[c] < 0;
+        const double* yc = W + (size_t)m * (act[q] ? c : best);
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int i = lane + 64 * t;
+          y[q][t] = (act[q] && i >= j && i < m) ? yc[i] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) acc += vr[t] * y[q][t];
+        const double f = tj * wave_sum(acc);
+        if (!act[q]) continue;
+        double* yc = W + (size_t)m * (cb + q);
+        double nn = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int i = lane + 64 * t;
+          if (i >= j && i < m) {
+            const double nv = y[q][t] - f * vr[t];
+            yc[i] = nv;
+            if (i > j) nn += nv * nv;
+          }
+        }
+        nn = wave_sum(nn);
+        if (lane == 0) nrm[cb + q] = nn;
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < b; c += NT) it.stepof[c] = stp[c];
+  if (tid == 0) ls.k[it.s] = k;
+  if (k > it.kcap && tid == 0) set_error(ls.err, level, it.s, kErrCapacity);
+}
+
+// ---------------------------------------------------------------------------
+// C <- U^T C for 64 near-field columns per workgroup; reflectors staged in
+// LDS 16 at a time, four columns per wave in registers.
+__global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ items, LevelState ls) {
+  extern __shared__ double lds[];
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  const int k = min(ls.k[it.s], it.kcap), a = ls.a[it.s];
+  const int c0 = blockIdx.y * 64;
+  if (m == 0 || k == 0 || c0 >= a) return;
+  const int c1 = min(a, c0 + 64);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double* Vs = lds;            // 16 x m
+  double* ts = lds + 16 * m;   // 16
+  const double* W = it.P + (size_t)m * (m + a);
+  double* C = it.P + (size_t)m * m;
+  for (int j0 = 0; j0 < k; j0 += 16) {
+    const int nj = min(16, k - j0);
+    __syncthreads();
+    for (int e = tid; e < nj * m; e += 256) {
+      const int jj = e / m, i = e - jj * m, j = j0 + jj;
+      Vs[jj * m + i] = (i == j) ? 1.0 : (i > j ? W[(size_t)m * it.piv[j] + i] : 0.0);
+    }
+    if (tid < nj) ts[tid] = it.tau[j0 + tid];
+    __syncthreads();
+    for (int cb = c0 + wv * 4; cb < c1; cb += 16) {
+      double y[4][kRegRows];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cb + q;
+#pragma unroll
+        for (int t = 0; t < kRegRows; ++t) {
+          const int i = lane + 64 * t;
+          y[q][t] = (c < c1 && i < m) ? C[(size_t)m * c + i] : 0.0;
+        }
+      }
+      for (int jj = 0; jj < nj; ++jj) {
+        const double* v = Vs + jj * m;
+        double s[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < kRegRows; ++t) {
+            const int i = lane + 64 * t;
+            if (i < m) acc += v[i] * y[q][t];
+          }
+          s[q] = wave_sum(acc) * ts[jj];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int t = 0; t < kRegRows; ++t) {
+            const int i = lane + 64 * t;
+            if (i < m) y[q][t] -= s[q] * v[i];
+          }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cb + q;
+        if (c >= c1) continue;
+#pragma unroll
+        for (int t = 0; t < kRegRows; ++t) {
+          const int i = lane + 64 * t;
+          if (i < m) C[(size_t)m * c + i] = y[q][t];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Scatter of one Schur-update element W[rr][cc] (rr >= cc) to its block.
+__device__ __forceinline__ void schur_put(const ItemD& it, int rr, int cc, double val, int32_t* err,
+                                          int level) {
+  const int sr = it.colseg[rr], sc = it.colseg[cc];
+  const int nr = it.colnat[rr], nc = it.colnat[cc];
+  const int i = min(sr, sc), j = max(sr, sc);
+  const PairD& pd = it.pair[j * (j + 1) / 2 + i];
+  int row, col;
+  if (pd.diag) {
+    row = max(nr, nc);
+    col = min(nr, nc);
+  } else {
+    const bool r_rows = (sr == (pd.rows_from_j ? j : i));
+    row = r_rows ? nr : nc;
+    const int cn = r_rows ? nc : nr;
+    col = pd.posmap ? pd.posmap[cn] : cn;
+  }
+  if (row < 0 || col < 0 || row >= pd.nrows || col >= pd.ncols) {
+    set_error(err, level, it.s, kErrIndex);
+    return;
+  }
+  pd.dst[(size_t)row + (size_t)pd.ld * col] -= val;
+}
+
+// X -= F^T F for one 32x32 lower tile of the a x a product; four waves own
+// its 16x16 quadrants.  PREC 0: fp64 MFMA; 1: fp32 inputs, fp32 accumulate;
+// 2: bf16 inputs (round to nearest even), fp32 accumulate.
+template <int PREC>
+__global__ void __launch_bounds__(256) schur_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                    int level) {
+  __shared__ double Fr[16][33];
+  __shared__ double Fc[16][33];
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  const int k = min(ls.k[it.s], it.kcap), a = ls.a[it.s];
+  if (m <= k || a == 0) return;
+  const int nt = (a + 31) >> 5;
+  if ((int)blockIdx.y >= nt * (nt + 1) / 2) return;
+  int R, Cq;
+  tri_tile(blockIdx.y, nt, R, Cq);
+  const int R0 = 32 * R, C0 = 32 * Cq;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int qr = wv >> 1, qc = wv & 1;
+  const bool live = !(R == Cq && qr < qc);  // strictly upper quadrant of a diagonal tile
+  const double* C = it.P + (size_t)m * m;
+  d4_t acc64 = {0.0, 0.0, 0.0, 0.0};
+  f4_t acc32 = {0.f, 0.f, 0.f, 0.f};
+  for (int i0 = k; i0 < m; i0 += 16) {
+    for (int e = tid; e < 2 * 16 * 32; e += 256) {
+      const int half = e >> 9, ee = e & 511;
+      const int col = ee >> 4, ii = ee & 15;
+      const int gi = i0 + ii, gc = (half ? C0 : R0) + col;
+      const double v = (gi < m && gc < a) ? C[(size_t)m * gc + gi] : 0.0;
+      if (half) Fc[ii][col] = v;
+      else Fr[ii][col] = v;
+    }
+    __syncthreads();
+    if (live) {
+      const int ar = 16 * qr + (lane & 15), bc = 16 * qc + (lane & 15);
+      if (PREC == 0) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const int ka = kk + (lane >> 4);
+          acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(Fr[ka][ar], Fc[ka][bc], acc64, 0, 0, 0);
+        }
+      } else if (PREC == 1) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const int ka = kk + (lane >> 4);
+          acc32 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)Fr[ka][ar], (float)Fc[ka][bc], acc32, 0, 0, 0);
+        }
+      } else {
+        s4_t av, bv;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int ka = 4 * (lane >> 4) + jj;
+          const uint32_t ua = __float_as_uint(round_bf16((float)Fr[ka][ar]));
+          const uint32_t ub = __float_as_uint(round_bf16((float)Fc[ka][bc]));
+          av[jj] = (short)(ua >> 16);
+          bv[jj] = (short)(ub >> 16);
+        }
+        acc32 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc32, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  if (!live) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rr = R0 + 16 * qr + (PREC == 0 ? mfma64_row(lane, i) : mfma32_row(lane, i));
+    const int cc = C0 + 16 * qc + (lane & 15);
+    if (rr < a && cc < a && rr >= cc) {
+      const double v = PREC == 0 ? acc64[i] : (double)acc32[i];
+      schur_put(it, rr, cc, v, ls.err, level);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse row of s, written to the blocks that keep it; identity diagonal.
+__global__ void __launch_bounds__(256) writeback_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                        int level) {
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  const int k = min(ls.k[it.s], it.kcap), a = ls.a[it.s], nb = a + ls.b[it.s];
+  if (m == 0 || k == 0) return;
+  const int tid = threadIdx.x;
+  if (blockIdx.y == 0)
+    for (int e = tid; e < k * k; e += 256) {
+      const int r = e % k, c = e / k;
+      it.D[(size_t)r + (size_t)m * c] = (r == c) ? 1.0 : 0.0;
+    }
+  const int c0 = blockIdx.y * 64;
+  if (c0 >= nb) return;
+  const int c1 = min(nb, c0 + 64);
+  for (int e = tid; e < k * (c1 - c0); e += 256) {
+    const int r = e % k, pc = c0 + e / k;
+    const WbD& t = it.wb[it.colseg[pc]];
+    const int cn = it.colnat[pc];
+    double v = it.P[(size_t)r + (size_t)m * (m + pc)];
+    if (pc >= a) {
+      const int st = it.stepof[pc - a];
+      if (st >= 0 && r > st) v = 0.0;
+    }
+    const int row = t.trans ? cn : r, col = t.trans ? r : cn;
+    if (row >= t.nrows || col >= t.ncols) {
+      set_error(ls.err, level, it.s, kErrIndex);
+      continue;
+    }
+    t.dst[(size_t)row + (size_t)t.ld * col] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims& d, LevelState ls,
+                       int level, double tol, int tol_mode, int prec, hipStream_t st) {
+  if (nitems <= 0) return;
+  static bool lds_set = false;
+  if (!lds_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(trsm_kernel<32>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(trsm_kernel<16>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(potrf_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    lds_set = true;
+  }
+  const int mm = d.max_m;
+  switch (step) {
+    case kSplitOffsets:
+      hipLaunchKernelGGL(seg_offsets_kernel, dim3(nitems), dim3(256), (size_t)(d.max_nseg + 1) * 4, st,
+                         items, ls, level);
+      break;
+    case kSplitGather:
+      hipLaunchKernelGGL(gather_panel_kernel, dim3(nitems, (mm + d.max_pcap + 31) / 32), dim3(256), 0,
+                         st, items, ls);
+      break;
+    case kSplitPotrf:
+      hipLaunchKernelGGL(potrf_kernel, dim3(nitems), dim3(512), (size_t)mm * 33 * 8, st, items, ls,
+                         level);
+      break;
+    case kSplitTrsm:
+      if (d.max_pcap <= 0) break;
+      if (mm <= 256)
+        hipLaunchKernelGGL(trsm_kernel<32>, dim3(nitems, (d.max_pcap + 31) / 32), dim3(256),
+                           (size_t)2 * mm * 33 * 8, st, items, ls);
+      else
+        hipLaunchKernelGGL(trsm_kernel<16>, dim3(nitems, (d.max_pcap + 15) / 16), dim3(256),
+                           (size_t)2 * mm * 17 * 8, st, items, ls);
+      break;
+    case kSplitCpqr: {
+      const size_t lds = (size_t)d.max_pcap * 12 + (size_t)mm * 8 + 64;
+      if (mm <= 256)
+        hipLaunchKernelGGL(cpqr_kernel<4>, dim3(nitems), dim3(1024), lds, st, items, ls, tol, tol_mode, level);
+      else
+        hipLaunchKernelGGL(cpqr_kernel<8>, dim3(nitems), dim3(1024), lds, st, items, ls, tol, tol_mode, level);
+      break;
+    }
+    case kSplitApplyq:
+      if (d.max_acap <= 0) break;
+      hipLaunchKernelGGL(applyq_kernel, dim3(nitems, (d.max_acap + 63) / 64), dim3(256),
+                         ((size_t)16 * mm + 16) * 8, st, items, ls);
+      break;
+    case kSplitSchur: {
+      if (d.max_acap <= 0) break;
+      const int nt = (d.max_acap + 31) / 32;
+      const dim3 g(nitems, nt * (nt + 1) / 2);
+      if (prec == 0) hipLaunchKernelGGL(schur_kernel<0>, g, dim3(256), 0, st, items, ls, level);
+      else if (prec == 1) hipLaunchKernelGGL(schur_kernel<1>, g, dim3(256), 0, st, items, ls, level);
+      else hipLaunchKernelGGL(schur_kernel<2>, g, dim3(256), 0, st, items, ls, level);
+      break;
+    }
+    case kSplitWriteback:
+      hipLaunchKernelGGL(writeback_kernel, dim3(nitems, (d.max_pcap + 63) / 64 + 1), dim3(256), 0, st,
+                         items, ls, level);
+      break;
+  }
+}
+
+}  // namespace lrsp

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblrsp.so")
 OK, ERR_ARG, ERR_NOT_SPD, ERR_HIP, ERR_OOM, ERR_NO_CONV, ERR_INTERNAL = range(7)
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 TOL_MODE = {"relative": 0, "absolute": 1}
+EXEC_MODE = {"auto": 0, "colour": 1, "level": 2, "split": 3}
 
 
 class LrspError(RuntimeError):
@@ -37,7 +38,7 @@ class CSR(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("tol_mode", C.c_int32), ("gemm_prec", C.c_int32), ("rank_mode", C.c_int32),
-                ("reserved0", C.c_int32), ("mlp_weights", C.c_void_p),
+                ("exec_mode", C.c_int32), ("mlp_weights", C.c_void_p),
                 ("reserved", C.c_int64 * 6)]
 
 
@@ -49,7 +50,8 @@ class TreeView(C.Structure):
 class Info(C.Structure):
     _fields_ = [("nlevels", C.c_int32), ("top_n", C.c_int32), ("top_clusters", C.c_int32),
                 ("reserved", C.c_int32), ("flops", C.c_double * 6), ("bytes_factor", C.c_double),
-                ("ms_levels", C.c_double), ("peak_bytes", C.c_int64)]
+                ("ms_levels", C.c_double), ("peak_bytes", C.c_int64), ("ms_analysis", C.c_double),
+                ("levels_reused", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class LevelView(C.Structure):
@@ -168,10 +170,11 @@ class Factor:
     """Hierarchical factor of a DeviceMatrix (lrsp_factor)."""
 
     def __init__(self, A: DeviceMatrix, tree: Tree, tol: float, tol_mode="relative",
-                 gemm_prec="f64", stream=None):
+                 gemm_prec="f64", exec_mode="auto", stream=None):
         o = Opts()
         o.tol_mode = TOL_MODE[tol_mode]
         o.gemm_prec = PREC[gemm_prec]
+        o.exec_mode = EXEC_MODE[exec_mode]
         h = C.c_void_p()
         self._csr = A.csr()
         self.A = A
@@ -185,7 +188,8 @@ class Factor:
         _check(lib().lrsp_factor_info(self.handle, C.byref(i)))
         return {"nlevels": i.nlevels, "top_n": i.top_n, "top_clusters": i.top_clusters,
                 "flops": dict(zip(("potrf", "trsm", "cpqr", "applyq", "schur", "top"), i.flops)),
-                "bytes_factor": i.bytes_factor, "ms": i.ms_levels}
+                "bytes_factor": i.bytes_factor, "ms": i.ms_levels, "ms_analysis": i.ms_analysis,
+                "levels_reused": i.levels_reused}
 
     def level(self, lev: int) -> dict:
         v = LevelView()
@@ -243,7 +247,9 @@ def pcg(A: DeviceMatrix, F: Factor, b, rtol=1e-8, maxit=1000, stream=None, raise
     return xo, np.array(it[:], dtype=np.int64), np.array(rr[:])
 
 
-TIMING_FAMILIES = {"eliminate": 0, "forward": 1, "backward": 2}
+TIMING_FAMILIES = {"eliminate": 0, "forward": 1, "backward": 2, "split_gather": 3,
+                   "split_potrf": 4, "split_trsm": 5, "split_cpqr": 6, "split_applyq": 7,
+                   "split_schur": 8, "split_writeback": 9, "fused": 10}
 
 
 def timing_enable(on: bool = True):

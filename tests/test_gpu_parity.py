@@ -47,26 +47,42 @@ CASES = {
     "slab_tol0": (lambda: slab_scalar(8, 8, 4, 1e3, lognormal_field((8, 8, 4), seed=3)), 16, 0.0),
     "strip4": (lambda: laplace2d(32, 2), 16, 0.5),
     "single_cluster": (lambda: laplace2d(6), 64, 1e-2),
+    "slab_split": (lambda: slab_scalar(24, 20, 8, 1e4, lognormal_field((20, 24, 8), seed=7)), 128, 1e-2),
+    "vector_split": (lambda: slab_vector(13, 11, 6, 1e3), 120, 1e-2),
     "slab64_full": (lambda: config("slab64"), 256, 1e-2),
 }
+# kernel schedules: one workgroup per cluster and one launch per colour; the
+# same in one cooperative launch per level; several workgroups per cluster
+MODES = ["colour", "level", "split"]
 
 
-def _run(torch, L, name):
+_ORACLE = {}
+
+
+def _oracle(name):
+    if name not in _ORACLE:
+        mk, leaf, tol = CASES[name]
+        pr = mk()
+        T = oracle.build_tree(pr.grid, leaf)
+        _ORACLE[name] = (pr, oracle.factor(pr.rowptr, pr.col, pr.val, T, tol))
+    return _ORACLE[name]
+
+
+def _run(torch, L, name, mode="auto"):
     mk, leaf, tol = CASES[name]
-    pr = mk()
-    _say(f"[case {name}] n={pr.n} leaf={leaf} tol={tol}")
-    T = oracle.build_tree(pr.grid, leaf)
-    Fo = oracle.factor(pr.rowptr, pr.col, pr.val, T, tol)
+    pr, Fo = _oracle(name)
+    _say(f"[case {name} / {mode}] n={pr.n} leaf={leaf} tol={tol}")
     A = L.DeviceMatrix.from_problem(pr)
     tree = L.Tree(pr.grid, leaf)
-    F = L.Factor(A, tree, tol)
+    F = L.Factor(A, tree, tol, exec_mode=mode)
     torch.cuda.synchronize()
     return pr, Fo, A, F
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("name", list(CASES))
-def test_schedule_and_apply(torch, L, name):
-    pr, Fo, A, F = _run(torch, L, name)
+def test_schedule_and_apply(torch, L, name, mode):
+    pr, Fo, A, F = _run(torch, L, name, mode)
     info = F.info()
     exact = CASES[name][2] == 0.0
     # at tol = 0 a rank is decided by whether a rounded column norm is
@@ -98,7 +114,7 @@ def test_schedule_and_apply(torch, L, name):
 
 
 @pytest.mark.parametrize("name", ["laplace64", "slab_ragged", "vector_ragged", "slab_aniso", "strip4",
-                                  "slab64_full"])
+                                  "slab_split", "slab64_full"])
 def test_pcg_iterations(torch, L, name):
     pr, Fo, A, F = _run(torch, L, name)
     b = rhs(pr.n, 0)
@@ -140,3 +156,47 @@ def test_precision_forms_converge(torch, L, prec):
     _say(f"  {prec}: apply rel diff vs fp64 {err:.2e}; pcg iters {it[0]} (fp64 {it64[0]}), relres {rr[0]:.1e}")
     assert rr[0] <= 1e-8
     assert err < (1e-4 if prec == "f32" else 5e-2)
+
+
+def test_analysis_reuse_gives_identical_factor(torch, L):
+    # a second factorization with the same tree and pattern reuses the
+    # cached analysis and workspaces; results must not change
+    pr = config("slab64")
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree(pr.grid, pr.leaf)
+    b = torch.from_numpy(rhs(pr.n, 3)).cuda()
+    F1 = L.Factor(A, tree, pr.tol)
+    x1 = L.apply(F1, b).clone()
+    assert F1.info()["levels_reused"] == 0
+    del F1
+    F2 = L.Factor(A, tree, pr.tol)
+    assert F2.info()["levels_reused"] == F2.info()["nlevels"] > 0
+    x2 = L.apply(F2, b)
+    assert torch.equal(x1, x2)
+    # two live factors from one tree: the second builds its own workspace
+    F3 = L.Factor(A, tree, pr.tol)
+    assert torch.equal(L.apply(F3, b), x2)
+    # new values with the same pattern: level 0 (pattern only) is reused;
+    # coarser levels are reused only if the ranks below are unchanged (the
+    # coarse diagonal blocks are identities, so 4A does not simply scale them)
+    val4 = 4.0 * pr.val
+    A2 = L.DeviceMatrix(pr.rowptr, pr.col, val4)
+    del F2, F3
+    F4 = L.Factor(A2, tree, pr.tol)
+    assert F4.info()["levels_reused"] >= 1
+    T = oracle.build_tree(pr.grid, pr.leaf)
+    Fo4 = oracle.factor(pr.rowptr, pr.col, val4, T, pr.tol)
+    x4 = L.apply(F4, b).cpu().numpy()
+    xo4 = oracle.solve(Fo4, b.cpu().numpy())
+    assert np.linalg.norm(x4 - xo4) <= APPLY_TOL * np.linalg.norm(xo4)
+    # another pattern on the same tree invalidates the cache
+    pr3 = slab_scalar(64, 64, 16, 1e2)
+    A3 = L.DeviceMatrix.from_problem(pr3)
+    F5 = L.Factor(A3, tree, pr.tol)
+    assert F5.info()["levels_reused"] == 0
+    T = oracle.build_tree(pr3.grid, pr.leaf)
+    Fo = oracle.factor(pr3.rowptr, pr3.col, pr3.val, T, pr.tol)
+    bb = rhs(pr3.n, 4)
+    x5 = L.apply(F5, torch.from_numpy(bb).cuda()).cpu().numpy()
+    xo = oracle.solve(Fo, bb)
+    assert np.linalg.norm(x5 - xo) <= APPLY_TOL * np.linalg.norm(xo)
