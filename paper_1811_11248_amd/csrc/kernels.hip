@@ -679,65 +679,121 @@ void launch_top_potrf(double* A, int n, int32_t* err, hipStream_t st) {
 // Triangular solves of the substitution phase, y in LDS, G (ld) in global.
 namespace {
 
-// y <- G^{-1} y, G lower (m x m, ld).  blk: 64*64 doubles of LDS.
+constexpr int kBlkLd = 65;  // row stride of a staged 64x64 block
+
+// y <- G^{-1} y, G lower (m x m, ld), y in LDS.  Per 64-row block: the
+// diagonal block is staged in LDS and solved by wave 0 with shuffles; the
+// rows below subtract their 64-wide dot products, each thread loading its
+// row's 64 entries at once.  blk: 64*65 doubles of LDS.
 __device__ void trsv_lower(const double* G, int ld, int m, double* y, double* blk) {
   const int tid = threadIdx.x, lane = tid & 63;
   for (int jb = 0; jb < m; jb += 64) {
     const int w = min(64, m - jb);
-    for (int e = tid; e < 64 * 64; e += kThreads) {
-      const int r = e & 63, c = e >> 6;
-      blk[e] = (r < w && c <= r) ? G[(size_t)(jb + r) + (size_t)ld * (jb + c)] : 0.0;
-    }
+    load_block_rowmajor<kThreads>(blk, kBlkLd, G + (size_t)jb * ld + jb, (size_t)ld, w, 64,
+                                  [&](int r, int c) { return c < w && c <= r; });
     __syncthreads();
     if (tid < 64) {
       double yl = (lane < w) ? y[jb + lane] : 0.0;
       for (int t = 0; t < w; ++t) {
-        const double yt = __shfl(yl, t, 64) / blk[t + 64 * t];
+        const double yt = __shfl(yl, t, 64) / blk[t * kBlkLd + t];
         if (lane == t) yl = yt;
-        else if (lane > t) yl -= blk[lane + 64 * t] * yt;
+        else if (lane > t) yl -= blk[lane * kBlkLd + t] * yt;
       }
       if (lane < w) y[jb + lane] = yl;
     }
     __syncthreads();
     for (int i = jb + w + tid; i < m; i += kThreads) {
+      const double* gi = G + (size_t)i + (size_t)ld * jb;
       double s = 0.0;
-      for (int t = 0; t < w; ++t) s += G[(size_t)i + (size_t)ld * (jb + t)] * y[jb + t];
+      for (int t0 = 0; t0 < w; t0 += 16) {
+        double g[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) g[t] = (t0 + t < w) ? gi[(size_t)ld * (t0 + t)] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s += g[t] * y[jb + min(t0 + t, w - 1)];
+      }
       y[i] -= s;
     }
     __syncthreads();
   }
 }
 
-// y <- G^{-T} y, G lower (m x m, ld).
+// y <- G^{-T} y, G lower (m x m, ld), y in LDS.  From the last 64-row block
+// up: subtract the dot products of the block's columns below the block with
+// y (one wave per column, four columns in flight), then solve the diagonal
+// block transposed in wave 0.
 __device__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* blk) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int R = kMaxClusterDofs / 64;
   const int nblk = (m + 63) / 64;
   for (int bi = nblk - 1; bi >= 0; --bi) {
     const int jb = bi * 64;
     const int w = min(64, m - jb);
-    // y[jb+t] -= sum_{i >= jb+w} G[i, jb+t] y[i]
-    for (int t = wv; t < w; t += kWaves) {
-      const double* g = G + (size_t)ld * (jb + t);
-      double s = 0.0;
-      for (int i = jb + w + lane; i < m; i += 64) s += g[i] * y[i];
-      s = wave_sum(s);
-      if (lane == 0) y[jb + t] -= s;
+    const int r0 = jb + w;
+    double yr[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = r0 + lane + 64 * t;
+      yr[t] = i < m ? y[i] : 0.0;
     }
-    for (int e = tid; e < 64 * 64; e += kThreads) {
-      const int r = e & 63, c = e >> 6;
-      blk[e] = (r < w && c <= r) ? G[(size_t)(jb + r) + (size_t)ld * (jb + c)] : 0.0;
+    for (int t0 = wv * 4; t0 < w; t0 += kWaves * 4) {
+      double g[4][R];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double* col = G + (size_t)ld * (jb + min(t0 + q, w - 1));
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int i = r0 + lane + 64 * t;
+          g[q][t] = (t0 + q < w && i < m) ? col[i] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) s += g[q][t] * yr[t];
+        s = wave_sum(s);
+        if (lane == 0 && t0 + q < w) y[jb + t0 + q] -= s;
+      }
     }
+    load_block_rowmajor<kThreads>(blk, kBlkLd, G + (size_t)jb * ld + jb, (size_t)ld, w, 64,
+                                  [&](int r, int c) { return c < w && c <= r; });
     __syncthreads();
     if (tid < 64) {
       double yl = (lane < w) ? y[jb + lane] : 0.0;
       for (int t = w - 1; t >= 0; --t) {
-        const double yt = __shfl(yl, t, 64) / blk[t + 64 * t];
+        const double yt = __shfl(yl, t, 64) / blk[t * kBlkLd + t];
         if (lane == t) yl = yt;
-        else if (lane < t) yl -= blk[t + 64 * lane] * yt;
+        else if (lane < t) yl -= blk[t * kBlkLd + lane] * yt;
       }
       if (lane < w) y[jb + lane] = yl;
     }
     __syncthreads();
+  }
+}
+
+// Stages reflectors j0..j0+nj-1 of the far-field block Wf (m rows) in LDS as
+// vs[jj*mp + i] (unit leading entry, zeros above).
+__device__ void stage_reflectors(const ItemD& it, const double* Wf, int m, int mp, int j0, int nj,
+                                 double* vs) {
+  const int n = nj * mp;
+  for (int e0 = threadIdx.x; e0 < n; e0 += kThreads * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads;
+      const int jj = e / mp, i = e - jj * mp, j = j0 + jj;
+      v[u] = 0.0;
+      if (e < n && i < m) {
+        if (i == j) v[u] = 1.0;
+        else if (i > j) v[u] = Wf[(size_t)m * it.piv[j] + i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < n) vs[e] = v[u];
+    }
   }
 }
 
@@ -746,43 +802,79 @@ __device__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* 
 namespace {
 
 // Forward substitution of one cluster: y_s <- U^T G^{-1} y_s, y_n -= F^T y_f.
-// lds: mp + 64*64 doubles (mp = m rounded up to 64).
+// lds: mp (y) + 64*65 (diagonal block) + 16*mp (reflectors) doubles.
 __device__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
   __shared__ double shd[kWaves];
   const int m = it.m;
   if (m == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int R = kMaxClusterDofs / 64;
   const int k = ls.k[it.s], a = ls.a[it.s];
+  const int mp = ((m + 63) / 64) * 64;
   double* y = lds;
-  double* blk = lds + ((m + 63) / 64) * 64;
+  double* blk = lds + mp;
+  double* vs = blk + 64 * kBlkLd;
   double* yg = vec + it.voff;
   for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
   __syncthreads();
   trsv_lower(it.P, m, m, y, blk);
   const double* Wf = it.P + (size_t)m * (m + a);
-  for (int j = 0; j < k; ++j) {
-    const double* x = Wf + (size_t)m * it.piv[j];
-    double s = 0.0;
-    for (int i = j + tid; i < m; i += kThreads) s += (i == j ? 1.0 : x[i]) * y[i];
-    s = block_sum(s, shd);
-    const double f = it.tau[j] * s;
-    for (int i = j + tid; i < m; i += kThreads) y[i] -= f * (i == j ? 1.0 : x[i]);
+  for (int j0 = 0; j0 < k; j0 += 16) {
+    const int nj = min(16, k - j0);
+    stage_reflectors(it, Wf, m, mp, j0, nj, vs);
     __syncthreads();
+    for (int jj = 0; jj < nj; ++jj) {
+      const int j = j0 + jj;
+      const double* v = vs + jj * mp;
+      double s = 0.0;
+      for (int i = j + tid; i < m; i += kThreads) s += v[i] * y[i];
+      s = block_sum(s, shd);
+      const double f = it.tau[j] * s;
+      for (int i = j + tid; i < m; i += kThreads) y[i] -= f * v[i];
+      __syncthreads();
+    }
+  }
+  // y_n -= F^T y_f: one wave per column, four columns in flight
+  double yr[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int i = lane + 64 * t;
+    yr[t] = (i >= k && i < m) ? y[i] : 0.0;
   }
   const double* C = it.P + (size_t)m * m;
-  for (int c = wv; c < a; c += kWaves) {
-    const double* f = C + (size_t)m * c;
-    double s = 0.0;
-    for (int i = k + lane; i < m; i += 64) s += f[i] * y[i];
-    s = wave_sum(s);
-    if (lane == 0) vec[it.vidx[c]] -= s;
+  for (int c0 = wv * 4; c0 < a; c0 += kWaves * 4) {
+    double g[4][R];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double* f = C + (size_t)m * min(c0 + q, a - 1);
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = lane + 64 * t;
+        g[q][t] = (c0 + q < a && i >= k && i < m) ? f[i] : 0.0;
+      }
+    }
+    double s[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) acc += g[q][t] * yr[t];
+      s[q] = wave_sum(acc);
+    }
+    if (lane < 4 && c0 + lane < a) {
+      double sv = s[0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+        if (q == lane) sv = s[q];
+      vec[it.vidx[c0 + lane]] -= sv;
+    }
   }
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
   __syncthreads();
 }
 
 // Backward substitution of one cluster: x_f -= F x_n, x_s <- G^{-T} U x_s.
-// lds: mp + 64*64 + 1024 doubles.
+// lds: mp + 64*65 + 16*mp + 1024 doubles.
 __device__ void bwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
   __shared__ double shd[kWaves];
   const int m = it.m;
@@ -792,7 +884,8 @@ __device__ void bwd_item(const ItemD& it, LevelState ls, double* vec, double* ld
   const int mp = ((m + 63) / 64) * 64;
   double* x = lds;
   double* blk = lds + mp;
-  double* xn = blk + 64 * 64;  // 1024-column chunks of x_n
+  double* vs = blk + 64 * kBlkLd;
+  double* xn = vs + 16 * mp;  // 1024-column chunks of x_n
   double* xg = vec + it.voff;
   for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
   const double* C = it.P + (size_t)m * m;
@@ -803,27 +896,43 @@ __device__ void bwd_item(const ItemD& it, LevelState ls, double* vec, double* ld
     __syncthreads();
     for (int i = k + tid; i < m; i += kThreads) {
       double s = 0.0;
-      for (int c = 0; c < nc; ++c) s += C[(size_t)i + (size_t)m * (c0 + c)] * xn[c];
+      for (int cb = 0; cb < nc; cb += 16) {
+        double f[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) f[q] = (cb + q < nc) ? C[(size_t)i + (size_t)m * (c0 + cb + q)] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (cb + q < nc) s += f[q] * xn[cb + q];
+      }
       x[i] -= s;
     }
   }
   __syncthreads();
   const double* Wf = it.P + (size_t)m * (m + a);
-  for (int j = k - 1; j >= 0; --j) {
-    const double* v = Wf + (size_t)m * it.piv[j];
-    double s = 0.0;
-    for (int i = j + tid; i < m; i += kThreads) s += (i == j ? 1.0 : v[i]) * x[i];
-    s = block_sum(s, shd);
-    const double f = it.tau[j] * s;
-    for (int i = j + tid; i < m; i += kThreads) x[i] -= f * (i == j ? 1.0 : v[i]);
+  for (int j1 = k; j1 > 0; j1 -= 16) {
+    const int j0 = max(0, j1 - 16), nj = j1 - j0;
+    stage_reflectors(it, Wf, m, mp, j0, nj, vs);
     __syncthreads();
+    for (int jj = nj - 1; jj >= 0; --jj) {
+      const int j = j0 + jj;
+      const double* v = vs + jj * mp;
+      double s = 0.0;
+      for (int i = j + tid; i < m; i += kThreads) s += v[i] * x[i];
+      s = block_sum(s, shd);
+      const double f = it.tau[j] * s;
+      for (int i = j + tid; i < m; i += kThreads) x[i] -= f * v[i];
+      __syncthreads();
+    }
   }
   trsv_lower_t(it.P, m, m, x, blk);
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
 }
 
-size_t sweep_lds(int max_m) { return ((size_t)((max_m + 63) / 64) * 64 + 64 * 64 + 1024) * sizeof(double); }
+size_t sweep_lds(int max_m) {
+  const size_t mp = (size_t)((max_m + 63) / 64) * 64;
+  return (mp + 64 * kBlkLd + 16 * mp + 1024) * sizeof(double);
+}
 
 }  // namespace
 
@@ -886,7 +995,7 @@ hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* c
 __global__ void __launch_bounds__(kThreads) top_solve_kernel(const double* L, int n, double* yg) {
   extern __shared__ double lds[];
   double* y = lds;
-  double* blk = lds + ((n + 63) / 64) * 64;
+  double* blk = lds + ((n + 63) / 64) * 64;  // 64*65 doubles
   for (int i = threadIdx.x; i < n; i += kThreads) y[i] = yg[i];
   __syncthreads();
   trsv_lower(L, n, n, y, blk);
@@ -896,7 +1005,7 @@ __global__ void __launch_bounds__(kThreads) top_solve_kernel(const double* L, in
 
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
   if (n <= 0) return;
-  size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * 64) * sizeof(double);
+  size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * kBlkLd) * sizeof(double);
   hipLaunchKernelGGL(top_solve_kernel, dim3(1), dim3(kThreads), lds, st, L, n, y);
 }
 
