@@ -101,6 +101,80 @@ def run_gpu(args):
     return pr, results, timing
 
 
+def run_batch(args):
+    """Batching form: all systems of the many-systems workload factored per
+    level in one launch (schedules from the autotuner), refactored by graph
+    replay, and solved by batched PCG on 4 right-hand sides per system; next
+    to the plain single-system path run system after system."""
+    import numpy as np
+    import torch
+
+    from paper_1811_11248_amd import lrsp
+    from synth import batch_params, batch_rhs, batch_system
+
+    P = batch_params(args.batch)
+    t0 = time.perf_counter()
+    probs = [batch_system(i, P) for i in range(args.batch)]
+    log(f"[batch] built {len(probs)} systems in {time.perf_counter() - t0:.1f} s, "
+        f"{sum(p.n for p in probs)} DoF")
+    mats = [lrsp.DeviceMatrix.from_problem(p) for p in probs]
+    trees = [lrsp.Tree(p.grid, p.leaf) for p in probs]
+    rhs = [batch_rhs(i, p.n, 4) for i, p in enumerate(probs)]
+    torch.cuda.synchronize()
+    out = {"systems": len(probs), "dof": int(sum(p.n for p in probs)), "nrhs": 4}
+    for prec in ("f64", "f32"):
+        t0 = time.perf_counter()
+        B = lrsp.Batch(mats, trees, 1e-2, gemm_prec=prec, autotune=(prec == "f64"))
+        torch.cuda.synchronize()
+        first_ms = (time.perf_counter() - t0) * 1e3
+        Bt = B.pack(rhs)
+        B.refactor()
+        B.pcg(Bt)
+        torch.cuda.synchronize()
+        nst = args.steps if prec == "f64" else max(1, min(args.steps, 3))
+        recs = []
+        t0 = time.perf_counter()
+        for _ in range(nst):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            B.refactor()
+            e1.record()
+            _, it, rr = B.pcg(Bt)
+            e2.record()
+            recs.append((e0, e1, e2, it, rr))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        inf = B.info()
+        fms = float(np.median([r[0].elapsed_time(r[1]) for r in recs]))
+        pms = float(np.median([r[1].elapsed_time(r[2]) for r in recs]))
+        it, rr = recs[-1][3], recs[-1][4]
+        fl = sum(inf["flops"].values())
+        out[prec] = dict(ms_per_step=(t1 - t0) * 1e3 / nst, refactor_ms=fms, pcg_ms=pms,
+                         first_factor_ms=first_ms, host_analysis_ms=inf["ms_analysis"],
+                         factor_gflops=fl / (fms * 1e-3) / 1e9, iters_max=int(it.max()),
+                         iters_mean=float(it.mean()), relres_max=float(rr.max()),
+                         graph_factor=inf["graph_factor"], graph_pcg=inf["graph_pcg"],
+                         refactor_fallbacks=inf["refactor_fallbacks"], sched=inf["sched"][:inf["nlevels"]],
+                         levels=inf["nlevels"])
+        log(f"[batch {prec}] {out[prec]}")
+        del B
+    # plain GPU form: one system after the other, factor + PCG on 4 columns
+    t0 = time.perf_counter()
+    iters = []
+    for i in range(len(probs)):
+        F = lrsp.Factor(mats[i], trees[i], 1e-2)
+        _, it, _ = lrsp.pcg(mats[i], F, torch.from_numpy(rhs[i]).cuda())
+        iters.append(it)
+        del F
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3
+    out["plain_sequential_ms"] = plain_ms
+    out["plain_iters_max"] = int(np.max(iters))
+    out["speedup_vs_plain"] = plain_ms / out["f64"]["ms_per_step"]
+    log(f"[batch plain] {plain_ms:.1f} ms for one pass, speedup {out['speedup_vs_plain']:.2f}")
+    return out
+
+
 def roofline(timing):
     """Roofline of the kernel family with the most GPU time in the timed region."""
     fam = max(timing, key=lambda f: timing[f]["total_ms"])
@@ -153,6 +227,7 @@ def main():
     ap.add_argument("--workload", default="slab64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--batch", type=int, default=512, help="systems of the batching form (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -192,6 +267,8 @@ def main():
                       if k in ("ms_per_step", "factor_ms", "pcg_ms", "iters", "relres", "factor_gflops")}
                   for p in res if p not in ("f64", "analysis")},
     }
+    if args.batch > 0:
+        out["batch"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in run_batch(args).items()}
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -67,6 +67,7 @@ typedef struct {
 
 typedef struct lrsp_tree lrsp_tree;
 typedef struct lrsp_factorization lrsp_factorization;
+typedef struct lrsp_batch lrsp_batch;
 
 /* Factorization options.  Zero-initialise, then set fields. */
 typedef struct {
@@ -84,7 +85,12 @@ typedef struct {
                          96..512 DoFs, else as 2 */
   const float* mlp_weights; /* rank_mode 1: host pointer to the packed MLP
                                parameters (lrsp_mlp_nparams() floats) */
-  int64_t reserved[6];
+  int32_t autotune;   /* exec_mode 0: 1 = time the candidate schedules of every
+                         level now and record the fastest in the autotuner
+                         table; 0 = use the table's entry for the level's
+                         shape if there is one, else the default schedule */
+  int32_t reserved32;
+  int64_t reserved[5];
 } lrsp_opts;
 
 /* ---- cluster tree ------------------------------------------------------
@@ -185,6 +191,88 @@ typedef struct {
   const int32_t* adj;
 } lrsp_level_view;
 lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_level_view* v);
+
+/* ---- batching form -------------------------------------------------------
+ * nsys independent systems, each with its own matrix and tree, factored
+ * together.  At every tree level the clusters of all systems that are still
+ * being eliminated form one work list ordered by colour (clusters of
+ * different systems never interact), and one persistent launch eliminates
+ * the whole level; systems reach their dense top at their own level, and
+ * all tops are factored by one launch.  Each system's factor is the one
+ * lrsp_factor computes for it with exec_mode 2 and the same options.
+ *
+ * Packed vectors: system i occupies rows off_i .. off_i + n_i - 1 with
+ * off_i = n_0 + ... + n_{i-1}; ntot = n_0 + ... + n_{nsys-1}; a block of
+ * nrhs vectors is ntot x nrhs, column-major, on the device.
+ *
+ * A[nsys], T[nsys]: as for lrsp_factor (A[i].h_rowptr / h_col recommended).
+ * status[nsys]: optional host output, LRSP_OK or LRSP_ERR_NOT_SPD per system.
+ * Returns LRSP_ERR_NOT_SPD when some system met a non-positive pivot; *F is
+ * then still returned (the other systems' factors are valid).  Any other
+ * error leaves *F = NULL.  The trees must outlive the batch. */
+lrsp_status lrsp_factor_batched(int32_t nsys, const lrsp_csr* A, lrsp_tree* const* T, double tol,
+                                const lrsp_opts* opts, void* stream, lrsp_batch** F,
+                                int32_t* status);
+
+/* Numeric refactorization with new values of the same patterns (A[i].val
+ * may point to new arrays).  The numeric phase that lrsp_factor_batched
+ * recorded (buffer clears, assembly, one elimination launch per level, the
+ * tops) is replayed as one captured HIP graph, with no host synchronisation
+ * between levels; the ranks are then read back once and compared with the
+ * recorded ones.  If some rank differs, the batch is factored again from
+ * scratch (lrsp_batch_info counts these fallbacks).  Results equal those of
+ * a fresh lrsp_factor_batched. */
+lrsp_status lrsp_refactor_batched(lrsp_batch* F, const lrsp_csr* A, void* stream, int32_t* status);
+lrsp_status lrsp_batch_free(lrsp_batch* F);
+
+/* x = M^{-1} b for every system (packed, nrhs columns; b == x allowed). */
+lrsp_status lrsp_apply_batched(lrsp_batch* F, const double* b, double* x, int32_t nrhs,
+                               void* stream);
+
+/* PCG on every (system, column) pair at once: one sparse product with all
+ * columns, dot products per pair, updates masked per pair; a pair stops at
+ * ||r||_2 <= rtol*||b||_2 while the others go on.  The body of an iteration
+ * runs as two captured HIP graphs (before and after the convergence test,
+ * which reads one integer).  A: the nsys matrices factored in F.
+ * iters, relres: host arrays of nrhs*nsys entries, index c*nsys + i (true
+ * relative residual).  ERR_NO_CONV if some pair did not converge. */
+lrsp_status lrsp_pcg_batched(const lrsp_csr* A, lrsp_batch* F, const double* b, double* x,
+                             int32_t nrhs, double rtol, int32_t maxit, int32_t* iters,
+                             double* relres, void* stream);
+
+typedef struct {
+  int32_t nsys;
+  int32_t nlevels;          /* levels with eliminations (over all systems) */
+  int64_t ntot;
+  double flops[6];          /* as lrsp_info, summed over systems */
+  double ms_factor;         /* host wall time of the last (re)factorization */
+  double ms_analysis;       /* host time of planning and setup (first factorization) */
+  int64_t peak_bytes;       /* device bytes held by the batch */
+  int32_t graph_factor;     /* 1: the last refactorization ran as a graph */
+  int32_t graph_pcg;        /* 1: the last batched PCG ran its iterations as graphs */
+  int32_t coop_in_graph;    /* always 0: graphs hold ordinary launches whose
+                               persistent kernels use a bounded software grid
+                               barrier (one workgroup per CU) */
+  int32_t refactor_fallbacks;
+  int32_t tuned_levels;     /* levels timed by the autotuner in the first factorization */
+  int32_t graph_timeouts;   /* graph runs redone eagerly because a grid barrier gave up */
+  int32_t sched[16];        /* schedule of levels 0..15 (0 persistent, 1 per colour, 2 split) */
+  int32_t grid_cap[16];     /* persistent grid cap of levels 0..15 (0 = full occupancy) */
+} lrsp_batch_info;
+lrsp_status lrsp_batch_info_get(const lrsp_batch* F, lrsp_batch_info* info);
+
+/* Schedule and ranks of one system of the batch, as lrsp_factor_level
+ * (level == the system's number of levels describes its dense top). */
+lrsp_status lrsp_batch_level(const lrsp_batch* F, int32_t sys, int32_t level, lrsp_level_view* v);
+lrsp_status lrsp_batch_system_levels(const lrsp_batch* F, int32_t sys, int32_t* nlevels);
+
+/* ---- autotuner table -----------------------------------------------------
+ * Schedules chosen by timing (opts.autotune = 1), keyed by level shape,
+ * shared by all factorizations of the process; saved and loaded as JSON. */
+lrsp_status lrsp_autotune_save(const char* path);
+lrsp_status lrsp_autotune_load(const char* path);
+lrsp_status lrsp_autotune_clear(void);
+int32_t lrsp_autotune_entries(void);
 
 /* ---- measurement ---------------------------------------------------------
  * When timing is on, the library records a pair of HIP events on the call's

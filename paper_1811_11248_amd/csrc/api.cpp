@@ -15,147 +15,12 @@
 #include "desc.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "runtime.hpp"
 
 using namespace lrsp;
+using namespace lrsp::rt;
 
 namespace {
-
-thread_local std::string g_last_error;
-
-lrsp_status fail(lrsp_status s, const std::string& msg) {
-  g_last_error = msg;
-  return s;
-}
-
-// Event timing of kernel families (lrsp_timing_*).
-constexpr int kFamilies = 11;
-struct TimingState {
-  bool on = false;
-  std::vector<hipEvent_t> pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kFamilies];
-  int64_t launches[kFamilies] = {};
-  double ms[kFamilies] = {};
-  double flops[kFamilies] = {};
-  double bytes[kFamilies] = {};
-};
-TimingState g_tm;
-
-hipEvent_t tm_event() {
-  if (!g_tm.pool.empty()) {
-    hipEvent_t e = g_tm.pool.back();
-    g_tm.pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  (void)hipEventCreate(&e);
-  return e;
-}
-
-// Records the start event of a timed launch; returns the pending index.
-struct TimedLaunch {
-  int fam;
-  hipStream_t st;
-  hipEvent_t a = nullptr;
-  TimedLaunch(int f, hipStream_t s) : fam(f), st(s) {
-    if (!g_tm.on) return;
-    a = tm_event();
-    (void)hipEventRecord(a, st);
-  }
-  ~TimedLaunch() {
-    if (!a) return;
-    hipEvent_t b = tm_event();
-    (void)hipEventRecord(b, st);
-    g_tm.pending[fam].push_back({a, b});
-    g_tm.launches[fam]++;
-  }
-};
-
-void tm_collect() {
-  for (int f = 0; f < kFamilies; ++f) {
-    for (auto& pr : g_tm.pending[f]) {
-      float ms = 0.f;
-      (void)hipEventSynchronize(pr.second);
-      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) g_tm.ms[f] += ms;
-      g_tm.pool.push_back(pr.first);
-      g_tm.pool.push_back(pr.second);
-    }
-    g_tm.pending[f].clear();
-  }
-}
-
-#define HIPCHK(expr)                                                                        \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(LRSP_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_));          \
-  } while (0)
-
-// Device buffer owned by the factor (stream-ordered allocator, cached pool).
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-
-bool g_pool_init = false;
-
-hipError_t dalloc(DevBuf* b, size_t bytes, hipStream_t st) {
-  if (!g_pool_init) {
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-      hipMemPool_t pool;
-      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-      }
-    }
-    g_pool_init = true;
-  }
-  b->bytes = bytes;
-  return hipMallocAsync(&b->p, std::max<size_t>(bytes, 256), st);
-}
-
-void dfree(DevBuf* b, hipStream_t st) {
-  if (b->p) (void)hipFreeAsync(b->p, st);
-  b->p = nullptr;
-  b->bytes = 0;
-}
-
-uint64_t g_level_ids = 0;
-
-struct LevelDev {
-  const uint64_t id = ++g_level_ids;  // unique per workspace
-  LevelPlan plan;
-  std::vector<int> k, a, b;
-  int max_m = 0;
-  DevBuf work, wints;      // D / fine / coarse halves; posmaps and column lists
-  DevBuf fac;              // panels, tau, norms (doubles)
-  DevBuf fints;            // colseg, colnat, stepof, piv, segoff (int32)
-  DevBuf fvidx;            // vidx (int64)
-  DevBuf desc;             // SegD / PairD / WbD / ItemD
-  DevBuf state;            // k, a, b, err
-  ItemD* d_items = nullptr;
-  LevelState ls{};
-  int64_t vbase = 0;       // offset of this level in the vector buffer
-  std::vector<int64_t> voff;
-  int64_t nvec = 0;
-  DevBuf gidx;             // level >= 1: indices into the previous level's vector
-  // adjacency export
-  std::vector<int> adj_ptr, adj, sizes_i, colour_i, order_i;
-  std::vector<double> sweep_bytes;  // per colour: bytes one sweep of it moves
-  std::vector<SplitDims> cdims;     // per colour capacities
-  int max_items = 0;                // largest colour
-  int max_nseg = 0;
-  bool split = false;               // several workgroups per cluster
-  const int32_t* d_cstart = nullptr;
-  DevBuf vals_off;                  // level 0: CSR entry -> work-arena offset
-  DevBuf tasks;                     // level >= 1: assembly copy tasks
-  int ntasks = 0;
-  uint64_t tasks_src = 0;           // id of the level the tasks read from
-  void free_all(hipStream_t st) {
-    dfree(&work, st); dfree(&wints, st); dfree(&fac, st); dfree(&fints, st); dfree(&fvidx, st);
-    dfree(&desc, st); dfree(&state, st); dfree(&gidx, st); dfree(&vals_off, st); dfree(&tasks, st);
-  }
-};
 
 // Analysis of the last pattern factored with a tree, and level workspaces
 // returned by freed factors.
@@ -227,299 +92,8 @@ struct lrsp_factorization {
   }
 };
 
-namespace {
 
-template <class T>
-T* at(const DevBuf& b, int64_t off) {
-  return reinterpret_cast<T*>(b.p) + off;
-}
-
-// Coupling c(x,y) between the coarse DoFs of two linked clusters of a
-// finished level: returns the source block and whether it is transposed.
-bool coupling(const LevelDev& L, int x, int y, const double** src, int* sld, int* trans) {
-  const LevelPlan& p = L.plan;
-  if (!std::binary_search(p.adj2[x].begin(), p.adj2[x].end(), y)) return false;
-  const int later = p.pos[x] > p.pos[y] ? x : y;
-  const int earlier = later == x ? y : x;
-  auto it = p.hc_off.find(pkey(later, earlier));
-  if (it == p.hc_off.end()) return false;
-  *src = at<double>(L.work, it->second);
-  *sld = p.m[later];
-  *trans = (later == x) ? 0 : 1;
-  return true;
-}
-
-// Tasks that move the coarse-coarse couplings of finished level `prev` into
-// block storage of the next level (fine halves of edges, diagonal blocks).
-bool assembly_tasks(const LevelDev& prev, const LevelDev& cur, std::vector<CopyD>* tasks) {
-  const LevelPlan& q = cur.plan;
-  const std::vector<int>& k = prev.k;
-  auto add = [&](const double* src, int sld, int trans, double* dst, int dld, int rows, int cols) {
-    if (rows <= 0 || cols <= 0) return;
-    CopyD c{src, dst, sld, dld, rows, cols, trans, 0};
-    tasks->push_back(c);
-  };
-  for (int P = 0; P < q.M; ++P) {
-    const int L = 2 * P, R = 2 * P + 1;
-    double* D = at<double>(cur.work, q.d_off[P]);
-    const int mP = q.m[P];
-    add(at<double>(prev.work, prev.plan.d_off[L]), prev.plan.m[L], 0, D, mP, k[L], k[L]);
-    add(at<double>(prev.work, prev.plan.d_off[R]), prev.plan.m[R], 0, D + (size_t)k[L] * mP + k[L],
-        mP, k[R], k[R]);
-    const double* src;
-    int sld, tr;
-    if (coupling(prev, R, L, &src, &sld, &tr)) add(src, sld, tr, D + k[L], mP, k[R], k[L]);
-  }
-  for (auto& kv : q.hf_off) {
-    const int e = (int)(kv.first >> 32), l = (int)(kv.first & 0xffffffffu);
-    if (!std::binary_search(q.adj[e].begin(), q.adj[e].end(), l)) continue;  // fill only
-    if ((int)q.zfin.at(kv.first).size() != q.m[l]) return false;
-    double* H = at<double>(cur.work, kv.second);
-    const int me = q.m[e];
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
-        const int x = 2 * e + a, y = 2 * l + b;
-        const double* src;
-        int sld, tr;
-        if (!coupling(prev, x, y, &src, &sld, &tr)) continue;
-        const int ro = a ? k[2 * e] : 0, co = b ? k[2 * l] : 0;
-        add(src, sld, tr, H + ro + (size_t)me * co, me, k[x], k[y]);
-      }
-  }
-  return true;
-}
-
-// Copies a host array into a new device buffer; waits for the copy, since
-// the host array may be pageable and short-lived.
-lrsp_status upload(DevBuf* b, const void* src, size_t bytes, hipStream_t st) {
-  HIPCHK(dalloc(b, bytes, st));
-  if (bytes) HIPCHK(hipMemcpyAsync(b->p, src, bytes, hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return LRSP_OK;
-}
-
-// Builds device storage and descriptors of one planned level.
-lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase) {
-  LevelPlan& p = L->plan;
-  const int M = p.M;
-  plan_layout(&p);
-  L->max_m = 0;
-  for (int x = 0; x < M; ++x) L->max_m = std::max(L->max_m, p.m[x]);
-  if (L->max_m > kMaxClusterDofs)
-    return fail(LRSP_ERR_ARG, "cluster larger than " + std::to_string(kMaxClusterDofs) +
-                                  " DoFs; use a smaller leaf size");
-  HIPCHK(dalloc(&L->work, sizeof(double) * p.work_doubles, st));
-  launch_zero(at<double>(L->work, 0), p.work_doubles, st);
-  // int arena: posmaps (-1 = absent) and column lists
-  std::vector<int32_t> hints(p.work_ints, -1);
-  for (auto& kv : p.zfin) {
-    const std::vector<int>& z = kv.second;
-    int32_t* pm = hints.data() + p.pos_off[kv.first];
-    for (size_t i = 0; i < z.size(); ++i) pm[z[i]] = (int32_t)i;
-    std::copy(z.begin(), z.end(), hints.data() + p.zl_off[kv.first]);
-  }
-  if (lrsp_status s = upload(&L->wints, hints.data(), hints.size() * 4, st)) return s;
-  // factor arenas
-  int64_t fd = 0, fi = 0, fv = 0;
-  std::vector<int64_t> poff(M), toff(M), noff(M), csoff(M), cnoff(M), stoff(M), pvoff(M),
-      sgoff(M), vxoff(M);
-  auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
-  for (int s = 0; s < M; ++s) {
-    const int64_t pc = p.acap[s] + p.bcap[s];
-    const int nseg = (int)(p.nlist[s].size() + p.wlist[s].size());
-    poff[s] = fd; fd += al((int64_t)p.m[s] * (p.m[s] + pc));
-    toff[s] = fd; fd += al(p.kcap[s]);
-    noff[s] = fd; fd += al(pc);
-    csoff[s] = fi; fi += al(pc);
-    cnoff[s] = fi; fi += al(pc);
-    stoff[s] = fi; fi += al(pc);
-    pvoff[s] = fi; fi += al(p.kcap[s]);
-    sgoff[s] = fi; fi += al(nseg + 1);
-    vxoff[s] = fv; fv += al(pc);
-  }
-  HIPCHK(dalloc(&L->fac, sizeof(double) * fd, st));
-  HIPCHK(dalloc(&L->fints, sizeof(int32_t) * fi, st));
-  HIPCHK(dalloc(&L->fvidx, sizeof(int64_t) * fv, st));
-  HIPCHK(dalloc(&L->state, sizeof(int32_t) * (3 * (size_t)M + 8), st));
-  int32_t* sb = at<int32_t>(L->state, 0);
-  L->ls.k = sb;
-  L->ls.a = sb + M;
-  L->ls.b = sb + 2 * M;
-  L->ls.err = sb + 3 * M;
-  launch_zero_i32(sb, 3 * (int64_t)M + 8, st);
-  // level vector offsets
-  L->voff.assign(M, 0);
-  int64_t vo = 0;
-  for (int x = 0; x < M; ++x) {
-    L->voff[x] = vbase + vo;
-    vo += p.m[x];
-  }
-  L->vbase = vbase;
-  L->nvec = vo;
-  // descriptors
-  std::vector<SegD> segs;
-  std::vector<PairD> pairs;
-  std::vector<WbD> wbs;
-  std::vector<ItemD> items(M);
-  std::vector<int64_t> seg0(M), pair0(M), wb0(M);
-  double* W = at<double>(L->work, 0);
-  int32_t* WI = at<int32_t>(L->wints, 0);
-  for (int idx = 0; idx < M; ++idx) {
-    const int s = p.order[idx];
-    const std::vector<int>& nl = p.nlist[s];
-    const std::vector<int>& wl = p.wlist[s];
-    seg0[s] = (int64_t)segs.size();
-    wb0[s] = (int64_t)wbs.size();
-    for (int pass = 0; pass < 2; ++pass)
-      for (int y : (pass ? wl : nl)) {
-        SegD sg{};
-        sg.y = y;
-        sg.isw = pass;
-        sg.voff = L->voff[y];
-        WbD wb{};
-        if (p.pos[y] < p.pos[s]) {
-          const int64_t o = p.hc_off.at(pkey(s, y));
-          sg.src = W + o;
-          sg.zl = nullptr;
-          sg.coarse = 1;
-          sg.cap = p.kcap[y];
-          wb.dst = W + o;
-          wb.ld = p.m[s];
-          wb.trans = 0;
-          wb.nrows = p.m[s];
-          wb.ncols = p.kcap[y];
-        } else {
-          const uint64_t key = pkey(s, y);
-          sg.src = W + p.hf_off.at(key);
-          sg.zl = WI + p.zl_off.at(key);
-          sg.coarse = 0;
-          sg.nfine = (int)p.zfin.at(key).size();
-          sg.cap = sg.nfine;
-          wb.dst = W + p.hc_off.at(pkey(y, s));
-          wb.ld = p.m[y];
-          wb.trans = 1;
-          wb.nrows = p.m[y];
-          wb.ncols = p.kcap[s];
-        }
-        segs.push_back(sg);
-        wbs.push_back(wb);
-      }
-    pair0[s] = (int64_t)pairs.size();
-    const int nn = (int)nl.size();
-    for (int j = 0; j < nn; ++j)
-      for (int i = 0; i <= j; ++i) {
-        PairD pd{};
-        const int pi = nl[i], qj = nl[j];
-        if (i == j) {
-          pd.dst = W + p.d_off[pi];
-          pd.ld = p.m[pi];
-          pd.diag = 1;
-          pd.nrows = p.m[pi];
-          pd.ncols = p.m[pi];
-        } else {
-          const int e = p.pos[pi] < p.pos[qj] ? pi : qj;
-          const int l = e == pi ? qj : pi;
-          if (p.pos[e] < p.pos[s]) {
-            pd.dst = W + p.hc_off.at(pkey(l, e));
-            pd.ld = p.m[l];
-            pd.rows_from_j = (l == qj);
-            pd.nrows = p.m[l];
-            pd.ncols = p.kcap[e];
-          } else {
-            const uint64_t key = pkey(e, l);
-            pd.dst = W + p.hf_off.at(key);
-            pd.posmap = WI + p.pos_off.at(key);
-            pd.ld = p.m[e];
-            pd.rows_from_j = (e == qj);
-            pd.nrows = p.m[e];
-            pd.ncols = (int)p.zfin.at(key).size();
-          }
-        }
-        pairs.push_back(pd);
-      }
-  }
-  const size_t bs = sizeof(SegD) * segs.size(), bp = sizeof(PairD) * pairs.size(),
-               bw = sizeof(WbD) * wbs.size(), bi = sizeof(ItemD) * M,
-               bc = sizeof(int32_t) * (p.ncolours + 1);
-  const size_t o1 = (bs + 255) & ~(size_t)255, o2 = o1 + ((bp + 255) & ~(size_t)255),
-               o3 = o2 + ((bw + 255) & ~(size_t)255), o4 = o3 + ((bi + 255) & ~(size_t)255);
-  HIPCHK(dalloc(&L->desc, o4 + bc, st));
-  char* db = reinterpret_cast<char*>(L->desc.p);
-  double* F = at<double>(L->fac, 0);
-  int32_t* FI = at<int32_t>(L->fints, 0);
-  int64_t* FV = at<int64_t>(L->fvidx, 0);
-  for (int idx = 0; idx < M; ++idx) {
-    const int s = p.order[idx];
-    ItemD& it = items[idx];
-    it.s = s;
-    it.m = p.m[s];
-    it.nseg = (int)(p.nlist[s].size() + p.wlist[s].size());
-    it.nsegn = (int)p.nlist[s].size();
-    it.pcap = p.acap[s] + p.bcap[s];
-    it.kcap = p.kcap[s];
-    it.seg = reinterpret_cast<const SegD*>(db) + seg0[s];
-    it.pair = reinterpret_cast<const PairD*>(db + o1) + pair0[s];
-    it.wb = reinterpret_cast<const WbD*>(db + o2) + wb0[s];
-    it.D = W + p.d_off[s];
-    it.P = F + poff[s];
-    it.tau = F + toff[s];
-    it.norms = F + noff[s];
-    it.colseg = FI + csoff[s];
-    it.colnat = FI + cnoff[s];
-    it.stepof = FI + stoff[s];
-    it.piv = FI + pvoff[s];
-    it.segoff = FI + sgoff[s];
-    it.vidx = FV + vxoff[s];
-    it.voff = L->voff[s];
-  }
-  std::vector<char> blob(o4 + bc, 0);
-  if (bs) std::memcpy(blob.data(), segs.data(), bs);
-  if (bp) std::memcpy(blob.data() + o1, pairs.data(), bp);
-  if (bw) std::memcpy(blob.data() + o2, wbs.data(), bw);
-  std::memcpy(blob.data() + o3, items.data(), bi);
-  std::memcpy(blob.data() + o4, p.cstart.data(), bc);
-  HIPCHK(hipMemcpyAsync(db, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
-  L->d_items = reinterpret_cast<ItemD*>(db + o3);
-  L->d_cstart = reinterpret_cast<const int32_t*>(db + o4);
-  // per-colour capacities
-  L->cdims.assign(p.ncolours, SplitDims{0, 0, 0, 0});
-  L->max_items = 0;
-  L->max_nseg = 0;
-  for (int c = 0; c < p.ncolours; ++c) {
-    L->max_items = std::max(L->max_items, p.cstart[c + 1] - p.cstart[c]);
-    SplitDims& d = L->cdims[c];
-    for (int idx = p.cstart[c]; idx < p.cstart[c + 1]; ++idx) {
-      const ItemD& it = items[idx];
-      d.max_m = std::max(d.max_m, it.m);
-      d.max_nseg = std::max(d.max_nseg, it.nseg);
-      d.max_pcap = std::max(d.max_pcap, it.pcap);
-      d.max_acap = std::max(d.max_acap, p.acap[it.s]);
-    }
-    L->max_nseg = std::max(L->max_nseg, d.max_nseg);
-  }
-  // hipMemcpyAsync from pageable memory may return before the copy is done
-  HIPCHK(hipStreamSynchronize(st));
-  // export copies
-  L->sizes_i = p.m;
-  L->colour_i = p.colour;
-  L->order_i = p.order;
-  L->adj_ptr.assign(1, 0);
-  L->adj.clear();
-  for (int x = 0; x < M; ++x) {
-    L->adj.insert(L->adj.end(), p.adj[x].begin(), p.adj[x].end());
-    L->adj_ptr.push_back((int)L->adj.size());
-  }
-  return LRSP_OK;
-}
-
-bool complete_graph(const std::vector<std::vector<int>>& adj) {
-  const int M = (int)adj.size();
-  for (int x = 0; x < M; ++x)
-    if ((int)adj[x].size() != M - 1) return false;
-  return true;
-}
-
-}  // namespace
+const TreeH& lrsp::rt::tree_of(const lrsp_tree* t) { return t->t; }
 
 extern "C" {
 
@@ -536,7 +110,7 @@ const char* lrsp_status_str(lrsp_status s) {
   return "unknown status";
 }
 
-const char* lrsp_last_error_info(void) { return g_last_error.c_str(); }
+const char* lrsp_last_error_info(void) { return last_error(); }
 
 lrsp_status lrsp_tree_build(const lrsp_grid* g, int32_t leaf_size, lrsp_tree** out) {
   if (!g || !out) return fail(LRSP_ERR_ARG, "null argument");
@@ -679,25 +253,8 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     if (level == 0 && L->vals_off.p) {
       launch_scatter_vals(A->val, at<int64_t>(L->vals_off, 0), A->nnz, at<double>(L->work, 0), st);
     } else if (level == 0) {
-      std::vector<int64_t> off(A->nnz, -1);
-      const LevelPlan& p = L->plan;
-      for (int64_t i = 0; i < tr.n; ++i) {
-        const int pc = tr.dof_cluster[i], li = tr.dof_local[i];
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-          const int j = cl[e];
-          const int q = tr.dof_cluster[j], lj = tr.dof_local[j];
-          if (q == pc) {
-            off[e] = p.d_off[pc] + li + (int64_t)p.m[pc] * lj;
-          } else if (p.pos[pc] < p.pos[q]) {
-            const uint64_t key = pkey(pc, q);
-            const std::vector<int>& z = p.zfin.at(key);
-            const int col = (int)(std::lower_bound(z.begin(), z.end(), lj) - z.begin());
-            if (col >= (int)z.size() || z[col] != lj)
-              return fail(LRSP_ERR_INTERNAL, "level-0 entry outside its fine column set");
-            off[e] = p.hf_off.at(key) + li + (int64_t)p.m[pc] * col;
-          }
-        }
-      }
+      std::vector<int64_t> off;
+      if (lrsp_status s = level0_offsets(tr, rp, cl, A->nnz, L->plan, &off)) return s;
       if (lrsp_status s = upload(&L->vals_off, off.data(), off.size() * 8, st)) return s;
       launch_scatter_vals(A->val, at<int64_t>(L->vals_off, 0), A->nnz, at<double>(L->work, 0), st);
     } else {
@@ -712,12 +269,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
         L->tasks_src = prev->id;
         // gather indices into the previous level's vector
         std::vector<int64_t> g;
-        g.reserve(L->nvec);
-        for (int P = 0; P < M; ++P)
-          for (int c = 0; c < 2; ++c) {
-            const int x = 2 * P + c;
-            for (int i = 0; i < prev->k[x]; ++i) g.push_back(prev->voff[x] + i);
-          }
+        coarse_gather_indices(*prev, M, &g);
         dfree(&L->gidx, st);
         if (lrsp_status s = upload(&L->gidx, g.data(), g.size() * 8, st)) return s;
       }
@@ -772,28 +324,20 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
                                          ") at level " + std::to_string(herr[1]) + " cluster " +
                                          std::to_string(herr[2]));
     }
+    double f[5];
+    level_stats(L, f);
     double lvl_flops = 0.0;
-    L->sweep_bytes.assign(p.ncolours, 0.0);
-    for (int s = 0; s < M; ++s) {
-      const double m = p.m[s], a = L->a[s], b = L->b[s], k = L->k[s];
-      double f[5] = {m * m * m / 3.0, m * m * (a + b), 0.0, 0.0, a * (a + 1.0) * (m - k)};
-      for (int j = 0; j < k; ++j) {
-        f[2] += 4.0 * (m - j) * (b - j);
-        f[3] += 4.0 * (m - j) * a;
-      }
-      for (int i = 0; i < 5; ++i) {
-        flops[i] += f[i];
-        lvl_flops += f[i];
-      }
-      if (g_tm.on && L->split) {
-        for (int i = 0; i < 5; ++i) g_tm.flops[4 + i] += f[i];
+    for (int i = 0; i < 5; ++i) {
+      flops[i] += f[i];
+      lvl_flops += f[i];
+      if (g_tm.on && L->split) g_tm.flops[4 + i] += f[i];
+    }
+    if (g_tm.on && L->split) {
+      for (int s = 0; s < M; ++s) {
+        const double m = p.m[s], a = L->a[s], b = L->b[s], k = L->k[s];
         g_tm.bytes[3] += 16.0 * m * (m + a + b);  // panel gathered: read + write
         g_tm.bytes[9] += 16.0 * k * (a + b);
       }
-      // one sweep reads G (lower), the k reflectors and F once, and reads
-      // and writes the cluster's and its near field's vector entries
-      L->sweep_bytes[p.colour[s]] +=
-          8.0 * (m * (m + 1) / 2.0 + k * m + (m - k) * a) + 8.0 * (2.0 * m + 2.0 * a);
     }
     if (g_tm.on) {
       g_tm.flops[0] += lvl_flops;
@@ -830,36 +374,15 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   double* Tm = at<double>(F->top, 0);
   launch_zero(Tm, (int64_t)ntop * ntop, st);
   if (level == 0) {
-    std::vector<int64_t> off(A->nnz, -1);
-    for (int64_t i = 0; i < tr.n; ++i) {
-      const int pc = tr.dof_cluster[i], li = tr.dof_local[i];
-      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-        const int j = cl[e];
-        const int q = tr.dof_cluster[j], lj = tr.dof_local[j];
-        off[e] = (toff[pc] + li) + (int64_t)ntop * (toff[q] + lj);
-      }
-    }
+    std::vector<int64_t> off;
+    top_offsets_level0(tr, rp, cl, A->nnz, toff, ntop, &off);
     DevBuf doff;
     if (lrsp_status s = upload(&doff, off.data(), off.size() * 8, st)) return s;
     launch_scatter_vals(A->val, at<int64_t>(doff, 0), A->nnz, Tm, st);
     dfree(&doff, st);
   } else {
     std::vector<CopyD> tasks;
-    const std::vector<int>& k = prev->k;
-    const int Mp = prev->plan.M;
-    std::vector<int64_t> xo(Mp);
-    for (int x = 0; x < Mp; ++x) xo[x] = toff[x / 2] + ((x & 1) ? k[x - 1] : 0);
-    for (int x = 0; x < Mp; ++x) {
-      if (k[x] > 0)
-        tasks.push_back(CopyD{at<double>(prev->work, prev->plan.d_off[x]), Tm + xo[x] + (size_t)ntop * xo[x],
-                              prev->plan.m[x], ntop, k[x], k[x], 0, 0});
-      for (int y : prev->plan.adj2[x]) {
-        const double* src;
-        int sld, trn;
-        if (k[x] > 0 && k[y] > 0 && coupling(*prev, x, y, &src, &sld, &trn))
-          tasks.push_back(CopyD{src, Tm + xo[x] + (size_t)ntop * xo[y], sld, ntop, k[x], k[y], trn, 0});
-      }
-    }
+    top_tasks(*prev, toff, ntop, Tm, &tasks);
     DevBuf dt;
     if (!tasks.empty()) {
       if (lrsp_status s = upload(&dt, tasks.data(), tasks.size() * sizeof(CopyD), st)) return s;
@@ -867,11 +390,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       dfree(&dt, st);
     }
     std::vector<int64_t> g;
-    for (int P = 0; P < M; ++P)
-      for (int c = 0; c < 2; ++c) {
-        const int x = 2 * P + c;
-        for (int i = 0; i < k[x]; ++i) g.push_back(prev->voff[x] + i);
-      }
+    coarse_gather_indices(*prev, M, &g);
     if (lrsp_status s = upload(&F->top_gidx, g.data(), g.size() * 8, st)) return s;
   }
   DevBuf terr;
@@ -902,9 +421,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   inf.ms_analysis = ms_an;
   inf.levels_reused = reused;
   int64_t held = 0;
-  for (auto& L : F->levels)
-    held += (int64_t)(L->work.bytes + L->wints.bytes + L->fac.bytes + L->fints.bytes + L->fvidx.bytes +
-                      L->desc.bytes + L->state.bytes + L->gidx.bytes + L->vals_off.bytes + L->tasks.bytes);
+  for (auto& L : F->levels) held += L->held_bytes();
   inf.peak_bytes = held + (int64_t)(F->top.bytes + F->vec.bytes + F->perm.bytes);
   *out = F.release();
   return LRSP_OK;
@@ -1050,7 +567,7 @@ lrsp_status lrsp_pcg(const lrsp_csr* A, const lrsp_factorization* F, const doubl
     relres[rhs] = nb > 0 ? std::sqrt(ht) / nb : 0.0;
     if (!conv) result = LRSP_ERR_NO_CONV;
   }
-  if (result != LRSP_OK) g_last_error = "PCG reached maxit";
+  if (result != LRSP_OK) (void)fail(result, "PCG reached maxit");
   return result;
 }
 

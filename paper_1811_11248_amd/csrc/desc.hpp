@@ -79,6 +79,8 @@ struct ItemD {
   double* norms;    // [pcap] scratch
   int32_t* segoff;  // [nseg+1] scratch
   int64_t voff;     // offset of s in the level vector
+  int32_t* serr;    // error bits (1 << ErrCode) of the system s belongs to,
+                    // or null (batched factorizations)
 };
 
 // Per-level dynamic results, indexed by cluster.
@@ -94,6 +96,40 @@ struct CopyD {
   const double* src;
   double* dst;
   int32_t sld, dld, rows, cols, trans, pad;
+};
+
+// Dense top system of one system of a batch: L (n x n, lower after the
+// factorization) and its segment of the vector buffer.
+struct TopD {
+  double* L;
+  int64_t voff;
+  int32_t* err;  // error bits of the system
+  int32_t n;
+  int32_t pad;
+};
+
+// base[off[e]] = val[e] for e < nnz with off[e] >= 0 (one system of a batch).
+struct ScatterD {
+  const double* val;
+  const int64_t* off;
+  double* base;
+  int64_t nnz;
+};
+
+// Software grid barrier of a persistent launch that is not cooperative
+// (launches recorded in graphs).  count returns to 0 after every barrier;
+// timeout is set when a wait gave up, after which results are invalid.
+struct GridBar {
+  uint32_t count;
+  uint32_t gen;
+  int32_t timeout;
+  int32_t pad;
+};
+
+// n doubles at p (buffer fills of a batch).
+struct SpanD {
+  double* p;
+  int64_t n;
 };
 
 enum ErrCode : int32_t {

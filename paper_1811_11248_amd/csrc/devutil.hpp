@@ -70,6 +70,41 @@ __device__ __forceinline__ void set_error(int32_t* err, int level, int cluster, 
   }
 }
 
+// Error of the cluster of an item: first error of the level, plus the bit of
+// the code in the item's system word.
+__device__ __forceinline__ void item_error(const ItemD& it, int32_t* err, int level, int code) {
+  set_error(err, level, it.s, code);
+  if (it.serr) atomicOr(it.serr, 1 << code);
+}
+
+// Grid-wide barrier over nblocks resident workgroups without a cooperative
+// launch.  Every wait is bounded: after kBarSpins polls the workgroup gives
+// up, records the timeout and goes on, so every wave still exits.
+constexpr uint32_t kBarSpins = 1u << 22;
+__device__ __forceinline__ void sw_grid_sync(GridBar* b, uint32_t nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t g = __hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > kBarSpins) {
+          __hip_atomic_store(&b->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
 // Column-major lower-triangular tile enumeration: index -> (R, C), R >= C.
 __device__ __forceinline__ void tri_tile(int idx, int nt, int& R, int& C) {
   double b = 2.0 * nt + 1.0;

@@ -413,7 +413,7 @@ __device__ void schur_scatter(const ItemD& it, const double* C, int ld, int m, i
           col = pd.posmap ? pd.posmap[cn] : cn;
         }
         if (row < 0 || col < 0 || row >= pd.nrows || col >= pd.ncols) {
-          set_error(err, level, it.s, kErrIndex);
+          item_error(it, err, level, kErrIndex);
           continue;
         }
         pd.dst[(size_t)row + (size_t)pd.ld * col] -= acc[r][q];
@@ -467,7 +467,7 @@ __device__ bool seg_scan(const ItemD& it, LevelState ls, int level, int* soff, i
   b_out = soff[nseg] - a_out;
   const bool bad = *flag || soff[nseg] > it.pcap;
   for (int i = tid; i <= nseg; i += kThreads) it.segoff[i] = soff[i];
-  if (bad && tid == 0) set_error(ls.err, level, it.s, kErrCapacity);
+  if (bad && tid == 0) item_error(it, ls.err, level, kErrCapacity);
   __syncthreads();
   return !bad;
 }
@@ -535,14 +535,14 @@ __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol,
   // S_s: Cholesky of A_ss and scaling of the block row
   chol_solve(P, m, m, P + ld * m, a + b, lds, &sbad);
   __syncthreads();
-  if (sbad && tid == 0) set_error(ls.err, level, it.s, kErrNotSPD);
+  if (sbad && tid == 0) item_error(it, ls.err, level, kErrNotSPD);
   // compression of the scaled far field G^{-1} A_sw
   double* Wf = P + ld * (m + a);
   int k = 0;
   if (b > 0 && m > 0)
     k = cpqr(Wf, m, m, b, tol, tol_mode, it.piv, it.stepof, it.tau, it.norms, shd, shi);
   if (k > it.kcap) {
-    if (tid == 0) set_error(ls.err, level, it.s, kErrCapacity);
+    if (tid == 0) item_error(it, ls.err, level, kErrCapacity);
     k = it.kcap;
   }
   __syncthreads();
@@ -564,7 +564,7 @@ __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol,
     }
     const int row = t.trans ? cn : r, col = t.trans ? r : cn;
     if (row >= t.nrows || col >= t.ncols) {
-      set_error(ls.err, level, it.s, kErrIndex);
+      item_error(it, ls.err, level, kErrIndex);
       continue;
     }
     t.dst[(size_t)row + (size_t)t.ld * col] = v;
@@ -592,20 +592,23 @@ __global__ void __launch_bounds__(kThreads) slre_kernel(const ItemD* __restrict_
   slre_item(items[blockIdx.x], ls, level, tol, tol_mode, prec, lds, soff);
 }
 
-// All colours of a level in one cooperative launch: workgroups stride over
+// All colours of a level in one persistent launch: workgroups stride over
 // the clusters of a colour, then wait at a grid barrier before the next.
+// SW = false: cooperative launch (grid_group barrier); SW = true: ordinary
+// launch with a co-resident grid and the bounded software barrier `bar`.
+template <bool SW>
 __global__ void __launch_bounds__(kThreads) slre_level_kernel(const ItemD* __restrict__ items,
                                                               const int32_t* __restrict__ cstart,
                                                               int ncolours, LevelState ls, int level,
                                                               double tol, int tol_mode, int prec,
-                                                              int max_m) {
+                                                              int max_m, GridBar* bar) {
   extern __shared__ double lds[];
   int* soff = reinterpret_cast<int*>(lds + (size_t)max_m * kNB + kNB * kNB + kNB * 256);
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int c = 0; c < ncolours; ++c) {
     for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x)
       slre_item(items[i], ls, level, tol, tol_mode, prec, lds, soff);
-    grid.sync();
+    if constexpr (SW) sw_grid_sync(bar, gridDim.x);
+    else cooperative_groups::this_grid().sync();
   }
 }
 
@@ -629,7 +632,7 @@ void launch_slre(const ItemD* items, int nitems, int max_m, int max_nseg, LevelS
                      ls, level, tol, tol_mode, prec, max_m);
 }
 
-static int coop_grid(const void* fn, size_t lds, int want) {
+int device_cus() {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0;
@@ -637,23 +640,52 @@ static int coop_grid(const void* fn, size_t lds, int want) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 1;
   }
+  return cus;
+}
+
+static int occupancy(const void* fn, size_t lds) {
   int per = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, lds) != hipSuccess || per < 1)
     per = 1;
-  return std::max(1, std::min(want, per * cus));
+  return per;
+}
+
+// Co-resident grid for a cooperative launch: at most `want` workgroups and
+// at most cap (when > 0).
+static int coop_grid(const void* fn, size_t lds, int want, int cap = 0) {
+  int g = std::min(want, occupancy(fn, lds) * device_cus());
+  if (cap > 0) g = std::min(g, cap);
+  return std::max(1, g);
+}
+
+int slre_level_occupancy(int max_m, int max_nseg) {
+  static bool lds_ok = false;
+  allow_lds(reinterpret_cast<const void*>(slre_level_kernel<false>), &lds_ok);
+  return occupancy(reinterpret_cast<const void*>(slre_level_kernel<false>), slre_lds(max_m, max_nseg));
 }
 
 hipError_t launch_slre_level(const ItemD* items, const int32_t* cstart, int ncolours, int max_items,
                              int max_m, int max_nseg, LevelState ls, int level, double tol,
-                             int tol_mode, int prec, hipStream_t st) {
-  static bool lds_ok = false;
-  allow_lds(reinterpret_cast<const void*>(slre_level_kernel), &lds_ok);
+                             int tol_mode, int prec, hipStream_t st, int grid_cap, GridBar* bar) {
+  static bool lds_ok[2] = {false, false};
   const size_t lds = slre_lds(max_m, max_nseg);
-  const int g = coop_grid(reinterpret_cast<const void*>(slre_level_kernel), lds, max_items);
+  if (bar) {
+    // one workgroup per CU at most: every workgroup of the grid is resident
+    const void* fn = reinterpret_cast<const void*>(slre_level_kernel<true>);
+    allow_lds(fn, &lds_ok[1]);
+    int g = std::max(1, std::min(max_items, device_cus()));
+    if (grid_cap > 0) g = std::min(g, grid_cap);
+    hipLaunchKernelGGL(slre_level_kernel<true>, dim3(g), dim3(kThreads), lds, st, items, cstart, ncolours,
+                       ls, level, tol, tol_mode, prec, max_m, bar);
+    return hipGetLastError();
+  }
+  const void* fn = reinterpret_cast<const void*>(slre_level_kernel<false>);
+  allow_lds(fn, &lds_ok[0]);
+  const int g = coop_grid(fn, lds, max_items, grid_cap);
+  GridBar* none = nullptr;
   void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&level,
-                  (void*)&tol, (void*)&tol_mode, (void*)&prec, (void*)&max_m};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(slre_level_kernel), dim3(g),
-                                    dim3(kThreads), args, lds, st);
+                  (void*)&tol, (void*)&tol_mode, (void*)&prec, (void*)&max_m, (void*)&none};
+  return hipLaunchCooperativeKernel(fn, dim3(g), dim3(kThreads), args, lds, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -948,47 +980,78 @@ __global__ void __launch_bounds__(kThreads) bwd_kernel(const ItemD* __restrict__
   bwd_item(items[blockIdx.x], ls, vec, lds);
 }
 
+template <bool SW>
 __global__ void __launch_bounds__(kThreads) fwd_level_kernel(const ItemD* __restrict__ items,
                                                              const int32_t* __restrict__ cstart,
-                                                             int ncolours, LevelState ls, double* vec) {
+                                                             int ncolours, LevelState ls, double* vec,
+                                                             GridBar* bar) {
   extern __shared__ double lds[];
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int c = 0; c < ncolours; ++c) {
     for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) fwd_item(items[i], ls, vec, lds);
-    grid.sync();
+    if constexpr (SW) sw_grid_sync(bar, gridDim.x);
+    else cooperative_groups::this_grid().sync();
   }
 }
 
+template <bool SW>
 __global__ void __launch_bounds__(kThreads) bwd_level_kernel(const ItemD* __restrict__ items,
                                                              const int32_t* __restrict__ cstart,
-                                                             int ncolours, LevelState ls, double* vec) {
+                                                             int ncolours, LevelState ls, double* vec,
+                                                             GridBar* bar) {
   extern __shared__ double lds[];
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int c = ncolours - 1; c >= 0; --c) {
     for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) bwd_item(items[i], ls, vec, lds);
-    grid.sync();
+    if constexpr (SW) sw_grid_sync(bar, gridDim.x);
+    else cooperative_groups::this_grid().sync();
   }
+}
+
+// Sweep kernels may use more than 64 KiB of dynamic LDS.
+static void allow_sweep_lds() {
+  static bool done[6] = {false, false, false, false, false, false};
+  allow_lds(reinterpret_cast<const void*>(fwd_kernel), &done[0]);
+  allow_lds(reinterpret_cast<const void*>(bwd_kernel), &done[1]);
+  allow_lds(reinterpret_cast<const void*>(fwd_level_kernel<false>), &done[2]);
+  allow_lds(reinterpret_cast<const void*>(bwd_level_kernel<false>), &done[3]);
+  allow_lds(reinterpret_cast<const void*>(fwd_level_kernel<true>), &done[4]);
+  allow_lds(reinterpret_cast<const void*>(bwd_level_kernel<true>), &done[5]);
 }
 
 void launch_fwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
                 hipStream_t st) {
   if (nitems <= 0) return;
+  allow_sweep_lds();
   hipLaunchKernelGGL(fwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, ls, vec);
 }
 
 void launch_bwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
                 hipStream_t st) {
   if (nitems <= 0) return;
+  allow_sweep_lds();
   hipLaunchKernelGGL(bwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, ls, vec);
 }
 
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
-                              int max_items, int max_m, LevelState ls, double* vec, hipStream_t st) {
-  const void* fn = forward ? reinterpret_cast<const void*>(fwd_level_kernel)
-                           : reinterpret_cast<const void*>(bwd_level_kernel);
+                              int max_items, int max_m, LevelState ls, double* vec, hipStream_t st,
+                              int grid_cap, GridBar* bar) {
+  allow_sweep_lds();
   const size_t lds = sweep_lds(max_m);
-  const int g = coop_grid(fn, lds, max_items);
-  void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&vec};
+  if (bar) {
+    int g = std::max(1, std::min(max_items, device_cus()));
+    if (grid_cap > 0) g = std::min(g, grid_cap);
+    if (forward)
+      hipLaunchKernelGGL(fwd_level_kernel<true>, dim3(g), dim3(kThreads), lds, st, items, cstart, ncolours,
+                         ls, vec, bar);
+    else
+      hipLaunchKernelGGL(bwd_level_kernel<true>, dim3(g), dim3(kThreads), lds, st, items, cstart, ncolours,
+                         ls, vec, bar);
+    return hipGetLastError();
+  }
+  const void* fn = forward ? reinterpret_cast<const void*>(fwd_level_kernel<false>)
+                           : reinterpret_cast<const void*>(bwd_level_kernel<false>);
+  const int g = coop_grid(fn, lds, max_items, grid_cap);
+  GridBar* none = nullptr;
+  void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&vec, (void*)&none};
   return hipLaunchCooperativeKernel(fn, dim3(g), dim3(kThreads), args, lds, st);
 }
 
@@ -1005,8 +1068,55 @@ __global__ void __launch_bounds__(kThreads) top_solve_kernel(const double* L, in
 
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
   if (n <= 0) return;
+  static bool lds_ok = false;
+  allow_lds(reinterpret_cast<const void*>(top_solve_kernel), &lds_ok);
   size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * kBlkLd) * sizeof(double);
   hipLaunchKernelGGL(top_solve_kernel, dim3(1), dim3(kThreads), lds, st, L, n, y);
+}
+
+// Dense tops of a batch: one workgroup per system.
+__global__ void __launch_bounds__(kThreads) top_potrf_batched_kernel(const TopD* __restrict__ tops) {
+  extern __shared__ double lds[];
+  __shared__ int sbad;
+  const TopD t = tops[blockIdx.x];
+  if (t.n <= 0) return;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  chol_solve(t.L, t.n, t.n, nullptr, 0, lds, &sbad);
+  __syncthreads();
+  if (sbad && threadIdx.x == 0) atomicOr(t.err, 1 << kErrNotSPD);
+}
+
+void launch_top_potrf_batched(const TopD* tops, int ntops, int max_n, hipStream_t st) {
+  if (ntops <= 0 || max_n <= 0) return;
+  static bool lds_ok = false;
+  allow_lds(reinterpret_cast<const void*>(top_potrf_batched_kernel), &lds_ok);
+  size_t lds = ((size_t)max_n * kNB + kNB * kNB + kNB * 256) * sizeof(double);
+  hipLaunchKernelGGL(top_potrf_batched_kernel, dim3(ntops), dim3(kThreads), lds, st, tops);
+}
+
+__global__ void __launch_bounds__(kThreads) top_solve_batched_kernel(const TopD* __restrict__ tops,
+                                                                     double* vec) {
+  extern __shared__ double lds[];
+  const TopD t = tops[blockIdx.x];
+  const int n = t.n;
+  if (n <= 0) return;
+  double* y = lds;
+  double* blk = lds + ((n + 63) / 64) * 64;
+  double* yg = vec + t.voff;
+  for (int i = threadIdx.x; i < n; i += kThreads) y[i] = yg[i];
+  __syncthreads();
+  trsv_lower(t.L, n, n, y, blk);
+  trsv_lower_t(t.L, n, n, y, blk);
+  for (int i = threadIdx.x; i < n; i += kThreads) yg[i] = y[i];
+}
+
+void launch_top_solve_batched(const TopD* tops, int ntops, int max_n, double* vec, hipStream_t st) {
+  if (ntops <= 0 || max_n <= 0) return;
+  static bool lds_ok = false;
+  allow_lds(reinterpret_cast<const void*>(top_solve_batched_kernel), &lds_ok);
+  size_t lds = ((size_t)((max_n + 63) / 64) * 64 + 64 * kBlkLd) * sizeof(double);
+  hipLaunchKernelGGL(top_solve_batched_kernel, dim3(ntops), dim3(kThreads), lds, st, tops, vec);
 }
 
 // ---------------------------------------------------------------------------
@@ -1047,6 +1157,21 @@ void launch_scatter_vals(const double* val, const int64_t* off, int64_t nnz, dou
   if (nnz <= 0) return;
   hipLaunchKernelGGL(scatter_vals_kernel, dim3(grid_for(nnz)), dim3(256), 0, st, val, off, nnz,
                      base);
+}
+
+__global__ void scatter_vals_multi_kernel(const ScatterD* __restrict__ d) {
+  const ScatterD t = d[blockIdx.y];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < t.nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = t.off[e];
+    if (o >= 0) t.base[o] = t.val[e];
+  }
+}
+
+void launch_scatter_vals_multi(const ScatterD* d, int nd, int64_t max_nnz, hipStream_t st) {
+  if (nd <= 0 || max_nnz <= 0) return;
+  const int gx = (int)std::min<int64_t>(64, (max_nnz + 255) / 256);
+  hipLaunchKernelGGL(scatter_vals_multi_kernel, dim3(gx, nd), dim3(256), 0, st, d);
 }
 
 __global__ void copy_blocks_kernel(const CopyD* tasks) {

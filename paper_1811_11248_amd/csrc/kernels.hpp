@@ -14,6 +14,8 @@ void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 void launch_scatter_vals(const double* val, const int64_t* off, int64_t nnz, double* base,
                          hipStream_t st);
 void launch_copy_blocks(const CopyD* tasks, int ntasks, hipStream_t st);
+// One ScatterD per system (blockIdx.y), max_nnz = largest nnz.
+void launch_scatter_vals_multi(const ScatterD* d, int nd, int64_t max_nnz, hipStream_t st);
 
 // One scaled low-rank elimination per item (all items of one colour), one
 // workgroup per cluster.
@@ -21,9 +23,17 @@ void launch_slre(const ItemD* items, int nitems, int max_m, int max_nseg, LevelS
                  double tol, int tol_mode, int prec, hipStream_t st);
 // All colours of a level in one cooperative launch (grid barrier between
 // colours); cstart is a device array of ncolours+1 item offsets.
+// grid_cap > 0 limits the persistent grid to grid_cap workgroups.  With
+// bar == null the launch is cooperative; with a GridBar (zeroed once) it is
+// an ordinary launch of at most one workgroup per CU using the bounded
+// software barrier, which can be recorded in a graph.
 hipError_t launch_slre_level(const ItemD* items, const int32_t* cstart, int ncolours, int max_items,
                              int max_m, int max_nseg, LevelState ls, int level, double tol,
-                             int tol_mode, int prec, hipStream_t st);
+                             int tol_mode, int prec, hipStream_t st, int grid_cap = 0,
+                             GridBar* bar = nullptr);
+// Workgroups per CU the persistent elimination kernel can hold at this LDS size.
+int slre_level_occupancy(int max_m, int max_nseg);
+int device_cus();
 
 // Capacities of one colour for the split (several workgroups per cluster) path.
 struct SplitDims {
@@ -47,8 +57,12 @@ void launch_fwd(const ItemD* items, int nitems, int max_m, LevelState ls, double
 void launch_bwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
                 hipStream_t st);
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
-                              int max_items, int max_m, LevelState ls, double* vec, hipStream_t st);
+                              int max_items, int max_m, LevelState ls, double* vec, hipStream_t st,
+                              int grid_cap = 0, GridBar* bar = nullptr);
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st);
+// Dense tops of a batch, one workgroup per system (n <= kMaxClusterDofs).
+void launch_top_potrf_batched(const TopD* tops, int ntops, int max_n, hipStream_t st);
+void launch_top_solve_batched(const TopD* tops, int ntops, int max_n, double* vec, hipStream_t st);
 
 void launch_gather(const double* src, const int64_t* idx, double* dst, int64_t n, hipStream_t st);
 void launch_scatter(const double* src, const int64_t* idx, double* dst, int64_t n,
@@ -70,5 +84,21 @@ void launch_pcg_p(double* p, const double* z, int64_t n, const double* num, cons
 // y = b - y
 void launch_residual(const double* b, double* y, int64_t n, hipStream_t st);
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
+
+// Batching form (packed vectors: column c of system i at c*ldv + off[i]).
+void launch_spmm(const int64_t* rowptr, const int32_t* col, const double* val, const double* x,
+                 double* y, int64_t n, int64_t ldv, int nrhs, hipStream_t st);
+void launch_seg_dot(const double* x, const double* y, const int64_t* off, int64_t ldv, int nsys,
+                    int nrhs, double* out, hipStream_t st);
+void launch_bpcg_xr(double* x, double* r, const double* p, const double* q, const int32_t* rowsys,
+                    int64_t ntot, int nsys, int nrhs, const double* rz, const double* pq,
+                    const int32_t* active, hipStream_t st);
+void launch_bpcg_p(double* p, const double* z, const int32_t* rowsys, int64_t ntot, int nsys,
+                   int nrhs, const double* rz_new, const double* rz, const int32_t* active,
+                   hipStream_t st);
+void launch_bpcg_state(int mode, int np, double rtol, const double* bb, const double* rr, double* rz,
+                       const double* rz_new, int32_t* active, int32_t* iters, int32_t* nactive,
+                       hipStream_t st);
+void launch_zero_multi(const SpanD* d, int nd, int64_t max_n, hipStream_t st);
 
 }  // namespace lrsp

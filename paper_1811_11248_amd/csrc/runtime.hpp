@@ -1,0 +1,168 @@
+// runtime.hpp -- host runtime shared by the single-system and batched
+// factorizations: error reporting, launch timing, device buffers, the device
+// storage of one planned tree level and the level-assembly helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lrsp.h"
+#include "desc.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace lrsp {
+namespace rt {
+
+// Records msg as the thread's last error and returns s.
+lrsp_status fail(lrsp_status s, const std::string& msg);
+const char* last_error();
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return ::lrsp::rt::fail(LRSP_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// Event timing of kernel families (lrsp_timing_*).
+constexpr int kFamilies = 11;
+struct TimingState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kFamilies];
+  int64_t launches[kFamilies] = {};
+  double ms[kFamilies] = {};
+  double flops[kFamilies] = {};
+  double bytes[kFamilies] = {};
+};
+extern TimingState g_tm;
+hipEvent_t tm_event();
+void tm_collect();
+
+// Records events around the launches issued during its lifetime.
+struct TimedLaunch {
+  int fam;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  TimedLaunch(int f, hipStream_t s) : fam(f), st(s) {
+    if (!g_tm.on) return;
+    a = tm_event();
+    (void)hipEventRecord(a, st);
+  }
+  ~TimedLaunch() {
+    if (!a) return;
+    hipEvent_t b = tm_event();
+    (void)hipEventRecord(b, st);
+    g_tm.pending[fam].push_back({a, b});
+    g_tm.launches[fam]++;
+  }
+};
+
+// Device buffer from the stream-ordered allocator (cached pool).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+hipError_t dalloc(DevBuf* b, size_t bytes, hipStream_t st);
+void dfree(DevBuf* b, hipStream_t st);
+
+template <class T>
+T* at(const DevBuf& b, int64_t off) {
+  return reinterpret_cast<T*>(b.p) + off;
+}
+
+uint64_t next_level_id();
+
+// Device storage, descriptors and results of one planned tree level.
+struct LevelDev {
+  const uint64_t id = next_level_id();  // unique per workspace
+  LevelPlan plan;
+  std::vector<int> k, a, b;
+  int max_m = 0;
+  DevBuf work, wints;      // D / fine / coarse halves; posmaps and column lists
+  DevBuf fac;              // panels, tau, norms (doubles)
+  DevBuf fints;            // colseg, colnat, stepof, piv, segoff (int32)
+  DevBuf fvidx;            // vidx (int64)
+  DevBuf desc;             // SegD / PairD / WbD / ItemD
+  DevBuf state;            // k, a, b, err (unless the level shares a batch state)
+  ItemD* d_items = nullptr;
+  std::vector<ItemD> h_items;  // host copy, in processing order
+  LevelState ls{};
+  int sbase = 0;           // cluster id offset in a shared state
+  int64_t vbase = 0;       // offset of this level in the vector buffer
+  std::vector<int64_t> voff;
+  int64_t nvec = 0;
+  DevBuf gidx;             // level >= 1: indices into the previous level's vector
+  // adjacency export
+  std::vector<int> adj_ptr, adj, sizes_i, colour_i, order_i;
+  std::vector<double> sweep_bytes;  // per colour: bytes one sweep of it moves
+  std::vector<SplitDims> cdims;     // per colour capacities
+  int max_items = 0;                // largest colour
+  int max_nseg = 0;
+  bool split = false;               // several workgroups per cluster
+  const int32_t* d_cstart = nullptr;
+  DevBuf vals_off;                  // level 0: CSR entry -> work-arena offset
+  DevBuf tasks;                     // level >= 1: assembly copy tasks
+  int ntasks = 0;
+  uint64_t tasks_src = 0;           // id of the level the tasks read from
+  void free_all(hipStream_t st) {
+    dfree(&work, st); dfree(&wints, st); dfree(&fac, st); dfree(&fints, st); dfree(&fvidx, st);
+    dfree(&desc, st); dfree(&state, st); dfree(&gidx, st); dfree(&vals_off, st); dfree(&tasks, st);
+  }
+  int64_t held_bytes() const {
+    return (int64_t)(work.bytes + wints.bytes + fac.bytes + fints.bytes + fvidx.bytes + desc.bytes +
+                     state.bytes + gidx.bytes + vals_off.bytes + tasks.bytes);
+  }
+};
+
+// Coupling c(x,y) between the coarse DoFs of two linked clusters of a
+// finished level: the source block and whether it is transposed.
+bool coupling(const LevelDev& L, int x, int y, const double** src, int* sld, int* trans);
+
+// Tasks that move the coarse-coarse couplings of finished level `prev` into
+// the block storage of the next level.  False if a fill block is not dense.
+bool assembly_tasks(const LevelDev& prev, const LevelDev& cur, std::vector<CopyD>* tasks);
+
+// Indices of the coarse DoFs of finished level `prev`, in the order of the
+// next level's (or the top's) clusters (parent P = children 2P, 2P+1).
+void coarse_gather_indices(const LevelDev& prev, int nparents, std::vector<int64_t>* g);
+
+// Copies a host array into a new device buffer and waits for the copy.
+lrsp_status upload(DevBuf* b, const void* src, size_t bytes, hipStream_t st);
+
+// Builds the device storage and descriptors of a planned level.  With
+// `shared` the level's k/a/b/err live in a batch-wide state at cluster ids
+// sbase.. (items and segments carry the shifted ids) and items report their
+// errors also to *serr.
+lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase = 0,
+                        const LevelState* shared = nullptr, int32_t* serr = nullptr);
+
+bool complete_graph(const std::vector<std::vector<int>>& adj);
+
+// Level-0 CSR entry -> offset in the level's work arena (-1: not stored).
+lrsp_status level0_offsets(const TreeH& tr, const int64_t* rp, const int32_t* cl, int64_t nnz,
+                           const LevelPlan& p, std::vector<int64_t>* off);
+
+// Dense top assembled from the CSR (no level eliminated): entry -> offset in
+// the ntop x ntop matrix (clusters in order, toff their first rows).
+void top_offsets_level0(const TreeH& tr, const int64_t* rp, const int32_t* cl, int64_t nnz,
+                        const std::vector<int64_t>& toff, int ntop, std::vector<int64_t>* off);
+
+// Dense top assembled from the coarse rows of the finished level `prev`.
+void top_tasks(const LevelDev& prev, const std::vector<int64_t>& toff, int ntop, double* Tm,
+               std::vector<CopyD>* tasks);
+
+// The cluster tree held by a tree handle.
+const TreeH& tree_of(const lrsp_tree* t);
+
+// Algorithmic flops (potrf, trsm, cpqr, applyq, schur) of a finished level
+// and the bytes of one sweep per colour (into L->sweep_bytes).
+void level_stats(LevelDev* L, double flops[5]);
+
+}  // namespace rt
+}  // namespace lrsp

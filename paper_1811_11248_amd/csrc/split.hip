@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256) seg_offsets_kernel(const ItemD* __restric
   __syncthreads();
   if (sbad) {
     if (tid == 0) {
-      set_error(ls.err, level, it.s, kErrCapacity);
+      item_error(it, ls.err, level, kErrCapacity);
       ls.a[it.s] = 0;
       ls.b[it.s] = 0;
     }
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(512) potrf_kernel(const ItemD* __restrict__ it
   __syncthreads();
   potrf_wg<512>(it.P, m, m, lds, &sbad);
   __syncthreads();
-  if (sbad && threadIdx.x == 0) set_error(ls.err, level, it.s, kErrNotSPD);
+  if (sbad && threadIdx.x == 0) item_error(it, ls.err, level, kErrNotSPD);
 }
 
 // ---------------------------------------------------------------------------
@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ it
   }
   for (int c = tid; c < b; c += NT) it.stepof[c] = stp[c];
   if (tid == 0) ls.k[it.s] = k;
-  if (k > it.kcap && tid == 0) set_error(ls.err, level, it.s, kErrCapacity);
+  if (k > it.kcap && tid == 0) item_error(it, ls.err, level, kErrCapacity);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,7 +573,7 @@ __device__ __forceinline__ void schur_put(const ItemD& it, int rr, int cc, doubl
     col = pd.posmap ? pd.posmap[cn] : cn;
   }
   if (row < 0 || col < 0 || row >= pd.nrows || col >= pd.ncols) {
-    set_error(err, level, it.s, kErrIndex);
+    item_error(it, err, level, kErrIndex);
     return;
   }
   pd.dst[(size_t)row + (size_t)pd.ld * col] -= val;
@@ -681,7 +681,7 @@ __global__ void __launch_bounds__(256) writeback_kernel(const ItemD* __restrict_
     }
     const int row = t.trans ? cn : r, col = t.trans ? r : cn;
     if (row >= t.nrows || col >= t.ncols) {
-      set_error(ls.err, level, it.s, kErrIndex);
+      item_error(it, ls.err, level, kErrIndex);
       continue;
     }
     t.dst[(size_t)row + (size_t)t.ld * col] = v;

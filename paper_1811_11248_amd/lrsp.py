@@ -39,7 +39,7 @@ class CSR(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("tol_mode", C.c_int32), ("gemm_prec", C.c_int32), ("rank_mode", C.c_int32),
                 ("exec_mode", C.c_int32), ("mlp_weights", C.c_void_p),
-                ("reserved", C.c_int64 * 6)]
+                ("autotune", C.c_int32), ("reserved32", C.c_int32), ("reserved", C.c_int64 * 5)]
 
 
 class TreeView(C.Structure):
@@ -61,6 +61,15 @@ class LevelView(C.Structure):
                 ("adj_ptr", C.POINTER(C.c_int32)), ("adj", C.POINTER(C.c_int32))]
 
 
+class BatchInfo(C.Structure):
+    _fields_ = [("nsys", C.c_int32), ("nlevels", C.c_int32), ("ntot", C.c_int64),
+                ("flops", C.c_double * 6), ("ms_factor", C.c_double), ("ms_analysis", C.c_double),
+                ("peak_bytes", C.c_int64), ("graph_factor", C.c_int32), ("graph_pcg", C.c_int32),
+                ("coop_in_graph", C.c_int32), ("refactor_fallbacks", C.c_int32),
+                ("tuned_levels", C.c_int32), ("graph_timeouts", C.c_int32),
+                ("sched", C.c_int32 * 16), ("grid_cap", C.c_int32 * 16)]
+
+
 class Timing(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("flops", C.c_double),
                 ("bytes", C.c_double)]
@@ -80,6 +89,22 @@ SIGNATURES = [
                            C.c_void_p]),
     ("lrsp_factor_info", C.c_int, [C.c_void_p, C.POINTER(Info)]),
     ("lrsp_factor_level", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(LevelView)]),
+    ("lrsp_factor_batched", C.c_int, [C.c_int32, C.POINTER(CSR), C.POINTER(C.c_void_p), C.c_double,
+                                      C.POINTER(Opts), C.c_void_p, C.POINTER(C.c_void_p),
+                                      C.POINTER(C.c_int32)]),
+    ("lrsp_refactor_batched", C.c_int, [C.c_void_p, C.POINTER(CSR), C.c_void_p, C.POINTER(C.c_int32)]),
+    ("lrsp_batch_free", C.c_int, [C.c_void_p]),
+    ("lrsp_apply_batched", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    ("lrsp_pcg_batched", C.c_int, [C.POINTER(CSR), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                   C.c_double, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_double), C.c_void_p]),
+    ("lrsp_batch_info_get", C.c_int, [C.c_void_p, C.POINTER(BatchInfo)]),
+    ("lrsp_batch_level", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(LevelView)]),
+    ("lrsp_batch_system_levels", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    ("lrsp_autotune_save", C.c_int, [C.c_char_p]),
+    ("lrsp_autotune_load", C.c_int, [C.c_char_p]),
+    ("lrsp_autotune_clear", C.c_int, []),
+    ("lrsp_autotune_entries", C.c_int32, []),
     ("lrsp_timing_enable", C.c_int, [C.c_int32]),
     ("lrsp_timing_reset", C.c_int, []),
     ("lrsp_timing_read", C.c_int, [C.c_int32, C.POINTER(Timing)]),
@@ -194,22 +219,147 @@ class Factor:
     def level(self, lev: int) -> dict:
         v = LevelView()
         _check(lib().lrsp_factor_level(self.handle, int(lev), C.byref(v)))
-        M = v.nclusters
-
-        def arr(p, n):
-            return np.ctypeslib.as_array(p, shape=(n,)).copy() if p and n else np.zeros(n, np.int32)
-        ptr = arr(v.adj_ptr, M + 1)
-        adj = arr(v.adj, int(ptr[-1])) if M else np.zeros(0, np.int32)
-        out = {"nclusters": M, "ncolours": v.ncolours, "sizes": arr(v.sizes, M),
-               "graph": [adj[ptr[c]:ptr[c + 1]].tolist() for c in range(M)]}
-        if v.colour:
-            out.update(colour=arr(v.colour, M), order=arr(v.order, M), ranks=arr(v.ranks, M))
-        return out
+        return _level_dict(v)
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.lrsp_factor_free(self.handle)
             self.handle = None
+
+
+def _level_dict(v: LevelView) -> dict:
+    M = v.nclusters
+
+    def arr(p, n):
+        return np.ctypeslib.as_array(p, shape=(n,)).copy() if p and n else np.zeros(n, np.int32)
+    ptr = arr(v.adj_ptr, M + 1)
+    adj = arr(v.adj, int(ptr[-1])) if M else np.zeros(0, np.int32)
+    out = {"nclusters": M, "ncolours": v.ncolours, "sizes": arr(v.sizes, M),
+           "graph": [adj[ptr[c]:ptr[c + 1]].tolist() for c in range(M)]}
+    if v.colour:
+        out.update(colour=arr(v.colour, M), order=arr(v.order, M), ranks=arr(v.ranks, M))
+    return out
+
+
+SCHED = {0: "persistent", 1: "per_colour", 2: "split"}
+
+
+class Batch:
+    """Batched factorization of several DeviceMatrix systems (lrsp_factor_batched).
+
+    Vectors are packed: system i occupies rows off[i]:off[i+1] of each column.
+    """
+
+    def __init__(self, mats, trees, tol: float, tol_mode="relative", gemm_prec="f64",
+                 exec_mode="auto", autotune=False, stream=None, raise_not_spd=True):
+        o = Opts()
+        o.tol_mode = TOL_MODE[tol_mode]
+        o.gemm_prec = PREC[gemm_prec]
+        o.exec_mode = EXEC_MODE[exec_mode]
+        o.autotune = 1 if autotune else 0
+        self.mats = list(mats)
+        self.trees = list(trees)
+        n = len(self.mats)
+        self._csrs = (CSR * n)(*[A.csr() for A in self.mats])
+        th = (C.c_void_p * n)(*[t.handle.value for t in self.trees])
+        h = C.c_void_p()
+        status = (C.c_int32 * n)()
+        st = lib().lrsp_factor_batched(n, self._csrs, th, float(tol), C.byref(o), _stream(stream),
+                                       C.byref(h), status)
+        self.handle = h if h.value else None
+        self.status = np.array(status[:], dtype=np.int32)
+        if st != ERR_NOT_SPD or raise_not_spd:
+            _check(st)
+        self.nsys = n
+        self.sizes = np.array([A.n for A in self.mats], dtype=np.int64)
+        self.off = np.concatenate([[0], np.cumsum(self.sizes)])
+
+    def refactor(self, mats=None, stream=None):
+        if mats is not None:
+            self.mats = list(mats)
+            self._csrs = (CSR * self.nsys)(*[A.csr() for A in self.mats])
+        status = (C.c_int32 * self.nsys)()
+        _check(lib().lrsp_refactor_batched(self.handle, self._csrs, _stream(stream), status))
+        self.status = np.array(status[:], dtype=np.int32)
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        _check(lib().lrsp_batch_info_get(self.handle, C.byref(i)))
+        nl = min(16, i.nlevels + 1)
+        return {"nsys": i.nsys, "nlevels": i.nlevels, "ntot": i.ntot,
+                "flops": dict(zip(("potrf", "trsm", "cpqr", "applyq", "schur", "top"), i.flops)),
+                "ms_factor": i.ms_factor, "ms_analysis": i.ms_analysis, "peak_bytes": i.peak_bytes,
+                "graph_factor": i.graph_factor, "graph_pcg": i.graph_pcg,
+                "refactor_fallbacks": i.refactor_fallbacks, "tuned_levels": i.tuned_levels,
+                "graph_timeouts": i.graph_timeouts,
+                "sched": [SCHED.get(i.sched[l], "?") for l in range(nl)],
+                "grid_cap": list(i.grid_cap[:nl])}
+
+    def system_levels(self, sys: int) -> int:
+        n = C.c_int32()
+        _check(lib().lrsp_batch_system_levels(self.handle, int(sys), C.byref(n)))
+        return int(n.value)
+
+    def level(self, sys: int, lev: int) -> dict:
+        v = LevelView()
+        _check(lib().lrsp_batch_level(self.handle, int(sys), int(lev), C.byref(v)))
+        return _level_dict(v)
+
+    def pack(self, vecs, device="cuda"):
+        """Packs per-system arrays ([n_i] or [n_i, nrhs]) into a device [ntot, nrhs] tensor."""
+        import torch
+        cols = [torch.as_tensor(np.asarray(v, dtype=np.float64)).reshape(len(v), -1) for v in vecs]
+        return torch.cat(cols, 0).to(device)
+
+    def unpack(self, X):
+        return [X[self.off[i]:self.off[i + 1]] for i in range(self.nsys)]
+
+    def apply(self, B, stream=None):
+        """x = M^{-1} b for a packed device tensor [ntot] or [ntot, nrhs]."""
+        import torch
+        nrhs = 1 if B.dim() == 1 else B.shape[1]
+        bb = B if B.dim() == 1 else B.t().contiguous()
+        out = torch.empty_like(bb)
+        _check(lib().lrsp_apply_batched(self.handle, bb.data_ptr(), out.data_ptr(), nrhs, _stream(stream)))
+        return out if B.dim() == 1 else out.view(nrhs, -1).t()
+
+    def pcg(self, B, rtol=1e-8, maxit=1000, stream=None, raise_no_conv=True, x=None):
+        """PCG on every (system, column); returns (X, iters[nrhs, nsys], relres[nrhs, nsys])."""
+        import torch
+        nrhs = 1 if B.dim() == 1 else B.shape[1]
+        bb = B if B.dim() == 1 else B.t().contiguous()
+        xx = torch.empty_like(bb) if x is None else x
+        np_ = nrhs * self.nsys
+        it = (C.c_int32 * np_)()
+        rr = (C.c_double * np_)()
+        st = lib().lrsp_pcg_batched(self._csrs, self.handle, bb.data_ptr(), xx.data_ptr(), nrhs,
+                                    float(rtol), int(maxit), it, rr, _stream(stream))
+        if st != ERR_NO_CONV or raise_no_conv:
+            _check(st)
+        X = xx if B.dim() == 1 else xx.view(nrhs, -1).t()
+        return (X, np.array(it[:], dtype=np.int64).reshape(nrhs, self.nsys),
+                np.array(rr[:]).reshape(nrhs, self.nsys))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lrsp_batch_free(self.handle)
+            self.handle = None
+
+
+def autotune_save(path: str):
+    _check(lib().lrsp_autotune_save(path.encode()))
+
+
+def autotune_load(path: str):
+    _check(lib().lrsp_autotune_load(path.encode()))
+
+
+def autotune_clear():
+    _check(lib().lrsp_autotune_clear())
+
+
+def autotune_entries() -> int:
+    return int(lib().lrsp_autotune_entries())
 
 
 def tree_build(grid, leaf):

@@ -12,6 +12,8 @@ from .problems import (  # noqa: F401
     lognormal_field,
     rhs,
     batch_params,
+    batch_system,
+    batch_rhs,
     config,
     CONFIG_NAMES,
 )

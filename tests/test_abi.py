@@ -52,3 +52,29 @@ def test_tree_errors(L):
     assert ex.value.status == L.ERR_ARG
     with pytest.raises(L.LrspError):
         L.Tree((1, 1, 8, 2), 15)
+
+
+def test_autotune_table_round_trip(tmp_path):
+    """The autotuner table is host state: save/load/clear need no GPU."""
+    from paper_1811_11248_amd import lrsp
+    lrsp.autotune_clear()
+    assert lrsp.autotune_entries() == 0
+    p = tmp_path / "t.json"
+    p.write_text('{"version": 1, "entries": [\n'
+                 '  {"key": "batch/m256/n1024/c8", "sched": 0, "grid_cap": 256, "ms": 1.5},\n'
+                 '  {"key": "single/m64/n16/c4", "sched": 2, "grid_cap": 0, "ms": 0.25}\n]}\n')
+    lrsp.autotune_load(str(p))
+    assert lrsp.autotune_entries() == 2
+    q = tmp_path / "u.json"
+    lrsp.autotune_save(str(q))
+    lrsp.autotune_clear()
+    lrsp.autotune_load(str(q))
+    assert lrsp.autotune_entries() == 2
+    assert "batch/m256/n1024/c8" in q.read_text()
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": [{"key": "x", "sched": 7, "grid_cap": 0, "ms": 1}]}')
+    with pytest.raises(lrsp.LrspError):
+        lrsp.autotune_load(str(bad))
+    with pytest.raises(lrsp.LrspError):
+        lrsp.autotune_load(str(tmp_path / "missing.json"))
+    lrsp.autotune_clear()
