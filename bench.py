@@ -175,6 +175,64 @@ def run_batch(args):
     return out
 
 
+def run_learned(args):
+    """Learned-rank form: the rank network trained on the GPU from the stored
+    (features, rank) pairs of the oracle, then first factorizations (fresh
+    tree, no reused analysis) plus PCG on the learned-rank workload with
+    worst-case rank capacities (plain fp64) and with learned capacities and
+    fp32 Schur products."""
+    import numpy as np
+    import torch
+
+    from paper_1811_11248_amd import lrsp
+    from synth import config, rhs
+
+    d = np.load(os.path.join(ROOT, "tests", "golden", "rank_pairs_cfg123.npz"))
+    X = torch.from_numpy(d["X"].astype(np.float32)).cuda()
+    t = torch.from_numpy(d["k"].astype(np.float32)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = lrsp.mlp_init(X, t, seed=3)
+    trace = lrsp.mlp_train(P, X, t, args.train_steps, lr=3e-3)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3
+    tr = trace.cpu().numpy()
+    out = {"train": {"pairs": int(X.shape[0]), "steps": args.train_steps, "ms": round(train_ms, 2),
+                     "loss_first": float(tr[0]), "loss_last": float(tr[-1])}}
+    log(f"[learned] trained in {train_ms:.0f} ms, loss {tr[0]:.3f} -> {tr[-1]:.3f}")
+    t0 = time.perf_counter()
+    pr = config(args.learned_workload)
+    log(f"[learned] built {args.learned_workload} ({pr.n} DoF) in {time.perf_counter() - t0:.1f} s")
+    A = lrsp.DeviceMatrix.from_problem(pr)
+    b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+    out["workload"] = f"{args.learned_workload}: {pr.grid[0]}x{pr.grid[1]}x{pr.grid[2]}x{pr.grid[3]}, {pr.n} DoF"
+    for name, kw in (("plain_f64", {}), ("learned_f32", {"mlp": P, "gemm_prec": "f32"}),
+                     ("learned_f64", {"mlp": P})):
+        tree = lrsp.Tree(pr.grid, pr.leaf)  # fresh tree: nothing reused
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = lrsp.Factor(A, tree, pr.tol, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8, maxit=1000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        inf = F.info()
+        rec = dict(factor_ms=(t1 - t0) * 1e3, pcg_ms=(t2 - t1) * 1e3, ms=(t2 - t0) * 1e3,
+                   iters=int(it[0]), relres=float(rr[0]), peak_bytes=inf["peak_bytes"],
+                   host_analysis_ms=inf["ms_analysis"], levels=inf["nlevels"])
+        if "mlp" in kw:
+            rec.update(rank_bytes=inf["rank_bytes"], rank_bytes_worst=inf["rank_bytes_worst"],
+                       rank_checks_passed=inf["rank_checks_passed"],
+                       rank_checks_failed=inf["rank_checks_failed"], rank_redo_levels=inf["rank_redo_levels"])
+        out[name] = {k: (round(v, 4) if isinstance(v, float) and k != "relres" else v) for k, v in rec.items()}
+        log(f"[learned {name}] {out[name]}")
+        del F, tree
+        torch.cuda.synchronize()
+    out["speedup_vs_plain"] = round(out["plain_f64"]["ms"] / out["learned_f32"]["ms"], 4)
+    return out
+
+
 def roofline(timing):
     """Roofline of the kernel family with the most GPU time in the timed region."""
     fam = max(timing, key=lambda f: timing[f]["total_ms"])
@@ -228,6 +286,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--batch", type=int, default=512, help="systems of the batching form (0: skip)")
+    ap.add_argument("--learned-workload", default="stokes256",
+                    help="workload of the learned-rank form ('none': skip)")
+    ap.add_argument("--train-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -269,6 +330,8 @@ def main():
     }
     if args.batch > 0:
         out["batch"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in run_batch(args).items()}
+    if args.learned_workload != "none":
+        out["learned"] = run_learned(args)
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

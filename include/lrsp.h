@@ -76,8 +76,8 @@ typedef struct {
   int32_t gemm_prec;  /* Schur-update product: 0 fp64, 1 fp32 inputs with fp32
                          accumulation, 2 bf16 inputs with fp32 accumulation;
                          the result is added to the fp64 matrix */
-  int32_t rank_mode;  /* 0: full column-pivoted QR; 1: learned rank (the
-                         predicted rank is checked, full QR continues on failure) */
+  int32_t rank_mode;  /* 0: worst-case rank capacities; 1: capacities from
+                         learned ranks (see "learned ranks" below) */
   int32_t exec_mode;  /* kernel schedule (results agree to rounding): 0 auto;
                          1 one workgroup per cluster, one launch per colour;
                          2 one workgroup per cluster, one cooperative launch per
@@ -172,6 +172,15 @@ typedef struct {
   int32_t levels_reused; /* levels whose analysis and workspace came from the
                             tree's cache (same pattern, same ranks below) */
   int32_t reserved2;
+  /* rank_mode 1 (zero otherwise): */
+  double rank_bytes;          /* bytes of coarse blocks and panels allocated
+                                 from the predicted rank capacities */
+  double rank_bytes_worst;    /* the same with worst-case capacities min(m, b) */
+  int32_t rank_checks_passed; /* clusters whose rank k <= the predicted k_hat */
+  int32_t rank_checks_failed; /* clusters whose QR went on past k_hat */
+  int32_t rank_redo_levels;   /* levels redone with worst-case capacities
+                                 because a rank exceeded its capacity */
+  int32_t reserved3;
 } lrsp_info;
 lrsp_status lrsp_factor_info(const lrsp_factorization* F, lrsp_info* info);
 
@@ -191,6 +200,40 @@ typedef struct {
   const int32_t* adj;
 } lrsp_level_view;
 lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_level_view* v);
+
+/* ---- learned ranks ---------------------------------------------------------
+ * rank_mode 1: before a level is eliminated, every cluster gets 12 features:
+ * log2(1+m); log2(1+b), b the level-start size of its far field when it is
+ * processed (from the symbolic elimination); from its level-start coupling
+ * with its neighbours (Jacobi-scaled, sketched with 8 Gaussian columns drawn
+ * from Philox4x32-10) log10 of the Frobenius norm and the 8 sketch singular
+ * values over that norm; the fraction of its neighbours processed before it.
+ * A 12-64-64-1 ReLU network (fp32) predicts the rank k_hat; the rank
+ * capacities, and with them the coarse blocks and panels, are sized
+ * ceil(2*k_hat + 4) instead of the worst case min(m, b).  The QR itself
+ * is unchanged (it stops at the rank the tolerance sets, so ranks and factor
+ * equal rank_mode 0); when a rank exceeds its capacity the level is redone
+ * with worst-case capacities.  Parameter vector (fp32, lrsp_mlp_nparams()):
+ * mu[12] isd[12] W1[64][12] b1[64] W2[64][64] b2[64] w3[64] b3; the input is
+ * (x - mu)*isd.  All arrays of the calls below are device memory. */
+int32_t lrsp_mlp_nparams(void);
+/* Input statistics of X [n][12] (mu, isd), b3 = mean(t), He-normal weights
+ * from Philox4x32-10 with the given seed, zero biases. */
+lrsp_status lrsp_mlp_init(float* params, const float* X, const float* t, int64_t n, uint64_t seed,
+                          void* stream);
+/* Loss 0.5*mean((y - t)^2) (*loss, device, may be NULL) and its gradient
+ * grad[nparams] by backpropagation (zero for mu, isd). */
+lrsp_status lrsp_mlp_loss_grad(const float* params, const float* X, const float* t, int64_t n,
+                               float* grad, float* loss, void* stream);
+/* steps full-batch Adam steps (beta 0.9, 0.999) with rate lr; loss_trace
+ * [steps] (device, may be NULL) receives the loss before each step. */
+lrsp_status lrsp_mlp_train(float* params, const float* X, const float* t, int64_t n, int32_t steps,
+                           float lr, float* loss_trace, void* stream);
+lrsp_status lrsp_mlp_predict(const float* params, const float* X, int64_t n, float* y, void* stream);
+/* Features (host [M][12], fp64) and predicted ranks (host [M]) of one
+ * level of a factor computed with rank_mode 1 (either may be NULL). */
+lrsp_status lrsp_factor_rank_features(const lrsp_factorization* F, int32_t level, double* feat,
+                                      float* pred);
 
 /* ---- batching form -------------------------------------------------------
  * nsys independent systems, each with its own matrix and tree, factored

@@ -18,6 +18,9 @@ with Applications to Ice Sheet Modeling"):
                   section "Scaled Low-rank Elimination"), the factorization
                   Algorithm 1 and the solve Algorithm 2.
 * ``pcg``      -- preconditioned conjugate gradients using the factor.
+* ``learned``  -- learned-rank form: Philox4x32-10 sketch, level-start
+                  features, the rank MLP (forward and backpropagation in
+                  fp64) and the (features, rank) training pairs.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test except
 the compressed factor as a whole at tol > 0, whose values the paper does not
@@ -34,3 +37,4 @@ from .hsolver import (  # noqa: F401
     Factor,
 )
 from .pcg import pcg  # noqa: F401
+from . import learned  # noqa: F401

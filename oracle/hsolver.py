@@ -290,8 +290,11 @@ def _coarsen(blocks, cur, M):
 
 
 def factor(rowptr, col, val, tree: ClusterTree, tol: float, tol_mode: str = "relative",
-           gemm_prec: str = "f64", checks: bool = False) -> Factor:
-    """Algorithm 1 over the cluster tree; returns the factor of ``A``."""
+           gemm_prec: str = "f64", checks: bool = False, level_hook=None) -> Factor:
+    """Algorithm 1 over the cluster tree; returns the factor of ``A``.
+
+    level_hook(level, blocks, sizes, graph), if given, sees the matrix at the
+    start of every eliminated level (read only)."""
     blocks, sizes, graph = _level0_blocks(tree, rowptr, col, val)
     flops = dict(potrf=0.0, trsm=0.0, cpqr=0.0, applyq=0.0, schur=0.0, top=0.0)
     levels = []
@@ -305,6 +308,8 @@ def factor(rowptr, col, val, tree: ClusterTree, tol: float, tol_mode: str = "rel
             flops["top"] += D.shape[0] ** 3 / 3.0
             return Factor(tree, tol, tol_mode, gemm_prec, levels, list(sizes),
                           [list(g) for g in graph], Ltop, flops, cor[0])
+        if level_hook is not None:
+            level_hook(li, blocks, sizes, graph)
         rec, cur = _eliminate_level(li, blocks, sizes, graph, tol, tol_mode, gemm_prec,
                                     flops, checks, cor)
         levels.append(rec)

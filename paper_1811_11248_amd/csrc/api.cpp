@@ -15,6 +15,7 @@
 #include "desc.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "learned.hpp"
 #include "runtime.hpp"
 
 using namespace lrsp;
@@ -152,8 +153,10 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   lrsp_opts o{};
   if (opts) o = *opts;
   if (o.gemm_prec < 0 || o.gemm_prec > 2 || o.tol_mode < 0 || o.tol_mode > 1 || o.exec_mode < 0 ||
-      o.exec_mode > 3)
+      o.exec_mode > 3 || o.rank_mode < 0 || o.rank_mode > 1 || o.autotune < 0 || o.autotune > 1)
     return fail(LRSP_ERR_ARG, "invalid option");
+  const bool learned = o.rank_mode == 1;
+  if (learned && !o.mlp_weights) return fail(LRSP_ERR_ARG, "rank_mode 1 needs mlp_weights");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
   // host copy of the pattern
@@ -224,12 +227,19 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   int level = 0;
   LevelDev* prev = nullptr;
   std::vector<int32_t> herr(4);
+  DevBuf d_mlp;  // learned ranks: the network's parameters on the device
+  if (learned) {
+    if (lrsp_status s = upload(&d_mlp, o.mlp_weights, sizeof(float) * kMlpParams, st)) return s;
+  }
+  double cap_bytes = 0.0, worst_bytes = 0.0;
+  int checks_pass = 0, checks_fail = 0, cap_redo = 0;
   while (true) {
     const int M = (int)sizes.size();
     if (M == 1 || complete_graph(adj)) break;
     std::unique_ptr<LevelDev> Lp;
     bool reuse = false;
-    if ((int)cache->levels.size() > level && cache->levels[level] &&
+    if (!learned && (int)cache->levels.size() > level && cache->levels[level] &&
+        !cache->levels[level]->capped &&
         cache->levels[level]->plan.m == sizes && cache->levels[level]->vbase == vbase) {
       Lp = std::move(cache->levels[level]);
       reuse = true;
@@ -242,9 +252,16 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       Lp->plan.m = sizes;
       Lp->plan.adj = adj;
       plan_level(&Lp->plan, level == 0 ? &cache->z0 : nullptr);
-      if (lrsp_status s = setup_level(Lp.get(), st, vbase)) return s;
+      if (lrsp_status s = setup_level_a(Lp.get(), st, vbase)) return s;
+      if (learned) {
+        // what the worst-case capacities min(m, b) would allocate
+        worst_bytes += 8.0 * (double)(Lp->plan.coarse_doubles + plan_panel_doubles(Lp->plan));
+      } else if (lrsp_status s = setup_level_b(Lp.get(), st)) {
+        return s;
+      }
     } else {
       launch_zero(at<double>(Lp->work, 0), Lp->plan.work_doubles, st);
+      launch_zero(at<double>(Lp->coarse, 0), Lp->plan.coarse_doubles, st);
       launch_zero_i32(at<int32_t>(Lp->state, 0), 3 * (int64_t)M + 8, st);
     }
     LevelDev* L = Lp.get();
@@ -258,7 +275,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       if (lrsp_status s = upload(&L->vals_off, off.data(), off.size() * 8, st)) return s;
       launch_scatter_vals(A->val, at<int64_t>(L->vals_off, 0), A->nnz, at<double>(L->work, 0), st);
     } else {
-      if (!(reuse && L->tasks_src == prev->id)) {
+      if (!(reuse && L->tasks_src == prev->id && L->tasks.p)) {
         std::vector<CopyD> tasks;
         if (!assembly_tasks(*prev, *L, &tasks))
           return fail(LRSP_ERR_INTERNAL, "coarse fine-half block is not dense");
@@ -275,11 +292,20 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       }
       if (L->ntasks > 0) launch_copy_blocks(at<CopyD>(L->tasks, 0), L->ntasks, st);
     }
+    if (learned) {
+      // level-start features -> predicted ranks -> rank capacities
+      if (lrsp_status s = predict_level(L, level, tol, at<float>(d_mlp, 0), st, &L->feat, &L->pred)) return s;
+      const std::vector<int> caps = rank_caps(L->pred);
+      plan_capacities(&L->plan, &caps);
+      L->capped = true;
+      if (lrsp_status s = setup_level_b(L, st)) return s;
+    }
     if (!reuse) ms_an += ms_since(ta);
     // eliminate the clusters colour by colour
     const LevelPlan& p = L->plan;
     const int mode = o.exec_mode == 0 ? 3 : o.exec_mode;
     L->split = mode == 3 && L->max_m >= kSplitMinDofs && L->max_m <= kSplitMaxDofs;
+  eliminate_level:
     bool done = false;
     if (L->split) {
       for (int c = 0; c < p.ncolours; ++c) {
@@ -315,6 +341,22 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     HIPCHK(hipMemcpyAsync(L->b.data(), L->ls.b, 4 * (size_t)M, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(herr.data(), L->ls.err, 16, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (herr[0] && herr[3] == kErrCapacity && L->capped) {
+      // a rank exceeded its predicted capacity: redo the level with the
+      // worst-case capacities (the level's input is assembled again)
+      ++cap_redo;
+      plan_capacities(&L->plan, nullptr);
+      L->capped = false;
+      if (lrsp_status s = setup_level_b(L, st)) return s;
+      launch_zero(at<double>(L->work, 0), L->plan.work_doubles, st);
+      if (level == 0) {
+        launch_scatter_vals(A->val, at<int64_t>(L->vals_off, 0), A->nnz, at<double>(L->work, 0), st);
+      } else if (L->ntasks > 0) {
+        launch_copy_blocks(at<CopyD>(L->tasks, 0), L->ntasks, st);
+      }
+      L->split = mode == 3 && L->max_m >= kSplitMinDofs && L->max_m <= kSplitMaxDofs;
+      goto eliminate_level;
+    }
     if (herr[0]) {
       if (herr[3] == kErrNotSPD)
         return fail(LRSP_ERR_NOT_SPD, "non-positive pivot in the diagonal block of cluster " +
@@ -323,6 +365,15 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       return fail(LRSP_ERR_INTERNAL, "device check failed (code " + std::to_string(herr[3]) +
                                          ") at level " + std::to_string(herr[1]) + " cluster " +
                                          std::to_string(herr[2]));
+    }
+    if (learned) {
+      cap_bytes += 8.0 * (double)(L->plan.coarse_doubles + plan_panel_doubles(L->plan));
+      for (int x = 0; x < M; ++x) {
+        // check of the predicted rank: the pivot after the predicted rank
+        // already met the stop rule (k <= k_hat), or the QR went on
+        if (L->k[x] <= (int)std::lround(std::max(0.0f, L->pred[x]))) ++checks_pass;
+        else ++checks_fail;
+      }
     }
     double f[5];
     level_stats(L, f);
@@ -420,6 +471,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   inf.ms_levels = std::chrono::duration<double, std::milli>(t1 - t0).count();
   inf.ms_analysis = ms_an;
   inf.levels_reused = reused;
+  inf.rank_bytes = learned ? cap_bytes : 0.0;
+  inf.rank_bytes_worst = learned ? worst_bytes : 0.0;
+  inf.rank_checks_passed = checks_pass;
+  inf.rank_checks_failed = checks_fail;
+  inf.rank_redo_levels = cap_redo;
   int64_t held = 0;
   for (auto& L : F->levels) held += L->held_bytes();
   inf.peak_bytes = held + (int64_t)(F->top.bytes + F->vec.bytes + F->perm.bytes);
@@ -598,6 +654,16 @@ lrsp_status lrsp_timing_read(int32_t family, lrsp_timing* out) {
 lrsp_status lrsp_factor_info(const lrsp_factorization* F, lrsp_info* info) {
   if (!F || !info) return fail(LRSP_ERR_ARG, "null argument");
   *info = F->info;
+  return LRSP_OK;
+}
+
+lrsp_status lrsp_factor_rank_features(const lrsp_factorization* F, int32_t level, double* feat,
+                                      float* pred) {
+  if (!F || level < 0 || level >= (int)F->levels.size()) return fail(LRSP_ERR_ARG, "invalid level");
+  const LevelDev& L = *F->levels[level];
+  if (L.feat.empty()) return fail(LRSP_ERR_ARG, "the factor was not computed with learned ranks");
+  if (feat) std::copy(L.feat.begin(), L.feat.end(), feat);
+  if (pred) std::copy(L.pred.begin(), L.pred.end(), pred);
   return LRSP_OK;
 }
 

@@ -279,6 +279,7 @@ lrsp_status check_opts(const lrsp_opts& o) {
   if (o.gemm_prec < 0 || o.gemm_prec > 2 || o.tol_mode < 0 || o.tol_mode > 1 || o.exec_mode < 0 ||
       o.exec_mode > 3 || o.autotune < 0 || o.autotune > 1)
     return fail(LRSP_ERR_ARG, "invalid option");
+  if (o.rank_mode != 0) return fail(LRSP_ERR_ARG, "batched factorizations use rank_mode 0");
   return LRSP_OK;
 }
 
@@ -438,6 +439,7 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
     for (size_t j = 0; j < B.sys.size(); ++j) {
       LevelDev& L = *Ls[j];
       zeros.push_back(SpanD{at<double>(L.work, 0), L.plan.work_doubles});
+      zeros.push_back(SpanD{at<double>(L.coarse, 0), L.plan.coarse_doubles});
     }
     for (int i : B.stop) {
       BSys& S = F->sys[i];

@@ -126,6 +126,27 @@ struct GridBar {
   int32_t pad;
 };
 
+// Rank features: one level-start neighbour block of cluster s.
+struct FeatSeg {
+  const double* H;     // fine half holding the coupling of s and y
+  const int32_t* zl;   // natural indices of H's columns
+  const double* Dy;    // diagonal block of y (m_y x m_y)
+  int32_t ld;          // rows of H
+  int32_t ncols;       // columns of H
+  int32_t y;           // neighbour cluster
+  int32_t my;          // its size
+  int32_t orient;      // 0: H = block row of s (columns in y); 1: H = block row of y (columns in s)
+  int32_t pad;
+};
+
+struct FeatItem {
+  const double* Ds;    // diagonal block of s
+  const FeatSeg* seg;
+  double before;       // fraction of the neighbours processed before s
+  int32_t m, nseg, s;
+  int32_t bsum;        // summed level-start sizes of the far field of s
+};
+
 // n doubles at p (buffer fills of a batch).
 struct SpanD {
   double* p;

@@ -198,8 +198,10 @@ __device__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* 
 // Pivot: lowest column among those with squared norm >= (1-kTie)*max.
 // Reflector j lives in column piv[j] (rows j+1.., unit leading entry); R_jj
 // >= 0 sits at row j of that column; other columns hold R in rows < k.
-__device__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, int* piv,
-                    int* stepof, double* tau, double* norms, double* shd, int* shi) {
+// At most kcap reflectors are stored: when pivot kcap does not meet the stop
+// rule, *over is set and kcap is returned.
+__device__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, int kcap, int* piv,
+                    int* stepof, double* tau, double* norms, double* shd, int* shi, bool* over) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int c = wv; c < b; c += kWaves) {
     const double* y = W + (size_t)ld * c;
@@ -235,6 +237,11 @@ __device__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, i
     const bool stop = (tol_mode == 0) ? (rjj <= tol * r00) : (rjj <= tol);
     if (stop || rjj == 0.0) {
       k = j;
+      break;
+    }
+    if (j >= kcap) {
+      k = kcap;
+      *over = true;
       break;
     }
     double* x = W + (size_t)ld * best;
@@ -539,11 +546,12 @@ __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol,
   // compression of the scaled far field G^{-1} A_sw
   double* Wf = P + ld * (m + a);
   int k = 0;
+  bool over = false;
   if (b > 0 && m > 0)
-    k = cpqr(Wf, m, m, b, tol, tol_mode, it.piv, it.stepof, it.tau, it.norms, shd, shi);
-  if (k > it.kcap) {
+    k = cpqr(Wf, m, m, b, tol, tol_mode, it.kcap, it.piv, it.stepof, it.tau, it.norms, shd, shi, &over);
+  if (over || k > it.kcap) {
     if (tid == 0) item_error(it, ls.err, level, kErrCapacity);
-    k = it.kcap;
+    k = min(k, it.kcap);
   }
   __syncthreads();
   // E_s: rotate the near-field columns, C = U^T G^{-1} A_sn

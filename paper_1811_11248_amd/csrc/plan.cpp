@@ -210,6 +210,24 @@ void plan_level(LevelPlan* lp, const std::unordered_map<uint64_t, std::vector<ui
   }
 }
 
+void plan_capacities(LevelPlan* lp, const std::vector<int>* caps) {
+  const int M = lp->M;
+  std::vector<char> done(M, 0);
+  for (int idx = 0; idx < M; ++idx) {
+    const int s = lp->order[idx];
+    int64_t acap = 0, bcap = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int y : pass ? lp->wlist[s] : lp->nlist[s])
+        (pass ? bcap : acap) += done[y] ? lp->kcap[y] : (int64_t)lp->zfin.at(pkey(s, y)).size();
+    lp->acap[s] = (int)acap;
+    lp->bcap[s] = (int)bcap;
+    int64_t kc = std::min<int64_t>(lp->m[s], bcap);
+    if (caps) kc = std::min<int64_t>(kc, std::max(0, (*caps)[s]));
+    lp->kcap[s] = (int)kc;
+    done[s] = 1;
+  }
+}
+
 void plan_layout(LevelPlan* lp) {
   const int M = lp->M;
   int64_t off = 0, ioff = 0;
@@ -223,14 +241,6 @@ void plan_layout(LevelPlan* lp) {
     lp->d_off[x] = off;
     off += al((int64_t)lp->m[x] * lp->m[x]);
   }
-  for (int x = 0; x < M; ++x)
-    for (int y : lp->adj2[x]) {
-      if (y <= x) continue;
-      const int e = lp->pos[x] < lp->pos[y] ? x : y;
-      const int l = e == x ? y : x;
-      lp->hc_off[pkey(l, e)] = off;
-      off += al((int64_t)lp->m[l] * lp->kcap[e]);
-    }
   for (auto& kv : lp->zfin) {
     const int e = (int)(kv.first >> 32), l = (int)(kv.first & 0xffffffffu);
     lp->hf_off[kv.first] = off;
@@ -242,6 +252,24 @@ void plan_layout(LevelPlan* lp) {
   }
   lp->work_doubles = off;
   lp->work_ints = ioff;
+  // coarse halves: their own region, the only one that depends on kcap
+  int64_t coff = 0;
+  for (int x = 0; x < M; ++x)
+    for (int y : lp->adj2[x]) {
+      if (y <= x) continue;
+      const int e = lp->pos[x] < lp->pos[y] ? x : y;
+      const int l = e == x ? y : x;
+      lp->hc_off[pkey(l, e)] = coff;
+      coff += al((int64_t)lp->m[l] * lp->kcap[e]);
+    }
+  lp->coarse_doubles = coff;
+}
+
+int64_t plan_panel_doubles(const LevelPlan& lp) {
+  int64_t t = 0;
+  for (int s = 0; s < lp.M; ++s)
+    t += (int64_t)lp.m[s] * (lp.m[s] + lp.acap[s] + lp.bcap[s]);
+  return t;
 }
 
 }  // namespace lrsp

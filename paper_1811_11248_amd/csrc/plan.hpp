@@ -44,10 +44,13 @@ struct LevelPlan {
   std::unordered_map<uint64_t, std::vector<int>> zfin;  // (s,y): y later, linked at s
   std::vector<int> kcap, acap, bcap;
 
-  // layout (offsets in doubles / ints, relative to the arenas)
+  // layout (offsets in doubles / ints, relative to the arenas).  The work
+  // arena holds the diagonal blocks and fine halves, whose sizes do not depend
+  // on the rank capacities; the coarse halves live in a region of their own.
   int64_t work_doubles = 0;
+  int64_t coarse_doubles = 0;
   std::vector<int64_t> d_off;                        // D_x
-  std::unordered_map<uint64_t, int64_t> hc_off;      // (l,e): coarse half, m_l x kcap_e
+  std::unordered_map<uint64_t, int64_t> hc_off;      // (l,e): coarse half, m_l x kcap_e (coarse region)
   std::unordered_map<uint64_t, int64_t> hf_off;      // (e,l): fine half, m_e x |zfin|
   std::unordered_map<uint64_t, int64_t> pos_off;     // (e,l): posmap (m_l ints) in int arena
   std::unordered_map<uint64_t, int64_t> zl_off;      // (e,l): zfin list in int arena
@@ -65,7 +68,16 @@ void coarsen_square(const std::vector<std::vector<int>>& adj, std::vector<std::v
 void plan_level(LevelPlan* lp,
                 const std::unordered_map<uint64_t, std::vector<uint64_t>>* zinit);
 
-// Work-arena layout of D, fine and coarse halves, posmaps and column lists.
+// Rank capacities kcap (and the near/far column capacities acap/bcap that
+// follow from them) in processing order: kcap_s = min(m_s, bcap_s, caps[s])
+// (caps == nullptr: the worst case min(m_s, bcap_s)).
+void plan_capacities(LevelPlan* lp, const std::vector<int>* caps);
+
+// Layout of D and the fine halves (work arena), posmaps and column lists
+// (int arena), and the coarse halves (coarse region).
 void plan_layout(LevelPlan* lp);
+
+// Doubles of all panels P_s (m_s x (m_s + acap_s + bcap_s)).
+int64_t plan_panel_doubles(const LevelPlan& lp);
 
 }  // namespace lrsp

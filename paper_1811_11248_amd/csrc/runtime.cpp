@@ -80,7 +80,7 @@ bool coupling(const LevelDev& L, int x, int y, const double** src, int* sld, int
   const int earlier = later == x ? y : x;
   auto it = p.hc_off.find(pkey(later, earlier));
   if (it == p.hc_off.end()) return false;
-  *src = at<double>(L.work, it->second);
+  *src = at<double>(L.coarse, it->second);
   *sld = p.m[later];
   *trans = (later == x) ? 0 : 1;
   return true;
@@ -142,6 +142,11 @@ lrsp_status upload(DevBuf* b, const void* src, size_t bytes, hipStream_t st) {
 
 lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase,
                         const LevelState* shared, int32_t* serr) {
+  if (lrsp_status s = setup_level_a(L, st, vbase)) return s;
+  return setup_level_b(L, st, sbase, shared, serr);
+}
+
+lrsp_status setup_level_a(LevelDev* L, hipStream_t st, int64_t vbase) {
   LevelPlan& p = L->plan;
   const int M = p.M;
   plan_layout(&p);
@@ -161,6 +166,31 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase,
     std::copy(z.begin(), z.end(), hints.data() + p.zl_off[kv.first]);
   }
   if (lrsp_status s = upload(&L->wints, hints.data(), hints.size() * 4, st)) return s;
+  // level vector offsets
+  L->voff.assign(M, 0);
+  int64_t vo = 0;
+  for (int x = 0; x < M; ++x) {
+    L->voff[x] = vbase + vo;
+    vo += p.m[x];
+  }
+  L->vbase = vbase;
+  L->nvec = vo;
+  return LRSP_OK;
+}
+
+lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelState* shared,
+                          int32_t* serr) {
+  LevelPlan& p = L->plan;
+  const int M = p.M;
+  // coarse halves (layout from the current rank capacities)
+  plan_layout(&p);
+  dfree(&L->coarse, st);
+  dfree(&L->fac, st);
+  dfree(&L->fints, st);
+  dfree(&L->fvidx, st);
+  dfree(&L->desc, st);
+  HIPCHK(dalloc(&L->coarse, sizeof(double) * p.coarse_doubles, st));
+  launch_zero(at<double>(L->coarse, 0), p.coarse_doubles, st);
   // factor arenas
   int64_t fd = 0, fi = 0, fv = 0;
   std::vector<int64_t> poff(M), toff(M), noff(M), csoff(M), cnoff(M), stoff(M), pvoff(M),
@@ -186,6 +216,7 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase,
   if (shared) {
     L->ls = *shared;
   } else {
+    dfree(&L->state, st);
     HIPCHK(dalloc(&L->state, sizeof(int32_t) * (3 * (size_t)M + 8), st));
     int32_t* sb = at<int32_t>(L->state, 0);
     L->ls.k = sb;
@@ -194,15 +225,6 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase,
     L->ls.err = sb + 3 * M;
     launch_zero_i32(sb, 3 * (int64_t)M + 8, st);
   }
-  // level vector offsets
-  L->voff.assign(M, 0);
-  int64_t vo = 0;
-  for (int x = 0; x < M; ++x) {
-    L->voff[x] = vbase + vo;
-    vo += p.m[x];
-  }
-  L->vbase = vbase;
-  L->nvec = vo;
   // descriptors
   std::vector<SegD> segs;
   std::vector<PairD> pairs;
@@ -210,6 +232,7 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase,
   std::vector<ItemD> items(M);
   std::vector<int64_t> seg0(M), pair0(M), wb0(M);
   double* W = at<double>(L->work, 0);
+  double* CR = at<double>(L->coarse, 0);
   int32_t* WI = at<int32_t>(L->wints, 0);
   for (int idx = 0; idx < M; ++idx) {
     const int s = p.order[idx];
@@ -226,11 +249,11 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase,
         WbD wb{};
         if (p.pos[y] < p.pos[s]) {
           const int64_t o = p.hc_off.at(pkey(s, y));
-          sg.src = W + o;
+          sg.src = CR + o;
           sg.zl = nullptr;
           sg.coarse = 1;
           sg.cap = p.kcap[y];
-          wb.dst = W + o;
+          wb.dst = CR + o;
           wb.ld = p.m[s];
           wb.trans = 0;
           wb.nrows = p.m[s];
@@ -242,7 +265,7 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase,
           sg.coarse = 0;
           sg.nfine = (int)p.zfin.at(key).size();
           sg.cap = sg.nfine;
-          wb.dst = W + p.hc_off.at(pkey(y, s));
+          wb.dst = CR + p.hc_off.at(pkey(y, s));
           wb.ld = p.m[y];
           wb.trans = 1;
           wb.nrows = p.m[y];
@@ -267,7 +290,7 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase,
           const int e = p.pos[pi] < p.pos[qj] ? pi : qj;
           const int l = e == pi ? qj : pi;
           if (p.pos[e] < p.pos[s]) {
-            pd.dst = W + p.hc_off.at(pkey(l, e));
+            pd.dst = CR + p.hc_off.at(pkey(l, e));
             pd.ld = p.m[l];
             pd.rows_from_j = (l == qj);
             pd.nrows = p.m[l];

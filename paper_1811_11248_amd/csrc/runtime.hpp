@@ -84,7 +84,8 @@ struct LevelDev {
   LevelPlan plan;
   std::vector<int> k, a, b;
   int max_m = 0;
-  DevBuf work, wints;      // D / fine / coarse halves; posmaps and column lists
+  DevBuf work, wints;      // D / fine halves; posmaps and column lists
+  DevBuf coarse;           // coarse halves (sized by the rank capacities)
   DevBuf fac;              // panels, tau, norms (doubles)
   DevBuf fints;            // colseg, colnat, stepof, piv, segoff (int32)
   DevBuf fvidx;            // vidx (int64)
@@ -110,12 +111,16 @@ struct LevelDev {
   DevBuf tasks;                     // level >= 1: assembly copy tasks
   int ntasks = 0;
   uint64_t tasks_src = 0;           // id of the level the tasks read from
+  bool capped = false;              // rank capacities from predicted ranks
+  std::vector<double> feat;         // learned ranks: features [M][12]
+  std::vector<float> pred;          // and predicted ranks [M]
   void free_all(hipStream_t st) {
-    dfree(&work, st); dfree(&wints, st); dfree(&fac, st); dfree(&fints, st); dfree(&fvidx, st);
+    dfree(&work, st); dfree(&wints, st); dfree(&coarse, st); dfree(&fac, st); dfree(&fints, st);
+    dfree(&fvidx, st);
     dfree(&desc, st); dfree(&state, st); dfree(&gidx, st); dfree(&vals_off, st); dfree(&tasks, st);
   }
   int64_t held_bytes() const {
-    return (int64_t)(work.bytes + wints.bytes + fac.bytes + fints.bytes + fvidx.bytes + desc.bytes +
+    return (int64_t)(work.bytes + wints.bytes + coarse.bytes + fac.bytes + fints.bytes + fvidx.bytes + desc.bytes +
                      state.bytes + gidx.bytes + vals_off.bytes + tasks.bytes);
   }
 };
@@ -141,6 +146,14 @@ lrsp_status upload(DevBuf* b, const void* src, size_t bytes, hipStream_t st);
 // errors also to *serr.
 lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase = 0,
                         const LevelState* shared = nullptr, int32_t* serr = nullptr);
+// The two phases of setup_level.  A: layout, work arena (diagonal blocks and
+// fine halves, cleared), column lists, vector offsets -- everything the
+// level's assembly needs, independent of the rank capacities.  B: coarse
+// region (cleared), panels and descriptors for the current capacities; it
+// may be called again after the capacities change.
+lrsp_status setup_level_a(LevelDev* L, hipStream_t st, int64_t vbase);
+lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase = 0,
+                          const LevelState* shared = nullptr, int32_t* serr = nullptr);
 
 bool complete_graph(const std::vector<std::vector<int>>& adj);
 
@@ -156,6 +169,15 @@ void top_offsets_level0(const TreeH& tr, const int64_t* rp, const int32_t* cl, i
 // Dense top assembled from the coarse rows of the finished level `prev`.
 void top_tasks(const LevelDev& prev, const std::vector<int64_t>& toff, int ntop, double* Tm,
                std::vector<CopyD>* tasks);
+
+// Learned ranks of a level whose work arena holds the level-start matrix:
+// features (host, [M][12]) and the network's predicted ranks (host, [M]).
+lrsp_status predict_level(LevelDev* L, int level, double tol, const float* d_params, hipStream_t st,
+                          std::vector<double>* feat, std::vector<float>* pred);
+// Rank capacities from predicted ranks: ceil(kRankCapScale*max(y,0) + kRankCapSlack).
+constexpr double kRankCapScale = 2.0;
+constexpr double kRankCapSlack = 4.0;
+std::vector<int> rank_caps(const std::vector<float>& pred);
 
 // The cluster tree held by a tree handle.
 const TreeH& tree_of(const lrsp_tree* t);

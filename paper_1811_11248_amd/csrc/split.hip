@@ -381,6 +381,7 @@ __global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ it
   const int kmax = min(m, b);
   double r00 = 0.0;
   int k = kmax;
+  bool over = false;
   for (int j = 0; j < kmax; ++j) {
     double mx = 0.0;
     for (int c = tid; c < b; c += NT)
@@ -400,6 +401,11 @@ __global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ it
     const bool stop = (tol_mode == 0) ? (rjj <= tol * r00) : (rjj <= tol);
     if (stop || rjj == 0.0) {
       k = j;
+      break;
+    }
+    if (j >= it.kcap) {  // rank beyond the capacity: no room for reflector j
+      k = it.kcap;
+      over = true;
       break;
     }
     double* x = W + (size_t)m * best;
@@ -480,7 +486,7 @@ __global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ it
   }
   for (int c = tid; c < b; c += NT) it.stepof[c] = stp[c];
   if (tid == 0) ls.k[it.s] = k;
-  if (k > it.kcap && tid == 0) item_error(it, ls.err, level, kErrCapacity);
+  if ((over || k > it.kcap) && tid == 0) item_error(it, ls.err, level, kErrCapacity);
 }
 
 // ---------------------------------------------------------------------------

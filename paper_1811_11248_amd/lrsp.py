@@ -51,7 +51,10 @@ class Info(C.Structure):
     _fields_ = [("nlevels", C.c_int32), ("top_n", C.c_int32), ("top_clusters", C.c_int32),
                 ("reserved", C.c_int32), ("flops", C.c_double * 6), ("bytes_factor", C.c_double),
                 ("ms_levels", C.c_double), ("peak_bytes", C.c_int64), ("ms_analysis", C.c_double),
-                ("levels_reused", C.c_int32), ("reserved2", C.c_int32)]
+                ("levels_reused", C.c_int32), ("reserved2", C.c_int32),
+                ("rank_bytes", C.c_double), ("rank_bytes_worst", C.c_double),
+                ("rank_checks_passed", C.c_int32), ("rank_checks_failed", C.c_int32),
+                ("rank_redo_levels", C.c_int32), ("reserved3", C.c_int32)]
 
 
 class LevelView(C.Structure):
@@ -105,6 +108,15 @@ SIGNATURES = [
     ("lrsp_autotune_load", C.c_int, [C.c_char_p]),
     ("lrsp_autotune_clear", C.c_int, []),
     ("lrsp_autotune_entries", C.c_int32, []),
+    ("lrsp_mlp_nparams", C.c_int32, []),
+    ("lrsp_mlp_init", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p]),
+    ("lrsp_mlp_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    ("lrsp_mlp_train", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_float,
+                                 C.c_void_p, C.c_void_p]),
+    ("lrsp_mlp_predict", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    ("lrsp_factor_rank_features", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                            C.POINTER(C.c_float)]),
     ("lrsp_timing_enable", C.c_int, [C.c_int32]),
     ("lrsp_timing_reset", C.c_int, []),
     ("lrsp_timing_read", C.c_int, [C.c_int32, C.POINTER(Timing)]),
@@ -192,14 +204,27 @@ class DeviceMatrix:
 
 
 class Factor:
-    """Hierarchical factor of a DeviceMatrix (lrsp_factor)."""
+    """Hierarchical factor of a DeviceMatrix (lrsp_factor).
+
+    mlp: parameters of the rank network (numpy float32 array or CPU/GPU
+    tensor of lrsp_mlp_nparams() floats) to size the rank capacities from
+    learned ranks (rank_mode 1)."""
 
     def __init__(self, A: DeviceMatrix, tree: Tree, tol: float, tol_mode="relative",
-                 gemm_prec="f64", exec_mode="auto", stream=None):
+                 gemm_prec="f64", exec_mode="auto", stream=None, mlp=None, autotune=False):
         o = Opts()
         o.tol_mode = TOL_MODE[tol_mode]
         o.gemm_prec = PREC[gemm_prec]
         o.exec_mode = EXEC_MODE[exec_mode]
+        o.autotune = 1 if autotune else 0
+        self._mlp = None
+        if mlp is not None:
+            w = mlp.detach().cpu().numpy() if hasattr(mlp, "detach") else np.asarray(mlp)
+            self._mlp = np.ascontiguousarray(w, dtype=np.float32)
+            if self._mlp.size != mlp_nparams():
+                raise ValueError("wrong number of MLP parameters")
+            o.rank_mode = 1
+            o.mlp_weights = self._mlp.ctypes.data
         h = C.c_void_p()
         self._csr = A.csr()
         self.A = A
@@ -214,7 +239,19 @@ class Factor:
         return {"nlevels": i.nlevels, "top_n": i.top_n, "top_clusters": i.top_clusters,
                 "flops": dict(zip(("potrf", "trsm", "cpqr", "applyq", "schur", "top"), i.flops)),
                 "bytes_factor": i.bytes_factor, "ms": i.ms_levels, "ms_analysis": i.ms_analysis,
-                "levels_reused": i.levels_reused}
+                "levels_reused": i.levels_reused, "peak_bytes": i.peak_bytes,
+                "rank_bytes": i.rank_bytes, "rank_bytes_worst": i.rank_bytes_worst,
+                "rank_checks_passed": i.rank_checks_passed, "rank_checks_failed": i.rank_checks_failed,
+                "rank_redo_levels": i.rank_redo_levels}
+
+    def rank_features(self, lev: int):
+        """(features [M, 12], predicted ranks [M]) of a level (rank_mode 1)."""
+        M = self.level(lev)["nclusters"]
+        f = np.zeros(M * 12)
+        p = np.zeros(M, dtype=np.float32)
+        _check(lib().lrsp_factor_rank_features(self.handle, int(lev), f.ctypes.data_as(C.POINTER(C.c_double)),
+                                               p.ctypes.data_as(C.POINTER(C.c_float))))
+        return f.reshape(M, 12), p
 
     def level(self, lev: int) -> dict:
         v = LevelView()
@@ -344,6 +381,45 @@ class Batch:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.lrsp_batch_free(self.handle)
             self.handle = None
+
+
+def mlp_nparams() -> int:
+    return int(lib().lrsp_mlp_nparams())
+
+
+def mlp_init(X, t, seed=1, stream=None):
+    """New parameter tensor (device, fp32) initialised from data X [n, 12], t [n]."""
+    import torch
+    P = torch.zeros(mlp_nparams(), dtype=torch.float32, device=X.device)
+    _check(lib().lrsp_mlp_init(P.data_ptr(), X.data_ptr(), t.data_ptr(), int(X.shape[0]), int(seed),
+                               _stream(stream)))
+    return P
+
+
+def mlp_loss_grad(P, X, t, stream=None):
+    import torch
+    g = torch.empty_like(P)
+    loss = torch.empty(1, dtype=torch.float32, device=P.device)
+    _check(lib().lrsp_mlp_loss_grad(P.data_ptr(), X.data_ptr(), t.data_ptr(), int(X.shape[0]),
+                                    g.data_ptr(), loss.data_ptr(), _stream(stream)))
+    return float(loss.item()), g
+
+
+def mlp_train(P, X, t, steps, lr=1e-2, stream=None):
+    """Trains P in place; returns the loss before every step (device tensor)."""
+    import torch
+    trace = torch.empty(max(1, steps), dtype=torch.float32, device=P.device)
+    _check(lib().lrsp_mlp_train(P.data_ptr(), X.data_ptr(), t.data_ptr(), int(X.shape[0]), int(steps),
+                                float(lr), trace.data_ptr(), _stream(stream)))
+    return trace[:steps]
+
+
+def mlp_predict(P, X, stream=None):
+    import torch
+    y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(lib().lrsp_mlp_predict(P.data_ptr(), X.data_ptr(), int(X.shape[0]), y.data_ptr(),
+                                  _stream(stream)))
+    return y
 
 
 def autotune_save(path: str):

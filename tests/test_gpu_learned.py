@@ -1,0 +1,163 @@
+"""Learned-rank form through the C-ABI.
+
+* the level-start features equal the oracle's (same Philox sketch);
+* the network's loss and gradient (fp32 kernels) equal the oracle's fp64
+  backpropagation to fp32 accuracy;
+* a network trained on the GPU from the oracle's (features, rank) pairs
+  sizes the rank capacities: ranks and M^{-1} b are exactly those of the
+  worst-case capacities, with less memory, and fewer levels redone than an
+  untrained network;
+* capacities far too small are caught and the level is redone.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as olearned
+from synth import lognormal_field, rhs, slab_scalar, slab_vector
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PAIRS = os.path.join(HERE, "golden", "rank_pairs_cfg123.npz")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1811_11248_amd import lrsp
+    return lrsp
+
+
+CASES = {
+    "slab_ragged": (lambda: slab_scalar(13, 11, 5, 1e3, lognormal_field((11, 13, 5), seed=2)), 40, 1e-2),
+    "vector_ragged": (lambda: slab_vector(10, 9, 4, 1e2), 48, 1e-2),
+    "slab_aniso": (lambda: slab_scalar(24, 20, 8, 1e4, lognormal_field((20, 24, 8), seed=5)), 64, 1e-2),
+}
+
+
+def _trained(torch, L, steps=1500):
+    d = np.load(PAIRS)
+    X = torch.from_numpy(d["X"].astype(np.float32)).cuda()
+    t = torch.from_numpy(d["k"].astype(np.float32)).cuda()
+    P = L.mlp_init(X, t, seed=3)
+    trace = L.mlp_train(P, X, t, steps, lr=3e-3).cpu().numpy()
+    return P, X, t, trace
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_features_match_oracle(torch, L, name):
+    mk, leaf, tol = CASES[name]
+    pr = mk()
+    _say(f"[features {name}] n={pr.n}")
+    feats = []
+    T = oracle.build_tree(pr.grid, leaf)
+    Fo = oracle.factor(pr.rowptr, pr.col, pr.val, T, tol,
+                       level_hook=lambda li, b, s, g: feats.append(olearned.level_features(li, b, s, g, tol)))
+    P = np.zeros(L.mlp_nparams(), np.float32)  # predicts 0: capacities 2, levels redone
+    A = L.DeviceMatrix.from_problem(pr)
+    F = L.Factor(A, L.Tree(pr.grid, leaf), tol, mlp=P)
+    assert F.info()["nlevels"] == len(Fo.levels)
+    for li, fo in enumerate(feats):
+        fg, _ = F.rank_features(li)
+        assert np.allclose(fg[:, [0, 1, 11]], fo[:, [0, 1, 11]], rtol=1e-14, atol=0)  # libm ulps
+        # level 0 reads the same matrix on both sides; coarse levels read each
+        # side's own coarse blocks, which agree to the factor's rounding (the
+        # 1e-10 bar of the solve), so log10 norms agree to ~1e-9
+        atol_n, rtol_s = (1e-12, 1e-9) if li == 0 else (1e-8, 1e-6)
+        assert np.allclose(fg[:, 2], fo[:, 2], rtol=0, atol=atol_n), f"level {li}"
+        # singular values of null directions are sqrt(eps) noise on both sides
+        assert np.allclose(fg[:, 3:11], fo[:, 3:11], rtol=rtol_s, atol=1e-6), f"level {li}"
+
+
+def test_mlp_loss_grad_matches_oracle(torch, L):
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((300, 12)).astype(np.float32)
+    t = rng.uniform(0, 20, 300).astype(np.float32)
+    Xd, td = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+    P = L.mlp_init(Xd, td, seed=11)
+    P += torch.from_numpy(rng.standard_normal(L.mlp_nparams()).astype(np.float32) * 0.01).cuda()
+    P[:24] = L.mlp_init(Xd, td, seed=11)[:24]
+    loss, g = L.mlp_loss_grad(P, Xd, td)
+    lo, go = olearned.mlp_loss_grad(P.cpu().numpy().astype(np.float64), X, t)
+    _say(f"[mlp grad] loss {loss:.6g} vs {lo:.6g}")
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    g = g.cpu().numpy()
+    assert np.max(np.abs(g - go)) <= 1e-4 * np.max(np.abs(go))
+    yo, _ = olearned.mlp_forward(P.cpu().numpy().astype(np.float64), X)
+    y = L.mlp_predict(P, Xd).cpu().numpy()
+    assert np.max(np.abs(y - yo)) <= 1e-4 * max(1.0, np.max(np.abs(yo)))
+    # statistics of the init: mean and inverse deviation of the inputs
+    P0 = L.mlp_init(Xd, td, seed=11).cpu().numpy()
+    assert np.allclose(P0[:12], X.mean(0), atol=1e-5)
+    assert np.allclose(P0[12:24], 1.0 / X.std(0), rtol=1e-4)
+
+
+def test_trained_network_sizes_capacities(torch, L):
+    P, X, t, trace = _trained(torch, L)
+    _say(f"[train] loss {trace[0]:.3f} -> {trace[-1]:.3f} over {len(trace)} steps, {X.shape[0]} pairs")
+    assert trace[-1] < 0.35 * trace[0]
+    pred = L.mlp_predict(P, X).cpu().numpy()
+    tt = t.cpu().numpy()
+    assert np.mean(np.abs(pred - tt)) < np.mean(np.abs(tt - tt.mean()))
+    Pu = L.mlp_init(X, t, seed=3)  # untrained
+    tot = {"bytes": 0.0, "worst": 0.0, "redo": 0, "redo_untrained": 0}
+    for name, (mk, leaf, tol) in CASES.items():
+        pr = mk()
+        A = L.DeviceMatrix.from_problem(pr)
+        tree = L.Tree(pr.grid, leaf)
+        F0 = L.Factor(A, tree, tol)
+        F1 = L.Factor(A, tree, tol, mlp=P)
+        Fu = L.Factor(A, tree, tol, mlp=Pu)
+        i1, iu = F1.info(), Fu.info()
+        _say(f"[learned {name}] bytes {i1['rank_bytes']:.3g} of worst {i1['rank_bytes_worst']:.3g}, "
+             f"redo {i1['rank_redo_levels']} (untrained {iu['rank_redo_levels']}), "
+             f"checks {i1['rank_checks_passed']}/{i1['rank_checks_failed']}")
+        assert i1["nlevels"] == F0.info()["nlevels"]
+        for li in range(i1["nlevels"]):
+            assert F1.level(li)["ranks"].tolist() == F0.level(li)["ranks"].tolist()
+        b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+        assert torch.equal(L.apply(F1, b), L.apply(F0, b))
+        assert torch.equal(L.apply(Fu, b), L.apply(F0, b))
+        tot["bytes"] += i1["rank_bytes"]
+        tot["worst"] += i1["rank_bytes_worst"]
+        tot["redo"] += i1["rank_redo_levels"]
+        tot["redo_untrained"] += iu["rank_redo_levels"]
+    _say(f"[learned total] {tot}")
+    # the gain: capacities (and memory) well below the worst case, with at
+    # most one level per problem redone
+    assert tot["bytes"] < 0.8 * tot["worst"]
+    assert tot["redo"] <= len(CASES)
+
+
+def test_tiny_capacities_are_redone(torch, L):
+    mk, leaf, tol = CASES["slab_aniso"]
+    pr = mk()
+    P = np.zeros(L.mlp_nparams(), np.float32)
+    P[-1] = -50.0  # every prediction negative: capacity 2
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree(pr.grid, leaf)
+    F0 = L.Factor(A, tree, tol)
+    F1 = L.Factor(A, tree, tol, mlp=P)
+    inf = F1.info()
+    _say(f"[tiny capacities] redo {inf['rank_redo_levels']} of {inf['nlevels']}")
+    assert inf["rank_redo_levels"] >= 1
+    b = torch.from_numpy(rhs(pr.n, 1)).cuda()
+    assert torch.equal(L.apply(F1, b), L.apply(F0, b))
+    for li in range(inf["nlevels"]):
+        assert F1.level(li)["ranks"].tolist() == F0.level(li)["ranks"].tolist()
