@@ -341,6 +341,30 @@ __device__ void apply_qt_cols(double* C, int ld, int m, int a, const double* W, 
   }
 }
 
+// Owning-block entry of the Schur element (rr, cc), cc <= rr, of the
+// near-field columns; null, after recording the error, when out of range.
+__device__ __forceinline__ double* schur_target(const ItemD& it, int rr, int cc, int32_t* err, int level) {
+  const int sr = it.colseg[rr], sc = it.colseg[cc];
+  const int nr = it.colnat[rr], nc = it.colnat[cc];
+  const int i = min(sr, sc), j = max(sr, sc);
+  const PairD& pd = it.pair[j * (j + 1) / 2 + i];
+  int row, col;
+  if (pd.diag) {
+    row = max(nr, nc);
+    col = min(nr, nc);
+  } else {
+    const bool r_is_rowseg = (sr == (pd.rows_from_j ? j : i));
+    row = r_is_rowseg ? nr : nc;
+    const int cn = r_is_rowseg ? nc : nr;
+    col = pd.posmap ? pd.posmap[cn] : cn;
+  }
+  if (row < 0 || col < 0 || row >= pd.nrows || col >= pd.ncols) {
+    item_error(it, err, level, kErrIndex);
+    return nullptr;
+  }
+  return pd.dst + (size_t)row + (size_t)pd.ld * col;
+}
+
 // Schur update X -= F^T F, F = rows k..m-1 of the a near-field columns C (ld).
 // Each unordered column pair (r >= c) is computed once and scattered to the
 // one block that owns it.
@@ -397,35 +421,26 @@ __device__ void schur_scatter(const ItemD& it, const double* C, int ld, int m, i
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[r][q] = (double)accf[r][q];
     }
+    // all targets first, then all loads, then all stores: sixteen
+    // read-modify-writes in flight instead of one after the other
+    double* t[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rr = 4 * R + r;
-      if (rr >= a) continue;
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int cc = 4 * Cc + q;
-        if (cc >= a || cc > rr) continue;
-        const int sr = it.colseg[rr], sc = it.colseg[cc];
-        const int nr = it.colnat[rr], nc = it.colnat[cc];
-        int i = min(sr, sc), j = max(sr, sc);
-        const PairD& pd = it.pair[j * (j + 1) / 2 + i];
-        int row, col;
-        if (pd.diag) {
-          row = max(nr, nc);
-          col = min(nr, nc);
-        } else {
-          const bool r_is_rowseg = (sr == (pd.rows_from_j ? j : i));
-          row = r_is_rowseg ? nr : nc;
-          const int cn = r_is_rowseg ? nc : nr;
-          col = pd.posmap ? pd.posmap[cn] : cn;
-        }
-        if (row < 0 || col < 0 || row >= pd.nrows || col >= pd.ncols) {
-          item_error(it, err, level, kErrIndex);
-          continue;
-        }
-        pd.dst[(size_t)row + (size_t)pd.ld * col] -= acc[r][q];
+        const int rr = 4 * R + r, cc = 4 * Cc + q;
+        t[r][q] = (rr < a && cc < a && cc <= rr) ? schur_target(it, rr, cc, err, level) : nullptr;
       }
-    }
+    double old[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) old[r][q] = t[r][q] ? *t[r][q] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (t[r][q]) *t[r][q] = old[r][q] - acc[r][q];
   }
 }
 
@@ -501,9 +516,57 @@ __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol,
   double* P = it.P;
   const size_t ld = (size_t)m;
   const int lane = tid & 63, wv = tid >> 6;
-  // gather [A_ss | A_sn | A_sw]: one column per wave, rows in registers
   const int ncols = m + a + b;
-  for (int c = wv; c < ncols; c += kWaves) {
+  // gather [A_ss | A_sn | A_sw].  When the column sources fit in the LDS
+  // scratch (free until the Cholesky), every element is copied by its own
+  // thread with eight loads in flight; else one column per wave.
+  const double** srcp = reinterpret_cast<const double**>(lds);
+  const bool table = (size_t)ncols <= (size_t)m * kNB + kNB * kNB + kNB * 256;
+  if (table) {
+    for (int c = tid; c < ncols; c += kThreads) {
+      const double* src;
+      if (c < m) {
+        src = it.D + ld * c;
+      } else {
+        const int pc = c - m;
+        int lo = 0, hi = it.nseg - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (soff[mid] <= pc) lo = mid;
+          else hi = mid - 1;
+        }
+        const SegD& sg = it.seg[lo];
+        const int loc = pc - soff[lo];
+        src = sg.src + ld * loc;
+        const int nat = sg.coarse ? loc : sg.zl[loc];
+        it.colseg[pc] = lo;
+        it.colnat[pc] = nat;
+        it.vidx[pc] = sg.voff + nat;
+      }
+      srcp[c] = src;
+    }
+    __syncthreads();
+    const int ne = m * ncols;
+    for (int e0 = tid; e0 < ne; e0 += kThreads * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        v[u] = 0.0;
+        if (e < ne) {
+          const int c = e / m, r = e - c * m;
+          v[u] = srcp[c][r];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < ne) P[e] = v[u];
+      }
+    }
+    __syncthreads();  // the scratch is the Cholesky's from here on
+  }
+  for (int c = wv; c < (table ? 0 : ncols); c += kWaves) {
     const double* src;
     if (c < m) {
       src = it.D + ld * c;
