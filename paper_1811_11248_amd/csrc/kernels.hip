@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kWaves = kThreads / 64;
 constexpr int kRegRows = kMaxClusterDofs / 64;  // column slots per lane
+constexpr int kColM = 64;  // up to this many rows, column operations run one column per thread
 
 __device__ __forceinline__ double block_sum(double v, double* sh) { return group_sum<kThreads>(v, sh); }
 __device__ __forceinline__ double block_max(double v, double* sh) { return group_max<kThreads>(v, sh); }
@@ -202,15 +203,29 @@ __device__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* 
 // rule, *over is set and kcap is returned.
 __device__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, int kcap, int* piv,
                     int* stepof, double* tau, double* norms, double* shd, int* shi, bool* over) {
+  __shared__ double vsh[kColM];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int c = wv; c < b; c += kWaves) {
-    const double* y = W + (size_t)ld * c;
-    double s = 0.0;
-    for (int i = lane; i < m; i += 64) s += y[i] * y[i];
-    s = wave_sum(s);
-    if (lane == 0) {
+  // m <= kColM: one column per thread (its rows loaded together); else one
+  // column per wave
+  const bool bycol = m <= kColM;
+  if (bycol) {
+    for (int c = tid; c < b; c += kThreads) {
+      const double* y = W + (size_t)ld * c;
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s += y[i] * y[i];
       norms[c] = s;
       stepof[c] = -1;
+    }
+  } else {
+    for (int c = wv; c < b; c += kWaves) {
+      const double* y = W + (size_t)ld * c;
+      double s = 0.0;
+      for (int i = lane; i < m; i += 64) s += y[i] * y[i];
+      s = wave_sum(s);
+      if (lane == 0) {
+        norms[c] = s;
+        stepof[c] = -1;
+      }
     }
   }
   __syncthreads();
@@ -268,6 +283,27 @@ __device__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, i
       tau[j] = tj;
     }
     __syncthreads();
+    if (bycol) {
+      // apply H_j to the remaining columns, one per thread, v in LDS
+      if (tid < m) vsh[tid] = tid == j ? 1.0 : (tid > j ? x[tid] : 0.0);
+      __syncthreads();
+      for (int c = tid; c < b; c += kThreads) {
+        if (stepof[c] >= 0) continue;
+        double* y = W + (size_t)ld * c;
+        double s = 0.0;
+        for (int i = j; i < m; ++i) s += vsh[i] * y[i];
+        const double f = tj * s;
+        double nn = 0.0;
+        for (int i = j; i < m; ++i) {
+          const double nv = y[i] - f * vsh[i];
+          y[i] = nv;
+          if (i > j) nn += nv * nv;
+        }
+        norms[c] = nn;
+      }
+      __syncthreads();
+      continue;
+    }
     // apply H_j to the remaining columns and recompute their norms below row j
     double v[kRegRows];
 #pragma unroll
@@ -306,10 +342,82 @@ __device__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, i
   return k;
 }
 
-// C <- U^T C for the a columns C (ld): reflectors 0..k-1 in order.
+// C <- U^T C for the a columns C (ld): reflectors 0..k-1 in order.  With
+// m <= kColM and room in the LDS scratch (scr doubles at lds), the
+// reflectors are staged in LDS and C passes through it in chunks of
+// columns (row-major in the chunk, so that the column of each thread is
+// conflict-free), every column rotated by its own thread; else one column
+// per wave from global memory.
 __device__ void apply_qt_cols(double* C, int ld, int m, int a, const double* W, const int* piv,
-                              const double* tau, int k) {
+                              const double* tau, int k, double* lds, size_t scr) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (m <= kColM && scr >= (size_t)(k + 1) * m + k) {
+    double* V = lds;                  // k x m, V[j*m + i]
+    double* ts = V + (size_t)k * m;   // k
+    double* Cs = ts + k;              // m x cw, Cs[i*cw + c]
+    const int cw = (int)min<size_t>((size_t)a, (scr - (size_t)k * m - k) / m);
+    const int nv = k * m;
+    for (int e0 = tid; e0 < nv; e0 += kThreads * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        v[u] = 0.0;
+        if (e < nv) {
+          const int j = e / m, i = e - j * m;
+          v[u] = i == j ? 1.0 : (i > j ? W[(size_t)i + (size_t)ld * piv[j]] : 0.0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < nv) V[e] = v[u];
+      }
+    }
+    for (int j = tid; j < k; j += kThreads) ts[j] = tau[j];
+    for (int c0 = 0; c0 < a; c0 += cw) {
+      const int nc = min(cw, a - c0), ne = nc * m;
+      double* Cg = C + (size_t)ld * c0;
+      for (int e0 = tid; e0 < ne; e0 += kThreads * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * kThreads;
+          v[u] = 0.0;
+          if (e < ne) {
+            const int c = e / m, i = e - c * m;
+            v[u] = Cg[(size_t)i + (size_t)ld * c];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * kThreads;
+          if (e < ne) {
+            const int c = e / m, i = e - c * m;
+            Cs[(size_t)i * cw + c] = v[u];
+          }
+        }
+      }
+      __syncthreads();
+      for (int c = tid; c < nc; c += kThreads) {
+        double* y = Cs + c;
+        for (int j = 0; j < k; ++j) {
+          const double* v = V + (size_t)j * m;
+          double s = 0.0;
+          for (int i = j; i < m; ++i) s += v[i] * y[(size_t)i * cw];
+          const double f = ts[j] * s;
+          for (int i = j; i < m; ++i) y[(size_t)i * cw] -= f * v[i];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < ne; e += kThreads) {
+        const int c = e / m, i = e - c * m;
+        Cg[(size_t)i + (size_t)ld * c] = Cs[(size_t)i * cw + c];
+      }
+      __syncthreads();
+    }
+    return;
+  }
   for (int c = wv; c < a; c += kWaves) {
     double* y = C + (size_t)ld * c;
     double yr[kRegRows];
@@ -619,7 +727,7 @@ __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol,
   __syncthreads();
   // E_s: rotate the near-field columns, C = U^T G^{-1} A_sn
   double* C = P + ld * m;
-  if (k > 0) apply_qt_cols(C, m, m, a, Wf, it.piv, it.tau, k);
+  if (k > 0) apply_qt_cols(C, m, m, a, Wf, it.piv, it.tau, k, lds, (size_t)m * kNB + kNB * kNB + kNB * 256);
   __syncthreads();
   // G_s: eliminate the fine DoFs, X_nn -= F^T F
   if (m > k && a > 0) schur_scatter(it, C, m, m, k, a, prec, ls.err, level);
