@@ -79,7 +79,8 @@ typedef struct {
   int32_t rank_mode;  /* 0: worst-case rank capacities; 1: capacities from
                          learned ranks (see "learned ranks" below) */
   int32_t exec_mode;  /* kernel schedule (results agree to rounding): 0 auto;
-                         1 one workgroup per cluster, one launch per colour;
+                         1 one workgroup per cluster, one launch per colour
+                         (the substitution sweeps of lrsp_apply too);
                          2 one workgroup per cluster, one cooperative launch per
                          level; 3 several workgroups per cluster for clusters of
                          96..512 DoFs, else as 2 */

@@ -56,6 +56,7 @@ struct lrsp_tree {
 
 struct lrsp_factorization {
   int64_t n = 0;
+  int exec_mode = 0;  // 1: the sweeps too run one launch per colour
   std::vector<std::unique_ptr<LevelDev>> levels;
   // dense top
   int top_n = 0;
@@ -177,6 +178,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   if (rp[A->n] != A->nnz) return fail(LRSP_ERR_ARG, "rowptr[n] != nnz");
   auto F = std::make_unique<lrsp_factorization>();
   F->n = A->n;
+  F->exec_mode = o.exec_mode;
   F->stream = st;
   double ms_an = 0.0;
   auto tick = [] { return std::chrono::steady_clock::now(); };
@@ -505,11 +507,14 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
     const LevelPlan& p = L.plan;
     {
       TimedLaunch tl(1, st);
-      if (launch_sweep_level(true, L.d_items, L.d_cstart, p.ncolours, L.max_items, L.max_m, L.ls, V,
+      // levels with split clusters run one launch per colour (plus its units)
+      const bool per_colour = F->exec_mode == 1 || sweep_units(true, L.max_m, L.max_acap) > 0;
+      if (per_colour ||
+          launch_sweep_level(true, L.d_items, L.d_cstart, p.ncolours, L.max_items, L.max_m, L.max_acap, L.ls, V,
                              st) != hipSuccess) {
-        (void)hipGetLastError();
+        if (!per_colour) (void)hipGetLastError();
         for (int c = 0; c < p.ncolours; ++c)
-          launch_fwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.ls, V, st);
+          launch_fwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st);
       }
       if (g_tm.on)
         for (double by : L.sweep_bytes) g_tm.bytes[1] += by;
@@ -533,11 +538,13 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
     }
     {
       TimedLaunch tl(2, st);
-      if (launch_sweep_level(false, L.d_items, L.d_cstart, p.ncolours, L.max_items, L.max_m, L.ls, V,
+      const bool per_colour = F->exec_mode == 1 || sweep_units(false, L.max_m, L.max_acap) > 0;
+      if (per_colour ||
+          launch_sweep_level(false, L.d_items, L.d_cstart, p.ncolours, L.max_items, L.max_m, L.max_acap, L.ls, V,
                              st) != hipSuccess) {
-        (void)hipGetLastError();
+        if (!per_colour) (void)hipGetLastError();
         for (int c = p.ncolours - 1; c >= 0; --c)
-          launch_bwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.ls, V, st);
+          launch_bwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st);
       }
       if (g_tm.on)
         for (double by : L.sweep_bytes) g_tm.bytes[2] += by;

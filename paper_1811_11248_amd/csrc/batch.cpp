@@ -86,7 +86,7 @@ struct BLevel {
   ItemD* d_items = nullptr;
   const int32_t* d_cstart = nullptr;
   std::vector<int> cstart;
-  int ncolours = 0, max_items = 0, max_m = 0, max_nseg = 0;
+  int ncolours = 0, max_items = 0, max_m = 0, max_nseg = 0, max_acap = 0;
   std::vector<SplitDims> cdims;
   DevBuf zero;             // SpanD: buffers cleared before assembly
   int nzero = 0;
@@ -530,6 +530,7 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
         }
         B.cstart.push_back((int)items.size());
         B.max_items = std::max(B.max_items, B.cstart[c + 1] - B.cstart[c]);
+        B.max_acap = std::max(B.max_acap, B.cdims[c].max_acap);
       }
       for (auto& L : Ls) {
         B.max_m = std::max(B.max_m, L->max_m);
@@ -717,12 +718,17 @@ lrsp_status apply_cols(lrsp_batch* F, const double* b, double* x, int nrhs, bool
       if (l > 0) launch_gather(V, at<int64_t>(B.gidx, 0), V + B.vbase, B.nvec, st);
       if (B.Mtot == 0) continue;
       TimedLaunch tl(1, st);
-      if (launch_sweep_level(true, B.d_items, B.d_cstart, B.ncolours, B.max_items, B.max_m, B.ls, V, st, 0,
+      // levels with split clusters run one launch per colour (plus its units)
+      const bool per_colour = sweep_units(true, B.max_m, B.max_acap) > 0;
+      if (per_colour ||
+          launch_sweep_level(true, B.d_items, B.d_cstart, B.ncolours, B.max_items, B.max_m, B.max_acap, B.ls, V, st, 0,
                              graph ? sweep_bar(F, l, true) : nullptr) != hipSuccess) {
-        if (graph) return fail(LRSP_ERR_HIP, "persistent sweep launch failed");
-        (void)hipGetLastError();
+        if (!per_colour) {
+          if (graph) return fail(LRSP_ERR_HIP, "persistent sweep launch failed");
+          (void)hipGetLastError();
+        }
         for (int c = 0; c < B.ncolours; ++c)
-          launch_fwd(B.d_items + B.cstart[c], B.cstart[c + 1] - B.cstart[c], B.max_m, B.ls, V, st);
+          launch_fwd(B.d_items + B.cstart[c], B.cstart[c + 1] - B.cstart[c], B.max_m, B.max_acap, B.ls, V, st);
       }
       if (g_tm.on)
         for (double by : B.sweep_bytes) g_tm.bytes[1] += by;
@@ -732,12 +738,16 @@ lrsp_status apply_cols(lrsp_batch* F, const double* b, double* x, int nrhs, bool
       const BLevel& B = F->lv[l];
       if (B.Mtot > 0) {
         TimedLaunch tl(2, st);
-        if (launch_sweep_level(false, B.d_items, B.d_cstart, B.ncolours, B.max_items, B.max_m, B.ls, V, st,
-                               0, graph ? sweep_bar(F, l, false) : nullptr) != hipSuccess) {
-          if (graph) return fail(LRSP_ERR_HIP, "persistent sweep launch failed");
-          (void)hipGetLastError();
+        const bool per_colour = sweep_units(false, B.max_m, B.max_acap) > 0;
+        if (per_colour ||
+            launch_sweep_level(false, B.d_items, B.d_cstart, B.ncolours, B.max_items, B.max_m, B.max_acap, B.ls, V,
+                               st, 0, graph ? sweep_bar(F, l, false) : nullptr) != hipSuccess) {
+          if (!per_colour) {
+            if (graph) return fail(LRSP_ERR_HIP, "persistent sweep launch failed");
+            (void)hipGetLastError();
+          }
           for (int c = B.ncolours - 1; c >= 0; --c)
-            launch_bwd(B.d_items + B.cstart[c], B.cstart[c + 1] - B.cstart[c], B.max_m, B.ls, V, st);
+            launch_bwd(B.d_items + B.cstart[c], B.cstart[c + 1] - B.cstart[c], B.max_m, B.max_acap, B.ls, V, st);
         }
         if (g_tm.on)
           for (double by : B.sweep_bytes) g_tm.bytes[2] += by;

@@ -16,6 +16,14 @@ typedef short s4_t __attribute__((ext_vector_type(4)));
 
 constexpr double kTie = 1e-10;  // pivot tie window of the column-pivoted QR
 
+// Value of v in lane l (l uniform across the wave).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -893,9 +893,11 @@ namespace {
 constexpr int kBlkLd = 65;  // row stride of a staged 64x64 block
 
 // y <- G^{-1} y, G lower (m x m, ld), y in LDS.  Per 64-row block: the
-// diagonal block is staged in LDS and solved by wave 0 with shuffles; the
-// rows below subtract their 64-wide dot products, each thread loading its
-// row's 64 entries at once.  blk: 64*65 doubles of LDS.
+// diagonal block is staged in LDS and solved by wave 0 (each lane one row,
+// the reciprocals of the diagonal taken first, the solved entries broadcast
+// with readlane); the rows below subtract their 64-wide dot products, each
+// thread loading sixteen entries of its row at a time.
+// blk: 64*65 doubles.
 __device__ void trsv_lower(const double* G, int ld, int m, double* y, double* blk) {
   const int tid = threadIdx.x, lane = tid & 63;
   for (int jb = 0; jb < m; jb += 64) {
@@ -904,11 +906,16 @@ __device__ void trsv_lower(const double* G, int ld, int m, double* y, double* bl
                                   [&](int r, int c) { return c < w && c <= r; });
     __syncthreads();
     if (tid < 64) {
+      const double* row = blk + lane * kBlkLd;
+      const double rd = 1.0 / (lane < w ? blk[lane * kBlkLd + lane] : 1.0);
       double yl = (lane < w) ? y[jb + lane] : 0.0;
-      for (int t = 0; t < w; ++t) {
-        const double yt = __shfl(yl, t, 64) / blk[t * kBlkLd + t];
-        if (lane == t) yl = yt;
-        else if (lane > t) yl -= blk[lane * kBlkLd + t] * yt;
+#pragma unroll 8
+      for (int t = 0; t < 64; ++t) {
+        if (t < w) {
+          const double yt = readlane_d(yl, t) * readlane_d(rd, t);
+          if (lane == t) yl = yt;
+          else if (lane > t) yl -= row[t] * yt;
+        }
       }
       if (lane < w) y[jb + lane] = yl;
     }
@@ -917,11 +924,11 @@ __device__ void trsv_lower(const double* G, int ld, int m, double* y, double* bl
       const double* gi = G + (size_t)i + (size_t)ld * jb;
       double s = 0.0;
       for (int t0 = 0; t0 < w; t0 += 16) {
-        double g[16];
+        double gg[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) g[t] = (t0 + t < w) ? gi[(size_t)ld * (t0 + t)] : 0.0;
+        for (int t = 0; t < 16; ++t) gg[t] = (t0 + t < w) ? gi[(size_t)ld * (t0 + t)] : 0.0;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) s += g[t] * y[jb + min(t0 + t, w - 1)];
+        for (int t = 0; t < 16; ++t) s += gg[t] * y[jb + min(t0 + t, w - 1)];
       }
       y[i] -= s;
     }
@@ -932,15 +939,18 @@ __device__ void trsv_lower(const double* G, int ld, int m, double* y, double* bl
 // y <- G^{-T} y, G lower (m x m, ld), y in LDS.  From the last 64-row block
 // up: subtract the dot products of the block's columns below the block with
 // y (one wave per column, four columns in flight), then solve the diagonal
-// block transposed in wave 0.
+// block transposed in wave 0 (each lane one column, the reciprocals of the
+// diagonal taken first, solved entries broadcast with readlane).
+template <int R>
 __device__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* blk) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  constexpr int R = kMaxClusterDofs / 64;
   const int nblk = (m + 63) / 64;
   for (int bi = nblk - 1; bi >= 0; --bi) {
     const int jb = bi * 64;
     const int w = min(64, m - jb);
     const int r0 = jb + w;
+    load_block_rowmajor<kThreads>(blk, kBlkLd, G + (size_t)jb * ld + jb, (size_t)ld, w, 64,
+                                  [&](int r, int c) { return c < w && c <= r; });
     double yr[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) {
@@ -967,15 +977,17 @@ __device__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* 
         if (lane == 0 && t0 + q < w) y[jb + t0 + q] -= s;
       }
     }
-    load_block_rowmajor<kThreads>(blk, kBlkLd, G + (size_t)jb * ld + jb, (size_t)ld, w, 64,
-                                  [&](int r, int c) { return c < w && c <= r; });
     __syncthreads();
     if (tid < 64) {
+      const double rd = 1.0 / (lane < w ? blk[lane * kBlkLd + lane] : 1.0);
       double yl = (lane < w) ? y[jb + lane] : 0.0;
-      for (int t = w - 1; t >= 0; --t) {
-        const double yt = __shfl(yl, t, 64) / blk[t * kBlkLd + t];
-        if (lane == t) yl = yt;
-        else if (lane < t) yl -= blk[t * kBlkLd + lane] * yt;
+#pragma unroll 8
+      for (int t = 63; t >= 0; --t) {
+        if (t < w) {
+          const double yt = readlane_d(yl, t) * readlane_d(rd, t);
+          if (lane == t) yl = yt;
+          else if (lane < t) yl -= blk[t * kBlkLd + lane] * yt;
+        }
       }
       if (lane < w) y[jb + lane] = yl;
     }
@@ -1008,44 +1020,68 @@ __device__ void stage_reflectors(const ItemD& it, const double* Wf, int m, int m
   }
 }
 
-}  // namespace
-
-namespace {
-
-// Forward substitution of one cluster: y_s <- U^T G^{-1} y_s, y_n -= F^T y_f.
-// lds: mp (y) + 64*65 (diagonal block) + 16*mp (reflectors) doubles.
-__device__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
-  __shared__ double shd[kWaves];
-  const int m = it.m;
-  if (m == 0) return;
+// y <- H_{k-1} ... H_0 y (forward: H_0 first) or y <- H_0 ... H_{k-1} y
+// (backward: H_{k-1} first) for the k reflectors of the far-field block Wf,
+// y in LDS (m).  Reflectors and their tau pass through LDS (vs, ts) sixteen
+// at a time; wave 0 applies them with y in registers and wave reductions.
+template <int R>
+__device__ void apply_reflectors(const ItemD& it, const double* Wf, int m, int mp, int k, bool fwd,
+                                 double* y, double* vs, double* ts) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  constexpr int R = kMaxClusterDofs / 64;
-  const int k = ls.k[it.s], a = ls.a[it.s];
-  const int mp = ((m + 63) / 64) * 64;
-  double* y = lds;
-  double* blk = lds + mp;
-  double* vs = blk + 64 * kBlkLd;
-  double* yg = vec + it.voff;
-  for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
-  __syncthreads();
-  trsv_lower(it.P, m, m, y, blk);
-  const double* Wf = it.P + (size_t)m * (m + a);
-  for (int j0 = 0; j0 < k; j0 += 16) {
-    const int nj = min(16, k - j0);
-    stage_reflectors(it, Wf, m, mp, j0, nj, vs);
-    __syncthreads();
-    for (int jj = 0; jj < nj; ++jj) {
-      const int j = j0 + jj;
-      const double* v = vs + jj * mp;
-      double s = 0.0;
-      for (int i = j + tid; i < m; i += kThreads) s += v[i] * y[i];
-      s = block_sum(s, shd);
-      const double f = it.tau[j] * s;
-      for (int i = j + tid; i < m; i += kThreads) y[i] -= f * v[i];
-      __syncthreads();
+  const int nt = (m + 63) >> 6;
+  double yr[R];
+  if (wv == 0) {
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = lane + 64 * t;
+      yr[t] = (t < nt && i < m) ? y[i] : 0.0;
     }
   }
-  // y_n -= F^T y_f: one wave per column, four columns in flight
+  const int nchunk = (k + 15) >> 4;
+  for (int q = 0; q < nchunk; ++q) {
+    const int j0 = fwd ? 16 * q : max(0, k - 16 * (q + 1));
+    const int nj = fwd ? min(16, k - j0) : (k - 16 * q) - j0;
+    stage_reflectors(it, Wf, m, mp, j0, nj, vs);
+    for (int jj = tid; jj < nj; jj += kThreads) ts[jj] = it.tau[j0 + jj];
+    __syncthreads();
+    if (wv == 0) {
+      for (int u = 0; u < nj; ++u) {
+        const int jj = fwd ? u : nj - 1 - u;
+        const int j = j0 + jj;
+        const double* v = vs + jj * mp;
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int i = lane + 64 * t;
+          if (t < nt && i >= j && i < m) s += v[i] * yr[t];
+        }
+        s = wave_sum(s);
+        const double f = ts[jj] * s;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int i = lane + 64 * t;
+          if (t < nt && i >= j && i < m) yr[t] -= f * v[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (wv == 0) {
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = lane + 64 * t;
+      if (t < nt && i < m) y[i] = yr[t];
+    }
+  }
+  __syncthreads();
+}
+
+// y_n -= F^T y_f over the columns [c0, c1) of F = C[k:m, :] (C = U^T G^{-1}
+// A_sn, ld m): one wave per column, four columns in flight.  y (m entries)
+// may be in LDS or global memory.
+template <int R>
+__device__ void fwd_near(const ItemD& it, int m, int k, int c0, int c1, const double* y, double* vec) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double yr[R];
 #pragma unroll
   for (int t = 0; t < R; ++t) {
@@ -1053,15 +1089,15 @@ __device__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* ld
     yr[t] = (i >= k && i < m) ? y[i] : 0.0;
   }
   const double* C = it.P + (size_t)m * m;
-  for (int c0 = wv * 4; c0 < a; c0 += kWaves * 4) {
+  for (int cb = c0 + wv * 4; cb < c1; cb += kWaves * 4) {
     double g[4][R];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const double* f = C + (size_t)m * min(c0 + q, a - 1);
+      const double* f = C + (size_t)m * min(cb + q, c1 - 1);
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         const int i = lane + 64 * t;
-        g[q][t] = (c0 + q < a && i >= k && i < m) ? f[i] : 0.0;
+        g[q][t] = (cb + q < c1 && i >= k && i < m) ? f[i] : 0.0;
       }
     }
     double s[4];
@@ -1072,22 +1108,149 @@ __device__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* ld
       for (int t = 0; t < R; ++t) acc += g[q][t] * yr[t];
       s[q] = wave_sum(acc);
     }
-    if (lane < 4 && c0 + lane < a) {
+    if (lane < 4 && cb + lane < c1) {
       double sv = s[0];
 #pragma unroll
       for (int q = 1; q < 4; ++q)
         if (q == lane) sv = s[q];
-      vec[it.vidx[c0 + lane]] -= sv;
+      vec[it.vidx[cb + lane]] -= sv;
     }
   }
+}
+
+}  // namespace
+
+namespace {
+
+// Forward substitution of one cluster: y_s <- U^T G^{-1} y_s, y_n -= F^T y_f.
+// lds: mp (y) + 64*65 (diagonal block) + 16*mp (reflectors) doubles.
+template <int R>
+__device__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
+  const int m = it.m;
+  if (m == 0) return;
+  const int tid = threadIdx.x;
+  const int k = ls.k[it.s], a = ls.a[it.s];
+  const int mp = ((m + 63) / 64) * 64;
+  double* y = lds;
+  double* blk = lds + mp;
+  double* vs = blk + 64 * kBlkLd;
+  double* yg = vec + it.voff;
+  for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
+  __syncthreads();
+  trsv_lower(it.P, m, m, y, blk);
+  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
+  fwd_near<R>(it, m, k, 0, a, y, vec);
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
+  __syncthreads();
+}
+
+// Forward sweep of a split cluster, per-cluster part: y_s <- U^T G^{-1} y_s,
+// written back to the vector (the near-field product follows in units).
+template <int R>
+__device__ void fwd_head(const ItemD& it, LevelState ls, double* vec, double* lds) {
+  const int m = it.m;
+  if (m == 0) return;
+  const int tid = threadIdx.x;
+  const int k = ls.k[it.s], a = ls.a[it.s];
+  const int mp = ((m + 63) / 64) * 64;
+  double* y = lds;
+  double* blk = lds + mp;
+  double* vs = blk + 64 * kBlkLd;
+  double* yg = vec + it.voff;
+  for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
+  __syncthreads();
+  trsv_lower(it.P, m, m, y, blk);
+  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
+  for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
+  __syncthreads();
+}
+
+// Forward sweep of a split cluster, unit `part`: y_n -= F^T y_f over columns
+// [part*kSweepCols, (part+1)*kSweepCols) of F, y_s read from the vector.
+template <int R>
+__device__ void fwd_unit(const ItemD& it, int part, LevelState ls, double* vec) {
+  const int m = it.m;
+  const int k = ls.k[it.s], a = ls.a[it.s];
+  const int c0 = part * kSweepCols;
+  if (m == 0 || c0 >= a) return;
+  fwd_near<R>(it, m, k, c0, min(a, c0 + kSweepCols), vec + it.voff, vec);
+}
+
+// Backward sweep of a split cluster, unit `part`: x_f -= F x_n for the rows
+// [part*kSweepRows, (part+1)*kSweepRows) of F that are fine (>= k).  32 rows x
+// 8 column groups (two per wave): every row sums its columns group by group
+// in a fixed order, then the eight group sums in order.  x_n passes through
+// LDS 1024 columns at a time.  lds: 1024 + 256 doubles.
+__device__ void bwd_unit(const ItemD& it, int part, LevelState ls, double* vec, double* lds) {
+  const int m = it.m;
+  const int k = ls.k[it.s], a = ls.a[it.s];
+  const int r0 = part * kSweepRows;
+  if (m == 0 || a == 0 || r0 >= m || r0 + kSweepRows <= k) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int row = r0 + (lane & 31), g = 2 * wv + (lane >> 5);
+  const bool act = row >= k && row < m;
+  double* xn = lds;
+  double* red = lds + 1024;
+  const double* C = it.P + (size_t)m * m;
+  double s = 0.0;
+  for (int c0 = 0; c0 < a; c0 += 1024) {
+    const int nc = min(1024, a - c0);
+    __syncthreads();
+    for (int c = tid; c < nc; c += kThreads) xn[c] = vec[it.vidx[c0 + c]];
+    __syncthreads();
+    if (act) {
+      const double* Cr = C + row + (size_t)m * c0;
+      for (int cb = g; cb < nc; cb += 8 * 16) {
+        double f[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int c = cb + 8 * q;
+          f[q] = c < nc ? Cr[(size_t)m * c] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int c = cb + 8 * q;
+          if (c < nc) s += f[q] * xn[c];
+        }
+      }
+    }
+  }
+  red[g * 32 + (lane & 31)] = s;
+  __syncthreads();
+  if (tid < 32 && r0 + tid >= k && r0 + tid < m) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t += red[q * 32 + tid];
+    vec[it.voff + r0 + tid] -= t;
+  }
+  __syncthreads();
+}
+
+// Backward sweep of a split cluster, per-cluster part (after its units):
+// x_s <- G^{-T} U x_s.
+template <int R>
+__device__ void bwd_tail(const ItemD& it, LevelState ls, double* vec, double* lds) {
+  const int m = it.m;
+  if (m == 0) return;
+  const int tid = threadIdx.x;
+  const int k = ls.k[it.s], a = ls.a[it.s];
+  const int mp = ((m + 63) / 64) * 64;
+  double* x = lds;
+  double* blk = lds + mp;
+  double* vs = blk + 64 * kBlkLd;
+  double* xg = vec + it.voff;
+  for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
+  __syncthreads();
+  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
+  trsv_lower_t<R>(it.P, m, m, x, blk);
+  for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
 }
 
 // Backward substitution of one cluster: x_f -= F x_n, x_s <- G^{-T} U x_s.
 // lds: mp + 64*65 + 16*mp + 1024 doubles.
+template <int R>
 __device__ void bwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
-  __shared__ double shd[kWaves];
   const int m = it.m;
   if (m == 0) return;
   const int tid = threadIdx.x;
@@ -1119,23 +1282,8 @@ __device__ void bwd_item(const ItemD& it, LevelState ls, double* vec, double* ld
     }
   }
   __syncthreads();
-  const double* Wf = it.P + (size_t)m * (m + a);
-  for (int j1 = k; j1 > 0; j1 -= 16) {
-    const int j0 = max(0, j1 - 16), nj = j1 - j0;
-    stage_reflectors(it, Wf, m, mp, j0, nj, vs);
-    __syncthreads();
-    for (int jj = nj - 1; jj >= 0; --jj) {
-      const int j = j0 + jj;
-      const double* v = vs + jj * mp;
-      double s = 0.0;
-      for (int i = j + tid; i < m; i += kThreads) s += v[i] * x[i];
-      s = block_sum(s, shd);
-      const double f = it.tau[j] * s;
-      for (int i = j + tid; i < m; i += kThreads) x[i] -= f * v[i];
-      __syncthreads();
-    }
-  }
-  trsv_lower_t(it.P, m, m, x, blk);
+  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
+  trsv_lower_t<R>(it.P, m, m, x, blk);
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
 }
@@ -1147,28 +1295,91 @@ size_t sweep_lds(int max_m) {
 
 }  // namespace
 
-__global__ void __launch_bounds__(kThreads) fwd_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                       double* vec) {
-  extern __shared__ double lds[];
-  fwd_item(items[blockIdx.x], ls, vec, lds);
+// Row slots per lane sized to the cluster (the slots beyond m hold zeros and
+// add exact zeros, so the results do not depend on the choice).
+#define LRSP_ROWS_DISPATCH(FN, ...)                      \
+  do {                                                   \
+    if (it.m <= 64) FN<1>(__VA_ARGS__);                  \
+    else if (it.m <= 256) FN<4>(__VA_ARGS__);            \
+    else FN<kMaxClusterDofs / 64>(__VA_ARGS__);          \
+  } while (0)
+
+__device__ __forceinline__ void fwd_any(const ItemD& it, bool split, LevelState ls, double* vec, double* lds) {
+  if (split && it.m >= kSweepSplitM) LRSP_ROWS_DISPATCH(fwd_head, it, ls, vec, lds);
+  else LRSP_ROWS_DISPATCH(fwd_item, it, ls, vec, lds);
 }
 
-__global__ void __launch_bounds__(kThreads) bwd_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                       double* vec) {
-  extern __shared__ double lds[];
-  bwd_item(items[blockIdx.x], ls, vec, lds);
+__device__ __forceinline__ void bwd_any(const ItemD& it, bool split, LevelState ls, double* vec, double* lds) {
+  if (split && it.m >= kSweepSplitM) LRSP_ROWS_DISPATCH(bwd_tail, it, ls, vec, lds);
+  else LRSP_ROWS_DISPATCH(bwd_item, it, ls, vec, lds);
 }
 
+__device__ __forceinline__ void fwd_unit_any(const ItemD& it, int part, LevelState ls, double* vec) {
+  if (it.m >= kSweepSplitM) LRSP_ROWS_DISPATCH(fwd_unit, it, part, ls, vec);
+}
+
+// Items of one colour; with split (a level holding clusters of at least
+// kSweepSplitM DoFs) those clusters only do their per-cluster part here.
+__global__ void __launch_bounds__(kThreads) fwd_kernel(const ItemD* __restrict__ items, int nitems,
+                                                       LevelState ls, double* vec, int split) {
+  extern __shared__ double lds[];
+  for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const ItemD& it = items[i];
+    fwd_any(it, split != 0, ls, vec, lds);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) bwd_kernel(const ItemD* __restrict__ items, int nitems,
+                                                       LevelState ls, double* vec, int split) {
+  extern __shared__ double lds[];
+  for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const ItemD& it = items[i];
+    bwd_any(it, split != 0, ls, vec, lds);
+  }
+}
+
+// Units of the split clusters of one colour: upi units per item.
+__global__ void __launch_bounds__(kThreads) fwd_units_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                             double* vec, int upi) {
+  const ItemD& it = items[blockIdx.x / upi];
+  fwd_unit_any(it, blockIdx.x % upi, ls, vec);
+}
+
+__global__ void __launch_bounds__(kThreads) bwd_units_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                             double* vec, int upi) {
+  extern __shared__ double lds[];
+  const ItemD& it = items[blockIdx.x / upi];
+  if (it.m >= kSweepSplitM) bwd_unit(it, blockIdx.x % upi, ls, vec, lds);
+}
+
+template <bool SW>
+__device__ __forceinline__ void level_sync(GridBar* bar) {
+  if constexpr (SW) sw_grid_sync(bar, gridDim.x);
+  else cooperative_groups::this_grid().sync();
+}
+
+// One launch per level and sweep direction; upi > 0: units per item of the
+// split clusters (an extra grid barrier per colour).
 template <bool SW>
 __global__ void __launch_bounds__(kThreads) fwd_level_kernel(const ItemD* __restrict__ items,
                                                              const int32_t* __restrict__ cstart,
                                                              int ncolours, LevelState ls, double* vec,
-                                                             GridBar* bar) {
+                                                             GridBar* bar, int upi) {
   extern __shared__ double lds[];
   for (int c = 0; c < ncolours; ++c) {
-    for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) fwd_item(items[i], ls, vec, lds);
-    if constexpr (SW) sw_grid_sync(bar, gridDim.x);
-    else cooperative_groups::this_grid().sync();
+    for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) {
+      const ItemD& it = items[i];
+      fwd_any(it, upi > 0, ls, vec, lds);
+    }
+    level_sync<SW>(bar);
+    if (upi > 0) {
+      const int n = (cstart[c + 1] - cstart[c]) * upi;
+      for (int u = blockIdx.x; u < n; u += gridDim.x) {
+        const ItemD& it = items[cstart[c] + u / upi];
+        fwd_unit_any(it, u % upi, ls, vec);
+      }
+      level_sync<SW>(bar);
+    }
   }
 }
 
@@ -1176,12 +1387,22 @@ template <bool SW>
 __global__ void __launch_bounds__(kThreads) bwd_level_kernel(const ItemD* __restrict__ items,
                                                              const int32_t* __restrict__ cstart,
                                                              int ncolours, LevelState ls, double* vec,
-                                                             GridBar* bar) {
+                                                             GridBar* bar, int upi) {
   extern __shared__ double lds[];
   for (int c = ncolours - 1; c >= 0; --c) {
-    for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) bwd_item(items[i], ls, vec, lds);
-    if constexpr (SW) sw_grid_sync(bar, gridDim.x);
-    else cooperative_groups::this_grid().sync();
+    if (upi > 0) {
+      const int n = (cstart[c + 1] - cstart[c]) * upi;
+      for (int u = blockIdx.x; u < n; u += gridDim.x) {
+        const ItemD& it = items[cstart[c] + u / upi];
+        if (it.m >= kSweepSplitM) bwd_unit(it, u % upi, ls, vec, lds);
+      }
+      level_sync<SW>(bar);
+    }
+    for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) {
+      const ItemD& it = items[i];
+      bwd_any(it, upi > 0, ls, vec, lds);
+    }
+    level_sync<SW>(bar);
   }
 }
 
@@ -1196,41 +1417,59 @@ static void allow_sweep_lds() {
   allow_lds(reinterpret_cast<const void*>(bwd_level_kernel<true>), &done[5]);
 }
 
-void launch_fwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
-                hipStream_t st) {
-  if (nitems <= 0) return;
-  allow_sweep_lds();
-  hipLaunchKernelGGL(fwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, ls, vec);
+int sweep_units(bool forward, int max_m, int max_acap) {
+  if (max_m < kSweepSplitM) return 0;
+  return forward ? std::max(1, (max_acap + kSweepCols - 1) / kSweepCols)
+                 : (max_m + kSweepRows - 1) / kSweepRows;
 }
 
-void launch_bwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
+void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
                 hipStream_t st) {
   if (nitems <= 0) return;
   allow_sweep_lds();
-  hipLaunchKernelGGL(bwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, ls, vec);
+  const int upi = sweep_units(true, max_m, max_acap);
+  hipLaunchKernelGGL(fwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, nitems, ls, vec,
+                     upi > 0 ? 1 : 0);
+  if (upi > 0)
+    hipLaunchKernelGGL(fwd_units_kernel, dim3(nitems * upi), dim3(kThreads), 0, st, items, ls, vec, upi);
+}
+
+void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
+                hipStream_t st) {
+  if (nitems <= 0) return;
+  allow_sweep_lds();
+  const int upi = sweep_units(false, max_m, max_acap);
+  if (upi > 0)
+    hipLaunchKernelGGL(bwd_units_kernel, dim3(nitems * upi), dim3(kThreads), (1024 + 256) * sizeof(double), st,
+                       items, ls, vec, upi);
+  hipLaunchKernelGGL(bwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, nitems, ls, vec,
+                     upi > 0 ? 1 : 0);
 }
 
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
-                              int max_items, int max_m, LevelState ls, double* vec, hipStream_t st,
-                              int grid_cap, GridBar* bar) {
+                              int max_items, int max_m, int max_acap, LevelState ls, double* vec,
+                              hipStream_t st, int grid_cap, GridBar* bar) {
   allow_sweep_lds();
   const size_t lds = sweep_lds(max_m);
+  int upi = sweep_units(forward, max_m, max_acap);
+  const int want = std::max(max_items, max_items * upi);
   if (bar) {
-    int g = std::max(1, std::min(max_items, device_cus()));
+    int g = std::max(1, std::min(want, device_cus()));
     if (grid_cap > 0) g = std::min(g, grid_cap);
     if (forward)
       hipLaunchKernelGGL(fwd_level_kernel<true>, dim3(g), dim3(kThreads), lds, st, items, cstart, ncolours,
-                         ls, vec, bar);
+                         ls, vec, bar, upi);
     else
       hipLaunchKernelGGL(bwd_level_kernel<true>, dim3(g), dim3(kThreads), lds, st, items, cstart, ncolours,
-                         ls, vec, bar);
+                         ls, vec, bar, upi);
     return hipGetLastError();
   }
   const void* fn = forward ? reinterpret_cast<const void*>(fwd_level_kernel<false>)
                            : reinterpret_cast<const void*>(bwd_level_kernel<false>);
-  const int g = coop_grid(fn, lds, max_items, grid_cap);
+  const int g = coop_grid(fn, lds, want, grid_cap);
   GridBar* none = nullptr;
-  void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&vec, (void*)&none};
+  void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&vec, (void*)&none,
+                  (void*)&upi};
   return hipLaunchCooperativeKernel(fn, dim3(g), dim3(kThreads), args, lds, st);
 }
 
@@ -1241,7 +1480,7 @@ __global__ void __launch_bounds__(kThreads) top_solve_kernel(const double* L, in
   for (int i = threadIdx.x; i < n; i += kThreads) y[i] = yg[i];
   __syncthreads();
   trsv_lower(L, n, n, y, blk);
-  trsv_lower_t(L, n, n, y, blk);
+  trsv_lower_t<kMaxClusterDofs / 64>(L, n, n, y, blk);
   for (int i = threadIdx.x; i < n; i += kThreads) yg[i] = y[i];
 }
 
@@ -1286,7 +1525,7 @@ __global__ void __launch_bounds__(kThreads) top_solve_batched_kernel(const TopD*
   for (int i = threadIdx.x; i < n; i += kThreads) y[i] = yg[i];
   __syncthreads();
   trsv_lower(t.L, n, n, y, blk);
-  trsv_lower_t(t.L, n, n, y, blk);
+  trsv_lower_t<kMaxClusterDofs / 64>(t.L, n, n, y, blk);
   for (int i = threadIdx.x; i < n; i += kThreads) yg[i] = y[i];
 }
 

@@ -51,14 +51,22 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
 // Dense Cholesky of the top system (lower, in place).
 void launch_top_potrf(double* A, int n, int32_t* err, hipStream_t st);
 
-// Substitution sweeps over the items of one colour.
-void launch_fwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
+// Substitution sweeps.  Clusters of at least kSweepSplitM DoFs spread their
+// near-field products over units of kSweepCols columns (forward) or
+// kSweepRows rows (backward); max_acap bounds the near-field width.
+constexpr int kSweepSplitM = 128;
+constexpr int kSweepCols = 64;
+constexpr int kSweepRows = 32;
+int sweep_units(bool forward, int max_m, int max_acap);
+// The items of one colour (one launch, plus one for the units).
+void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
                 hipStream_t st);
-void launch_bwd(const ItemD* items, int nitems, int max_m, LevelState ls, double* vec,
+void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
                 hipStream_t st);
+// A whole level in one persistent launch.
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
-                              int max_items, int max_m, LevelState ls, double* vec, hipStream_t st,
-                              int grid_cap = 0, GridBar* bar = nullptr);
+                              int max_items, int max_m, int max_acap, LevelState ls, double* vec,
+                              hipStream_t st, int grid_cap = 0, GridBar* bar = nullptr);
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st);
 // Dense tops of a batch, one workgroup per system (n <= kMaxClusterDofs).
 void launch_top_potrf_batched(const TopD* tops, int ntops, int max_n, hipStream_t st);

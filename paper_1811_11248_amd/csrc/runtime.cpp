@@ -356,6 +356,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
   L->cdims.assign(p.ncolours, SplitDims{0, 0, 0, 0});
   L->max_items = 0;
   L->max_nseg = 0;
+  L->max_acap = 0;
   for (int c = 0; c < p.ncolours; ++c) {
     L->max_items = std::max(L->max_items, p.cstart[c + 1] - p.cstart[c]);
     SplitDims& d = L->cdims[c];
@@ -367,6 +368,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
       d.max_acap = std::max(d.max_acap, p.acap[it.s - sbase]);
     }
     L->max_nseg = std::max(L->max_nseg, d.max_nseg);
+    L->max_acap = std::max(L->max_acap, d.max_acap);
   }
   // hipMemcpyAsync from pageable memory may return before the copy is done
   HIPCHK(hipStreamSynchronize(st));

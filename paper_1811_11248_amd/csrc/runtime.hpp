@@ -104,6 +104,7 @@ struct LevelDev {
   std::vector<double> sweep_bytes;  // per colour: bytes one sweep of it moves
   std::vector<SplitDims> cdims;     // per colour capacities
   int max_items = 0;                // largest colour
+  int max_acap = 0;                 // widest near field (capacity)
   int max_nseg = 0;
   bool split = false;               // several workgroups per cluster
   const int32_t* d_cstart = nullptr;
