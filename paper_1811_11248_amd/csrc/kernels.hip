@@ -48,7 +48,7 @@ __device__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* 
 #pragma unroll
       for (int u = 0; u < kNB; ++u) {
         if (u < w) {
-          double d = __shfl(row[u], u, 64);
+          double d = readlane_d(row[u], u);
           if (!(d > 0.0)) {
             if (tid == 0) *bad = 1;
             d = 1.0;
@@ -58,7 +58,7 @@ __device__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* 
           else if (tid > u) row[u] = row[u] / d;
 #pragma unroll
           for (int v = u + 1; v < kNB; ++v) {
-            double lvu = __shfl(row[u], v, 64);
+            const double lvu = readlane_d(row[u], v);
             if (v < w && tid >= v && tid < w) row[v] -= row[u] * lvu;
           }
         }
@@ -552,6 +552,156 @@ __device__ void schur_scatter(const ItemD& it, const double* C, int ld, int m, i
   }
 }
 
+// Staged form of schur_scatter for small panels: F (rows k..m-1 of the a
+// columns), the segment and natural index of every column and the pair table
+// of the near segments pass through the LDS scratch (scr doubles at lds) in
+// one element-parallel copy; each thread then forms its 4x4 tile from LDS
+// (same products in the same order as the global form) and resolves its
+// targets eight at a time, their posmap loads, old values and stores each
+// issued together.  Returns false, doing nothing, when the staging does not fit.
+__device__ bool schur_scatter_staged(const ItemD& it, const double* C, int ld, int m, int k, int a, int prec,
+                                     int32_t* err, int level, double* lds, size_t scr) {
+  const int tid = threadIdx.x;
+  const int nf = m - k;
+  const int nsn = it.nsegn;
+  const int np = nsn * (nsn + 1) / 2;
+  constexpr int kPairD = (int)(sizeof(PairD) / sizeof(double));
+  static_assert(sizeof(PairD) % sizeof(double) == 0, "PairD is staged as doubles");
+  const size_t need = (size_t)nf * a + (size_t)a + (size_t)kPairD * np + 1;
+  if (need > scr) return false;
+  double* Fs = lds;                                               // nf x a, ld nf
+  int32_t* cs = reinterpret_cast<int32_t*>(Fs + (size_t)nf * a);  // a
+  int32_t* cn = cs + a;                                           // a
+  PairD* ps = reinterpret_cast<PairD*>(Fs + (size_t)nf * a + a);  // np
+  double* dummy = reinterpret_cast<double*>(ps + np);
+  {
+    const int nF = nf * a;
+    for (int e0 = tid; e0 < nF; e0 += kThreads * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        const int c = e / max(nf, 1), r = e - c * nf;
+        v[u] = e < nF ? C[(size_t)(k + r) + (size_t)ld * c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < nF) Fs[e] = v[u];
+      }
+    }
+    for (int c = tid; c < a; c += kThreads) {
+      cs[c] = it.colseg[c];
+      cn[c] = it.colnat[c];
+    }
+    const double* src = reinterpret_cast<const double*>(it.pair);
+    double* dst = reinterpret_cast<double*>(ps);
+    for (int e = tid; e < kPairD * np; e += kThreads) dst[e] = src[e];
+    if (tid == 0) *dummy = 0.0;
+  }
+  __syncthreads();
+  const int nt = (a + 3) >> 2;
+  const int ntiles = nt * (nt + 1) / 2;
+  for (int idx = tid; idx < ntiles; idx += kThreads) {
+    int R, Cc;
+    tri_tile(idx, nt, R, Cc);
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
+    if (prec == 0) {
+      for (int i = 0; i < nf; ++i) {
+        double fr[4], fc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fr[r] = (4 * R + r < a) ? Fs[i + (size_t)nf * (4 * R + r)] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fc[q] = (4 * Cc + q < a) ? Fs[i + (size_t)nf * (4 * Cc + q)] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[r][q] += fr[r] * fc[q];
+      }
+    } else {
+      float accf[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) accf[r][q] = 0.0f;
+      for (int i = 0; i < nf; ++i) {
+        float fr[4], fc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float t = (4 * R + r < a) ? (float)Fs[i + (size_t)nf * (4 * R + r)] : 0.0f;
+          fr[r] = prec == 2 ? round_bf16(t) : t;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float t = (4 * Cc + q < a) ? (float)Fs[i + (size_t)nf * (4 * Cc + q)] : 0.0f;
+          fc[q] = prec == 2 ? round_bf16(t) : t;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) accf[r][q] = fmaf(fr[r], fc[q], accf[r][q]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] = (double)accf[r][q];
+    }
+    // targets, eight at a time: pair and row from LDS, column through the
+    // pair's posmap
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int pi[8], row[8], cidx[8];
+      bool ok[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int rr = 4 * R + 2 * h + (e >> 2), cc = 4 * Cc + (e & 3);
+        ok[e] = rr < a && cc < a && cc <= rr;
+        const int rs = ok[e] ? rr : 0, csn = ok[e] ? cc : 0;
+        const int sr = cs[rs], sc = cs[csn], nr = cn[rs], ncn = cn[csn];
+        const int i = min(sr, sc), j = max(sr, sc);
+        pi[e] = j * (j + 1) / 2 + i;
+        const bool diag = ps[pi[e]].diag != 0;
+        const bool r_is_rowseg = (sr == (ps[pi[e]].rows_from_j ? j : i));
+        row[e] = diag ? max(nr, ncn) : (r_is_rowseg ? nr : ncn);
+        cidx[e] = diag ? min(nr, ncn) : (r_is_rowseg ? ncn : nr);
+      }
+      int col[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int32_t* pm = ps[pi[e]].diag ? nullptr : ps[pi[e]].posmap;
+        col[e] = *(pm ? pm + cidx[e] : it.colnat);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int32_t* pm = ps[pi[e]].diag ? nullptr : ps[pi[e]].posmap;
+        if (!pm) col[e] = cidx[e];
+      }
+      double* t[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const PairD& pd = ps[pi[e]];
+        t[e] = nullptr;
+        if (ok[e]) {
+          if (row[e] < 0 || col[e] < 0 || row[e] >= pd.nrows || col[e] >= pd.ncols) item_error(it, err, level, kErrIndex);
+          else t[e] = pd.dst + (size_t)row[e] + (size_t)pd.ld * col[e];
+        }
+      }
+      double old[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) old[e] = *(t[e] ? t[e] : dummy);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (t[e]) *t[e] = old[e] - acc[2 * h + (e >> 2)][e & 3];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
 // Widths of the column segments (coarse ones are earlier ranks), their
 // exclusive prefix sum into soff[0..nseg] (LDS) and it.segoff, and the near
 // and far widths.  Returns false (after recording the error) when a width
@@ -730,7 +880,9 @@ __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol,
   if (k > 0) apply_qt_cols(C, m, m, a, Wf, it.piv, it.tau, k, lds, (size_t)m * kNB + kNB * kNB + kNB * 256);
   __syncthreads();
   // G_s: eliminate the fine DoFs, X_nn -= F^T F
-  if (m > k && a > 0) schur_scatter(it, C, m, m, k, a, prec, ls.err, level);
+  if (m > k && a > 0 &&
+      !schur_scatter_staged(it, C, m, m, k, a, prec, ls.err, level, lds, (size_t)m * kNB + kNB * kNB + kNB * 256))
+    schur_scatter(it, C, m, m, k, a, prec, ls.err, level);
   // coarse row of s: [I_k | C[:k] | V1^T]
   for (int e = tid; e < k * (a + b); e += kThreads) {
     const int r = e % k, pc = e / k;
@@ -1295,23 +1447,188 @@ size_t sweep_lds(int max_m) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Sweeps of small clusters (m <= kSweepWaveM) by one wave each: lane i holds
+// entry i of the cluster's vector, solved entries are broadcast with
+// readlane, the near-field products run one lane per column (forward) or
+// per row (backward).  MB >= m bounds the row slots kept in registers.
+
+// y_s <- U^T G^{-1} y_s; y_n -= F^T y_f.
+template <int MB>
+__device__ void fwd_wave(const ItemD& it, LevelState ls, double* vec) {
+  const int lane = threadIdx.x & 63;
+  const int m = it.m;
+  if (m == 0) return;
+  const int k = ls.k[it.s], a = ls.a[it.s];
+  const bool on = lane < m;
+  const double* G = it.P;
+  double g[MB];  // row `lane` of G, columns < lane
+#pragma unroll
+  for (int j = 0; j < MB; ++j) g[j] = (on && j < lane) ? G[lane + (size_t)m * j] : 0.0;
+  const double rd = 1.0 / (on ? G[lane + (size_t)m * lane] : 1.0);
+  const int pv = lane < k ? it.piv[lane] : 0;
+  const double tv = lane < k ? it.tau[lane] : 0.0;
+  double* yg = vec + it.voff;
+  double y = on ? yg[lane] : 0.0;
+  // G^{-1}
+#pragma unroll
+  for (int j = 0; j < MB; ++j) {
+    if (j < m) {
+      const double yj = readlane_d(y, j) * readlane_d(rd, j);
+      if (lane == j) y = yj;
+      else y -= g[j] * yj;
+    }
+  }
+  // U^T: reflectors 0..k-1
+  const double* Wf = it.P + (size_t)m * (m + a);
+  for (int j = 0; j < k; ++j) {
+    const int pj = __builtin_amdgcn_readlane(pv, j);
+    const double v = lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0);
+    const double sj = wave_sum(v * y);
+    y -= (readlane_d(tv, j) * sj) * v;
+  }
+  if (on) yg[lane] = y;
+  // y_n -= F^T y_f, F = C[k:m, :], one lane per column
+  const double* C = it.P + (size_t)m * m;
+  for (int c0 = 0; c0 < a; c0 += 64) {
+    const int c = c0 + lane;
+    const bool cv = c < a;
+    const double* Cc = C + (size_t)m * (cv ? c : 0);
+    double s = 0.0;
+    for (int i0 = 0; i0 < m; i0 += 16) {
+      double f[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int i = i0 + u;
+        f[u] = (cv && i >= k && i < m) ? Cc[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int i = i0 + u;
+        const double yi = readlane_d(y, min(i, 63));
+        if (cv && i >= k && i < m) s += f[u] * yi;
+      }
+    }
+    if (cv) vec[it.vidx[c]] -= s;
+  }
+}
+
+// x_f -= F x_n; x_s <- G^{-T} U x_s.
+template <int MB>
+__device__ void bwd_wave(const ItemD& it, LevelState ls, double* vec) {
+  const int lane = threadIdx.x & 63;
+  const int m = it.m;
+  if (m == 0) return;
+  const int k = ls.k[it.s], a = ls.a[it.s];
+  const bool on = lane < m;
+  const double* G = it.P;
+  const double rd = 1.0 / (on ? G[lane + (size_t)m * lane] : 1.0);
+  const int pv = lane < k ? it.piv[lane] : 0;
+  const double tv = lane < k ? it.tau[lane] : 0.0;
+  double* xg = vec + it.voff;
+  double x = on ? xg[lane] : 0.0;
+  // x_f -= F x_n, one lane per row, columns in order
+  const double* C = it.P + (size_t)m * m;
+  const bool fine = on && lane >= k;
+  double s = 0.0;
+  for (int c0 = 0; c0 < a; c0 += 64) {
+    const int nc = min(64, a - c0);
+    const double xn = lane < nc ? vec[it.vidx[c0 + lane]] : 0.0;
+    const double* Cr = C + (size_t)(fine ? lane : 0) + (size_t)m * c0;
+    for (int cb = 0; cb < nc; cb += 16) {
+      double f[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) f[q] = (fine && cb + q < nc) ? Cr[(size_t)m * (cb + q)] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double xq = readlane_d(xn, min(cb + q, 63));
+        if (cb + q < nc) s += f[q] * xq;
+      }
+    }
+  }
+  if (fine) x -= s;
+  // U: reflectors k-1..0
+  const double* Wf = it.P + (size_t)m * (m + a);
+  for (int j = k - 1; j >= 0; --j) {
+    const int pj = __builtin_amdgcn_readlane(pv, j);
+    const double v = lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0);
+    const double sj = wave_sum(v * x);
+    x -= (readlane_d(tv, j) * sj) * v;
+  }
+  // G^{-T}
+  double gc[MB];  // column `lane` of G, rows > lane
+#pragma unroll
+  for (int j = 0; j < MB; ++j) gc[j] = (on && j > lane && j < m) ? G[j + (size_t)m * lane] : 0.0;
+#pragma unroll
+  for (int j = MB - 1; j >= 0; --j) {
+    if (j < m) {
+      const double xj = readlane_d(x, j) * readlane_d(rd, j);
+      if (lane == j) x = xj;
+      else x -= gc[j] * xj;
+    }
+  }
+  if (on) xg[lane] = x;
+}
+
+#define LRSP_WAVE_DISPATCH(FN, ...)         \
+  do {                                      \
+    if (it.m <= 16) FN<16>(__VA_ARGS__);    \
+    else if (it.m <= 32) FN<32>(__VA_ARGS__); \
+    else FN<64>(__VA_ARGS__);               \
+  } while (0)
+
+// One launch per level and sweep direction for levels whose clusters all
+// have at most kSweepWaveM DoFs: every wave takes a cluster of the colour;
+// one workgroup needs no grid barrier between colours.
+template <bool FWD, bool SW>
+__global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const ItemD* __restrict__ items,
+                                                                       const int32_t* __restrict__ cstart,
+                                                                       int ncolours, LevelState ls,
+                                                                       double* vec, GridBar* bar) {
+  const int wv = threadIdx.x >> 6, nw = kSweepWaveThreads / 64;
+  for (int q = 0; q < ncolours; ++q) {
+    const int c = FWD ? q : ncolours - 1 - q;
+    for (int i = cstart[c] + blockIdx.x * nw + wv; i < cstart[c + 1]; i += gridDim.x * nw) {
+      const ItemD& it = items[i];
+      if (FWD) LRSP_WAVE_DISPATCH(fwd_wave, it, ls, vec);
+      else LRSP_WAVE_DISPATCH(bwd_wave, it, ls, vec);
+    }
+    if (gridDim.x == 1) __syncthreads();
+    else if constexpr (SW) sw_grid_sync(bar, gridDim.x);
+    else cooperative_groups::this_grid().sync();
+  }
+}
+
 // Row slots per lane sized to the cluster (the slots beyond m hold zeros and
 // add exact zeros, so the results do not depend on the choice).
 #define LRSP_ROWS_DISPATCH(FN, ...)                      \
   do {                                                   \
-    if (it.m <= 64) FN<1>(__VA_ARGS__);                  \
-    else if (it.m <= 256) FN<4>(__VA_ARGS__);            \
+    if (it.m <= 256) FN<4>(__VA_ARGS__);                 \
     else FN<kMaxClusterDofs / 64>(__VA_ARGS__);          \
   } while (0)
 
+// Clusters of at most kSweepWaveM DoFs run the wave form in wave 0 whatever
+// the schedule, so that every schedule gives the same bits.
 __device__ __forceinline__ void fwd_any(const ItemD& it, bool split, LevelState ls, double* vec, double* lds) {
-  if (split && it.m >= kSweepSplitM) LRSP_ROWS_DISPATCH(fwd_head, it, ls, vec, lds);
-  else LRSP_ROWS_DISPATCH(fwd_item, it, ls, vec, lds);
+  if (it.m <= kSweepWaveM) {
+    if (threadIdx.x < 64) LRSP_WAVE_DISPATCH(fwd_wave, it, ls, vec);
+    __syncthreads();
+  } else if (split && it.m >= kSweepSplitM) {
+    LRSP_ROWS_DISPATCH(fwd_head, it, ls, vec, lds);
+  } else {
+    LRSP_ROWS_DISPATCH(fwd_item, it, ls, vec, lds);
+  }
 }
 
 __device__ __forceinline__ void bwd_any(const ItemD& it, bool split, LevelState ls, double* vec, double* lds) {
-  if (split && it.m >= kSweepSplitM) LRSP_ROWS_DISPATCH(bwd_tail, it, ls, vec, lds);
-  else LRSP_ROWS_DISPATCH(bwd_item, it, ls, vec, lds);
+  if (it.m <= kSweepWaveM) {
+    if (threadIdx.x < 64) LRSP_WAVE_DISPATCH(bwd_wave, it, ls, vec);
+    __syncthreads();
+  } else if (split && it.m >= kSweepSplitM) {
+    LRSP_ROWS_DISPATCH(bwd_tail, it, ls, vec, lds);
+  } else {
+    LRSP_ROWS_DISPATCH(bwd_item, it, ls, vec, lds);
+  }
 }
 
 __device__ __forceinline__ void fwd_unit_any(const ItemD& it, int part, LevelState ls, double* vec) {
@@ -1449,6 +1766,27 @@ void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelSt
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
                               int max_items, int max_m, int max_acap, LevelState ls, double* vec,
                               hipStream_t st, int grid_cap, GridBar* bar) {
+  if (max_m <= kSweepWaveM) {
+    constexpr int nw = kSweepWaveThreads / 64;
+    int want = std::max(1, (max_items + nw - 1) / nw);
+    if (grid_cap > 0) want = std::min(want, grid_cap);
+    if (want == 1 || bar) {
+      const int g = std::min(want, device_cus());
+      if (forward)
+        hipLaunchKernelGGL((sweep_wave_kernel<true, true>), dim3(g), dim3(kSweepWaveThreads), 0, st, items, cstart,
+                           ncolours, ls, vec, bar);
+      else
+        hipLaunchKernelGGL((sweep_wave_kernel<false, true>), dim3(g), dim3(kSweepWaveThreads), 0, st, items,
+                           cstart, ncolours, ls, vec, bar);
+      return hipGetLastError();
+    }
+    const void* fn = forward ? reinterpret_cast<const void*>(sweep_wave_kernel<true, false>)
+                             : reinterpret_cast<const void*>(sweep_wave_kernel<false, false>);
+    const int g = coop_grid(fn, 0, want, grid_cap);
+    GridBar* none = nullptr;
+    void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&vec, (void*)&none};
+    return hipLaunchCooperativeKernel(fn, dim3(g), dim3(kSweepWaveThreads), args, 0, st);
+  }
   allow_sweep_lds();
   const size_t lds = sweep_lds(max_m);
   int upi = sweep_units(forward, max_m, max_acap);

@@ -57,6 +57,10 @@ void launch_top_potrf(double* A, int n, int32_t* err, hipStream_t st);
 constexpr int kSweepSplitM = 128;
 constexpr int kSweepCols = 64;
 constexpr int kSweepRows = 32;
+// Clusters of at most kSweepWaveM DoFs are swept by one wave; levels of such
+// clusters run in workgroups of kSweepWaveThreads threads.
+constexpr int kSweepWaveM = 64;
+constexpr int kSweepWaveThreads = 512;
 int sweep_units(bool forward, int max_m, int max_acap);
 // The items of one colour (one launch, plus one for the units).
 void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,

@@ -155,7 +155,7 @@ __device__ void potrf_wg(double* A, int ld, int m, double* lds, int* bad) {
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         if (u < w) {
-          double d = __shfl(row[u], u, 64);
+          double d = readlane_d(row[u], u);
           if (!(d > 0.0)) {
             if (lane == 0) *bad = 1;
             d = 1.0;
@@ -165,7 +165,7 @@ __device__ void potrf_wg(double* A, int ld, int m, double* lds, int* bad) {
           else if (lane > u) row[u] = row[u] / d;
 #pragma unroll
           for (int v = u + 1; v < NB; ++v) {
-            const double lvu = __shfl(row[u], v, 64);
+            const double lvu = readlane_d(row[u], v);
             if (v < w && lane >= v && lane < w) row[v] -= row[u] * lvu;
           }
         }
