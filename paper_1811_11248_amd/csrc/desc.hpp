@@ -23,6 +23,7 @@ namespace lrsp {
 constexpr int kThreads = 256;       // threads of a cluster workgroup
 constexpr int kNB = 16;             // panel width of the blocked Cholesky
 constexpr int kMaxClusterDofs = 768;
+constexpr int kInvMaxDofs = 256;    // clusters whose G^{-1} is formed explicitly
 
 // One column segment of the block row of the cluster being processed.
 struct SegD {
@@ -70,6 +71,7 @@ struct ItemD {
   const WbD* wb;
   double* D;        // m x m
   double* P;        // m x (m + pcap)
+  double* Gi;       // m x m, G^{-1} (lower) for m <= kInvMaxDofs, else null
   int32_t* colseg;  // [pcap] segment of each panel column
   int32_t* colnat;  // [pcap] natural index of each panel column
   int64_t* vidx;    // [pcap] level-vector index of each near-field column

@@ -194,7 +194,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
   // factor arenas
   int64_t fd = 0, fi = 0, fv = 0;
   std::vector<int64_t> poff(M), toff(M), noff(M), csoff(M), cnoff(M), stoff(M), pvoff(M),
-      sgoff(M), vxoff(M);
+      sgoff(M), vxoff(M), gioff(M, -1);
   auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
   for (int s = 0; s < M; ++s) {
     const int64_t pc = p.acap[s] + p.bcap[s];
@@ -202,6 +202,10 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     poff[s] = fd; fd += al((int64_t)p.m[s] * (p.m[s] + pc));
     toff[s] = fd; fd += al(p.kcap[s]);
     noff[s] = fd; fd += al(pc);
+    if (p.m[s] > 0 && p.m[s] <= kInvMaxDofs) {
+      gioff[s] = fd;
+      fd += al((int64_t)p.m[s] * p.m[s]);
+    }
     csoff[s] = fi; fi += al(pc);
     cnoff[s] = fi; fi += al(pc);
     stoff[s] = fi; fi += al(pc);
@@ -333,6 +337,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     it.wb = reinterpret_cast<const WbD*>(db + o2) + wb0[s];
     it.D = W + p.d_off[s];
     it.P = F + poff[s];
+    it.Gi = gioff[s] >= 0 ? F + gioff[s] : nullptr;
     it.tau = F + toff[s];
     it.norms = F + noff[s];
     it.colseg = FI + csoff[s];

@@ -4,8 +4,10 @@
 //
 //   seg_offsets  segment widths -> panel column offsets, column metadata
 //   gather       [A_ss | A_sn | A_sw] -> panel P (several wgs per cluster)
-//   potrf        A_ss = G G^T, one 512-thread wg per cluster
-//   trsm         G^{-1}[A_sn | A_sw] by column chunks, MFMA f64 updates;
+//   potrf        A_ss = G G^T, one 512-thread wg per cluster; up to
+//                kInvMaxDofs DoFs also G^{-1}, the matrix held in registers
+//   trsm         G^{-1}[A_sn | A_sw] by column chunks: products with G^{-1}
+//                on MFMA (up to kInvMaxDofs DoFs), else blocked solves;
 //                also the squared norms of the far-field columns
 //   cpqr         column-pivoted QR of the scaled far field (one wg)
 //   applyq       C = U^T G^{-1} A_sn by column chunks
@@ -251,6 +253,334 @@ __global__ void __launch_bounds__(512) potrf_kernel(const ItemD* __restrict__ it
   potrf_wg<512>(it.P, m, m, lds, &sbad);
   __syncthreads();
   if (sbad && threadIdx.x == 0) item_error(it, ls.err, level, kErrNotSPD);
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky factor G and explicit inverse G^{-1} of the diagonal block of a
+// cluster of at most kInvMaxDofs DoFs by one workgroup of 1024 threads, the
+// matrix resident in registers: 16x16 tiles in the accumulator layout of
+// v_mfma_f64_16x16x4 (lane l, slot v: row 4v + l/16, column l%16).  Tile rows
+// r and 15 - r (17 tiles) belong to waves r and r + 8, which take the even
+// and the odd tiles of the pair.  Padding beyond m is the identity.
+//   G: right-looking by tile columns p.  The diagonal tile is factored by
+//   wave 0 (readlane broadcasts), the tiles below it are solved row by row
+//   through LDS, the trailing tiles are updated on MFMA.
+//   G^{-1}: forward substitution G X = I by tile rows p.  X_pp = G_pp^{-1},
+//   X_pj = G_pp^{-1} acc_pj; then acc_ij -= G_ip X_pj for the rows i > p
+//   (acc_ij starts at zero, the identity having no entries below the
+//   diagonal).
+// G goes to the diagonal block of the panel (lower triangle), G^{-1} to Gi
+// (lower tiles, zeros above the diagonal inside the diagonal tiles).
+constexpr int kInvLdP = 17;           // row stride of the LDS tiles
+constexpr int kInvLdX = 16 * 16 + 1;  // row stride of the X row-block buffer
+constexpr int kInvSlots = 9;          // tiles per wave
+constexpr size_t kInvLds = (size_t)(256 * kInvLdP + 2 * 16 * kInvLdP + 16 * kInvLdX + 16) * sizeof(double);
+
+// Tile (r, c) of slot j of wave w; false when the slot is unused.
+__device__ __forceinline__ bool inv_slot(int w, int j, int& r, int& c) {
+  const int pr = w & 7, g = 2 * j + (w >> 3);
+  if (g <= pr) {
+    r = pr;
+    c = g;
+  } else {
+    r = 15 - pr;
+    c = g - pr - 1;
+  }
+  return g < 17;
+}
+
+__global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                        int level) {
+  extern __shared__ double lds[];
+  double* Pc = lds;                  // 256 x kInvLdP: tile column p
+  double* Dd = Pc + 256 * kInvLdP;   // 16 x kInvLdP: diagonal tile
+  double* Di = Dd + 16 * kInvLdP;    // 16 x kInvLdP: its inverse
+  double* Xr = Di + 16 * kInvLdP;    // 16 x kInvLdX: tile row p of X
+  double* rd = Xr + 16 * kInvLdX;    // 16: reciprocals of the diagonal
+  __shared__ int sbad;
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  if (m == 0) return;
+  if (m > kInvMaxDofs || !it.Gi) {
+    if (threadIdx.x == 0) item_error(it, ls.err, level, kErrTooLarge);
+    return;
+  }
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // tile coordinates in scalar registers
+  const int lr = lane >> 4, lc = lane & 15;
+  const int nt = (m + 15) >> 4;
+  double* A = it.P;
+  double* Xg = it.Gi;
+  if (tid == 0) sbad = 0;
+  d4_t T[kInvSlots];
+#pragma unroll
+  for (int j = 0; j < kInvSlots; ++j) {
+    int r, c;
+    const bool on = inv_slot(w, j, r, c) && r < nt;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gr = 16 * r + 4 * v + lr, gc = 16 * c + lc;
+      double x = 0.0;
+      if (on && gc <= gr) x = gr < m ? A[gr + (size_t)m * gc] : (gr == gc ? 1.0 : 0.0);
+      T[j][v] = x;
+    }
+  }
+  // ---- G ----
+  for (int p = 0; p < nt; ++p) {
+    // tile coordinates are recomputed every step rather than kept live
+    int wq = w;
+    asm volatile("" : "+s"(wq));
+#pragma unroll
+    for (int j = 0; j < kInvSlots; ++j) {
+      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
+      int r, c;
+      if (inv_slot(wq, j, r, c) && r < nt && c == p) {
+        double* dst = r == p ? Dd : Pc + (size_t)16 * r * kInvLdP;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(4 * v + lr) * kInvLdP + lc] = T[j][v];
+      }
+    }
+    __syncthreads();
+    if (w == 0) {
+      double row[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) row[u] = lane < 16 ? Dd[lane * kInvLdP + u] : 0.0;
+      double rdl = 1.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        double d = readlane_d(row[u], u);
+        if (!(d > 0.0)) {
+          if (lane == 0) sbad = 1;
+          d = 1.0;
+        }
+        d = sqrt(d);
+        if (lane == u) {
+          row[u] = d;
+          rdl = 1.0 / d;
+        } else if (lane > u) {
+          row[u] = row[u] / d;
+        }
+#pragma unroll
+        for (int v = u + 1; v < 16; ++v) {
+          const double lvu = readlane_d(row[u], v);
+          if (lane >= v && lane < 16) row[v] -= row[u] * lvu;
+        }
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) Dd[lane * kInvLdP + u] = u <= lane ? row[u] : 0.0;
+        rd[lane] = rdl;
+      }
+    }
+    __syncthreads();
+    // tiles below: x G_pp^T = a, one thread per row
+    if (tid < 16 * (nt - 1 - p)) {  // in place in LDS: the row is private to this thread
+      double* xr = Pc + (size_t)(16 * (p + 1) + tid) * kInvLdP;
+      for (int u = 0; u < 16; ++u) {
+        double s = xr[u];
+        for (int v = 0; v < u; ++v) s -= Dd[u * kInvLdP + v] * xr[v];
+        xr[u] = s * rd[u];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kInvSlots; ++j) {
+      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
+      int r, c;
+      if (!inv_slot(wq, j, r, c) || r >= nt || r < p) continue;
+      if (c == p) {
+        const double* src = r == p ? Dd : Pc + (size_t)16 * r * kInvLdP;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double x = src[(4 * v + lr) * kInvLdP + lc];
+          T[j][v] = x;
+          const int gr = 16 * r + 4 * v + lr, gc = 16 * p + lc;
+          if (gr < m && gc <= gr) A[gr + (size_t)m * gc] = x;
+        }
+      } else if (c > p) {
+        d4_t acc = T[j];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const double av = Pc[(16 * r + lc) * kInvLdP + 4 * s4 + lr];
+          const double bv = Pc[(16 * c + lc) * kInvLdP + 4 * s4 + lr];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av, bv, acc, 0, 0, 0);
+        }
+        T[j] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  if (sbad) {
+    if (tid == 0) item_error(it, ls.err, level, kErrNotSPD);
+    return;
+  }
+  // ---- G^{-1} ----
+  for (int p = 0; p < nt; ++p) {
+    int wq = w;
+    asm volatile("" : "+s"(wq));
+#pragma unroll
+    for (int j = 0; j < kInvSlots; ++j) {
+      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
+      int r, c;
+      if (inv_slot(wq, j, r, c) && r < nt && c == p) {
+        double* dst = r == p ? Dd : Pc + (size_t)16 * r * kInvLdP;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(4 * v + lr) * kInvLdP + lc] = T[j][v];
+      }
+    }
+    __syncthreads();
+    if (w == 0 && lane < 16) {  // column `lane` of G_pp^{-1}, in place in LDS (private column)
+      for (int r = 0; r < 16; ++r) {
+        double s = r == lane ? 1.0 : 0.0;
+        for (int q = 0; q < r; ++q) s -= Dd[r * kInvLdP + q] * Di[q * kInvLdP + lane];
+        Di[r * kInvLdP + lane] = s / Dd[r * kInvLdP + r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kInvSlots; ++j) {
+      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
+      int r, c;
+      if (!inv_slot(wq, j, r, c) || r != p || c > p) continue;
+      d4_t x = {0.0, 0.0, 0.0, 0.0};
+      if (c == p) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = Di[(4 * v + lr) * kInvLdP + lc];
+      } else {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          x = __builtin_amdgcn_mfma_f64_16x16x4f64(Di[lc * kInvLdP + 4 * s4 + lr], T[j][s4], x, 0, 0, 0);
+      }
+      T[j] = x;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Xr[(4 * v + lr) * kInvLdX + 16 * c + lc] = x[v];
+        const int gr = 16 * p + 4 * v + lr, gc = 16 * c + lc;
+        if (gr < m && gc < m) Xg[gr + (size_t)m * gc] = x[v];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kInvSlots; ++j) {
+      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
+      int r, c;
+      if (!inv_slot(wq, j, r, c) || r >= nt || r <= p || c > p) continue;
+      d4_t acc = T[j];
+      if (c == p) acc = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const double av = Pc[(16 * r + lc) * kInvLdP + 4 * s4 + lr];
+        const double bv = Xr[(4 * s4 + lr) * kInvLdX + 16 * c + lc];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av, bv, acc, 0, 0, 0);
+      }
+      T[j] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// B <- G^{-1} B for 32 columns of [A_sn | A_sw] per workgroup with the
+// inverse from chol_inv_kernel (512 threads): the column chunk is staged in
+// LDS, wave w computes the output tiles of tile rows w and 15 - w on MFMA
+// (the k <= i tiles of G^{-1}, eight tiles of it loaded at a time), writes
+// them back in place; the squared norms of the far-field columns are summed
+// over the tile rows in order.  LDS: kTrsmInvLds bytes.
+constexpr int kTrsmInvLdB = 33;
+constexpr size_t kTrsmInvLds = (size_t)(256 * kTrsmInvLdB + 16 * 32) * sizeof(double);
+
+__global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                       int level) {
+  extern __shared__ double lds[];
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  if (m == 0) return;
+  const int a = ls.a[it.s], nb = a + ls.b[it.s];
+  const int c0 = blockIdx.y * 32;
+  if (c0 >= nb) return;
+  if (m > kInvMaxDofs || !it.Gi) {
+    if (threadIdx.x == 0) item_error(it, ls.err, level, kErrTooLarge);
+    return;
+  }
+  const int wc = min(32, nb - c0);
+  const int nt = (m + 15) >> 4;
+  const int nr = 16 * nt;
+  double* Bs = lds;                          // nr x kTrsmInvLdB
+  double* red = Bs + 256 * kTrsmInvLdB;      // 16 x 32
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane >> 4, lc = lane & 15;
+  double* B = it.P + (size_t)m * (m + c0);
+  const double* Gi = it.Gi;
+  {
+    const int n = nr * 32;
+    for (int e0 = tid; e0 < n; e0 += 512 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 512;
+        const int c = e / nr, r = e - c * nr;
+        v[u] = (e < n && r < m && c < wc) ? B[r + (size_t)m * c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 512;
+        const int c = e / nr, r = e - c * nr;
+        if (e < n) Bs[r * kTrsmInvLdB + c] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = h == 0 ? w : 15 - w;
+    if (i >= nt) continue;
+    d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const int gr = 16 * i + lc;
+    for (int k0 = 0; k0 <= i; k0 += 8) {
+      double av[8][4];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int gk = 16 * (k0 + kk) + 4 * s4 + lr;
+          av[kk][s4] = (k0 + kk <= i && gr < m && gk < m && gk <= gr) ? Gi[gr + (size_t)m * gk] : 0.0;
+        }
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        if (k0 + kk > i) break;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const double* br = Bs + (16 * (k0 + kk) + 4 * s4 + lr) * kTrsmInvLdB;
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk][s4], br[lc], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk][s4], br[16 + lc], acc1, 0, 0, 0);
+        }
+      }
+    }
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * i + 4 * v + lr;
+      if (r < m) {
+        if (lc < wc) B[r + (size_t)m * lc] = acc0[v];
+        if (16 + lc < wc) B[r + (size_t)m * (16 + lc)] = acc1[v];
+        s0 += acc0[v] * acc0[v];
+        s1 += acc1[v] * acc1[v];
+      }
+    }
+    s0 += __shfl_xor(s0, 16, 64);
+    s0 += __shfl_xor(s0, 32, 64);
+    s1 += __shfl_xor(s1, 16, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    if (lr == 0) {
+      red[i * 32 + lc] = s0;
+      red[i * 32 + 16 + lc] = s1;
+    }
+  }
+  __syncthreads();
+  if (tid < wc && c0 + tid >= a) {
+    double t = 0.0;
+    for (int i = 0; i < nt; ++i) t += red[i * 32 + tid];
+    it.norms[c0 + tid - a] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -706,6 +1036,10 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
                               hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(potrf_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(chol_inv_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInvLds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(trsm_inv_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsmInvLds);
     lds_set = true;
   }
   const int mm = d.max_m;
@@ -719,12 +1053,18 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
                          st, items, ls);
       break;
     case kSplitPotrf:
-      hipLaunchKernelGGL(potrf_kernel, dim3(nitems), dim3(512), (size_t)mm * 33 * 8, st, items, ls,
-                         level);
+      if (mm <= kInvMaxDofs)
+        hipLaunchKernelGGL(chol_inv_kernel, dim3(nitems), dim3(1024), kInvLds, st, items, ls, level);
+      else
+        hipLaunchKernelGGL(potrf_kernel, dim3(nitems), dim3(512), (size_t)mm * 33 * 8, st, items, ls,
+                           level);
       break;
     case kSplitTrsm:
       if (d.max_pcap <= 0) break;
-      if (mm <= 256)
+      if (mm <= kInvMaxDofs)
+        hipLaunchKernelGGL(trsm_inv_kernel, dim3(nitems, (d.max_pcap + 31) / 32), dim3(512), kTrsmInvLds, st,
+                           items, ls, level);
+      else if (mm <= 256)
         hipLaunchKernelGGL(trsm_kernel<32>, dim3(nitems, (d.max_pcap + 31) / 32), dim3(256),
                            (size_t)2 * mm * 33 * 8, st, items, ls);
       else
