@@ -264,7 +264,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     } else {
       launch_zero(at<double>(Lp->work, 0), Lp->plan.work_doubles, st);
       launch_zero(at<double>(Lp->coarse, 0), Lp->plan.coarse_doubles, st);
-      launch_zero_i32(at<int32_t>(Lp->state, 0), 3 * (int64_t)M + 8, st);
+      launch_zero_i32(at<int32_t>(Lp->state, 0), 4 * (int64_t)M + 8, st);
     }
     LevelDev* L = Lp.get();
     vbase += L->nvec;

@@ -193,7 +193,7 @@ lrsp_status upload_vec(DevBuf* b, const void* src, size_t bytes, hipStream_t st)
 
 // Clears and assembles the input of block B (levels and tops starting at B).
 void assemble(const BLevel& B, hipStream_t st) {
-  if (B.Mtot > 0) launch_zero_i32(B.ls.k, 3 * (int64_t)B.Mtot + 8, st);
+  if (B.Mtot > 0) launch_zero_i32(B.ls.k, 4 * (int64_t)B.Mtot + 8, st);
   launch_zero_multi(at<SpanD>(B.zero, 0), B.nzero, B.max_zero, st);
   if (B.nscat > 0) launch_scatter_vals_multi(at<ScatterD>(B.scat, 0), B.nscat, B.max_nnz, st);
   if (B.ntasks > 0) launch_copy_blocks(at<CopyD>(B.tasks, 0), B.ntasks, st);
@@ -421,10 +421,10 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
       B.Mtot += Ls[j]->plan.M;
     }
     if (B.Mtot > 0) {
-      HIPCHK(dalloc(&B.state, 4 * (3 * (size_t)B.Mtot + 8), st));
+      HIPCHK(dalloc(&B.state, 4 * (4 * (size_t)B.Mtot + 8), st));
       int32_t* sb = at<int32_t>(B.state, 0);
-      B.ls = LevelState{sb, sb + B.Mtot, sb + 2 * B.Mtot, sb + 3 * B.Mtot};
-      launch_zero_i32(sb, 3 * (int64_t)B.Mtot + 8, st);
+      B.ls = LevelState{sb, sb + B.Mtot, sb + 2 * B.Mtot, sb + 3 * B.Mtot, sb + 3 * B.Mtot + 8};
+      launch_zero_i32(sb, 4 * (int64_t)B.Mtot + 8, st);
     }
     for (size_t j = 0; j < B.sys.size(); ++j) {
       const int i = B.sys[j];

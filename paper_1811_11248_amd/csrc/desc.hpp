@@ -72,6 +72,7 @@ struct ItemD {
   double* D;        // m x m
   double* P;        // m x (m + pcap)
   double* Gi;       // m x m, G^{-1} (lower) for m <= kInvMaxDofs, else null
+  double* GiT;      // m x m, G^{-T} (upper), same condition
   int32_t* colseg;  // [pcap] segment of each panel column
   int32_t* colnat;  // [pcap] natural index of each panel column
   int64_t* vidx;    // [pcap] level-vector index of each near-field column
@@ -90,7 +91,8 @@ struct LevelState {
   int32_t* k;     // rank (coarse DoFs kept)
   int32_t* a;     // near-field columns
   int32_t* b;     // far-field columns
-  int32_t* err;   // [4]: flag, level, cluster, code
+  int32_t* err;   // [4]: flag, level, cluster, code (then 4 words of grid barrier)
+  int32_t* giok;  // 1: the factorization left G^{-1} in ItemD::Gi (and G^{-T} in GiT)
 };
 
 // dst[r + dld*c] = trans ? src[c + sld*r] : src[r + sld*c], r < rows, c < cols

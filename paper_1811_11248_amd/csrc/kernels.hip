@@ -768,6 +768,7 @@ __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol,
       ls.k[it.s] = 0;
       ls.a[it.s] = 0;
       ls.b[it.s] = 0;
+      ls.giok[it.s] = 0;
     }
     return;
   }
@@ -908,6 +909,7 @@ __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol,
     ls.k[it.s] = k;
     ls.a[it.s] = a;
     ls.b[it.s] = b;
+    ls.giok[it.s] = 0;
   }
   __syncthreads();
 }
@@ -1147,6 +1149,52 @@ __device__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* 
   }
 }
 
+// y <- M y for M (m x m, ld m, m <= 256) lower triangular (upper: upper
+// triangular), y in LDS: the 64x64 tiles of the triangle are spread over the
+// waves, each lane one row of a tile with its entries loaded 32 at a time;
+// the partial sums of the column blocks are added in order.  red: 4*256
+// doubles of LDS.
+__device__ void gemv_tri(const double* M, int m, bool upper, double* y, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nb = (m + 63) >> 6;
+  const int ntl = nb * (nb + 1) / 2;
+  for (int t = wv; t < ntl; t += kWaves) {
+    int rb = 0;
+    while ((rb + 1) * (rb + 2) / 2 <= t) ++rb;
+    const int cl = t - rb * (rb + 1) / 2;
+    const int ib = upper ? cl : rb, jb = upper ? rb : cl;
+    const int i = 64 * ib + lane;
+    const double* Mi = M + min(i, m - 1);
+    double s = 0.0;
+#pragma unroll 1
+    for (int q0 = 0; q0 < 64; q0 += 32) {
+      double g[32];
+#pragma unroll
+      for (int q = 0; q < 32; ++q) {
+        const int j = 64 * jb + q0 + q;
+        const bool ok = i < m && j < m && (upper ? j >= i : j <= i);
+        g[q] = ok ? Mi[(size_t)m * j] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 32; ++q) s += g[q] * y[min(64 * jb + q0 + q, m - 1)];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (i < m) red[jb * 256 + i] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += kThreads) {
+    const int ib = i >> 6;
+    double t = 0.0;
+    if (upper) {
+      for (int jb = ib; jb < nb; ++jb) t += red[jb * 256 + i];
+    } else {
+      for (int jb = 0; jb <= ib; ++jb) t += red[jb * 256 + i];
+    }
+    y[i] = t;
+  }
+  __syncthreads();
+}
+
 // Stages reflectors j0..j0+nj-1 of the far-field block Wf (m rows) in LDS as
 // vs[jj*mp + i] (unit leading entry, zeros above).
 __device__ void stage_reflectors(const ItemD& it, const double* Wf, int m, int mp, int j0, int nj,
@@ -1289,7 +1337,8 @@ __device__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* ld
   double* yg = vec + it.voff;
   for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
   __syncthreads();
-  trsv_lower(it.P, m, m, y, blk);
+  if (ls.giok[it.s]) gemv_tri(it.Gi, m, false, y, blk);  // G^{-1} formed by the factorization
+  else trsv_lower(it.P, m, m, y, blk);
   apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
   fwd_near<R>(it, m, k, 0, a, y, vec);
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
@@ -1311,7 +1360,8 @@ __device__ void fwd_head(const ItemD& it, LevelState ls, double* vec, double* ld
   double* yg = vec + it.voff;
   for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
   __syncthreads();
-  trsv_lower(it.P, m, m, y, blk);
+  if (ls.giok[it.s]) gemv_tri(it.Gi, m, false, y, blk);  // G^{-1} formed by the factorization
+  else trsv_lower(it.P, m, m, y, blk);
   apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
   __syncthreads();
@@ -1394,7 +1444,8 @@ __device__ void bwd_tail(const ItemD& it, LevelState ls, double* vec, double* ld
   for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
   __syncthreads();
   apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
-  trsv_lower_t<R>(it.P, m, m, x, blk);
+  if (ls.giok[it.s]) gemv_tri(it.GiT, m, true, x, blk);  // G^{-T} formed by the factorization
+  else trsv_lower_t<R>(it.P, m, m, x, blk);
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
 }
@@ -1435,7 +1486,8 @@ __device__ void bwd_item(const ItemD& it, LevelState ls, double* vec, double* ld
   }
   __syncthreads();
   apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
-  trsv_lower_t<R>(it.P, m, m, x, blk);
+  if (ls.giok[it.s]) gemv_tri(it.GiT, m, true, x, blk);  // G^{-T} formed by the factorization
+  else trsv_lower_t<R>(it.P, m, m, x, blk);
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
 }

@@ -204,7 +204,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     noff[s] = fd; fd += al(pc);
     if (p.m[s] > 0 && p.m[s] <= kInvMaxDofs) {
       gioff[s] = fd;
-      fd += al((int64_t)p.m[s] * p.m[s]);
+      fd += 2 * al((int64_t)p.m[s] * p.m[s]);
     }
     csoff[s] = fi; fi += al(pc);
     cnoff[s] = fi; fi += al(pc);
@@ -221,13 +221,14 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     L->ls = *shared;
   } else {
     dfree(&L->state, st);
-    HIPCHK(dalloc(&L->state, sizeof(int32_t) * (3 * (size_t)M + 8), st));
+    HIPCHK(dalloc(&L->state, sizeof(int32_t) * (4 * (size_t)M + 8), st));
     int32_t* sb = at<int32_t>(L->state, 0);
     L->ls.k = sb;
     L->ls.a = sb + M;
     L->ls.b = sb + 2 * M;
     L->ls.err = sb + 3 * M;
-    launch_zero_i32(sb, 3 * (int64_t)M + 8, st);
+    L->ls.giok = sb + 3 * M + 8;
+    launch_zero_i32(sb, 4 * (int64_t)M + 8, st);
   }
   // descriptors
   std::vector<SegD> segs;
@@ -338,6 +339,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     it.D = W + p.d_off[s];
     it.P = F + poff[s];
     it.Gi = gioff[s] >= 0 ? F + gioff[s] : nullptr;
+    it.GiT = gioff[s] >= 0 ? F + gioff[s] + al((int64_t)p.m[s] * p.m[s]) : nullptr;
     it.tau = F + toff[s];
     it.norms = F + noff[s];
     it.colseg = FI + csoff[s];

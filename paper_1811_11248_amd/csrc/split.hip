@@ -252,6 +252,7 @@ __global__ void __launch_bounds__(512) potrf_kernel(const ItemD* __restrict__ it
   __syncthreads();
   potrf_wg<512>(it.P, m, m, lds, &sbad);
   __syncthreads();
+  if (threadIdx.x == 0) ls.giok[it.s] = 0;
   if (sbad && threadIdx.x == 0) item_error(it, ls.err, level, kErrNotSPD);
 }
 
@@ -265,16 +266,17 @@ __global__ void __launch_bounds__(512) potrf_kernel(const ItemD* __restrict__ it
 //   G: right-looking by tile columns p.  The diagonal tile is factored by
 //   wave 0 (readlane broadcasts), the tiles below it are solved row by row
 //   through LDS, the trailing tiles are updated on MFMA.
-//   G^{-1}: forward substitution G X = I by tile rows p.  X_pp = G_pp^{-1},
-//   X_pj = G_pp^{-1} acc_pj; then acc_ij -= G_ip X_pj for the rows i > p
-//   (acc_ij starts at zero, the identity having no entries below the
-//   diagonal).
+//   G^{-1}: the inverses of the diagonal tiles first, all at once; then
+//   forward substitution G X = I by tile rows p: X_pp = G_pp^{-1} and
+//   X_pj = G_pp^{-1} acc_pj (one wave per tile), then acc_ij -= G_ip X_pj for
+//   the rows i > p (acc_ij starts at zero, the identity having no entries
+//   below the diagonal).
 // G goes to the diagonal block of the panel (lower triangle), G^{-1} to Gi
 // (lower tiles, zeros above the diagonal inside the diagonal tiles).
 constexpr int kInvLdP = 17;           // row stride of the LDS tiles
 constexpr int kInvLdX = 16 * 16 + 1;  // row stride of the X row-block buffer
 constexpr int kInvSlots = 9;          // tiles per wave
-constexpr size_t kInvLds = (size_t)(256 * kInvLdP + 2 * 16 * kInvLdP + 16 * kInvLdX + 16) * sizeof(double);
+constexpr size_t kInvLds = (size_t)(256 * kInvLdP + 16 * kInvLdP + 2 * 16 * kInvLdX + 16) * sizeof(double);
 
 // Tile (r, c) of slot j of wave w; false when the slot is unused.
 __device__ __forceinline__ bool inv_slot(int w, int j, int& r, int& c) {
@@ -294,14 +296,14 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
   extern __shared__ double lds[];
   double* Pc = lds;                  // 256 x kInvLdP: tile column p
   double* Dd = Pc + 256 * kInvLdP;   // 16 x kInvLdP: diagonal tile
-  double* Di = Dd + 16 * kInvLdP;    // 16 x kInvLdP: its inverse
-  double* Xr = Di + 16 * kInvLdP;    // 16 x kInvLdX: tile row p of X
-  double* rd = Xr + 16 * kInvLdX;    // 16: reciprocals of the diagonal
+  double* Xr = Dd + 16 * kInvLdP;    // 16 x kInvLdX: tile row p of X
+  double* Ar = Xr + 16 * kInvLdX;    // 16 x kInvLdX: accumulators of tile row p
+  double* rd = Ar + 16 * kInvLdX;    // 16: reciprocals of the diagonal
   __shared__ int sbad;
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   if (m == 0) return;
-  if (m > kInvMaxDofs || !it.Gi) {
+  if (m > kInvMaxDofs || !it.Gi || !it.GiT) {
     if (threadIdx.x == 0) item_error(it, ls.err, level, kErrTooLarge);
     return;
   }
@@ -311,6 +313,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
   const int nt = (m + 15) >> 4;
   double* A = it.P;
   double* Xg = it.Gi;
+  double* XgT = it.GiT;
   if (tid == 0) sbad = 0;
   d4_t T[kInvSlots];
 #pragma unroll
@@ -354,11 +357,12 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
           d = 1.0;
         }
         d = sqrt(d);
+        const double di = 1.0 / d;
         if (lane == u) {
           row[u] = d;
-          rdl = 1.0 / d;
+          rdl = di;
         } else if (lane > u) {
-          row[u] = row[u] / d;
+          row[u] = row[u] * di;
         }
 #pragma unroll
         for (int v = u + 1; v < 16; ++v) {
@@ -374,13 +378,20 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
     }
     __syncthreads();
     // tiles below: x G_pp^T = a, one thread per row
-    if (tid < 16 * (nt - 1 - p)) {  // in place in LDS: the row is private to this thread
+    if (tid < 16 * (nt - 1 - p)) {
       double* xr = Pc + (size_t)(16 * (p + 1) + tid) * kInvLdP;
+      double x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = xr[u];
+#pragma unroll
       for (int u = 0; u < 16; ++u) {
-        double s = xr[u];
-        for (int v = 0; v < u; ++v) s -= Dd[u * kInvLdP + v] * xr[v];
-        xr[u] = s * rd[u];
+        double s = x[u];
+#pragma unroll
+        for (int v = 0; v < u; ++v) s -= Dd[u * kInvLdP + v] * x[v];
+        x[u] = s * rd[u];
       }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) xr[u] = x[u];
     }
     __syncthreads();
 #pragma unroll
@@ -415,54 +426,85 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
     return;
   }
   // ---- G^{-1} ----
-  for (int p = 0; p < nt; ++p) {
+  // inverses of the diagonal tiles, all at once: the owners put G_qq in Pc
+  // (rows 16q..), wave q solves column `lane` < 16 of G_qq^{-1} into the
+  // columns 16q.. of Xr.  Step p overwrites only the columns 16j.., j <= p, of
+  // Xr, so G_qq^{-1} stays there until step q.
+  {
     int wq = w;
     asm volatile("" : "+s"(wq));
 #pragma unroll
     for (int j = 0; j < kInvSlots; ++j) {
-      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
+      __builtin_amdgcn_sched_barrier(0);
       int r, c;
-      if (inv_slot(wq, j, r, c) && r < nt && c == p) {
-        double* dst = r == p ? Dd : Pc + (size_t)16 * r * kInvLdP;
+      if (inv_slot(wq, j, r, c) && r < nt && c == r) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dst[(4 * v + lr) * kInvLdP + lc] = T[j][v];
+        for (int v = 0; v < 4; ++v) Pc[(16 * r + 4 * v + lr) * kInvLdP + lc] = T[j][v];
       }
     }
     __syncthreads();
-    if (w == 0 && lane < 16) {  // column `lane` of G_pp^{-1}, in place in LDS (private column)
+    if (w < nt && lane < 16) {
+      const double* Lq = Pc + (size_t)16 * w * kInvLdP;
+      double y[16];
+#pragma unroll
       for (int r = 0; r < 16; ++r) {
         double s = r == lane ? 1.0 : 0.0;
-        for (int q = 0; q < r; ++q) s -= Dd[r * kInvLdP + q] * Di[q * kInvLdP + lane];
-        Di[r * kInvLdP + lane] = s / Dd[r * kInvLdP + r];
+#pragma unroll
+        for (int q = 0; q < r; ++q) s -= Lq[r * kInvLdP + q] * y[q];
+        y[r] = s / Lq[r * kInvLdP + r];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Xr[r * kInvLdX + 16 * w + lane] = y[r];
+    }
+    __syncthreads();
+  }
+  for (int p = 0; p < nt; ++p) {
+    int wq = w;
+    asm volatile("" : "+s"(wq));
+    // tile column p of G to Pc; the accumulators of tile row p to Ar
+#pragma unroll
+    for (int j = 0; j < kInvSlots; ++j) {
+      __builtin_amdgcn_sched_barrier(0);
+      int r, c;
+      if (!inv_slot(wq, j, r, c) || r >= nt) continue;
+      if (r > p && c == p) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Pc[(16 * r + 4 * v + lr) * kInvLdP + lc] = T[j][v];
+      } else if (r == p && c < p) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Ar[(4 * v + lr) * kInvLdX + 16 * c + lc] = T[j][v];
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kInvSlots; ++j) {
-      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
-      int r, c;
-      if (!inv_slot(wq, j, r, c) || r != p || c > p) continue;
+    // X_pj = G_pp^{-1} acc_pj by wave j (j < p); X_pp = G_pp^{-1} by wave p
+    if (w <= p) {
       d4_t x = {0.0, 0.0, 0.0, 0.0};
-      if (c == p) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) x[v] = Di[(4 * v + lr) * kInvLdP + lc];
-      } else {
+      if (w < p) {
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
-          x = __builtin_amdgcn_mfma_f64_16x16x4f64(Di[lc * kInvLdP + 4 * s4 + lr], T[j][s4], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f64_16x16x4f64(Xr[lc * kInvLdX + 16 * p + 4 * s4 + lr],
+                                                   Ar[(4 * s4 + lr) * kInvLdX + 16 * w + lc], x, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = Xr[(4 * v + lr) * kInvLdX + 16 * p + lc];
       }
-      T[j] = x;
+      // columns 16w.. of Xr: wave w < p writes X_pw there (no wave reads
+      // them in this phase); for w == p they already hold X_pp
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        Xr[(4 * v + lr) * kInvLdX + 16 * c + lc] = x[v];
-        const int gr = 16 * p + 4 * v + lr, gc = 16 * c + lc;
-        if (gr < m && gc < m) Xg[gr + (size_t)m * gc] = x[v];
+        if (w < p) Xr[(4 * v + lr) * kInvLdX + 16 * w + lc] = x[v];
+        const int gr = 16 * p + 4 * v + lr, gc = 16 * w + lc;
+        if (gr < m && gc < m) {
+          Xg[gr + (size_t)m * gc] = x[v];
+          XgT[gc + (size_t)m * gr] = x[v];
+        }
       }
     }
     __syncthreads();
+    // rows i > p: acc_ij -= G_ip X_pj (j < p); tile (i, p) becomes -G_ip X_pp
 #pragma unroll
     for (int j = 0; j < kInvSlots; ++j) {
-      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
+      __builtin_amdgcn_sched_barrier(0);
       int r, c;
       if (!inv_slot(wq, j, r, c) || r >= nt || r <= p || c > p) continue;
       d4_t acc = T[j];
@@ -477,6 +519,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
     }
     __syncthreads();
   }
+  if (tid == 0) ls.giok[it.s] = 1;
 }
 
 // B <- G^{-1} B for 32 columns of [A_sn | A_sw] per workgroup with the
