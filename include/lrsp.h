@@ -339,6 +339,9 @@ typedef struct {
   double bytes;
 } lrsp_timing;
 lrsp_status lrsp_timing_enable(int32_t on);
+/* Families that record events while timing is on (bit f = family f; all by
+ * default): fewer events, less disturbance of the timed work. */
+lrsp_status lrsp_timing_families(uint32_t mask);
 lrsp_status lrsp_timing_reset(void);
 lrsp_status lrsp_timing_read(int32_t family, lrsp_timing* out);
 

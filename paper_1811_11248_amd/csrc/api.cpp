@@ -639,6 +639,11 @@ lrsp_status lrsp_timing_enable(int32_t on) {
   return LRSP_OK;
 }
 
+lrsp_status lrsp_timing_families(uint32_t mask) {
+  g_tm.mask = mask;
+  return LRSP_OK;
+}
+
 lrsp_status lrsp_timing_reset(void) {
   tm_collect();
   for (int f = 0; f < kFamilies; ++f) {

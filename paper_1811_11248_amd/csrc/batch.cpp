@@ -515,7 +515,7 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
       std::vector<ItemD> items;
       B.cstart.assign(1, 0);
       for (auto& L : Ls) B.ncolours = std::max(B.ncolours, L->plan.ncolours);
-      B.cdims.assign(B.ncolours, SplitDims{0, 0, 0, 0});
+      B.cdims.assign(B.ncolours, SplitDims{0, 0, 0, 0, 0});
       for (int c = 0; c < B.ncolours; ++c) {
         for (auto& L : Ls) {
           const LevelPlan& p = L->plan;
@@ -527,6 +527,7 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
           d.max_nseg = std::max(d.max_nseg, e.max_nseg);
           d.max_pcap = std::max(d.max_pcap, e.max_pcap);
           d.max_acap = std::max(d.max_acap, e.max_acap);
+          d.max_bcap = std::max(d.max_bcap, e.max_bcap);
         }
         B.cstart.push_back((int)items.size());
         B.max_items = std::max(B.max_items, B.cstart[c + 1] - B.cstart[c]);

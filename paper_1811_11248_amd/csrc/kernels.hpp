@@ -37,7 +37,7 @@ int device_cus();
 
 // Capacities of one colour for the split (several workgroups per cluster) path.
 struct SplitDims {
-  int max_m, max_nseg, max_pcap, max_acap;
+  int max_m, max_nseg, max_pcap, max_acap, max_bcap;
 };
 constexpr int kSplitMaxDofs = 512;   // LDS limit of the split kernels
 constexpr int kSplitMinDofs = 96;    // below this one workgroup per cluster wins

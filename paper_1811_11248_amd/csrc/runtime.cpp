@@ -360,7 +360,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
   L->d_items = reinterpret_cast<ItemD*>(db + o3);
   L->d_cstart = reinterpret_cast<const int32_t*>(db + o4);
   // per-colour capacities
-  L->cdims.assign(p.ncolours, SplitDims{0, 0, 0, 0});
+  L->cdims.assign(p.ncolours, SplitDims{0, 0, 0, 0, 0});
   L->max_items = 0;
   L->max_nseg = 0;
   L->max_acap = 0;
@@ -373,6 +373,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
       d.max_nseg = std::max(d.max_nseg, it.nseg);
       d.max_pcap = std::max(d.max_pcap, it.pcap);
       d.max_acap = std::max(d.max_acap, p.acap[it.s - sbase]);
+      d.max_bcap = std::max(d.max_bcap, p.bcap[it.s - sbase]);
     }
     L->max_nseg = std::max(L->max_nseg, d.max_nseg);
     L->max_acap = std::max(L->max_acap, d.max_acap);

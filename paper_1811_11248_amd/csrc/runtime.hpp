@@ -33,6 +33,7 @@ const char* last_error();
 constexpr int kFamilies = 11;
 struct TimingState {
   bool on = false;
+  uint32_t mask = ~0u;  // families that record events
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kFamilies];
   int64_t launches[kFamilies] = {};
@@ -50,7 +51,7 @@ struct TimedLaunch {
   hipStream_t st;
   hipEvent_t a = nullptr;
   TimedLaunch(int f, hipStream_t s) : fam(f), st(s) {
-    if (!g_tm.on) return;
+    if (!g_tm.on || !((g_tm.mask >> f) & 1u)) return;
     a = tm_event();
     (void)hipEventRecord(a, st);
   }

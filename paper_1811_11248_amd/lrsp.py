@@ -119,6 +119,7 @@ SIGNATURES = [
                                             C.POINTER(C.c_float)]),
     ("lrsp_timing_enable", C.c_int, [C.c_int32]),
     ("lrsp_timing_reset", C.c_int, []),
+    ("lrsp_timing_families", C.c_int, [C.c_uint32]),
     ("lrsp_timing_read", C.c_int, [C.c_int32, C.POINTER(Timing)]),
     ("lrsp_last_error_info", C.c_char_p, []),
     ("lrsp_status_str", C.c_char_p, [C.c_int]),
@@ -480,6 +481,12 @@ TIMING_FAMILIES = {"eliminate": 0, "forward": 1, "backward": 2, "split_gather": 
 
 def timing_enable(on: bool = True):
     _check(lib().lrsp_timing_enable(1 if on else 0))
+
+
+def timing_families(names=None):
+    """Restrict event recording to the named families (None: all)."""
+    mask = 0xFFFFFFFF if names is None else sum(1 << TIMING_FAMILIES[n] for n in names)
+    _check(lib().lrsp_timing_families(mask))
 
 
 def timing_reset():
