@@ -335,14 +335,14 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       }
     }
     HIPCHK(hipGetLastError());
-    L->k.resize(M);
-    L->a.resize(M);
-    L->b.resize(M);
-    HIPCHK(hipMemcpyAsync(L->k.data(), L->ls.k, 4 * (size_t)M, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(L->a.data(), L->ls.a, 4 * (size_t)M, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(L->b.data(), L->ls.b, 4 * (size_t)M, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(herr.data(), L->ls.err, 16, hipMemcpyDeviceToHost, st));
+    // k, a, b and the error words lie back to back in the state buffer: one copy
+    std::vector<int32_t> kab(3 * (size_t)M + 4);
+    HIPCHK(hipMemcpyAsync(kab.data(), L->ls.k, 4 * kab.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    L->k.assign(kab.begin(), kab.begin() + M);
+    L->a.assign(kab.begin() + M, kab.begin() + 2 * M);
+    L->b.assign(kab.begin() + 2 * M, kab.begin() + 3 * M);
+    herr.assign(kab.begin() + 3 * M, kab.end());
     if (herr[0] && herr[3] == kErrCapacity && L->capped) {
       // a rank exceeded its predicted capacity: redo the level with the
       // worst-case capacities (the level's input is assembled again)
@@ -399,8 +399,10 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     // next level
     std::vector<int> nsz(M / 2);
     for (int P = 0; P < M / 2; ++P) nsz[P] = L->k[2 * P] + L->k[2 * P + 1];
-    std::vector<std::vector<int>> nadj;
-    coarsen_square(adj, &nadj);
+    // the next graph depends on the structure only: kept with the level's
+    // workspace and reused with it
+    if (!reuse || L->next_adj.size() != (size_t)(M + 1) / 2) coarsen_square(adj, &L->next_adj);
+    std::vector<std::vector<int>> nadj = L->next_adj;
     sizes.swap(nsz);
     adj.swap(nadj);
     prev = L;

@@ -113,6 +113,7 @@ struct LevelDev {
   DevBuf tasks;                     // level >= 1: assembly copy tasks
   int ntasks = 0;
   uint64_t tasks_src = 0;           // id of the level the tasks read from
+  std::vector<std::vector<int>> next_adj;  // cluster graph of the next level (structure only)
   bool capped = false;              // rank capacities from predicted ranks
   std::vector<double> feat;         // learned ranks: features [M][12]
   std::vector<float> pred;          // and predicted ranks [M]
