@@ -16,6 +16,14 @@ typedef short s4_t __attribute__((ext_vector_type(4)));
 
 constexpr double kTie = 1e-10;  // pivot tie window of the column-pivoted QR
 
+// Workgroup barrier that orders LDS only: pending global stores are not
+// waited for (for phases that exchange data through LDS alone).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Value of v in lane l (l uniform across the wave).
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long b = __double_as_longlong(v);

@@ -263,20 +263,21 @@ __global__ void __launch_bounds__(512) potrf_kernel(const ItemD* __restrict__ it
 // v_mfma_f64_16x16x4 (lane l, slot v: row 4v + l/16, column l%16).  Tile rows
 // r and 15 - r (17 tiles) belong to waves r and r + 8, which take the even
 // and the odd tiles of the pair.  Padding beyond m is the identity.
-//   G: right-looking by tile columns p.  The diagonal tile is factored by
-//   wave 0 (readlane broadcasts), the tiles below it are solved row by row
-//   through LDS, the trailing tiles are updated on MFMA.
-//   G^{-1}: the inverses of the diagonal tiles first, all at once; then
-//   forward substitution G X = I by tile rows p: X_pp = G_pp^{-1} and
+//   G: right-looking by tile columns p.  Wave 0 factors the diagonal tile
+//   (readlane broadcasts, reciprocal square roots) and inverts it; the tiles
+//   below are G_ip = A_ip G_pp^{-T} on MFMA; the trailing tiles are updated on
+//   MFMA.
+//   G^{-1}: forward substitution G X = I by tile rows p: X_pp = G_pp^{-1} and
 //   X_pj = G_pp^{-1} acc_pj (one wave per tile), then acc_ij -= G_ip X_pj for
 //   the rows i > p (acc_ij starts at zero, the identity having no entries
 //   below the diagonal).
 // G goes to the diagonal block of the panel (lower triangle), G^{-1} to Gi
-// (lower tiles, zeros above the diagonal inside the diagonal tiles).
+// (lower tiles, zeros above the diagonal inside the diagonal tiles); no
+// thread reads these stores back, so the barriers order LDS only.
 constexpr int kInvLdP = 17;           // row stride of the LDS tiles
 constexpr int kInvLdX = 16 * 16 + 1;  // row stride of the X row-block buffer
 constexpr int kInvSlots = 9;          // tiles per wave
-constexpr size_t kInvLds = (size_t)(256 * kInvLdP + 16 * kInvLdP + 2 * 16 * kInvLdX + 16) * sizeof(double);
+constexpr size_t kInvLds = (size_t)(2 * 256 * kInvLdP + 16 * kInvLdP + 2 * 16 * kInvLdX + 16) * sizeof(double);
 
 // Tile (r, c) of slot j of wave w; false when the slot is unused.
 __device__ __forceinline__ bool inv_slot(int w, int j, int& r, int& c) {
@@ -294,11 +295,12 @@ __device__ __forceinline__ bool inv_slot(int w, int j, int& r, int& c) {
 __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict__ items, LevelState ls,
                                                         int level) {
   extern __shared__ double lds[];
-  double* Pc = lds;                  // 256 x kInvLdP: tile column p
-  double* Dd = Pc + 256 * kInvLdP;   // 16 x kInvLdP: diagonal tile
+  double* Pc = lds;                  // 256 x kInvLdP: tile column p (two buffers
+  double* Pc2 = Pc + 256 * kInvLdP;  //   in turn during the Cholesky)
+  double* Dd = Pc2 + 256 * kInvLdP;  // 16 x kInvLdP: diagonal tile
   double* Xr = Dd + 16 * kInvLdP;    // 16 x kInvLdX: tile row p of X
   double* Ar = Xr + 16 * kInvLdX;    // 16 x kInvLdX: accumulators of tile row p
-  double* rd = Ar + 16 * kInvLdX;    // 16: reciprocals of the diagonal
+  double* ri = Ar + 16 * kInvLdX;    // 16: reciprocals of the diagonal of G_pp
   __shared__ int sbad;
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
@@ -329,135 +331,136 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
     }
   }
   // ---- G ----
+  // tile column 0 to LDS; later columns are put there by the step before
+#pragma unroll
+  for (int j = 0; j < kInvSlots; ++j) {
+    int r, c;
+    if (inv_slot(w, j, r, c) && r < nt && c == 0) {
+      double* dst = r == 0 ? Dd : Pc + (size_t)16 * r * kInvLdP;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[(4 * v + lr) * kInvLdP + lc] = T[j][v];
+    }
+  }
+  lds_barrier();
   for (int p = 0; p < nt; ++p) {
     // tile coordinates are recomputed every step rather than kept live
     int wq = w;
     asm volatile("" : "+s"(wq));
-#pragma unroll
-    for (int j = 0; j < kInvSlots; ++j) {
-      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
-      int r, c;
-      if (inv_slot(wq, j, r, c) && r < nt && c == p) {
-        double* dst = r == p ? Dd : Pc + (size_t)16 * r * kInvLdP;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dst[(4 * v + lr) * kInvLdP + lc] = T[j][v];
-      }
-    }
-    __syncthreads();
+    double* Pcur = (p & 1) ? Pc2 : Pc;   // tile column p
+    double* Pnext = (p & 1) ? Pc : Pc2;  // tile column p + 1
+    // wave 0: G_pp (lane r holds row r; reciprocal square roots from
+    // v_rsq_f64 refined by one Newton step), then G_pp^{-1} (lane c: column
+    // c) into the columns 16p.. of Xr, where the inverse below expects it
     if (w == 0) {
-      double row[16];
+      {
+        double row[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) row[u] = lane < 16 ? Dd[lane * kInvLdP + u] : 0.0;
-      double rdl = 1.0;
+        for (int u = 0; u < 16; ++u) row[u] = lane < 16 ? Dd[lane * kInvLdP + u] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        double d = readlane_d(row[u], u);
-        if (!(d > 0.0)) {
-          if (lane == 0) sbad = 1;
-          d = 1.0;
+        for (int u = 0; u < 16; ++u) {
+          double d = readlane_d(row[u], u);
+          if (!(d > 0.0)) {
+            if (lane == 0) sbad = 1;
+            d = 1.0;
+          }
+          double y = __builtin_amdgcn_rsq(d);
+          y = y + y * (0.5 - 0.5 * d * y * y);
+          if (lane == u) {
+            row[u] = d * y;
+            ri[u] = y;
+          } else if (lane > u) {
+            row[u] = row[u] * y;
+          }
+#pragma unroll
+          for (int v = u + 1; v < 16; ++v) {
+            const double lvu = readlane_d(row[u], v);
+            if (lane >= v && lane < 16) row[v] -= row[u] * lvu;
+          }
         }
-        d = sqrt(d);
-        const double di = 1.0 / d;
-        if (lane == u) {
-          row[u] = d;
-          rdl = di;
-        } else if (lane > u) {
-          row[u] = row[u] * di;
-        }
+        if (lane < 16) {
 #pragma unroll
-        for (int v = u + 1; v < 16; ++v) {
-          const double lvu = readlane_d(row[u], v);
-          if (lane >= v && lane < 16) row[v] -= row[u] * lvu;
+          for (int u = 0; u < 16; ++u) Dd[lane * kInvLdP + u] = u <= lane ? row[u] : 0.0;
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");  // Dd, ri written before read
+      __builtin_amdgcn_wave_barrier();
       if (lane < 16) {
+        double y[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) Dd[lane * kInvLdP + u] = u <= lane ? row[u] : 0.0;
-        rd[lane] = rdl;
+        for (int r = 0; r < 16; ++r) {
+          double s0 = r == lane ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+          for (int q = 0; q + 1 < r; q += 2) {
+            s0 -= Dd[r * kInvLdP + q] * y[q];
+            s1 -= Dd[r * kInvLdP + q + 1] * y[q + 1];
+          }
+          if (r & 1) s0 -= Dd[r * kInvLdP + r - 1] * y[r - 1];
+          y[r] = (s0 + s1) * ri[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Xr[r * kInvLdX + 16 * p + lane] = y[r];
       }
     }
-    __syncthreads();
-    // tiles below: x G_pp^T = a, one thread per row
-    if (tid < 16 * (nt - 1 - p)) {
-      double* xr = Pc + (size_t)(16 * (p + 1) + tid) * kInvLdP;
-      double x[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) x[u] = xr[u];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        double s = x[u];
-#pragma unroll
-        for (int v = 0; v < u; ++v) s -= Dd[u * kInvLdP + v] * x[v];
-        x[u] = s * rd[u];
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) xr[u] = x[u];
-    }
-    __syncthreads();
+    lds_barrier();
+    // tile column p of G: G_pp from Dd; G_ip = A_ip G_pp^{-T} on MFMA, back to
+    // the tile's rows of Pcur for the trailing update
 #pragma unroll
     for (int j = 0; j < kInvSlots; ++j) {
-      __builtin_amdgcn_sched_barrier(0);  // keep one slot's values live at a time
+      __builtin_amdgcn_sched_barrier(0);
       int r, c;
-      if (!inv_slot(wq, j, r, c) || r >= nt || r < p) continue;
-      if (c == p) {
-        const double* src = r == p ? Dd : Pc + (size_t)16 * r * kInvLdP;
+      if (!inv_slot(wq, j, r, c) || r >= nt || r < p || c != p) continue;
+      d4_t x = {0.0, 0.0, 0.0, 0.0};
+      if (r == p) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double x = src[(4 * v + lr) * kInvLdP + lc];
-          T[j][v] = x;
-          const int gr = 16 * r + 4 * v + lr, gc = 16 * p + lc;
-          if (gr < m && gc <= gr) A[gr + (size_t)m * gc] = x;
-        }
-      } else if (c > p) {
-        d4_t acc = T[j];
+        for (int v = 0; v < 4; ++v) x[v] = Dd[(4 * v + lr) * kInvLdP + lc];
+      } else {
+        double* rows = Pcur + (size_t)16 * r * kInvLdP;
+        double av[4];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-          const double av = Pc[(16 * r + lc) * kInvLdP + 4 * s4 + lr];
-          const double bv = Pc[(16 * c + lc) * kInvLdP + 4 * s4 + lr];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av, bv, acc, 0, 0, 0);
-        }
-        T[j] = acc;
+        for (int s4 = 0; s4 < 4; ++s4) av[s4] = rows[lc * kInvLdP + 4 * s4 + lr];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          x = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], Xr[lc * kInvLdX + 16 * p + 4 * s4 + lr], x, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rows[(4 * v + lr) * kInvLdP + lc] = x[v];
+      }
+      T[j] = x;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gr = 16 * r + 4 * v + lr, gc = 16 * p + lc;
+        if (gr < m && gc <= gr) A[gr + (size_t)m * gc] = x[v];
       }
     }
-    __syncthreads();
+    lds_barrier();
+    // trailing tiles: T_rc -= G_rp G_cp^T; the tiles of column p + 1, final
+    // now, go to Dd and Pnext for the next step
+#pragma unroll
+    for (int j = 0; j < kInvSlots; ++j) {
+      __builtin_amdgcn_sched_barrier(0);
+      int r, c;
+      if (!inv_slot(wq, j, r, c) || r >= nt || r <= p || c <= p) continue;
+      d4_t acc = T[j];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const double av = Pcur[(16 * r + lc) * kInvLdP + 4 * s4 + lr];
+        const double bv = Pcur[(16 * c + lc) * kInvLdP + 4 * s4 + lr];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av, bv, acc, 0, 0, 0);
+      }
+      T[j] = acc;
+      if (c == p + 1) {
+        double* dst = r == p + 1 ? Dd : Pnext + (size_t)16 * r * kInvLdP;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(4 * v + lr) * kInvLdP + lc] = acc[v];
+      }
+    }
+    lds_barrier();
   }
   if (sbad) {
     if (tid == 0) item_error(it, ls.err, level, kErrNotSPD);
     return;
   }
-  // ---- G^{-1} ----
-  // inverses of the diagonal tiles, all at once: the owners put G_qq in Pc
-  // (rows 16q..), wave q solves column `lane` < 16 of G_qq^{-1} into the
-  // columns 16q.. of Xr.  Step p overwrites only the columns 16j.., j <= p, of
-  // Xr, so G_qq^{-1} stays there until step q.
-  {
-    int wq = w;
-    asm volatile("" : "+s"(wq));
-#pragma unroll
-    for (int j = 0; j < kInvSlots; ++j) {
-      __builtin_amdgcn_sched_barrier(0);
-      int r, c;
-      if (inv_slot(wq, j, r, c) && r < nt && c == r) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Pc[(16 * r + 4 * v + lr) * kInvLdP + lc] = T[j][v];
-      }
-    }
-    __syncthreads();
-    if (w < nt && lane < 16) {
-      const double* Lq = Pc + (size_t)16 * w * kInvLdP;
-      double y[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        double s = r == lane ? 1.0 : 0.0;
-#pragma unroll
-        for (int q = 0; q < r; ++q) s -= Lq[r * kInvLdP + q] * y[q];
-        y[r] = s / Lq[r * kInvLdP + r];
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) Xr[r * kInvLdX + 16 * w + lane] = y[r];
-    }
-    __syncthreads();
-  }
+  // G_qq^{-1} sits in the columns 16q.. of Xr (formed by the Cholesky); step
+  // p overwrites only the columns 16j.., j <= p, so it stays there until step q
   for (int p = 0; p < nt; ++p) {
     int wq = w;
     asm volatile("" : "+s"(wq));
@@ -475,7 +478,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
         for (int v = 0; v < 4; ++v) Ar[(4 * v + lr) * kInvLdX + 16 * c + lc] = T[j][v];
       }
     }
-    __syncthreads();
+    lds_barrier();
     // X_pj = G_pp^{-1} acc_pj by wave j (j < p); X_pp = G_pp^{-1} by wave p
     if (w <= p) {
       d4_t x = {0.0, 0.0, 0.0, 0.0};
@@ -500,7 +503,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     // rows i > p: acc_ij -= G_ip X_pj (j < p); tile (i, p) becomes -G_ip X_pp
 #pragma unroll
     for (int j = 0; j < kInvSlots; ++j) {
@@ -517,7 +520,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
       }
       T[j] = acc;
     }
-    __syncthreads();
+    lds_barrier();
   }
   if (tid == 0) ls.giok[it.s] = 1;
 }
@@ -571,7 +574,7 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int i = h == 0 ? w : 15 - w;
@@ -618,7 +621,7 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
       red[i * 32 + 16 + lc] = s1;
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (tid < wc && c0 + tid >= a) {
     double t = 0.0;
     for (int i = 0; i < nt; ++i) t += red[i * 32 + tid];
