@@ -274,26 +274,35 @@ __global__ void __launch_bounds__(512) potrf_kernel(const ItemD* __restrict__ it
 // G goes to the diagonal block of the panel (lower triangle), G^{-1} to Gi
 // (lower tiles, zeros above the diagonal inside the diagonal tiles); no
 // thread reads these stores back, so the barriers order LDS only.
+constexpr int kInvWaves = 8;          // waves of the Cholesky-inverse workgroup
 constexpr int kInvLdP = 17;           // row stride of the LDS tiles
 constexpr int kInvLdX = 16 * 16 + 1;  // row stride of the X row-block buffer
-constexpr int kInvSlots = 9;          // tiles per wave
 constexpr size_t kInvLds = (size_t)(2 * 256 * kInvLdP + 16 * kInvLdP + 2 * 16 * kInvLdX + 16) * sizeof(double);
-
-// Tile (r, c) of slot j of wave w; false when the slot is unused.
-__device__ __forceinline__ bool inv_slot(int w, int j, int& r, int& c) {
-  const int pr = w & 7, g = 2 * j + (w >> 3);
-  if (g <= pr) {
-    r = pr;
-    c = g;
-  } else {
-    r = 15 - pr;
-    c = g - pr - 1;
+// Waves of the workgroup: tile rows r and 15 - r (17 tiles) belong to wave r
+// (NW = 8), or to waves r and r + 8, which take the even and the odd tiles
+// of the pair (NW = 16).
+template <int NW>
+struct InvMap {
+  static constexpr int kSlots = NW == 8 ? 17 : 9;  // tiles per wave
+  // Tile (r, c) of slot j of wave w; false when the slot is unused.
+  __device__ static __forceinline__ bool slot(int w, int j, int& r, int& c) {
+    const int pr = w & 7, g = NW == 8 ? j : 2 * j + (w >> 3);
+    if (g <= pr) {
+      r = pr;
+      c = g;
+    } else {
+      r = 15 - pr;
+      c = g - pr - 1;
+    }
+    return g < 17;
   }
-  return g < 17;
-}
+};
 
-__global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                        int level) {
+template <int NW>
+__global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                           int level) {
+  using Map = InvMap<NW>;
+  constexpr int kInvSlots = Map::kSlots;
   extern __shared__ double lds[];
   double* Pc = lds;                  // 256 x kInvLdP: tile column p (two buffers
   double* Pc2 = Pc + 256 * kInvLdP;  //   in turn during the Cholesky)
@@ -321,7 +330,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
 #pragma unroll
   for (int j = 0; j < kInvSlots; ++j) {
     int r, c;
-    const bool on = inv_slot(w, j, r, c) && r < nt;
+    const bool on = Map::slot(w, j, r, c) && r < nt;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gr = 16 * r + 4 * v + lr, gc = 16 * c + lc;
@@ -335,7 +344,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
 #pragma unroll
   for (int j = 0; j < kInvSlots; ++j) {
     int r, c;
-    if (inv_slot(w, j, r, c) && r < nt && c == 0) {
+    if (Map::slot(w, j, r, c) && r < nt && c == 0) {
       double* dst = r == 0 ? Dd : Pc + (size_t)16 * r * kInvLdP;
 #pragma unroll
       for (int v = 0; v < 4; ++v) dst[(4 * v + lr) * kInvLdP + lc] = T[j][v];
@@ -408,7 +417,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
     for (int j = 0; j < kInvSlots; ++j) {
       __builtin_amdgcn_sched_barrier(0);
       int r, c;
-      if (!inv_slot(wq, j, r, c) || r >= nt || r < p || c != p) continue;
+      if (!Map::slot(wq, j, r, c) || r >= nt || r < p || c != p) continue;
       d4_t x = {0.0, 0.0, 0.0, 0.0};
       if (r == p) {
 #pragma unroll
@@ -438,7 +447,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
     for (int j = 0; j < kInvSlots; ++j) {
       __builtin_amdgcn_sched_barrier(0);
       int r, c;
-      if (!inv_slot(wq, j, r, c) || r >= nt || r <= p || c <= p) continue;
+      if (!Map::slot(wq, j, r, c) || r >= nt || r <= p || c <= p) continue;
       d4_t acc = T[j];
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
@@ -469,7 +478,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
     for (int j = 0; j < kInvSlots; ++j) {
       __builtin_amdgcn_sched_barrier(0);
       int r, c;
-      if (!inv_slot(wq, j, r, c) || r >= nt) continue;
+      if (!Map::slot(wq, j, r, c) || r >= nt) continue;
       if (r > p && c == p) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) Pc[(16 * r + 4 * v + lr) * kInvLdP + lc] = T[j][v];
@@ -479,24 +488,25 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
       }
     }
     lds_barrier();
-    // X_pj = G_pp^{-1} acc_pj by wave j (j < p); X_pp = G_pp^{-1} by wave p
-    if (w <= p) {
+    // X_pj = G_pp^{-1} acc_pj (j < p) and X_pp = G_pp^{-1}, one tile per wave
+    // at a time
+    for (int jt = w; jt <= p; jt += NW) {
       d4_t x = {0.0, 0.0, 0.0, 0.0};
-      if (w < p) {
+      if (jt < p) {
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
           x = __builtin_amdgcn_mfma_f64_16x16x4f64(Xr[lc * kInvLdX + 16 * p + 4 * s4 + lr],
-                                                   Ar[(4 * s4 + lr) * kInvLdX + 16 * w + lc], x, 0, 0, 0);
+                                                   Ar[(4 * s4 + lr) * kInvLdX + 16 * jt + lc], x, 0, 0, 0);
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) x[v] = Xr[(4 * v + lr) * kInvLdX + 16 * p + lc];
       }
-      // columns 16w.. of Xr: wave w < p writes X_pw there (no wave reads
-      // them in this phase); for w == p they already hold X_pp
+      // columns 16jt.. of Xr: X_pj goes there for jt < p (no wave reads them
+      // in this phase); for jt == p they already hold X_pp
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        if (w < p) Xr[(4 * v + lr) * kInvLdX + 16 * w + lc] = x[v];
-        const int gr = 16 * p + 4 * v + lr, gc = 16 * w + lc;
+        if (jt < p) Xr[(4 * v + lr) * kInvLdX + 16 * jt + lc] = x[v];
+        const int gr = 16 * p + 4 * v + lr, gc = 16 * jt + lc;
         if (gr < m && gc < m) {
           Xg[gr + (size_t)m * gc] = x[v];
           XgT[gc + (size_t)m * gr] = x[v];
@@ -509,7 +519,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const ItemD* __restrict_
     for (int j = 0; j < kInvSlots; ++j) {
       __builtin_amdgcn_sched_barrier(0);
       int r, c;
-      if (!inv_slot(wq, j, r, c) || r >= nt || r <= p || c > p) continue;
+      if (!Map::slot(wq, j, r, c) || r >= nt || r <= p || c > p) continue;
       d4_t acc = T[j];
       if (c == p) acc = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1082,7 +1092,7 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
                               hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(potrf_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(chol_inv_kernel),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(chol_inv_kernel<kInvWaves>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInvLds);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(trsm_inv_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsmInvLds);
@@ -1100,7 +1110,8 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
       break;
     case kSplitPotrf:
       if (mm <= kInvMaxDofs)
-        hipLaunchKernelGGL(chol_inv_kernel, dim3(nitems), dim3(1024), kInvLds, st, items, ls, level);
+        hipLaunchKernelGGL(chol_inv_kernel<kInvWaves>, dim3(nitems), dim3(kInvWaves * 64), kInvLds, st, items, ls,
+                           level);
       else
         hipLaunchKernelGGL(potrf_kernel, dim3(nitems), dim3(512), (size_t)mm * 33 * 8, st, items, ls,
                            level);
