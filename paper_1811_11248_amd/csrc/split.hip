@@ -309,7 +309,6 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
   double* Dd = Pc2 + 256 * kInvLdP;  // 16 x kInvLdP: diagonal tile
   double* Xr = Dd + 16 * kInvLdP;    // 16 x kInvLdX: tile row p of X
   double* Ar = Xr + 16 * kInvLdX;    // 16 x kInvLdX: accumulators of tile row p
-  double* ri = Ar + 16 * kInvLdX;    // 16: reciprocals of the diagonal of G_pp
   __shared__ int sbad;
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
@@ -358,56 +357,56 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
     double* Pcur = (p & 1) ? Pc2 : Pc;   // tile column p
     double* Pnext = (p & 1) ? Pc : Pc2;  // tile column p + 1
     // wave 0: G_pp (lane r holds row r; reciprocal square roots from
-    // v_rsq_f64 refined by one Newton step), then G_pp^{-1} (lane c: column
-    // c) into the columns 16p.. of Xr, where the inverse below expects it
+    // v_rsq_f64 refined by one Newton step), then row r of G_pp^{-1} in the
+    // same lane by forward substitution across the lanes (readlane
+    // broadcasts), into the columns 16p.. of Xr, where the inverse below
+    // expects it
     if (w == 0) {
-      {
-        double row[16];
+      double row[16], rdl = 1.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) row[u] = lane < 16 ? Dd[lane * kInvLdP + u] : 0.0;
+      for (int u = 0; u < 16; ++u) row[u] = lane < 16 ? Dd[lane * kInvLdP + u] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          double d = readlane_d(row[u], u);
-          if (!(d > 0.0)) {
-            if (lane == 0) sbad = 1;
-            d = 1.0;
-          }
-          double y = __builtin_amdgcn_rsq(d);
-          y = y + y * (0.5 - 0.5 * d * y * y);
-          if (lane == u) {
-            row[u] = d * y;
-            ri[u] = y;
-          } else if (lane > u) {
-            row[u] = row[u] * y;
-          }
-#pragma unroll
-          for (int v = u + 1; v < 16; ++v) {
-            const double lvu = readlane_d(row[u], v);
-            if (lane >= v && lane < 16) row[v] -= row[u] * lvu;
-          }
+      for (int u = 0; u < 16; ++u) {
+        double d = readlane_d(row[u], u);
+        if (!(d > 0.0)) {
+          if (lane == 0) sbad = 1;
+          d = 1.0;
         }
-        if (lane < 16) {
+        double y = __builtin_amdgcn_rsq(d);
+        y = y + y * (0.5 - 0.5 * d * y * y);
+        if (lane == u) {
+          row[u] = d * y;
+          rdl = y;
+        } else if (lane > u) {
+          row[u] = row[u] * y;
+        }
 #pragma unroll
-          for (int u = 0; u < 16; ++u) Dd[lane * kInvLdP + u] = u <= lane ? row[u] : 0.0;
+        for (int v = u + 1; v < 16; ++v) {
+          const double lvu = readlane_d(row[u], v);
+          if (lane >= v && lane < 16) row[v] -= row[u] * lvu;
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");  // Dd, ri written before read
-      __builtin_amdgcn_wave_barrier();
-      if (lane < 16) {
-        double y[16];
+      double Y[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          double s0 = r == lane ? 1.0 : 0.0, s1 = 0.0;
+      for (int c = 0; c < 16; ++c) Y[c] = 0.0;
 #pragma unroll
-          for (int q = 0; q + 1 < r; q += 2) {
-            s0 -= Dd[r * kInvLdP + q] * y[q];
-            s1 -= Dd[r * kInvLdP + q + 1] * y[q + 1];
-          }
-          if (r & 1) s0 -= Dd[r * kInvLdP + r - 1] * y[r - 1];
-          y[r] = (s0 + s1) * ri[r];
+      for (int q = 0; q < 16; ++q) {
+        if (lane == q) {
+#pragma unroll
+          for (int c = 0; c <= q; ++c) Y[c] = ((c == q ? 1.0 : 0.0) - Y[c]) * rdl;
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) Xr[r * kInvLdX + 16 * p + lane] = y[r];
+        for (int c = 0; c <= q; ++c) {
+          const double yqc = readlane_d(Y[c], q);
+          if (lane > q) Y[c] += row[q] * yqc;
+        }
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          Dd[lane * kInvLdP + u] = u <= lane ? row[u] : 0.0;
+          Xr[lane * kInvLdX + 16 * p + u] = u <= lane ? Y[u] : 0.0;
+        }
       }
     }
     lds_barrier();
