@@ -512,7 +512,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
       // levels with split clusters run one launch per colour (plus its units)
       const bool per_colour = F->exec_mode == 1 || sweep_units(true, L.max_m, L.max_acap) > 0;
       if (per_colour ||
-          launch_sweep_level(true, L.d_items, L.d_cstart, p.ncolours, L.max_items, L.max_m, L.max_acap, L.ls, V,
+          launch_sweep_level(true, L.d_items, L.d_cstart, p.ncolours, p.cstart.back(), L.max_items, L.max_m, L.max_acap, L.ls, V,
                              st) != hipSuccess) {
         if (!per_colour) (void)hipGetLastError();
         for (int c = 0; c < p.ncolours; ++c)
@@ -542,7 +542,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
       TimedLaunch tl(2, st);
       const bool per_colour = F->exec_mode == 1 || sweep_units(false, L.max_m, L.max_acap) > 0;
       if (per_colour ||
-          launch_sweep_level(false, L.d_items, L.d_cstart, p.ncolours, L.max_items, L.max_m, L.max_acap, L.ls, V,
+          launch_sweep_level(false, L.d_items, L.d_cstart, p.ncolours, p.cstart.back(), L.max_items, L.max_m, L.max_acap, L.ls, V,
                              st) != hipSuccess) {
         if (!per_colour) (void)hipGetLastError();
         for (int c = p.ncolours - 1; c >= 0; --c)

@@ -722,7 +722,7 @@ lrsp_status apply_cols(lrsp_batch* F, const double* b, double* x, int nrhs, bool
       // levels with split clusters run one launch per colour (plus its units)
       const bool per_colour = sweep_units(true, B.max_m, B.max_acap) > 0;
       if (per_colour ||
-          launch_sweep_level(true, B.d_items, B.d_cstart, B.ncolours, B.max_items, B.max_m, B.max_acap, B.ls, V, st, 0,
+          launch_sweep_level(true, B.d_items, B.d_cstart, B.ncolours, B.cstart.back(), B.max_items, B.max_m, B.max_acap, B.ls, V, st, 0,
                              graph ? sweep_bar(F, l, true) : nullptr) != hipSuccess) {
         if (!per_colour) {
           if (graph) return fail(LRSP_ERR_HIP, "persistent sweep launch failed");
@@ -741,7 +741,7 @@ lrsp_status apply_cols(lrsp_batch* F, const double* b, double* x, int nrhs, bool
         TimedLaunch tl(2, st);
         const bool per_colour = sweep_units(false, B.max_m, B.max_acap) > 0;
         if (per_colour ||
-            launch_sweep_level(false, B.d_items, B.d_cstart, B.ncolours, B.max_items, B.max_m, B.max_acap, B.ls, V,
+            launch_sweep_level(false, B.d_items, B.d_cstart, B.ncolours, B.cstart.back(), B.max_items, B.max_m, B.max_acap, B.ls, V,
                                st, 0, graph ? sweep_bar(F, l, false) : nullptr) != hipSuccess) {
           if (!per_colour) {
             if (graph) return fail(LRSP_ERR_HIP, "persistent sweep launch failed");

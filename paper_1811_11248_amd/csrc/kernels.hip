@@ -1505,23 +1505,61 @@ size_t sweep_lds(int max_m) {
 // readlane, the near-field products run one lane per column (forward) or
 // per row (backward).  MB >= m bounds the row slots kept in registers.
 
-// y_s <- U^T G^{-1} y_s; y_n -= F^T y_f.
+// What a wave needs of a small cluster in the sweeps (piv may point to an
+// LDS copy).
+struct WaveItem {
+  const double* P;
+  const double* tau;
+  const int64_t* vidx;
+  const int32_t* piv;
+  int64_t voff;
+  int32_t m, k, a, pad;
+};
+
+static_assert(sizeof(WaveItem) + 4 * kSweepWaveM <= kSweepWaveTableBytes, "wave table entry");
+
+__device__ __forceinline__ WaveItem wave_item(const ItemD& it, LevelState ls) {
+  return WaveItem{it.P, it.tau, it.vidx, it.piv, it.voff, it.m, ls.k[it.s], ls.a[it.s], 0};
+}
+
+// y_s <- U^T G^{-1} y_s; y_n -= F^T y_f.  For MB <= 32 every load that does
+// not depend on the computation (G, the reflectors, the first 64 columns of
+// F with their targets and the targets' old values) is issued up front.
 template <int MB>
-__device__ void fwd_wave(const ItemD& it, LevelState ls, double* vec) {
+__device__ void fwd_wave(const WaveItem& wi, double* vec) {
+  constexpr bool PF = MB <= 32;
   const int lane = threadIdx.x & 63;
-  const int m = it.m;
+  const int m = wi.m;
   if (m == 0) return;
-  const int k = ls.k[it.s], a = ls.a[it.s];
+  const int k = wi.k, a = wi.a;
   const bool on = lane < m;
-  const double* G = it.P;
+  const double* G = wi.P;
+  const double* Wf = wi.P + (size_t)m * (m + a);
+  const double* C = wi.P + (size_t)m * m;
   double g[MB];  // row `lane` of G, columns < lane
 #pragma unroll
   for (int j = 0; j < MB; ++j) g[j] = (on && j < lane) ? G[lane + (size_t)m * j] : 0.0;
-  const double rd = 1.0 / (on ? G[lane + (size_t)m * lane] : 1.0);
-  const int pv = lane < k ? it.piv[lane] : 0;
-  const double tv = lane < k ? it.tau[lane] : 0.0;
-  double* yg = vec + it.voff;
+  const double gd = on ? G[lane + (size_t)m * lane] : 1.0;
+  const int pv = lane < k ? wi.piv[lane] : 0;
+  const double tv = lane < k ? wi.tau[lane] : 0.0;
+  double* yg = vec + wi.voff;
   double y = on ? yg[lane] : 0.0;
+  double vr[PF ? 16 : 1];  // reflector j < 16 at row `lane`
+  double f0[PF ? MB : 1];  // column `lane` of F (first 64 columns)
+  double old0 = 0.0;
+  const bool cv0 = lane < a;
+  if constexpr (PF) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int pj = __builtin_amdgcn_readlane(pv, j);
+      vr[j] = (j < k) ? (lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0)) : 0.0;
+    }
+    const double* Cc = C + (size_t)m * (cv0 ? lane : 0);
+#pragma unroll
+    for (int i = 0; i < MB; ++i) f0[i] = (cv0 && i >= k && i < m) ? Cc[i] : 0.0;
+    if (cv0) old0 = vec[wi.vidx[lane]];
+  }
+  const double rd = 1.0 / gd;
   // G^{-1}
 #pragma unroll
   for (int j = 0; j < MB; ++j) {
@@ -1531,22 +1569,41 @@ __device__ void fwd_wave(const ItemD& it, LevelState ls, double* vec) {
       else y -= g[j] * yj;
     }
   }
-  // U^T: reflectors 0..k-1
-  const double* Wf = it.P + (size_t)m * (m + a);
-  for (int j = 0; j < k; ++j) {
-    const int pj = __builtin_amdgcn_readlane(pv, j);
-    const double v = lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0);
-    const double sj = wave_sum(v * y);
-    y -= (readlane_d(tv, j) * sj) * v;
+  // U^T: reflectors 0..k-1 (the first 16 prefetched)
+  int j1 = 0;
+  if constexpr (PF) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j < k) {
+        const double sj = wave_sum(vr[j] * y);
+        y -= (readlane_d(tv, j) * sj) * vr[j];
+      }
+    }
+    j1 = 16;
   }
-  if (on) yg[lane] = y;
+  {
+    for (int j = j1; j < k; ++j) {
+      const int pj = __builtin_amdgcn_readlane(pv, j);
+      const double v = lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0);
+      const double sj = wave_sum(v * y);
+      y -= (readlane_d(tv, j) * sj) * v;
+    }
+  }
   // y_n -= F^T y_f, F = C[k:m, :], one lane per column
-  const double* C = it.P + (size_t)m * m;
   for (int c0 = 0; c0 < a; c0 += 64) {
     const int c = c0 + lane;
     const bool cv = c < a;
-    const double* Cc = C + (size_t)m * (cv ? c : 0);
     double s = 0.0;
+    if (PF && c0 == 0) {
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        const double yi = readlane_d(y, i);
+        if (cv && i >= k && i < m) s += f0[i] * yi;
+      }
+      if (cv) vec[wi.vidx[c]] = old0 - s;
+      continue;
+    }
+    const double* Cc = C + (size_t)m * (cv ? c : 0);
     for (int i0 = 0; i0 < m; i0 += 16) {
       double f[16];
 #pragma unroll
@@ -1561,31 +1618,63 @@ __device__ void fwd_wave(const ItemD& it, LevelState ls, double* vec) {
         if (cv && i >= k && i < m) s += f[u] * yi;
       }
     }
-    if (cv) vec[it.vidx[c]] -= s;
+    if (cv) vec[wi.vidx[c]] -= s;
   }
+  if (on) yg[lane] = y;
 }
 
-// x_f -= F x_n; x_s <- G^{-T} U x_s.
+// x_f -= F x_n; x_s <- G^{-T} U x_s.  For MB <= 32 the loads of G, the
+// reflectors, the first 32 columns of F and their x_n are issued up front.
 template <int MB>
-__device__ void bwd_wave(const ItemD& it, LevelState ls, double* vec) {
+__device__ void bwd_wave(const WaveItem& wi, double* vec) {
+  constexpr bool PF = MB <= 32;
   const int lane = threadIdx.x & 63;
-  const int m = it.m;
+  const int m = wi.m;
   if (m == 0) return;
-  const int k = ls.k[it.s], a = ls.a[it.s];
+  const int k = wi.k, a = wi.a;
   const bool on = lane < m;
-  const double* G = it.P;
-  const double rd = 1.0 / (on ? G[lane + (size_t)m * lane] : 1.0);
-  const int pv = lane < k ? it.piv[lane] : 0;
-  const double tv = lane < k ? it.tau[lane] : 0.0;
-  double* xg = vec + it.voff;
-  double x = on ? xg[lane] : 0.0;
-  // x_f -= F x_n, one lane per row, columns in order
-  const double* C = it.P + (size_t)m * m;
+  const double* G = wi.P;
+  const double* Wf = wi.P + (size_t)m * (m + a);
+  const double* C = wi.P + (size_t)m * m;
   const bool fine = on && lane >= k;
+  const double gd = on ? G[lane + (size_t)m * lane] : 1.0;
+  const int pv = lane < k ? wi.piv[lane] : 0;
+  const double tv = lane < k ? wi.tau[lane] : 0.0;
+  double* xg = vec + wi.voff;
+  double x = on ? xg[lane] : 0.0;
+  double gc[MB];  // column `lane` of G, rows > lane
+#pragma unroll
+  for (int j = 0; j < MB; ++j) gc[j] = (on && j > lane && j < m) ? G[j + (size_t)m * lane] : 0.0;
+  double vr[PF ? 16 : 1];   // reflector j < 16 at row `lane`
+  double f0[PF ? 32 : 1];  // row `lane` of F, first 32 columns
+  double xn0 = 0.0;
+  const int nc0 = min(32, a);
+  if constexpr (PF) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int pj = __builtin_amdgcn_readlane(pv, j);
+      vr[j] = (j < k) ? (lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0)) : 0.0;
+    }
+    const double* Cr = C + (size_t)(fine ? lane : 0);
+#pragma unroll
+    for (int q = 0; q < 32; ++q) f0[q] = (fine && q < nc0) ? Cr[(size_t)m * q] : 0.0;
+    if (lane < nc0) xn0 = vec[wi.vidx[lane]];
+  }
+  const double rd = 1.0 / gd;
+  // x_f -= F x_n, one lane per row, columns in order
   double s = 0.0;
-  for (int c0 = 0; c0 < a; c0 += 64) {
+  int c0 = 0;
+  if constexpr (PF) {
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const double xq = readlane_d(xn0, q);
+      if (q < nc0) s += f0[q] * xq;
+    }
+    c0 = nc0;
+  }
+  for (; c0 < a; c0 += 64) {
     const int nc = min(64, a - c0);
-    const double xn = lane < nc ? vec[it.vidx[c0 + lane]] : 0.0;
+    const double xn = lane < nc ? vec[wi.vidx[c0 + lane]] : 0.0;
     const double* Cr = C + (size_t)(fine ? lane : 0) + (size_t)m * c0;
     for (int cb = 0; cb < nc; cb += 16) {
       double f[16];
@@ -1599,18 +1688,23 @@ __device__ void bwd_wave(const ItemD& it, LevelState ls, double* vec) {
     }
   }
   if (fine) x -= s;
-  // U: reflectors k-1..0
-  const double* Wf = it.P + (size_t)m * (m + a);
-  for (int j = k - 1; j >= 0; --j) {
+  // U: reflectors k-1..0 (the first 16 prefetched)
+  for (int j = k - 1; j >= (PF ? 16 : 0); --j) {
     const int pj = __builtin_amdgcn_readlane(pv, j);
     const double v = lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0);
     const double sj = wave_sum(v * x);
     x -= (readlane_d(tv, j) * sj) * v;
   }
-  // G^{-T}
-  double gc[MB];  // column `lane` of G, rows > lane
+  if constexpr (PF) {
 #pragma unroll
-  for (int j = 0; j < MB; ++j) gc[j] = (on && j > lane && j < m) ? G[j + (size_t)m * lane] : 0.0;
+    for (int j = 15; j >= 0; --j) {
+      if (j < k) {
+        const double sj = wave_sum(vr[j] * x);
+        x -= (readlane_d(tv, j) * sj) * vr[j];
+      }
+    }
+  }
+  // G^{-T}
 #pragma unroll
   for (int j = MB - 1; j >= 0; --j) {
     if (j < m) {
@@ -1624,26 +1718,44 @@ __device__ void bwd_wave(const ItemD& it, LevelState ls, double* vec) {
 
 #define LRSP_WAVE_DISPATCH(FN, ...)         \
   do {                                      \
-    if (it.m <= 16) FN<16>(__VA_ARGS__);    \
-    else if (it.m <= 32) FN<32>(__VA_ARGS__); \
-    else FN<64>(__VA_ARGS__);               \
+    if (wi.m <= 16) FN<16>(__VA_ARGS__);    \
+    else FN<32>(__VA_ARGS__);               \
   } while (0)
 
 // One launch per level and sweep direction for levels whose clusters all
 // have at most kSweepWaveM DoFs: every wave takes a cluster of the colour;
-// one workgroup needs no grid barrier between colours.
+// one workgroup needs no grid barrier between colours.  With table != 0 the
+// descriptors, ranks and pivots of all the level's clusters are first copied
+// to LDS (kSweepWaveTableBytes per cluster), which takes their loads off the
+// path of every colour.
 template <bool FWD, bool SW>
 __global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const ItemD* __restrict__ items,
                                                                        const int32_t* __restrict__ cstart,
                                                                        int ncolours, LevelState ls,
-                                                                       double* vec, GridBar* bar) {
+                                                                       double* vec, GridBar* bar, int table) {
+  extern __shared__ double dlds[];
   const int wv = threadIdx.x >> 6, nw = kSweepWaveThreads / 64;
+  const int ni = cstart[ncolours];
+  WaveItem* tab = reinterpret_cast<WaveItem*>(dlds);
+  int32_t* pvs = reinterpret_cast<int32_t*>(tab + (table ? ni : 0));
+  if (table) {
+    for (int i = threadIdx.x; i < ni; i += kSweepWaveThreads) tab[i] = wave_item(items[i], ls);
+    __syncthreads();
+    for (int e = threadIdx.x; e < ni * kSweepWaveM; e += kSweepWaveThreads) {
+      const int i = e / kSweepWaveM, j = e - i * kSweepWaveM;
+      pvs[e] = j < tab[i].k ? tab[i].piv[j] : 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ni; i += kSweepWaveThreads) tab[i].piv = pvs + (size_t)kSweepWaveM * i;
+    __syncthreads();
+  }
   for (int q = 0; q < ncolours; ++q) {
     const int c = FWD ? q : ncolours - 1 - q;
     for (int i = cstart[c] + blockIdx.x * nw + wv; i < cstart[c + 1]; i += gridDim.x * nw) {
       const ItemD& it = items[i];
-      if (FWD) LRSP_WAVE_DISPATCH(fwd_wave, it, ls, vec);
-      else LRSP_WAVE_DISPATCH(bwd_wave, it, ls, vec);
+      const WaveItem wi = table ? tab[i] : wave_item(it, ls);
+      if (FWD) LRSP_WAVE_DISPATCH(fwd_wave, wi, vec);
+      else LRSP_WAVE_DISPATCH(bwd_wave, wi, vec);
     }
     if (gridDim.x == 1) __syncthreads();
     else if constexpr (SW) sw_grid_sync(bar, gridDim.x);
@@ -1663,7 +1775,10 @@ __global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const Ite
 // the schedule, so that every schedule gives the same bits.
 __device__ __forceinline__ void fwd_any(const ItemD& it, bool split, LevelState ls, double* vec, double* lds) {
   if (it.m <= kSweepWaveM) {
-    if (threadIdx.x < 64) LRSP_WAVE_DISPATCH(fwd_wave, it, ls, vec);
+    if (threadIdx.x < 64) {
+      const WaveItem wi = wave_item(it, ls);
+      LRSP_WAVE_DISPATCH(fwd_wave, wi, vec);
+    }
     __syncthreads();
   } else if (split && it.m >= kSweepSplitM) {
     LRSP_ROWS_DISPATCH(fwd_head, it, ls, vec, lds);
@@ -1674,7 +1789,10 @@ __device__ __forceinline__ void fwd_any(const ItemD& it, bool split, LevelState 
 
 __device__ __forceinline__ void bwd_any(const ItemD& it, bool split, LevelState ls, double* vec, double* lds) {
   if (it.m <= kSweepWaveM) {
-    if (threadIdx.x < 64) LRSP_WAVE_DISPATCH(bwd_wave, it, ls, vec);
+    if (threadIdx.x < 64) {
+      const WaveItem wi = wave_item(it, ls);
+      LRSP_WAVE_DISPATCH(bwd_wave, wi, vec);
+    }
     __syncthreads();
   } else if (split && it.m >= kSweepSplitM) {
     LRSP_ROWS_DISPATCH(bwd_tail, it, ls, vec, lds);
@@ -1816,28 +1934,37 @@ void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelSt
 }
 
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
-                              int max_items, int max_m, int max_acap, LevelState ls, double* vec,
+                              int nitems, int max_items, int max_m, int max_acap, LevelState ls, double* vec,
                               hipStream_t st, int grid_cap, GridBar* bar) {
   if (max_m <= kSweepWaveM) {
     constexpr int nw = kSweepWaveThreads / 64;
     int want = std::max(1, (max_items + nw - 1) / nw);
     if (grid_cap > 0) want = std::min(want, grid_cap);
+    static bool lds_ok[4] = {false, false, false, false};
+    const size_t tbytes = (size_t)nitems * kSweepWaveTableBytes;
+    int table = tbytes <= kSweepWaveTableMax ? 1 : 0;
+    const size_t lds = table ? tbytes : 0;
     if (want == 1 || bar) {
       const int g = std::min(want, device_cus());
+      const void* fn = forward ? reinterpret_cast<const void*>(sweep_wave_kernel<true, true>)
+                               : reinterpret_cast<const void*>(sweep_wave_kernel<false, true>);
+      allow_lds(fn, &lds_ok[forward ? 0 : 1]);
       if (forward)
-        hipLaunchKernelGGL((sweep_wave_kernel<true, true>), dim3(g), dim3(kSweepWaveThreads), 0, st, items, cstart,
-                           ncolours, ls, vec, bar);
+        hipLaunchKernelGGL((sweep_wave_kernel<true, true>), dim3(g), dim3(kSweepWaveThreads), lds, st, items, cstart,
+                           ncolours, ls, vec, bar, table);
       else
-        hipLaunchKernelGGL((sweep_wave_kernel<false, true>), dim3(g), dim3(kSweepWaveThreads), 0, st, items,
-                           cstart, ncolours, ls, vec, bar);
+        hipLaunchKernelGGL((sweep_wave_kernel<false, true>), dim3(g), dim3(kSweepWaveThreads), lds, st, items,
+                           cstart, ncolours, ls, vec, bar, table);
       return hipGetLastError();
     }
     const void* fn = forward ? reinterpret_cast<const void*>(sweep_wave_kernel<true, false>)
                              : reinterpret_cast<const void*>(sweep_wave_kernel<false, false>);
-    const int g = coop_grid(fn, 0, want, grid_cap);
+    allow_lds(fn, &lds_ok[forward ? 2 : 3]);
+    const int g = coop_grid(fn, lds, want, grid_cap);
     GridBar* none = nullptr;
-    void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&vec, (void*)&none};
-    return hipLaunchCooperativeKernel(fn, dim3(g), dim3(kSweepWaveThreads), args, 0, st);
+    void* args[] = {(void*)&items, (void*)&cstart, (void*)&ncolours, (void*)&ls, (void*)&vec, (void*)&none,
+                    (void*)&table};
+    return hipLaunchCooperativeKernel(fn, dim3(g), dim3(kSweepWaveThreads), args, lds, st);
   }
   allow_sweep_lds();
   const size_t lds = sweep_lds(max_m);

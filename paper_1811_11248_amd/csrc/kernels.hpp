@@ -59,8 +59,10 @@ constexpr int kSweepCols = 64;
 constexpr int kSweepRows = 32;
 // Clusters of at most kSweepWaveM DoFs are swept by one wave; levels of such
 // clusters run in workgroups of kSweepWaveThreads threads.
-constexpr int kSweepWaveM = 64;
+constexpr int kSweepWaveM = 32;
 constexpr int kSweepWaveThreads = 512;
+constexpr size_t kSweepWaveTableBytes = 56 + 4 * kSweepWaveM;  // per cluster: descriptor + pivots
+constexpr size_t kSweepWaveTableMax = 96 * 1024;
 int sweep_units(bool forward, int max_m, int max_acap);
 // The items of one colour (one launch, plus one for the units).
 void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
@@ -69,7 +71,7 @@ void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelSt
                 hipStream_t st);
 // A whole level in one persistent launch.
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
-                              int max_items, int max_m, int max_acap, LevelState ls, double* vec,
+                              int nitems, int max_items, int max_m, int max_acap, LevelState ls, double* vec,
                               hipStream_t st, int grid_cap = 0, GridBar* bar = nullptr);
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st);
 // Dense tops of a batch, one workgroup per system (n <= kMaxClusterDofs).
