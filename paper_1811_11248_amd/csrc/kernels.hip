@@ -752,8 +752,462 @@ __device__ bool seg_scan(const ItemD& it, LevelState ls, int level, int* soff, i
   return !bad;
 }
 
+// ---------------------------------------------------------------------------
+// Clusters of at most kTinyM DoFs whose block row fits kTinyLdsBytes of LDS:
+// the block row [A_ss | A_sn | A_sw] is gathered once into LDS; the
+// Cholesky, the scaling, the pivoted QR and the rotation then run in wave 0
+// on that copy (one column per lane, lanes exchange data through LDS within
+// the wave, no workgroup barrier); all waves join again for the Schur
+// scatter, the coarse row and the store of the factor pieces.  The pivot and
+// stop rules are those of cpqr.  Whether a cluster takes this form depends
+// on its sizes alone, so every schedule gives it the same arithmetic.
+constexpr int kTinyM = 32;
+constexpr size_t kTinyLdsBytes = 64 * 1024;
+
+// LDS scratch (doubles) of the per-cluster elimination for clusters of at
+// most max_m DoFs: the blocked Cholesky's panels, and room for the
+// small-cluster form.
+__host__ __device__ __forceinline__ size_t slre_scratch(int max_m) {
+  const size_t chol = (size_t)max_m * kNB + kNB * kNB + kNB * 256;
+  return chol > kTinyLdsBytes / 8 ? chol : kTinyLdsBytes / 8;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__host__ __device__ __forceinline__ size_t tiny_al(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// Byte offsets of the LDS sections of the small-cluster form.  The pair
+// descriptors are staged only when they fit too (else read from memory).
+struct TinyLayout {
+  int ldp;  // odd leading dimension of the panel copy
+  size_t p, src, nrm, tau, cseg, cnat, stp, piv, wb, pair, end, end_pairs;
+};
+
+__host__ __device__ __forceinline__ TinyLayout tiny_layout(int m, int a, int b, int nseg, int np) {
+  TinyLayout L;
+  const size_t nc = (size_t)m + a + b;
+  L.ldp = m | 1;
+  L.p = 0;
+  L.src = L.p + tiny_al(8 * (size_t)L.ldp * nc);
+  L.nrm = L.src + tiny_al(8 * nc);
+  L.tau = L.nrm + tiny_al(8 * (size_t)b);
+  L.cseg = L.tau + tiny_al(8 * (size_t)kTinyM);
+  L.cnat = L.cseg + tiny_al(4 * ((size_t)a + b));
+  L.stp = L.cnat + tiny_al(4 * ((size_t)a + b));
+  L.piv = L.stp + tiny_al(4 * (size_t)b);
+  L.wb = L.piv + tiny_al(4 * (size_t)kTinyM);
+  L.pair = L.wb + tiny_al(sizeof(WbD) * (size_t)nseg);
+  L.end = L.pair;
+  L.end_pairs = L.pair + tiny_al(sizeof(PairD) * (size_t)np);
+  return L;
+}
+
+__device__ __forceinline__ bool tiny_fits(int m, int a, int b, int nseg, int nsegn) {
+  return m <= kTinyM && tiny_layout(m, a, b, nseg, nsegn * (nsegn + 1) / 2).end <= kTinyLdsBytes;
+}
+
+// Cholesky of the m x m lower triangle of the panel copy (ld ldp) by one
+// wave, lane i holding row i; pivots that are not > 0 set bad and are
+// replaced by 1.
+template <int MB>
+__device__ void tiny_chol(double* Ps, int ldp, int m, int lane, bool& bad) {
+  double row[MB];
+#pragma unroll
+  for (int u = 0; u < MB; ++u) row[u] = (lane < m && u <= lane) ? Ps[lane + ldp * u] : 0.0;
+#pragma unroll
+  for (int u = 0; u < MB; ++u) {
+    if (u < m) {
+      double d = readlane_d(row[u], u);
+      if (!(d > 0.0)) {
+        bad = true;
+        d = 1.0;
+      }
+      d = sqrt(d);
+      if (lane == u) row[u] = d;
+      else if (lane > u) row[u] = row[u] / d;
+#pragma unroll
+      for (int v = u + 1; v < MB; ++v) {
+        if (v < m) {
+          const double lvu = readlane_d(row[u], v);
+          if (lane >= v && lane < m) row[v] -= row[u] * lvu;
+        }
+      }
+    }
+  }
+  if (lane < m) {
+#pragma unroll
+    for (int u = 0; u < MB; ++u)
+      if (u <= lane) Ps[lane + ldp * u] = row[u];
+  }
+}
+
+// x <- G^{-1} x for the a + b off-diagonal columns of the panel copy, one
+// column per lane; squared norms of the far-field columns into nrm.
+template <int MB>
+__device__ void tiny_scale(double* Ps, int ldp, int m, int a, int b, double* nrm, int* stp, int lane) {
+  for (int c = lane; c < a + b; c += 64) {
+    double* y = Ps + (size_t)ldp * (m + c);
+    double x[MB];
+#pragma unroll
+    for (int u = 0; u < MB; ++u) x[u] = u < m ? y[u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+      if (u < m) {
+        double s = x[u];
+#pragma unroll
+        for (int v = 0; v < u; ++v) s -= Ps[u + ldp * v] * x[v];
+        x[u] = s / Ps[u + ldp * u];
+      }
+    }
+    double nn = 0.0;
+#pragma unroll
+    for (int u = 0; u < MB; ++u)
+      if (u < m) {
+        y[u] = x[u];
+        nn += x[u] * x[u];
+      }
+    if (c >= a) {
+      nrm[c - a] = nn;
+      stp[c - a] = -1;
+    }
+  }
+}
+
+__device__ void slre_tiny(const ItemD& it, LevelState ls, int level, double tol, int tol_mode, int prec,
+                          char* lds, const int* soff, int a, int b) {
+  __shared__ int sk, sbad2, sover;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = it.m, nseg = it.nseg, nsn = it.nsegn;
+  const int np = nsn * (nsn + 1) / 2;
+  const TinyLayout L = tiny_layout(m, a, b, nseg, np);
+  const bool pairs_lds = L.end_pairs <= kTinyLdsBytes;
+  const int ldp = L.ldp;
+  const int nc = m + a + b;
+  double* Ps = reinterpret_cast<double*>(lds + L.p);
+  const double** srcp = reinterpret_cast<const double**>(lds + L.src);
+  double* nrm = reinterpret_cast<double*>(lds + L.nrm);
+  double* taus = reinterpret_cast<double*>(lds + L.tau);
+  int* cseg = reinterpret_cast<int*>(lds + L.cseg);
+  int* cnat = reinterpret_cast<int*>(lds + L.cnat);
+  int* stp = reinterpret_cast<int*>(lds + L.stp);
+  int* pv = reinterpret_cast<int*>(lds + L.piv);
+  WbD* wbs = reinterpret_cast<WbD*>(lds + L.wb);
+  PairD* ps = reinterpret_cast<PairD*>(lds + L.pair);
+  // column sources and indices; write-back and pair descriptors to LDS
+  for (int pc = tid; pc < a + b; pc += kThreads) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (soff[mid] <= pc) lo = mid;
+      else hi = mid - 1;
+    }
+    const SegD& sg = it.seg[lo];
+    const int loc = pc - soff[lo];
+    const int nat = sg.coarse ? loc : sg.zl[loc];
+    cseg[pc] = lo;
+    cnat[pc] = nat;
+    it.colseg[pc] = lo;
+    it.colnat[pc] = nat;
+    it.vidx[pc] = sg.voff + nat;
+    srcp[m + pc] = sg.src + (size_t)m * loc;
+  }
+  for (int c = tid; c < m; c += kThreads) srcp[c] = it.D + (size_t)m * c;
+  {
+    constexpr int kW = (int)(sizeof(WbD) / sizeof(double));
+    constexpr int kP = (int)(sizeof(PairD) / sizeof(double));
+    static_assert(sizeof(WbD) % sizeof(double) == 0 && sizeof(PairD) % sizeof(double) == 0, "staged as doubles");
+    const int nw = kW * nseg, npd = pairs_lds ? kP * np : 0;
+    const double* ws = reinterpret_cast<const double*>(it.wb);
+    const double* pg = reinterpret_cast<const double*>(it.pair);
+    double* wd = reinterpret_cast<double*>(wbs);
+    double* pd = reinterpret_cast<double*>(ps);
+    for (int e0 = tid; e0 < nw + npd; e0 += kThreads * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        v[u] = e < nw ? ws[e] : (e < nw + npd ? pg[e - nw] : 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < nw) wd[e] = v[u];
+        else if (e < nw + npd) pd[e - nw] = v[u];
+      }
+    }
+  }
+  if (tid == 0) {
+    sbad2 = 0;
+    sover = 0;
+  }
+  __syncthreads();
+  // gather the block row, sixteen loads in flight per thread
+  const int ne = m * nc;
+  for (int e0 = tid; e0 < ne; e0 += kThreads * 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + u * kThreads;
+      v[u] = 0.0;
+      if (e < ne) {
+        const int c = e / m, r = e - c * m;
+        v[u] = srcp[c][r];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < ne) {
+        const int c = e / m, r = e - c * m;
+        Ps[r + (size_t)ldp * c] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  if (wv == 0) {
+    // S_s: Cholesky and scaling of the block row
+    bool bad = false;
+    if (m <= 8) {
+      tiny_chol<8>(Ps, ldp, m, lane, bad);
+      wave_lds_sync();
+      tiny_scale<8>(Ps, ldp, m, a, b, nrm, stp, lane);
+    } else if (m <= 16) {
+      tiny_chol<16>(Ps, ldp, m, lane, bad);
+      wave_lds_sync();
+      tiny_scale<16>(Ps, ldp, m, a, b, nrm, stp, lane);
+    } else {
+      tiny_chol<32>(Ps, ldp, m, lane, bad);
+      wave_lds_sync();
+      tiny_scale<32>(Ps, ldp, m, a, b, nrm, stp, lane);
+    }
+    wave_lds_sync();
+    // compression of the scaled far field
+    double* Wf = Ps + (size_t)ldp * (m + a);
+    const int kmax = min(m, b);
+    int k = kmax;
+    bool over = false;
+    double r00 = 0.0;
+    for (int j = 0; j < kmax; ++j) {
+      double mx = 0.0;
+      for (int c = lane; c < b; c += 64)
+        if (stp[c] < 0) mx = fmax(mx, nrm[c]);
+      mx = wave_max(mx);
+      const double thr = (1.0 - kTie) * mx;
+      int best = INT_MAX;
+      for (int c = lane; c < b; c += 64)
+        if (stp[c] < 0 && nrm[c] >= thr) best = min(best, c);
+      best = wave_min_int(best);
+      if (best == INT_MAX) {
+        k = j;
+        break;
+      }
+      const double rjj = sqrt(nrm[best]);
+      if (j == 0) r00 = rjj;
+      const bool stop = (tol_mode == 0) ? (rjj <= tol * r00) : (rjj <= tol);
+      if (stop || rjj == 0.0) {
+        k = j;
+        break;
+      }
+      if (j >= it.kcap) {
+        k = it.kcap;
+        over = true;
+        break;
+      }
+      double* x = Wf + (size_t)ldp * best;
+      const double xi = (lane > j && lane < m) ? x[lane] : 0.0;
+      const double rest = wave_sum(xi * xi);
+      const double alpha = x[j];
+      double d, tj;
+      if (alpha <= 0.0) {
+        d = alpha - rjj;
+        tj = (rjj - alpha) / rjj;
+      } else {
+        d = -rest / (alpha + rjj);
+        tj = rest / (rjj * (rjj + alpha));
+      }
+      if (d == 0.0) tj = 0.0;
+      wave_lds_sync();
+      if (d != 0.0 && lane > j && lane < m) x[lane] = xi / d;
+      if (lane == 0) {
+        x[j] = rjj;
+        pv[j] = best;
+        taus[j] = tj;
+        stp[best] = j;
+        it.piv[j] = best;
+        it.tau[j] = tj;
+      }
+      wave_lds_sync();
+      for (int c = lane; c < b; c += 64) {
+        if (stp[c] >= 0) continue;
+        double* y = Wf + (size_t)ldp * c;
+        double s = 0.0;
+        for (int i = j; i < m; ++i) s += (i == j ? 1.0 : x[i]) * y[i];
+        const double f = tj * s;
+        double nn = 0.0;
+        for (int i = j; i < m; ++i) {
+          const double nv = y[i] - f * (i == j ? 1.0 : x[i]);
+          y[i] = nv;
+          if (i > j) nn += nv * nv;
+        }
+        nrm[c] = nn;
+      }
+      wave_lds_sync();
+    }
+    // E_s: rotate the near-field columns, C = U^T G^{-1} A_sn
+    for (int c = lane; c < a; c += 64) {
+      double* y = Ps + (size_t)ldp * (m + c);
+      for (int j = 0; j < k; ++j) {
+        const double* x = Wf + (size_t)ldp * pv[j];
+        double s = 0.0;
+        for (int i = j; i < m; ++i) s += (i == j ? 1.0 : x[i]) * y[i];
+        const double f = taus[j] * s;
+        for (int i = j; i < m; ++i) y[i] -= f * (i == j ? 1.0 : x[i]);
+      }
+    }
+    if (lane == 0) {
+      sk = k;
+      sbad2 = bad ? 1 : 0;
+      sover = over ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  const int k = sk;
+  if (tid == 0) {
+    if (sbad2) item_error(it, ls.err, level, kErrNotSPD);
+    if (sover) item_error(it, ls.err, level, kErrCapacity);
+  }
+  // G_s: X_nn -= F^T F, F = rows k.. of the rotated near-field columns;
+  // eight read-modify-writes in flight per thread
+  if (m > k && a > 0) {
+    const int nel = a * (a + 1) / 2;
+    const PairD* pt = pairs_lds ? ps : it.pair;
+    for (int p0 = tid; p0 < nel; p0 += kThreads * 8) {
+      double val[8];
+      int cidx[8], row[8];
+      const PairD* pp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int p = p0 + u * kThreads;
+        val[u] = 0.0;
+        pp[u] = nullptr;
+        cidx[u] = 0;
+        row[u] = 0;
+        if (p < nel) {
+          int rr = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+          while (rr * (rr + 1) / 2 > p) --rr;
+          while ((rr + 1) * (rr + 2) / 2 <= p) ++rr;
+          const int cc = p - rr * (rr + 1) / 2;
+          const double* fr = Ps + (size_t)ldp * (m + rr);
+          const double* fc = Ps + (size_t)ldp * (m + cc);
+          if (prec == 0) {
+            double acc = 0.0;
+            for (int i = k; i < m; ++i) acc += fr[i] * fc[i];
+            val[u] = acc;
+          } else {
+            float accf = 0.0f;
+            for (int i = k; i < m; ++i) {
+              float x0 = (float)fr[i], x1 = (float)fc[i];
+              if (prec == 2) {
+                x0 = round_bf16(x0);
+                x1 = round_bf16(x1);
+              }
+              accf = fmaf(x0, x1, accf);
+            }
+            val[u] = (double)accf;
+          }
+          const int sr = cseg[rr], sc = cseg[cc], nr = cnat[rr], ncn = cnat[cc];
+          const int i = min(sr, sc), j = max(sr, sc);
+          const PairD* pd = pt + (j * (j + 1) / 2 + i);
+          pp[u] = pd;
+          if (pd->diag) {
+            row[u] = max(nr, ncn);
+            cidx[u] = min(nr, ncn);
+          } else {
+            const bool r_is_rowseg = (sr == (pd->rows_from_j ? j : i));
+            row[u] = r_is_rowseg ? nr : ncn;
+            cidx[u] = r_is_rowseg ? ncn : nr;
+          }
+        }
+      }
+      int col[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int32_t* pm = (pp[u] && !pp[u]->diag) ? pp[u]->posmap : nullptr;
+        col[u] = pm ? pm[cidx[u]] : cidx[u];
+      }
+      double* t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        t[u] = nullptr;
+        if (pp[u]) {
+          if (row[u] < 0 || col[u] < 0 || row[u] >= pp[u]->nrows || col[u] >= pp[u]->ncols)
+            item_error(it, ls.err, level, kErrIndex);
+          else
+            t[u] = pp[u]->dst + (size_t)row[u] + (size_t)pp[u]->ld * col[u];
+        }
+      }
+      double old[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) old[u] = t[u] ? *t[u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (t[u]) *t[u] = old[u] - val[u];
+    }
+  }
+  // coarse row of s: [I_k | C[:k] | V1^T]
+  for (int e = tid; e < k * (a + b); e += kThreads) {
+    const int r = e % k, pc = e / k;
+    const WbD& t = wbs[cseg[pc]];
+    const int cn = cnat[pc];
+    double v = Ps[r + (size_t)ldp * (m + pc)];
+    if (pc >= a) {
+      const int st = stp[pc - a];
+      if (st >= 0 && r > st) v = 0.0;
+    }
+    const int row = t.trans ? cn : r, col = t.trans ? r : cn;
+    if (row >= t.nrows || col >= t.ncols) {
+      item_error(it, ls.err, level, kErrIndex);
+      continue;
+    }
+    t.dst[(size_t)row + (size_t)t.ld * col] = v;
+  }
+  // factor pieces for the sweeps (the panel, column-major with ld m)
+  for (int e = tid; e < ne; e += kThreads) {
+    const int c = e / m, r = e - c * m;
+    it.P[e] = Ps[r + (size_t)ldp * c];
+  }
+  for (int e = tid; e < k * k; e += kThreads) {
+    const int r = e % k, c = e / k;
+    it.D[(size_t)r + (size_t)m * c] = (r == c) ? 1.0 : 0.0;
+  }
+  for (int c = tid; c < b; c += kThreads) it.stepof[c] = stp[c];
+  if (tid == 0) {
+    ls.k[it.s] = k;
+    ls.a[it.s] = a;
+    ls.b[it.s] = b;
+    ls.giok[it.s] = 0;
+  }
+  __syncthreads();
+}
+
 // One scaled low-rank elimination W_s = P_s G_s E_s S_s by one workgroup.
-// lds: m*kNB + kNB*kNB + kNB*256 doubles, then nseg+1 ints.
+// lds: slre_scratch(m) doubles, then nseg+1 ints.
 __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol, int tol_mode,
                           int prec, double* lds, int* soff) {
   __shared__ double shd[kWaves];
@@ -770,6 +1224,10 @@ __device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol,
       ls.b[it.s] = 0;
       ls.giok[it.s] = 0;
     }
+    return;
+  }
+  if (tiny_fits(m, a, b, it.nseg, it.nsegn)) {
+    slre_tiny(it, ls, level, tol, tol_mode, prec, reinterpret_cast<char*>(lds), soff, a, b);
     return;
   }
   double* P = it.P;
@@ -921,14 +1379,18 @@ __global__ void __launch_bounds__(kThreads) slre_kernel(const ItemD* __restrict_
                                                         int level, double tol, int tol_mode, int prec,
                                                         int max_m) {
   extern __shared__ double lds[];
-  int* soff = reinterpret_cast<int*>(lds + (size_t)max_m * kNB + kNB * kNB + kNB * 256);
+  int* soff = reinterpret_cast<int*>(lds + slre_scratch(max_m));
   slre_item(items[blockIdx.x], ls, level, tol, tol_mode, prec, lds, soff);
 }
 
 // All colours of a level in one persistent launch: workgroups stride over
 // the clusters of a colour, then wait at a grid barrier before the next.
-// SW = false: cooperative launch (grid_group barrier); SW = true: ordinary
-// launch with a co-resident grid and the bounded software barrier `bar`.
+// Two consecutive colours of at most one cluster each both run on workgroup
+// 0, whose own barrier at the end of a cluster orders them: no grid barrier
+// between them (coarse levels are mostly such colours).  No barrier follows
+// the last colour.  SW = false: cooperative launch (grid_group barrier);
+// SW = true: ordinary launch with a co-resident grid and the bounded
+// software barrier `bar`.
 template <bool SW>
 __global__ void __launch_bounds__(kThreads) slre_level_kernel(const ItemD* __restrict__ items,
                                                               const int32_t* __restrict__ cstart,
@@ -936,10 +1398,15 @@ __global__ void __launch_bounds__(kThreads) slre_level_kernel(const ItemD* __res
                                                               double tol, int tol_mode, int prec,
                                                               int max_m, GridBar* bar) {
   extern __shared__ double lds[];
-  int* soff = reinterpret_cast<int*>(lds + (size_t)max_m * kNB + kNB * kNB + kNB * 256);
+  int* soff = reinterpret_cast<int*>(lds + slre_scratch(max_m));
   for (int c = 0; c < ncolours; ++c) {
     for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x)
       slre_item(items[i], ls, level, tol, tol_mode, prec, lds, soff);
+    if (c + 1 == ncolours) break;
+    if (cstart[c + 1] - cstart[c] <= 1 && cstart[c + 2] - cstart[c + 1] <= 1) {
+      __syncthreads();
+      continue;
+    }
     if constexpr (SW) sw_grid_sync(bar, gridDim.x);
     else cooperative_groups::this_grid().sync();
   }
@@ -953,7 +1420,7 @@ static void allow_lds(const void* fn, bool* done) {
 }
 
 static size_t slre_lds(int max_m, int max_nseg) {
-  return ((size_t)max_m * kNB + kNB * kNB + kNB * 256) * sizeof(double) + (size_t)(max_nseg + 1) * 4;
+  return slre_scratch(max_m) * sizeof(double) + (size_t)(max_nseg + 1) * 4;
 }
 
 void launch_slre(const ItemD* items, int nitems, int max_m, int max_nseg, LevelState ls, int level,
@@ -1757,7 +2224,11 @@ __global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const Ite
       if (FWD) LRSP_WAVE_DISPATCH(fwd_wave, wi, vec);
       else LRSP_WAVE_DISPATCH(bwd_wave, wi, vec);
     }
-    if (gridDim.x == 1) __syncthreads();
+    if (q + 1 == ncolours) break;
+    const int cn = FWD ? c + 1 : c - 1;
+    // colours of at most nw clusters run on workgroup 0 alone
+    const bool local = cstart[c + 1] - cstart[c] <= nw && cstart[cn + 1] - cstart[cn] <= nw;
+    if (gridDim.x == 1 || local) __syncthreads();
     else if constexpr (SW) sw_grid_sync(bar, gridDim.x);
     else cooperative_groups::this_grid().sync();
   }
@@ -1846,7 +2317,9 @@ __device__ __forceinline__ void level_sync(GridBar* bar) {
 }
 
 // One launch per level and sweep direction; upi > 0: units per item of the
-// split clusters (an extra grid barrier per colour).
+// split clusters (an extra grid barrier per colour).  Without units, two
+// consecutive colours of at most one cluster each run on workgroup 0 alone
+// and need no grid barrier between them; none follows the last colour.
 template <bool SW>
 __global__ void __launch_bounds__(kThreads) fwd_level_kernel(const ItemD* __restrict__ items,
                                                              const int32_t* __restrict__ cstart,
@@ -1857,6 +2330,13 @@ __global__ void __launch_bounds__(kThreads) fwd_level_kernel(const ItemD* __rest
     for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) {
       const ItemD& it = items[i];
       fwd_any(it, upi > 0, ls, vec, lds);
+    }
+    if (upi == 0) {
+      if (c + 1 == ncolours) break;
+      if (cstart[c + 1] - cstart[c] <= 1 && cstart[c + 2] - cstart[c + 1] <= 1) {
+        __syncthreads();
+        continue;
+      }
     }
     level_sync<SW>(bar);
     if (upi > 0) {
@@ -1888,6 +2368,13 @@ __global__ void __launch_bounds__(kThreads) bwd_level_kernel(const ItemD* __rest
     for (int i = cstart[c] + blockIdx.x; i < cstart[c + 1]; i += gridDim.x) {
       const ItemD& it = items[i];
       bwd_any(it, upi > 0, ls, vec, lds);
+    }
+    if (upi == 0) {
+      if (c == 0) break;
+      if (cstart[c + 1] - cstart[c] <= 1 && cstart[c] - cstart[c - 1] <= 1) {
+        __syncthreads();
+        continue;
+      }
     }
     level_sync<SW>(bar);
   }
