@@ -24,6 +24,19 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Loads and stores through the global address space, for plain pointers to
+// device memory held in descriptors: they count on the vector-memory counter
+// only, so that waits for LDS results do not also wait for them (accesses
+// through generic pointers count on both).
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gstore(T* p, const T& v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 // Value of v in lane l (l uniform across the wave).
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long b = __double_as_longlong(v);

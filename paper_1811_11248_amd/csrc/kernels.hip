@@ -32,7 +32,7 @@ __device__ __forceinline__ int block_min_int(int v, int* sh) { return group_min_
 // (ld), fused with the triangular solve B <- G^{-1} B of the nb columns B
 // (same ld).  Pivots that are not > 0 raise *bad and are replaced by 1 so
 // that the sweep stays finite.  LDS: m*kNB + kNB*kNB + kNB*256 doubles.
-__device__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* lds, int* bad) {
+__device__ __forceinline__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* lds, int* bad) {
   double* Lp = lds;                // (m) x kNB, row-major
   double* Dg = Lp + (size_t)m * kNB;  // kNB x kNB, row-major
   double* Bb = Dg + kNB * kNB;     // kNB x 256, row-major
@@ -201,7 +201,7 @@ __device__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* 
 // >= 0 sits at row j of that column; other columns hold R in rows < k.
 // At most kcap reflectors are stored: when pivot kcap does not meet the stop
 // rule, *over is set and kcap is returned.
-__device__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, int kcap, int* piv,
+__device__ __forceinline__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, int kcap, int* piv,
                     int* stepof, double* tau, double* norms, double* shd, int* shi, bool* over) {
   __shared__ double vsh[kColM];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -348,7 +348,7 @@ __device__ int cpqr(double* W, int ld, int m, int b, double tol, int tol_mode, i
 // columns (row-major in the chunk, so that the column of each thread is
 // conflict-free), every column rotated by its own thread; else one column
 // per wave from global memory.
-__device__ void apply_qt_cols(double* C, int ld, int m, int a, const double* W, const int* piv,
+__device__ __forceinline__ void apply_qt_cols(double* C, int ld, int m, int a, const double* W, const int* piv,
                               const double* tau, int k, double* lds, size_t scr) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (m <= kColM && scr >= (size_t)(k + 1) * m + k) {
@@ -476,7 +476,7 @@ __device__ __forceinline__ double* schur_target(const ItemD& it, int rr, int cc,
 // Schur update X -= F^T F, F = rows k..m-1 of the a near-field columns C (ld).
 // Each unordered column pair (r >= c) is computed once and scattered to the
 // one block that owns it.
-__device__ void schur_scatter(const ItemD& it, const double* C, int ld, int m, int k, int a, int prec,
+__device__ __forceinline__ void schur_scatter(const ItemD& it, const double* C, int ld, int m, int k, int a, int prec,
                               int32_t* err, int level) {
   const int tid = threadIdx.x;
   const int nt = (a + 3) >> 2;
@@ -559,7 +559,7 @@ __device__ void schur_scatter(const ItemD& it, const double* C, int ld, int m, i
 // (same products in the same order as the global form) and resolves its
 // targets eight at a time, their posmap loads, old values and stores each
 // issued together.  Returns false, doing nothing, when the staging does not fit.
-__device__ bool schur_scatter_staged(const ItemD& it, const double* C, int ld, int m, int k, int a, int prec,
+__device__ __forceinline__ bool schur_scatter_staged(const ItemD& it, const double* C, int ld, int m, int k, int a, int prec,
                                      int32_t* err, int level, double* lds, size_t scr) {
   const int tid = threadIdx.x;
   const int nf = m - k;
@@ -596,7 +596,19 @@ __device__ bool schur_scatter_staged(const ItemD& it, const double* C, int ld, i
     }
     const double* src = reinterpret_cast<const double*>(it.pair);
     double* dst = reinterpret_cast<double*>(ps);
-    for (int e = tid; e < kPairD * np; e += kThreads) dst[e] = src[e];
+    for (int e0 = tid; e0 < kPairD * np; e0 += kThreads * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        v[u] = e < kPairD * np ? src[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < kPairD * np) dst[e] = v[u];
+      }
+    }
     if (tid == 0) *dummy = 0.0;
   }
   __syncthreads();
@@ -705,21 +717,23 @@ __device__ bool schur_scatter_staged(const ItemD& it, const double* C, int ld, i
 // Widths of the column segments (coarse ones are earlier ranks), their
 // exclusive prefix sum into soff[0..nseg] (LDS) and it.segoff, and the near
 // and far widths.  Returns false (after recording the error) when a width
-// exceeds its capacity.
-__device__ bool seg_scan(const ItemD& it, LevelState ls, int level, int* soff, int* wsum, int* flag,
+// exceeds its capacity.  Its barriers order LDS only (it.segoff is not read
+// by the elimination that follows).
+__device__ __forceinline__ bool seg_scan(const ItemD& it, LevelState ls, int level, int* soff, int* wsum, int* flag,
                          int& a_out, int& b_out) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nseg = it.nseg;
   if (tid == 0) *flag = 0;
-  __syncthreads();
+  lds_barrier();
   int carry = 0;
   for (int base = 0; base < nseg; base += kThreads) {
     const int i = base + tid;
     int w = 0;
     if (i < nseg) {
-      const SegD& sg = it.seg[i];
-      w = sg.coarse ? ls.k[sg.y] : sg.nfine;
-      if (w < 0 || w > sg.cap) {
+      const SegD* sg = it.seg + i;
+      const int coarse = gload(&sg->coarse), y = gload(&sg->y), nfine = gload(&sg->nfine), cap = gload(&sg->cap);
+      w = coarse ? gload(ls.k + y) : nfine;
+      if (w < 0 || w > cap) {
         *flag = 1;
         w = 0;
       }
@@ -731,7 +745,7 @@ __device__ bool seg_scan(const ItemD& it, LevelState ls, int level, int* soff, i
       if (lane >= o) x += y;
     }
     if (lane == 63) wsum[wv] = x;
-    __syncthreads();
+    lds_barrier();
     int pre = 0;
     for (int q = 0; q < wv; ++q) pre += wsum[q];
     int tot = 0;
@@ -739,28 +753,28 @@ __device__ bool seg_scan(const ItemD& it, LevelState ls, int level, int* soff, i
     for (int q = 0; q < kWaves; ++q) tot += wsum[q];
     if (i < nseg) soff[i] = carry + pre + x - w;
     carry += tot;
-    __syncthreads();
+    lds_barrier();
   }
   if (tid == 0) soff[nseg] = carry;
-  __syncthreads();
+  lds_barrier();
   a_out = soff[it.nsegn];
   b_out = soff[nseg] - a_out;
   const bool bad = *flag || soff[nseg] > it.pcap;
-  for (int i = tid; i <= nseg; i += kThreads) it.segoff[i] = soff[i];
+  for (int i = tid; i <= nseg; i += kThreads) gstore(it.segoff + i, soff[i]);
   if (bad && tid == 0) item_error(it, ls.err, level, kErrCapacity);
-  __syncthreads();
+  lds_barrier();
   return !bad;
 }
 
 // ---------------------------------------------------------------------------
 // Clusters of at most kTinyM DoFs whose block row fits kTinyLdsBytes of LDS:
-// the block row [A_ss | A_sn | A_sw] is gathered once into LDS; the
-// Cholesky, the scaling, the pivoted QR and the rotation then run in wave 0
-// on that copy (one column per lane, lanes exchange data through LDS within
-// the wave, no workgroup barrier); all waves join again for the Schur
-// scatter, the coarse row and the store of the factor pieces.  The pivot and
-// stop rules are those of cpqr.  Whether a cluster takes this form depends
-// on its sizes alone, so every schedule gives it the same arithmetic.
+// the block row [A_ss | A_sn | A_sw] is gathered once into LDS and every
+// step works on that copy.  The Cholesky and the pivoted QR (serial chains)
+// run in wave 0 with cross-lane register exchanges; the scaling and the
+// rotation take one column per thread of the workgroup; phases exchange data
+// through LDS-only barriers.  The pivot, tie and stop rules are those of
+// cpqr.  Whether a cluster takes this form depends on its sizes alone, so
+// every schedule gives it the same arithmetic.
 constexpr int kTinyM = 32;
 constexpr size_t kTinyLdsBytes = 64 * 1024;
 
@@ -772,28 +786,53 @@ __host__ __device__ __forceinline__ size_t slre_scratch(int max_m) {
   return chol > kTinyLdsBytes / 8 ? chol : kTinyLdsBytes / 8;
 }
 
+// Orders LDS accesses of the lanes of one wave (no workgroup barrier).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+// Data-parallel-primitive lane exchange within rows of 16 lanes (every
+// source lane lies in the row, all lanes active).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <- 7-i in rows of 8
+constexpr int kDppMirror = 0x140;     // lane i <- 15-i in rows of 16
 
-__device__ __forceinline__ int wave_min_int(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
+// Wave-wide max / sum / min: every 16-lane row reduces by register
+// exchanges (each lane of a row ends with the same value), then the four
+// row results combine in a fixed order; all lanes get the result.
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp_d<kDppXor1>(v));
+  v = fmax(v, dpp_d<kDppXor2>(v));
+  v = fmax(v, dpp_d<kDppHalfMirror>(v));
+  v = fmax(v, dpp_d<kDppMirror>(v));
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ __forceinline__ int wave_min_dpp(int v) {
+  v = min(v, dpp_i<kDppXor1>(v));
+  v = min(v, dpp_i<kDppXor2>(v));
+  v = min(v, dpp_i<kDppHalfMirror>(v));
+  v = min(v, dpp_i<kDppMirror>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 __host__ __device__ __forceinline__ size_t tiny_al(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// Byte offsets of the LDS sections of the small-cluster form.  The pair
-// descriptors are staged only when they fit too (else read from memory).
+// Byte offsets of the LDS sections of the small-cluster form (the pair
+// descriptors last).
 struct TinyLayout {
   int ldp;  // odd leading dimension of the panel copy
   size_t p, src, nrm, tau, cseg, cnat, stp, piv, wb, pair, end, end_pairs;
@@ -819,14 +858,14 @@ __host__ __device__ __forceinline__ TinyLayout tiny_layout(int m, int a, int b, 
 }
 
 __device__ __forceinline__ bool tiny_fits(int m, int a, int b, int nseg, int nsegn) {
-  return m <= kTinyM && tiny_layout(m, a, b, nseg, nsegn * (nsegn + 1) / 2).end <= kTinyLdsBytes;
+  return m <= kTinyM && tiny_layout(m, a, b, nseg, nsegn * (nsegn + 1) / 2).end_pairs <= kTinyLdsBytes;
 }
 
 // Cholesky of the m x m lower triangle of the panel copy (ld ldp) by one
 // wave, lane i holding row i; pivots that are not > 0 set bad and are
 // replaced by 1.
 template <int MB>
-__device__ void tiny_chol(double* Ps, int ldp, int m, int lane, bool& bad) {
+__device__ __forceinline__ void tiny_chol(double* Ps, int ldp, int m, int lane, bool& bad) {
   double row[MB];
 #pragma unroll
   for (int u = 0; u < MB; ++u) row[u] = (lane < m && u <= lane) ? Ps[lane + ldp * u] : 0.0;
@@ -858,10 +897,11 @@ __device__ void tiny_chol(double* Ps, int ldp, int m, int lane, bool& bad) {
 }
 
 // x <- G^{-1} x for the a + b off-diagonal columns of the panel copy, one
-// column per lane; squared norms of the far-field columns into nrm.
+// column per thread of the workgroup; squared norms of the far-field
+// columns into nrm.
 template <int MB>
-__device__ void tiny_scale(double* Ps, int ldp, int m, int a, int b, double* nrm, int* stp, int lane) {
-  for (int c = lane; c < a + b; c += 64) {
+__device__ __forceinline__ void tiny_scale(double* Ps, int ldp, int m, int a, int b, double* nrm, int* stp) {
+  for (int c = threadIdx.x; c < a + b; c += kThreads) {
     double* y = Ps + (size_t)ldp * (m + c);
     double x[MB];
 #pragma unroll
@@ -889,14 +929,210 @@ __device__ void tiny_scale(double* Ps, int ldp, int m, int a, int b, double* nrm
   }
 }
 
-__device__ void slre_tiny(const ItemD& it, LevelState ls, int level, double tol, int tol_mode, int prec,
-                          char* lds, const int* soff, int a, int b) {
+// Column-pivoted Householder QR of the b scaled far-field columns Wf (ld
+// ldp) by one wave: the pivot, tie and stop rules of cpqr, columns held in
+// registers while a reflector is applied.  Returns k.
+template <int MB>
+__device__ __forceinline__ int tiny_cpqr(double* Wf, int ldp, int m, int b, double tol, int tol_mode, int kcap, double* nrm,
+                         int* stp, int* pv, double* taus, int32_t* gpiv, double* gtau, int lane, bool& over) {
+  const int kmax = min(m, b);
+  double r00 = 0.0;
+  for (int j = 0; j < kmax; ++j) {
+    double mx = 0.0;
+    for (int c = lane; c < b; c += 64)
+      if (stp[c] < 0) mx = fmax(mx, nrm[c]);
+    mx = wave_max_dpp(mx);
+    const double thr = (1.0 - kTie) * mx;
+    int best = INT_MAX;
+    for (int c = lane; c < b; c += 64)
+      if (stp[c] < 0 && nrm[c] >= thr) best = min(best, c);
+    best = wave_min_dpp(best);
+    if (best == INT_MAX) return j;  // only NaN norms left
+    const double rjj = sqrt(nrm[best]);
+    if (j == 0) r00 = rjj;
+    const bool stop = (tol_mode == 0) ? (rjj <= tol * r00) : (rjj <= tol);
+    if (stop || rjj == 0.0) return j;
+    if (j >= kcap) {
+      over = true;
+      return kcap;
+    }
+    double* x = Wf + (size_t)ldp * best;
+    double v[MB];
+#pragma unroll
+    for (int u = 0; u < MB; ++u) v[u] = (u > j && u < m) ? x[u] : 0.0;
+    const double alpha = x[j];
+    double rest = 0.0;
+#pragma unroll
+    for (int u = 0; u < MB; ++u) rest += v[u] * v[u];
+    double d, tj;
+    if (alpha <= 0.0) {
+      d = alpha - rjj;
+      tj = (rjj - alpha) / rjj;
+    } else {
+      d = -rest / (alpha + rjj);
+      tj = rest / (rjj * (rjj + alpha));
+    }
+    if (d == 0.0) tj = 0.0;
+    // reflector j: unit entry at row j, v / d below
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+      if (u == j) v[u] = 1.0;
+      else if (u > j && u < m && d != 0.0) v[u] = v[u] / d;
+    }
+    double mine = 0.0;
+#pragma unroll
+    for (int u = 0; u < MB; ++u) mine = (u == lane) ? v[u] : mine;
+    wave_lds_sync();
+    if (lane > j && lane < m) x[lane] = mine;
+    if (lane == 0) {
+      x[j] = rjj;
+      pv[j] = best;
+      taus[j] = tj;
+      stp[best] = j;
+      gstore(gpiv + j, best);
+      gstore(gtau + j, tj);
+    }
+    wave_lds_sync();
+    for (int c = lane; c < b; c += 64) {
+      if (stp[c] >= 0) continue;
+      double* y = Wf + (size_t)ldp * c;
+      double yr[MB];
+#pragma unroll
+      for (int u = 0; u < MB; ++u) yr[u] = (u >= j && u < m) ? y[u] : 0.0;
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < MB; ++u)
+        if (u >= j && u < m) s += v[u] * yr[u];
+      const double f = tj * s;
+      double nn = 0.0;
+#pragma unroll
+      for (int u = 0; u < MB; ++u)
+        if (u >= j && u < m) {
+          const double nv = yr[u] - f * v[u];
+          y[u] = nv;
+          if (u > j) nn += nv * nv;
+        }
+      nrm[c] = nn;
+    }
+    wave_lds_sync();
+  }
+  return kmax;
+}
+
+// C <- U^T C for the a near-field columns (ld ldp), one column per thread
+// of the workgroup, reflectors 0..k-1 in order.
+template <int MB>
+__device__ __forceinline__ void tiny_rotate(double* C, const double* Wf, int ldp, int m, int a, int k, const int* pv,
+                            const double* taus) {
+  for (int c = threadIdx.x; c < a; c += kThreads) {
+    double* y = C + (size_t)ldp * c;
+    double yr[MB];
+#pragma unroll
+    for (int u = 0; u < MB; ++u) yr[u] = u < m ? y[u] : 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double* x = Wf + (size_t)ldp * pv[j];
+      double v[MB];
+#pragma unroll
+      for (int u = 0; u < MB; ++u) v[u] = (u > j && u < m) ? x[u] : (u == j ? 1.0 : 0.0);
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < MB; ++u)
+        if (u >= j && u < m) s += v[u] * yr[u];
+      const double f = taus[j] * s;
+#pragma unroll
+      for (int u = 0; u < MB; ++u)
+        if (u >= j && u < m) yr[u] -= f * v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < MB; ++u)
+      if (u < m) y[u] = yr[u];
+  }
+}
+
+// Lower-triangle index p -> (rr, cc), cc <= rr, rows of the triangle in order.
+__device__ __forceinline__ void tri_index(int p, int& rr, int& cc) {
+  int r = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+  while (r * (r + 1) / 2 > p) --r;
+  while ((r + 1) * (r + 2) / 2 <= p) ++r;
+  rr = r;
+  cc = p - r * (r + 1) / 2;
+}
+
+// Owning-block entry of the Schur element (rr, cc), cc <= rr, of the
+// near-field columns (segment and natural index of every column and the pair
+// descriptors in LDS); null, after recording the error, when out of range.
+__device__ __forceinline__ double* tiny_target(const ItemD& it, int rr, int cc, const int* cseg, const int* cnat,
+                                               const PairD* ps, int32_t* err, int level) {
+  const int sr = cseg[rr], sc = cseg[cc], nr = cnat[rr], ncn = cnat[cc];
+  const int i = min(sr, sc), j = max(sr, sc);
+  const PairD& pd = ps[j * (j + 1) / 2 + i];
+  int row, col;
+  if (pd.diag) {
+    row = max(nr, ncn);
+    col = min(nr, ncn);
+  } else {
+    const bool r_is_rowseg = (sr == (pd.rows_from_j ? j : i));
+    row = r_is_rowseg ? nr : ncn;
+    const int cn = r_is_rowseg ? ncn : nr;
+    col = pd.posmap ? gload(pd.posmap + cn) : cn;
+  }
+  if (row < 0 || col < 0 || row >= pd.nrows || col >= pd.ncols) {
+    item_error(it, err, level, kErrIndex);
+    return nullptr;
+  }
+  return pd.dst + (size_t)row + (size_t)pd.ld * col;
+}
+
+// Element (rr, cc) of F^T F, F = rows k..m-1 of the columns C (ld ldp, LDS),
+// summed in row order.
+__device__ __forceinline__ double tiny_dot(const double* C, int ldp, int k, int m, int rr, int cc, int prec) {
+  const double* fr = C + (size_t)ldp * rr;
+  const double* fc = C + (size_t)ldp * cc;
+  if (prec == 0) {
+    double acc = 0.0;
+    int i = k;
+    for (; i + 4 <= m; i += 4) {
+      const double r0 = fr[i], r1 = fr[i + 1], r2 = fr[i + 2], r3 = fr[i + 3];
+      const double c0 = fc[i], c1 = fc[i + 1], c2 = fc[i + 2], c3 = fc[i + 3];
+      acc += r0 * c0;
+      acc += r1 * c1;
+      acc += r2 * c2;
+      acc += r3 * c3;
+    }
+    for (; i < m; ++i) acc += fr[i] * fc[i];
+    return acc;
+  }
+  float accf = 0.0f;
+  for (int i = k; i < m; ++i) {
+    float x0 = (float)fr[i], x1 = (float)fc[i];
+    if (prec == 2) {
+      x0 = round_bf16(x0);
+      x1 = round_bf16(x1);
+    }
+    accf = fmaf(x0, x1, accf);
+  }
+  return (double)accf;
+}
+
+#define LRSP_TINY_DISPATCH(FN, ...)       \
+  do {                                    \
+    if (m <= 8) FN<8>(__VA_ARGS__);       \
+    else if (m <= 16) FN<16>(__VA_ARGS__); \
+    else FN<32>(__VA_ARGS__);             \
+  } while (0)
+
+// Schur elements whose targets waves 1..3 look up, and whose old values they
+// load, while wave 0 factors the diagonal block: (kThreads - 64) * kTinyPre.
+constexpr int kTinyPre = 2;
+constexpr int kTinyPreN = (kThreads - 64) * kTinyPre;
+
+__device__ __forceinline__ void slre_tiny(const ItemD& it, LevelState ls, int level, double tol, int tol_mode,
+                                          int prec, char* lds, const int* soff, int a, int b) {
   __shared__ int sk, sbad2, sover;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m = it.m, nseg = it.nseg, nsn = it.nsegn;
   const int np = nsn * (nsn + 1) / 2;
   const TinyLayout L = tiny_layout(m, a, b, nseg, np);
-  const bool pairs_lds = L.end_pairs <= kTinyLdsBytes;
   const int ldp = L.ldp;
   const int nc = m + a + b;
   double* Ps = reinterpret_cast<double*>(lds + L.p);
@@ -917,22 +1153,26 @@ __device__ void slre_tiny(const ItemD& it, LevelState ls, int level, double tol,
       if (soff[mid] <= pc) lo = mid;
       else hi = mid - 1;
     }
-    const SegD& sg = it.seg[lo];
+    const SegD* sg = it.seg + lo;
     const int loc = pc - soff[lo];
-    const int nat = sg.coarse ? loc : sg.zl[loc];
+    const int coarse = gload(&sg->coarse);
+    const int32_t* zl = gload(&sg->zl);
+    const double* src = gload(&sg->src);
+    const int64_t voff = gload(&sg->voff);
+    const int nat = coarse ? loc : gload(zl + loc);
     cseg[pc] = lo;
     cnat[pc] = nat;
-    it.colseg[pc] = lo;
-    it.colnat[pc] = nat;
-    it.vidx[pc] = sg.voff + nat;
-    srcp[m + pc] = sg.src + (size_t)m * loc;
+    gstore(it.colseg + pc, lo);
+    gstore(it.colnat + pc, nat);
+    gstore(it.vidx + pc, voff + nat);
+    srcp[m + pc] = src + (size_t)m * loc;
   }
   for (int c = tid; c < m; c += kThreads) srcp[c] = it.D + (size_t)m * c;
   {
     constexpr int kW = (int)(sizeof(WbD) / sizeof(double));
     constexpr int kP = (int)(sizeof(PairD) / sizeof(double));
     static_assert(sizeof(WbD) % sizeof(double) == 0 && sizeof(PairD) % sizeof(double) == 0, "staged as doubles");
-    const int nw = kW * nseg, npd = pairs_lds ? kP * np : 0;
+    const int nw = kW * nseg, npd = kP * np;
     const double* ws = reinterpret_cast<const double*>(it.wb);
     const double* pg = reinterpret_cast<const double*>(it.pair);
     double* wd = reinterpret_cast<double*>(wbs);
@@ -942,7 +1182,7 @@ __device__ void slre_tiny(const ItemD& it, LevelState ls, int level, double tol,
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * kThreads;
-        v[u] = e < nw ? ws[e] : (e < nw + npd ? pg[e - nw] : 0.0);
+        v[u] = e < nw ? gload(ws + e) : (e < nw + npd ? gload(pg + (e - nw)) : 0.0);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -956,7 +1196,7 @@ __device__ void slre_tiny(const ItemD& it, LevelState ls, int level, double tol,
     sbad2 = 0;
     sover = 0;
   }
-  __syncthreads();
+  lds_barrier();
   // gather the block row, sixteen loads in flight per thread
   const int ne = m * nc;
   for (int e0 = tid; e0 < ne; e0 += kThreads * 16) {
@@ -967,7 +1207,7 @@ __device__ void slre_tiny(const ItemD& it, LevelState ls, int level, double tol,
       v[u] = 0.0;
       if (e < ne) {
         const int c = e / m, r = e - c * m;
-        v[u] = srcp[c][r];
+        v[u] = gload(srcp[c] + r);
       }
     }
 #pragma unroll
@@ -979,195 +1219,91 @@ __device__ void slre_tiny(const ItemD& it, LevelState ls, int level, double tol,
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
+  // S_s: Cholesky of the diagonal block (wave 0); meanwhile the other waves
+  // look up the first Schur targets and load their old values
+  const int nel = a * (a + 1) / 2;
+  double* tp[kTinyPre] = {};
+  double ov[kTinyPre];
   if (wv == 0) {
-    // S_s: Cholesky and scaling of the block row
     bool bad = false;
-    if (m <= 8) {
-      tiny_chol<8>(Ps, ldp, m, lane, bad);
-      wave_lds_sync();
-      tiny_scale<8>(Ps, ldp, m, a, b, nrm, stp, lane);
-    } else if (m <= 16) {
-      tiny_chol<16>(Ps, ldp, m, lane, bad);
-      wave_lds_sync();
-      tiny_scale<16>(Ps, ldp, m, a, b, nrm, stp, lane);
-    } else {
-      tiny_chol<32>(Ps, ldp, m, lane, bad);
-      wave_lds_sync();
-      tiny_scale<32>(Ps, ldp, m, a, b, nrm, stp, lane);
+    LRSP_TINY_DISPATCH(tiny_chol, Ps, ldp, m, lane, bad);
+    if (lane == 0 && bad) sbad2 = 1;
+  } else {
+#pragma unroll
+    for (int u = 0; u < kTinyPre; ++u) {
+      const int p = (tid - 64) + (kThreads - 64) * u;
+      tp[u] = nullptr;
+      if (p < nel) {
+        int rr, cc;
+        tri_index(p, rr, cc);
+        tp[u] = tiny_target(it, rr, cc, cseg, cnat, ps, ls.err, level);
+      }
     }
-    wave_lds_sync();
-    // compression of the scaled far field
-    double* Wf = Ps + (size_t)ldp * (m + a);
-    const int kmax = min(m, b);
-    int k = kmax;
+#pragma unroll
+    for (int u = 0; u < kTinyPre; ++u) ov[u] = tp[u] ? gload(tp[u]) : 0.0;
+  }
+  lds_barrier();
+  LRSP_TINY_DISPATCH(tiny_scale, Ps, ldp, m, a, b, nrm, stp);
+  lds_barrier();
+  // compression of the scaled far field (wave 0)
+  double* Wf = Ps + (size_t)ldp * (m + a);
+  if (wv == 0) {
     bool over = false;
-    double r00 = 0.0;
-    for (int j = 0; j < kmax; ++j) {
-      double mx = 0.0;
-      for (int c = lane; c < b; c += 64)
-        if (stp[c] < 0) mx = fmax(mx, nrm[c]);
-      mx = wave_max(mx);
-      const double thr = (1.0 - kTie) * mx;
-      int best = INT_MAX;
-      for (int c = lane; c < b; c += 64)
-        if (stp[c] < 0 && nrm[c] >= thr) best = min(best, c);
-      best = wave_min_int(best);
-      if (best == INT_MAX) {
-        k = j;
-        break;
-      }
-      const double rjj = sqrt(nrm[best]);
-      if (j == 0) r00 = rjj;
-      const bool stop = (tol_mode == 0) ? (rjj <= tol * r00) : (rjj <= tol);
-      if (stop || rjj == 0.0) {
-        k = j;
-        break;
-      }
-      if (j >= it.kcap) {
-        k = it.kcap;
-        over = true;
-        break;
-      }
-      double* x = Wf + (size_t)ldp * best;
-      const double xi = (lane > j && lane < m) ? x[lane] : 0.0;
-      const double rest = wave_sum(xi * xi);
-      const double alpha = x[j];
-      double d, tj;
-      if (alpha <= 0.0) {
-        d = alpha - rjj;
-        tj = (rjj - alpha) / rjj;
-      } else {
-        d = -rest / (alpha + rjj);
-        tj = rest / (rjj * (rjj + alpha));
-      }
-      if (d == 0.0) tj = 0.0;
-      wave_lds_sync();
-      if (d != 0.0 && lane > j && lane < m) x[lane] = xi / d;
-      if (lane == 0) {
-        x[j] = rjj;
-        pv[j] = best;
-        taus[j] = tj;
-        stp[best] = j;
-        it.piv[j] = best;
-        it.tau[j] = tj;
-      }
-      wave_lds_sync();
-      for (int c = lane; c < b; c += 64) {
-        if (stp[c] >= 0) continue;
-        double* y = Wf + (size_t)ldp * c;
-        double s = 0.0;
-        for (int i = j; i < m; ++i) s += (i == j ? 1.0 : x[i]) * y[i];
-        const double f = tj * s;
-        double nn = 0.0;
-        for (int i = j; i < m; ++i) {
-          const double nv = y[i] - f * (i == j ? 1.0 : x[i]);
-          y[i] = nv;
-          if (i > j) nn += nv * nv;
-        }
-        nrm[c] = nn;
-      }
-      wave_lds_sync();
-    }
-    // E_s: rotate the near-field columns, C = U^T G^{-1} A_sn
-    for (int c = lane; c < a; c += 64) {
-      double* y = Ps + (size_t)ldp * (m + c);
-      for (int j = 0; j < k; ++j) {
-        const double* x = Wf + (size_t)ldp * pv[j];
-        double s = 0.0;
-        for (int i = j; i < m; ++i) s += (i == j ? 1.0 : x[i]) * y[i];
-        const double f = taus[j] * s;
-        for (int i = j; i < m; ++i) y[i] -= f * (i == j ? 1.0 : x[i]);
-      }
-    }
+    int k = 0;
+    LRSP_TINY_DISPATCH(k = tiny_cpqr, Wf, ldp, m, b, tol, tol_mode, it.kcap, nrm, stp, pv, taus, it.piv,
+                       it.tau, lane, over);
     if (lane == 0) {
       sk = k;
-      sbad2 = bad ? 1 : 0;
       sover = over ? 1 : 0;
     }
   }
-  __syncthreads();
+  lds_barrier();
   const int k = sk;
   if (tid == 0) {
     if (sbad2) item_error(it, ls.err, level, kErrNotSPD);
     if (sover) item_error(it, ls.err, level, kErrCapacity);
   }
-  // G_s: X_nn -= F^T F, F = rows k.. of the rotated near-field columns;
-  // eight read-modify-writes in flight per thread
+  // E_s: rotate the near-field columns, C = U^T G^{-1} A_sn
+  double* C = Ps + (size_t)ldp * m;
+  if (k > 0) {
+    LRSP_TINY_DISPATCH(tiny_rotate, C, Wf, ldp, m, a, k, pv, taus);
+    lds_barrier();
+  }
+  // G_s: X_nn -= F^T F, F = rows k.. of the rotated near-field columns
   if (m > k && a > 0) {
-    const int nel = a * (a + 1) / 2;
-    const PairD* pt = pairs_lds ? ps : it.pair;
-    for (int p0 = tid; p0 < nel; p0 += kThreads * 8) {
+    if (wv > 0) {
+#pragma unroll
+      for (int u = 0; u < kTinyPre; ++u) {
+        const int p = (tid - 64) + (kThreads - 64) * u;
+        if (tp[u]) {
+          int rr, cc;
+          tri_index(p, rr, cc);
+          gstore(tp[u], ov[u] - tiny_dot(C, ldp, k, m, rr, cc, prec));
+        }
+      }
+    }
+    for (int p0 = kTinyPreN + tid; p0 < nel; p0 += kThreads * 8) {
+      double* t[8];
       double val[8];
-      int cidx[8], row[8];
-      const PairD* pp[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int p = p0 + u * kThreads;
-        val[u] = 0.0;
-        pp[u] = nullptr;
-        cidx[u] = 0;
-        row[u] = 0;
-        if (p < nel) {
-          int rr = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
-          while (rr * (rr + 1) / 2 > p) --rr;
-          while ((rr + 1) * (rr + 2) / 2 <= p) ++rr;
-          const int cc = p - rr * (rr + 1) / 2;
-          const double* fr = Ps + (size_t)ldp * (m + rr);
-          const double* fc = Ps + (size_t)ldp * (m + cc);
-          if (prec == 0) {
-            double acc = 0.0;
-            for (int i = k; i < m; ++i) acc += fr[i] * fc[i];
-            val[u] = acc;
-          } else {
-            float accf = 0.0f;
-            for (int i = k; i < m; ++i) {
-              float x0 = (float)fr[i], x1 = (float)fc[i];
-              if (prec == 2) {
-                x0 = round_bf16(x0);
-                x1 = round_bf16(x1);
-              }
-              accf = fmaf(x0, x1, accf);
-            }
-            val[u] = (double)accf;
-          }
-          const int sr = cseg[rr], sc = cseg[cc], nr = cnat[rr], ncn = cnat[cc];
-          const int i = min(sr, sc), j = max(sr, sc);
-          const PairD* pd = pt + (j * (j + 1) / 2 + i);
-          pp[u] = pd;
-          if (pd->diag) {
-            row[u] = max(nr, ncn);
-            cidx[u] = min(nr, ncn);
-          } else {
-            const bool r_is_rowseg = (sr == (pd->rows_from_j ? j : i));
-            row[u] = r_is_rowseg ? nr : ncn;
-            cidx[u] = r_is_rowseg ? ncn : nr;
-          }
-        }
-      }
-      int col[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int32_t* pm = (pp[u] && !pp[u]->diag) ? pp[u]->posmap : nullptr;
-        col[u] = pm ? pm[cidx[u]] : cidx[u];
-      }
-      double* t[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
         t[u] = nullptr;
-        if (pp[u]) {
-          if (row[u] < 0 || col[u] < 0 || row[u] >= pp[u]->nrows || col[u] >= pp[u]->ncols)
-            item_error(it, ls.err, level, kErrIndex);
-          else
-            t[u] = pp[u]->dst + (size_t)row[u] + (size_t)pp[u]->ld * col[u];
+        val[u] = 0.0;
+        if (p < nel) {
+          int rr, cc;
+          tri_index(p, rr, cc);
+          t[u] = tiny_target(it, rr, cc, cseg, cnat, ps, ls.err, level);
+          val[u] = tiny_dot(C, ldp, k, m, rr, cc, prec);
         }
       }
       double old[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) old[u] = t[u] ? *t[u] : 0.0;
+      for (int u = 0; u < 8; ++u) old[u] = t[u] ? gload(t[u]) : 0.0;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (t[u]) *t[u] = old[u] - val[u];
+        if (t[u]) gstore(t[u], old[u] - val[u]);
     }
   }
   // coarse row of s: [I_k | C[:k] | V1^T]
@@ -1185,30 +1321,30 @@ __device__ void slre_tiny(const ItemD& it, LevelState ls, int level, double tol,
       item_error(it, ls.err, level, kErrIndex);
       continue;
     }
-    t.dst[(size_t)row + (size_t)t.ld * col] = v;
+    gstore(t.dst + (size_t)row + (size_t)t.ld * col, v);
   }
   // factor pieces for the sweeps (the panel, column-major with ld m)
   for (int e = tid; e < ne; e += kThreads) {
     const int c = e / m, r = e - c * m;
-    it.P[e] = Ps[r + (size_t)ldp * c];
+    gstore(it.P + e, Ps[r + (size_t)ldp * c]);
   }
   for (int e = tid; e < k * k; e += kThreads) {
     const int r = e % k, c = e / k;
-    it.D[(size_t)r + (size_t)m * c] = (r == c) ? 1.0 : 0.0;
+    gstore(it.D + (size_t)r + (size_t)m * c, (r == c) ? 1.0 : 0.0);
   }
-  for (int c = tid; c < b; c += kThreads) it.stepof[c] = stp[c];
+  for (int c = tid; c < b; c += kThreads) gstore(it.stepof + c, stp[c]);
   if (tid == 0) {
-    ls.k[it.s] = k;
-    ls.a[it.s] = a;
-    ls.b[it.s] = b;
-    ls.giok[it.s] = 0;
+    gstore(ls.k + it.s, k);
+    gstore(ls.a + it.s, a);
+    gstore(ls.b + it.s, b);
+    gstore(ls.giok + it.s, 0);
   }
   __syncthreads();
 }
 
 // One scaled low-rank elimination W_s = P_s G_s E_s S_s by one workgroup.
 // lds: slre_scratch(m) doubles, then nseg+1 ints.
-__device__ void slre_item(const ItemD& it, LevelState ls, int level, double tol, int tol_mode,
+__device__ __forceinline__ void slre_item(const ItemD& it, LevelState ls, int level, double tol, int tol_mode,
                           int prec, double* lds, int* soff) {
   __shared__ double shd[kWaves];
   __shared__ int shi[kWaves];
@@ -1519,7 +1655,7 @@ constexpr int kBlkLd = 65;  // row stride of a staged 64x64 block
 // with readlane); the rows below subtract their 64-wide dot products, each
 // thread loading sixteen entries of its row at a time.
 // blk: 64*65 doubles.
-__device__ void trsv_lower(const double* G, int ld, int m, double* y, double* blk) {
+__device__ __forceinline__ void trsv_lower(const double* G, int ld, int m, double* y, double* blk) {
   const int tid = threadIdx.x, lane = tid & 63;
   for (int jb = 0; jb < m; jb += 64) {
     const int w = min(64, m - jb);
@@ -1563,7 +1699,7 @@ __device__ void trsv_lower(const double* G, int ld, int m, double* y, double* bl
 // block transposed in wave 0 (each lane one column, the reciprocals of the
 // diagonal taken first, solved entries broadcast with readlane).
 template <int R>
-__device__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* blk) {
+__device__ __forceinline__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* blk) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nblk = (m + 63) / 64;
   for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -1621,7 +1757,7 @@ __device__ void trsv_lower_t(const double* G, int ld, int m, double* y, double* 
 // waves, each lane one row of a tile with its entries loaded 32 at a time;
 // the partial sums of the column blocks are added in order.  red: 4*256
 // doubles of LDS.
-__device__ void gemv_tri(const double* M, int m, bool upper, double* y, double* red) {
+__device__ __forceinline__ void gemv_tri(const double* M, int m, bool upper, double* y, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = (m + 63) >> 6;
   const int ntl = nb * (nb + 1) / 2;
@@ -1664,7 +1800,7 @@ __device__ void gemv_tri(const double* M, int m, bool upper, double* y, double* 
 
 // Stages reflectors j0..j0+nj-1 of the far-field block Wf (m rows) in LDS as
 // vs[jj*mp + i] (unit leading entry, zeros above).
-__device__ void stage_reflectors(const ItemD& it, const double* Wf, int m, int mp, int j0, int nj,
+__device__ __forceinline__ void stage_reflectors(const ItemD& it, const double* Wf, int m, int mp, int j0, int nj,
                                  double* vs) {
   const int n = nj * mp;
   for (int e0 = threadIdx.x; e0 < n; e0 += kThreads * 8) {
@@ -1692,7 +1828,7 @@ __device__ void stage_reflectors(const ItemD& it, const double* Wf, int m, int m
 // y in LDS (m).  Reflectors and their tau pass through LDS (vs, ts) sixteen
 // at a time; wave 0 applies them with y in registers and wave reductions.
 template <int R>
-__device__ void apply_reflectors(const ItemD& it, const double* Wf, int m, int mp, int k, bool fwd,
+__device__ __forceinline__ void apply_reflectors(const ItemD& it, const double* Wf, int m, int mp, int k, bool fwd,
                                  double* y, double* vs, double* ts) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nt = (m + 63) >> 6;
@@ -1747,7 +1883,7 @@ __device__ void apply_reflectors(const ItemD& it, const double* Wf, int m, int m
 // A_sn, ld m): one wave per column, four columns in flight.  y (m entries)
 // may be in LDS or global memory.
 template <int R>
-__device__ void fwd_near(const ItemD& it, int m, int k, int c0, int c1, const double* y, double* vec) {
+__device__ __forceinline__ void fwd_near(const ItemD& it, int m, int k, int c0, int c1, const double* y, double* vec) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double yr[R];
 #pragma unroll
@@ -1792,7 +1928,7 @@ namespace {
 // Forward substitution of one cluster: y_s <- U^T G^{-1} y_s, y_n -= F^T y_f.
 // lds: mp (y) + 64*65 (diagonal block) + 16*mp (reflectors) doubles.
 template <int R>
-__device__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
+__device__ __forceinline__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
   const int m = it.m;
   if (m == 0) return;
   const int tid = threadIdx.x;
@@ -1815,7 +1951,7 @@ __device__ void fwd_item(const ItemD& it, LevelState ls, double* vec, double* ld
 // Forward sweep of a split cluster, per-cluster part: y_s <- U^T G^{-1} y_s,
 // written back to the vector (the near-field product follows in units).
 template <int R>
-__device__ void fwd_head(const ItemD& it, LevelState ls, double* vec, double* lds) {
+__device__ __forceinline__ void fwd_head(const ItemD& it, LevelState ls, double* vec, double* lds) {
   const int m = it.m;
   if (m == 0) return;
   const int tid = threadIdx.x;
@@ -1837,7 +1973,7 @@ __device__ void fwd_head(const ItemD& it, LevelState ls, double* vec, double* ld
 // Forward sweep of a split cluster, unit `part`: y_n -= F^T y_f over columns
 // [part*kSweepCols, (part+1)*kSweepCols) of F, y_s read from the vector.
 template <int R>
-__device__ void fwd_unit(const ItemD& it, int part, LevelState ls, double* vec) {
+__device__ __forceinline__ void fwd_unit(const ItemD& it, int part, LevelState ls, double* vec) {
   const int m = it.m;
   const int k = ls.k[it.s], a = ls.a[it.s];
   const int c0 = part * kSweepCols;
@@ -1850,7 +1986,7 @@ __device__ void fwd_unit(const ItemD& it, int part, LevelState ls, double* vec) 
 // 8 column groups (two per wave): every row sums its columns group by group
 // in a fixed order, then the eight group sums in order.  x_n passes through
 // LDS 1024 columns at a time.  lds: 1024 + 256 doubles.
-__device__ void bwd_unit(const ItemD& it, int part, LevelState ls, double* vec, double* lds) {
+__device__ __forceinline__ void bwd_unit(const ItemD& it, int part, LevelState ls, double* vec, double* lds) {
   const int m = it.m;
   const int k = ls.k[it.s], a = ls.a[it.s];
   const int r0 = part * kSweepRows;
@@ -1898,7 +2034,7 @@ __device__ void bwd_unit(const ItemD& it, int part, LevelState ls, double* vec, 
 // Backward sweep of a split cluster, per-cluster part (after its units):
 // x_s <- G^{-T} U x_s.
 template <int R>
-__device__ void bwd_tail(const ItemD& it, LevelState ls, double* vec, double* lds) {
+__device__ __forceinline__ void bwd_tail(const ItemD& it, LevelState ls, double* vec, double* lds) {
   const int m = it.m;
   if (m == 0) return;
   const int tid = threadIdx.x;
@@ -1920,7 +2056,7 @@ __device__ void bwd_tail(const ItemD& it, LevelState ls, double* vec, double* ld
 // Backward substitution of one cluster: x_f -= F x_n, x_s <- G^{-T} U x_s.
 // lds: mp + 64*65 + 16*mp + 1024 doubles.
 template <int R>
-__device__ void bwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
+__device__ __forceinline__ void bwd_item(const ItemD& it, LevelState ls, double* vec, double* lds) {
   const int m = it.m;
   if (m == 0) return;
   const int tid = threadIdx.x;
@@ -1993,7 +2129,7 @@ __device__ __forceinline__ WaveItem wave_item(const ItemD& it, LevelState ls) {
 // not depend on the computation (G, the reflectors, the first 64 columns of
 // F with their targets and the targets' old values) is issued up front.
 template <int MB>
-__device__ void fwd_wave(const WaveItem& wi, double* vec) {
+__device__ __forceinline__ void fwd_wave(const WaveItem& wi, double* vec) {
   constexpr bool PF = MB <= 32;
   const int lane = threadIdx.x & 63;
   const int m = wi.m;
@@ -2093,7 +2229,7 @@ __device__ void fwd_wave(const WaveItem& wi, double* vec) {
 // x_f -= F x_n; x_s <- G^{-T} U x_s.  For MB <= 32 the loads of G, the
 // reflectors, the first 32 columns of F and their x_n are issued up front.
 template <int MB>
-__device__ void bwd_wave(const WaveItem& wi, double* vec) {
+__device__ __forceinline__ void bwd_wave(const WaveItem& wi, double* vec) {
   constexpr bool PF = MB <= 32;
   const int lane = threadIdx.x & 63;
   const int m = wi.m;
