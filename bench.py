@@ -250,11 +250,53 @@ def run_learned(args):
 KERNEL_FAMILIES = {
     "split_potrf": ("chol_inv_kernel (diagonal-block Cholesky and inverse, MFMA fp64)", "mfma"),
     "split_trsm": ("trsm_inv_kernel (scaling by G^-1, MFMA fp64)", "mfma"),
-    "split_cpqr": ("qr_rot_kernel + cpqr_kernel (pivoted QR)", "alu"),
+    "split_cpqr": ("cpqr_kernel (pivoted QR)", "alu"),
     "split_applyq": ("applyq_kernel (U^T rotation)", "alu"),
     "split_schur": ("schur_kernel (F^T F on MFMA)", "mfma"),
     "fused": ("slre_level_kernel (one workgroup per cluster)", "alu"),
 }
+# kernel symbol of each family in the profiler's counter tables
+KERNEL_SYMBOLS = {
+    "split_potrf": "void chol_inv_kernel<8>",
+    "split_trsm": "trsm_inv_kernel",
+    "split_cpqr": "void cpqr_kernel<4>",
+    "split_applyq": "applyq_kernel",
+    "split_schur": "void schur_kernel<0>",
+    "fused": "void slre_level_kernel<false>",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "slab64_traffic.md")
+
+
+def kernel_sources_hash():
+    """sha256 over the kernel and runtime sources (file names and contents in
+    name order): the counters in the traffic table hold for this hash only."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1811_11248_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(fam, workload):
+    """HBM bytes per launch of the family's kernel from the committed counter
+    table (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel
+    calibration), or None when the table was taken on other sources or
+    another workload."""
+    if workload != "slab64" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    if ("Kernel sources sha256: " + kernel_sources_hash()) not in text:
+        return None
+    sym = KERNEL_SYMBOLS.get(fam)
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 5 and cells[0] == sym:
+            return round(float(cells[4]) * 1e6)
+    return None
 
 
 def dominant_family(timing):
@@ -262,7 +304,7 @@ def dominant_family(timing):
     return max(KERNEL_FAMILIES, key=lambda f: timing.get(f, {}).get("total_ms", 0.0))
 
 
-def roofline(timing):
+def roofline(timing, workload):
     """Roofline of the dominant single kernel, from the HIP events around its
     launches (on the library's stream) over the timed steps."""
     fam = next(k[len("roofline_"):] for k in timing if k.startswith("roofline_"))
@@ -271,7 +313,8 @@ def roofline(timing):
     sec = t["total_ms"] * 1e-3
     n = max(1, t["launches"])
     base = {"kernel": name, "family": fam, "launches": t["launches"],
-            "avg_launch_us": round(t["total_ms"] * 1e3 / n, 2), "traffic": None}
+            "avg_launch_us": round(t["total_ms"] * 1e3 / n, 2),
+            "traffic": measured_traffic(fam, workload), "traffic_unit": "byte per launch"}
     if bound == "hbm":
         ach = t["bytes"] / sec / 1e9 if sec > 0 else 0.0
         base.update(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -349,7 +392,7 @@ def main():
         "pcg_ms": round(f64["pcg_ms"], 4),
         "pcg_iters": f64["iters"],
         "relres": f64["relres"],
-        "roofline": roofline(timing),
+        "roofline": roofline(timing, args.workload),
         "kernel_families": {f: {"launches": t["launches"], "total_ms": round(t["total_ms"], 4)}
                             for f, t in timing.items() if t["launches"] and not f.startswith("roofline_")},
         "factor_gflops": round(f64["factor_gflops"], 2),
