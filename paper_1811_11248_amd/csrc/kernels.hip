@@ -793,42 +793,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Data-parallel-primitive lane exchange within rows of 16 lanes (every
-// source lane lies in the row, all lanes active).
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
-constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
-constexpr int kDppHalfMirror = 0x141; // lane i <- 7-i in rows of 8
-constexpr int kDppMirror = 0x140;     // lane i <- 15-i in rows of 16
-
-// Wave-wide max / sum / min: every 16-lane row reduces by register
-// exchanges (each lane of a row ends with the same value), then the four
-// row results combine in a fixed order; all lanes get the result.
-__device__ __forceinline__ double wave_max_dpp(double v) {
-  v = fmax(v, dpp_d<kDppXor1>(v));
-  v = fmax(v, dpp_d<kDppXor2>(v));
-  v = fmax(v, dpp_d<kDppHalfMirror>(v));
-  v = fmax(v, dpp_d<kDppMirror>(v));
-  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
-}
-__device__ __forceinline__ int wave_min_dpp(int v) {
-  v = min(v, dpp_i<kDppXor1>(v));
-  v = min(v, dpp_i<kDppXor2>(v));
-  v = min(v, dpp_i<kDppHalfMirror>(v));
-  v = min(v, dpp_i<kDppMirror>(v));
-  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
-
 __host__ __device__ __forceinline__ size_t tiny_al(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // Byte offsets of the LDS sections of the small-cluster form (the pair

@@ -736,22 +736,26 @@ __global__ void __launch_bounds__(256) trsm_kernel(const ItemD* __restrict__ ite
 }
 
 // ---------------------------------------------------------------------------
-// Column-pivoted QR of the far-field block (same rule as the fused kernel).
-// 1024 threads; norms and pivot flags in LDS; each update pass streams the
-// remaining columns with CPW columns x R rows per lane in flight.
-template <int R>
-__global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                    double tol, int tol_mode, int level) {
-  constexpr int NT = 1024, NW = NT / 64, CPW = (R <= 4 ? 6 : (R <= 8 ? 3 : 2));
+// Column-pivoted QR of the far-field block (same rules as the fused kernel).
+// NT threads; column c belongs to wave (c / CPW) % NW, which streams it in
+// and out with R rows per lane.  Per reflector: wave 0 picks the pivot from
+// the norms in LDS, the pivot column's wave forms the reflector (it wrote the
+// column itself, so it reads it back without a barrier) and stages it in LDS,
+// every wave updates its columns and their norms.  The barriers order LDS
+// only: no wave waits for the column stores of another.
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) cpqr_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                  double tol, int tol_mode, int level) {
+  constexpr int NW = NT / 64, CPW = (R <= 4 ? 6 : (R <= 8 ? 3 : 2));
   extern __shared__ double lds[];
-  __shared__ double shd[NW];
-  __shared__ int shi[NW];
+  __shared__ int s_best, s_code;
+  __shared__ double s_rjj, s_tj;
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
-  const int a = ls.a[it.s], b = ls.b[it.s];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int a = gload(ls.a + it.s), b = gload(ls.b + it.s);
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (m == 0 || b == 0) {
-    if (tid == 0) ls.k[it.s] = 0;
+    if (tid == 0) gstore(ls.k + it.s, 0);
     return;
   }
   double* nrm = lds;                          // b
@@ -759,77 +763,104 @@ __global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ it
   int* stp = reinterpret_cast<int*>(vs + m);  // b
   double* W = it.P + (size_t)m * (m + a);
   for (int c = tid; c < b; c += NT) {
-    nrm[c] = it.norms[c];
+    nrm[c] = gload(it.norms + c);
     stp[c] = -1;
   }
-  __syncthreads();
+  lds_barrier();
   const int kmax = min(m, b);
-  double r00 = 0.0;
+  double r00 = 0.0;  // wave 0 only
   int k = kmax;
   bool over = false;
   for (int j = 0; j < kmax; ++j) {
-    double mx = 0.0;
-    for (int c = tid; c < b; c += NT)
-      if (stp[c] < 0) mx = fmax(mx, nrm[c]);
-    mx = group_max<NT>(mx, shd);
-    const double thr = (1.0 - kTie) * mx;
-    int best = INT_MAX;
-    for (int c = tid; c < b; c += NT)
-      if (stp[c] < 0 && nrm[c] >= thr) best = min(best, c);
-    best = group_min_int<NT>(best, shi);
-    if (best == INT_MAX) {
-      k = j;
+    if (wv == 0) {
+      double mx = 0.0;
+      for (int c = lane; c < b; c += 64)
+        if (stp[c] < 0) mx = fmax(mx, nrm[c]);
+      mx = wave_max_dpp(mx);
+      const double thr = (1.0 - kTie) * mx;
+      int best = INT_MAX;
+      for (int c = lane; c < b; c += 64)
+        if (stp[c] < 0 && nrm[c] >= thr) best = min(best, c);
+      best = wave_min_dpp(best);
+      int code = 0;
+      double rjj = 0.0;
+      if (best == INT_MAX) {  // only NaN norms left
+        code = 1;
+      } else {
+        rjj = sqrt(nrm[best]);
+        if (j == 0) r00 = rjj;
+        const bool stop = (tol_mode == 0) ? (rjj <= tol * r00) : (rjj <= tol);
+        if (stop || rjj == 0.0) code = 1;
+        else if (j >= it.kcap) code = 2;  // rank beyond the capacity
+      }
+      if (lane == 0) {
+        s_best = best;
+        s_code = code;
+        s_rjj = rjj;
+      }
+    }
+    lds_barrier();
+    const int code = __builtin_amdgcn_readfirstlane(s_code);
+    if (code) {
+      k = code == 2 ? it.kcap : j;
+      over = code == 2;
       break;
     }
-    const double rjj = sqrt(nrm[best]);
-    if (j == 0) r00 = rjj;
-    const bool stop = (tol_mode == 0) ? (rjj <= tol * r00) : (rjj <= tol);
-    if (stop || rjj == 0.0) {
-      k = j;
-      break;
+    const int best = __builtin_amdgcn_readfirstlane(s_best);
+    if (wv == (best / CPW) % NW) {
+      // reflector j from the pivot column: unit entry at row j, R_jj there
+      const double rjj = s_rjj;
+      double* x = W + (size_t)m * best;
+      double xv[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = lane + 64 * t;
+        xv[t] = i < m ? gload(x + i) : 0.0;
+      }
+      double rest = 0.0, xj = 0.0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = lane + 64 * t;
+        if (i > j && i < m) rest += xv[t] * xv[t];
+        xj = t == (j >> 6) ? xv[t] : xj;
+      }
+      rest = wave_sum(rest);
+      const double alpha = readlane_d(xj, j & 63);
+      double d, tj;
+      if (alpha <= 0.0) {
+        d = alpha - rjj;
+        tj = (rjj - alpha) / rjj;
+      } else {
+        d = -rest / (alpha + rjj);
+        tj = rest / (rjj * (rjj + alpha));
+      }
+      if (d == 0.0) tj = 0.0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = lane + 64 * t;
+        if (i < m) {
+          double v = 0.0;
+          if (i == j) v = 1.0;
+          else if (i > j) v = (d != 0.0) ? xv[t] / d : 0.0;
+          vs[i] = v;
+          if (i == j) gstore(x + i, rjj);
+          else if (i > j) gstore(x + i, v);
+        }
+      }
+      if (lane == 0) {
+        s_tj = tj;
+        stp[best] = j;
+        gstore(it.piv + j, best);
+        gstore(it.tau + j, tj);
+      }
     }
-    if (j >= it.kcap) {  // rank beyond the capacity: no room for reflector j
-      k = it.kcap;
-      over = true;
-      break;
-    }
-    double* x = W + (size_t)m * best;
-    double xv = 0.0, rest = 0.0;
-    for (int i = j + 1 + tid; i < m; i += NT) {
-      xv = x[i];
-      rest += xv * xv;
-    }
-    rest = group_sum<NT>(rest, shd);
-    const double alpha = x[j];
-    double d, tj;
-    if (alpha <= 0.0) {
-      d = alpha - rjj;
-      tj = (rjj - alpha) / rjj;
-    } else {
-      d = -rest / (alpha + rjj);
-      tj = rest / (rjj * (rjj + alpha));
-    }
-    if (d == 0.0) tj = 0.0;
-    for (int i = tid; i < m; i += NT) {
-      double v = 0.0;
-      if (i == j) v = 1.0;
-      else if (i > j) v = (d != 0.0) ? x[i] / d : 0.0;
-      vs[i] = v;
-    }
-    __syncthreads();
-    for (int i = j + 1 + tid; i < m; i += NT) x[i] = vs[i];
-    if (tid == 0) {
-      x[j] = rjj;
-      it.piv[j] = best;
-      stp[best] = j;
-      it.tau[j] = tj;
-    }
-    __syncthreads();
+    lds_barrier();
+    const double tj = s_tj;
     double vr[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) {
       const int i = lane + 64 * t;
-      vr[t] = i < m ? vs[i] : 0.0;
+      vr[t] = (i >= j && i < m) ? vs[i] : 0.0;
     }
     for (int cb = wv * CPW; cb < b; cb += NW * CPW) {
       double y[CPW][R];
@@ -842,7 +873,7 @@ __global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ it
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const int i = lane + 64 * t;
-          y[q][t] = (act[q] && i >= j && i < m) ? yc[i] : 0.0;
+          y[q][t] = (act[q] && i >= j && i < m) ? gload(yc + i) : 0.0;
         }
       }
 #pragma unroll
@@ -859,7 +890,7 @@ __global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ it
           const int i = lane + 64 * t;
           if (i >= j && i < m) {
             const double nv = y[q][t] - f * vr[t];
-            yc[i] = nv;
+            gstore(yc + i, nv);
             if (i > j) nn += nv * nv;
           }
         }
@@ -867,10 +898,10 @@ __global__ void __launch_bounds__(1024) cpqr_kernel(const ItemD* __restrict__ it
         if (lane == 0) nrm[cb + q] = nn;
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
-  for (int c = tid; c < b; c += NT) it.stepof[c] = stp[c];
-  if (tid == 0) ls.k[it.s] = k;
+  for (int c = tid; c < b; c += NT) gstore(it.stepof + c, stp[c]);
+  if (tid == 0) gstore(ls.k + it.s, k);
   if ((over || k > it.kcap) && tid == 0) item_error(it, ls.err, level, kErrCapacity);
 }
 
@@ -1130,9 +1161,11 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
     case kSplitCpqr: {
       const size_t lds = (size_t)d.max_pcap * 12 + (size_t)mm * 8 + 64;
       if (mm <= 256)
-        hipLaunchKernelGGL(cpqr_kernel<4>, dim3(nitems), dim3(1024), lds, st, items, ls, tol, tol_mode, level);
+        hipLaunchKernelGGL((cpqr_kernel<4, 1024>), dim3(nitems), dim3(1024), lds, st, items, ls, tol, tol_mode,
+                           level);
       else
-        hipLaunchKernelGGL(cpqr_kernel<8>, dim3(nitems), dim3(1024), lds, st, items, ls, tol, tol_mode, level);
+        hipLaunchKernelGGL((cpqr_kernel<8, 1024>), dim3(nitems), dim3(1024), lds, st, items, ls, tol, tol_mode,
+                           level);
       break;
     }
     case kSplitApplyq:
