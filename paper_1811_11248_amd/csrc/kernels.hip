@@ -2326,6 +2326,12 @@ __global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const Ite
     }
     if (q + 1 == ncolours) break;
     const int cn = FWD ? c + 1 : c - 1;
+    // colours of at most one cluster run on wave 0 of workgroup 0: its own
+    // program order orders them (no barrier, no wait for its stores)
+    if (cstart[c + 1] - cstart[c] <= 1 && cstart[cn + 1] - cstart[cn] <= 1) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      continue;
+    }
     // colours of at most nw clusters run on workgroup 0 alone
     const bool local = cstart[c + 1] - cstart[c] <= nw && cstart[cn + 1] - cstart[cn] <= nw;
     if (gridDim.x == 1 || local) __syncthreads();
