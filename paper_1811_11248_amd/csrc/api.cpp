@@ -513,7 +513,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
       const bool per_colour = F->exec_mode == 1 || sweep_units(true, L.max_m, L.max_acap) > 0;
       if (per_colour ||
           launch_sweep_level(true, L.d_items, L.d_cstart, p.ncolours, p.cstart.back(), L.max_items, L.max_m, L.max_acap, L.ls, V,
-                             st) != hipSuccess) {
+                             st, 0, nullptr, L.vbase, L.nvec) != hipSuccess) {
         if (!per_colour) (void)hipGetLastError();
         for (int c = 0; c < p.ncolours; ++c)
           launch_fwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st);
@@ -543,7 +543,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
       const bool per_colour = F->exec_mode == 1 || sweep_units(false, L.max_m, L.max_acap) > 0;
       if (per_colour ||
           launch_sweep_level(false, L.d_items, L.d_cstart, p.ncolours, p.cstart.back(), L.max_items, L.max_m, L.max_acap, L.ls, V,
-                             st) != hipSuccess) {
+                             st, 0, nullptr, L.vbase, L.nvec) != hipSuccess) {
         if (!per_colour) (void)hipGetLastError();
         for (int c = p.ncolours - 1; c >= 0; --c)
           launch_bwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st);

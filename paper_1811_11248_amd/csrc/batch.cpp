@@ -723,7 +723,7 @@ lrsp_status apply_cols(lrsp_batch* F, const double* b, double* x, int nrhs, bool
       const bool per_colour = sweep_units(true, B.max_m, B.max_acap) > 0;
       if (per_colour ||
           launch_sweep_level(true, B.d_items, B.d_cstart, B.ncolours, B.cstart.back(), B.max_items, B.max_m, B.max_acap, B.ls, V, st, 0,
-                             graph ? sweep_bar(F, l, true) : nullptr) != hipSuccess) {
+                             graph ? sweep_bar(F, l, true) : nullptr, 0, F->vec_total) != hipSuccess) {
         if (!per_colour) {
           if (graph) return fail(LRSP_ERR_HIP, "persistent sweep launch failed");
           (void)hipGetLastError();
@@ -742,7 +742,7 @@ lrsp_status apply_cols(lrsp_batch* F, const double* b, double* x, int nrhs, bool
         const bool per_colour = sweep_units(false, B.max_m, B.max_acap) > 0;
         if (per_colour ||
             launch_sweep_level(false, B.d_items, B.d_cstart, B.ncolours, B.cstart.back(), B.max_items, B.max_m, B.max_acap, B.ls, V,
-                               st, 0, graph ? sweep_bar(F, l, false) : nullptr) != hipSuccess) {
+                               st, 0, graph ? sweep_bar(F, l, false) : nullptr, 0, F->vec_total) != hipSuccess) {
           if (!per_colour) {
             if (graph) return fail(LRSP_ERR_HIP, "persistent sweep launch failed");
             (void)hipGetLastError();

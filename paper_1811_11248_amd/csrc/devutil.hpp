@@ -81,10 +81,16 @@ __device__ __forceinline__ int wave_min_dpp(int v) {
              min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
+// Sum over the 64 lanes (all active), every lane gets the result: rows of
+// 16 lanes reduce by register exchanges (all lanes of a row end with the
+// same value, the additions being commutative), then the row sums combine
+// as (r0 + r1) + (r2 + r3).  A fixed order: the same bits on every call.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<kDppXor1>(v);
+  v += dpp_d<kDppXor2>(v);
+  v += dpp_d<kDppHalfMirror>(v);
+  v += dpp_d<kDppMirror>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // Sum over the workgroup (nt threads, nt/64 <= 16 waves); every thread gets
@@ -103,8 +109,7 @@ __device__ __forceinline__ double group_sum(double v, double* sh) {
 
 template <int NT>
 __device__ __forceinline__ double group_max(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  v = wave_max_dpp(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -116,8 +121,7 @@ __device__ __forceinline__ double group_max(double v, double* sh) {
 
 template <int NT>
 __device__ __forceinline__ int group_min_int(int v, int* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  v = wave_min_dpp(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();

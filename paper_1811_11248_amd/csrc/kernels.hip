@@ -2079,14 +2079,15 @@ struct WaveItem {
   const double* tau;
   const int64_t* vidx;
   const int32_t* piv;
+  const int32_t* vix;  // LDS copy of the first kSweepWaveVix entries of vidx, or null
   int64_t voff;
   int32_t m, k, a, pad;
 };
 
-static_assert(sizeof(WaveItem) + 4 * kSweepWaveM <= kSweepWaveTableBytes, "wave table entry");
+static_assert(sizeof(WaveItem) + 4 * kSweepWaveM + 4 * kSweepWaveVix <= kSweepWaveTableBytes, "wave table entry");
 
 __device__ __forceinline__ WaveItem wave_item(const ItemD& it, LevelState ls) {
-  return WaveItem{it.P, it.tau, it.vidx, it.piv, it.voff, it.m, ls.k[it.s], ls.a[it.s], 0};
+  return WaveItem{it.P, it.tau, it.vidx, it.piv, nullptr, it.voff, it.m, ls.k[it.s], ls.a[it.s], 0};
 }
 
 // y_s <- U^T G^{-1} y_s; y_n -= F^T y_f.  For MB <= 32 every load that does
@@ -2124,7 +2125,7 @@ __device__ __forceinline__ void fwd_wave(const WaveItem& wi, double* vec) {
     const double* Cc = C + (size_t)m * (cv0 ? lane : 0);
 #pragma unroll
     for (int i = 0; i < MB; ++i) f0[i] = (cv0 && i >= k && i < m) ? Cc[i] : 0.0;
-    if (cv0) old0 = vec[wi.vidx[lane]];
+    if (cv0) old0 = vec[wi.vix ? (int64_t)wi.vix[lane] : wi.vidx[lane]];
   }
   const double rd = 1.0 / gd;
   // G^{-1}
@@ -2167,7 +2168,7 @@ __device__ __forceinline__ void fwd_wave(const WaveItem& wi, double* vec) {
         const double yi = readlane_d(y, i);
         if (cv && i >= k && i < m) s += f0[i] * yi;
       }
-      if (cv) vec[wi.vidx[c]] = old0 - s;
+      if (cv) vec[wi.vix ? (int64_t)wi.vix[c] : wi.vidx[c]] = old0 - s;
       continue;
     }
     const double* Cc = C + (size_t)m * (cv ? c : 0);
@@ -2225,7 +2226,7 @@ __device__ __forceinline__ void bwd_wave(const WaveItem& wi, double* vec) {
     const double* Cr = C + (size_t)(fine ? lane : 0);
 #pragma unroll
     for (int q = 0; q < 32; ++q) f0[q] = (fine && q < nc0) ? Cr[(size_t)m * q] : 0.0;
-    if (lane < nc0) xn0 = vec[wi.vidx[lane]];
+    if (lane < nc0) xn0 = vec[wi.vix ? (int64_t)wi.vix[lane] : wi.vidx[lane]];
   }
   const double rd = 1.0 / gd;
   // x_f -= F x_n, one lane per row, columns in order
@@ -2294,7 +2295,9 @@ __device__ __forceinline__ void bwd_wave(const WaveItem& wi, double* vec) {
 // one workgroup needs no grid barrier between colours.  With table != 0 the
 // descriptors, ranks and pivots of all the level's clusters are first copied
 // to LDS (kSweepWaveTableBytes per cluster), which takes their loads off the
-// path of every colour.
+// path of every colour; with table == 2 also the level-vector indices of the
+// first kSweepWaveVix near-field columns (32-bit), so that the vector loads
+// of a cluster do not wait for its index loads.
 template <bool FWD, bool SW>
 __global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const ItemD* __restrict__ items,
                                                                        const int32_t* __restrict__ cstart,
@@ -2305,6 +2308,7 @@ __global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const Ite
   const int ni = cstart[ncolours];
   WaveItem* tab = reinterpret_cast<WaveItem*>(dlds);
   int32_t* pvs = reinterpret_cast<int32_t*>(tab + (table ? ni : 0));
+  int32_t* vxs = pvs + (table ? (size_t)ni * kSweepWaveM : 0);
   if (table) {
     for (int i = threadIdx.x; i < ni; i += kSweepWaveThreads) tab[i] = wave_item(items[i], ls);
     __syncthreads();
@@ -2312,8 +2316,16 @@ __global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const Ite
       const int i = e / kSweepWaveM, j = e - i * kSweepWaveM;
       pvs[e] = j < tab[i].k ? tab[i].piv[j] : 0;
     }
+    if (table > 1)
+      for (int e = threadIdx.x; e < ni * kSweepWaveVix; e += kSweepWaveThreads) {
+        const int i = e / kSweepWaveVix, j = e - i * kSweepWaveVix;
+        vxs[e] = j < tab[i].a ? (int32_t)tab[i].vidx[j] : 0;
+      }
     __syncthreads();
-    for (int i = threadIdx.x; i < ni; i += kSweepWaveThreads) tab[i].piv = pvs + (size_t)kSweepWaveM * i;
+    for (int i = threadIdx.x; i < ni; i += kSweepWaveThreads) {
+      tab[i].piv = pvs + (size_t)kSweepWaveM * i;
+      if (table > 1) tab[i].vix = vxs + (size_t)kSweepWaveVix * i;
+    }
     __syncthreads();
   }
   for (int q = 0; q < ncolours; ++q) {
@@ -2528,7 +2540,7 @@ void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelSt
 
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
                               int nitems, int max_items, int max_m, int max_acap, LevelState ls, double* vec,
-                              hipStream_t st, int grid_cap, GridBar* bar) {
+                              hipStream_t st, int grid_cap, GridBar* bar, int64_t vlo, int64_t vn) {
   if (max_m <= kSweepWaveM) {
     constexpr int nw = kSweepWaveThreads / 64;
     int want = std::max(1, (max_items + nw - 1) / nw);
@@ -2536,6 +2548,8 @@ hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* c
     static bool lds_ok[4] = {false, false, false, false};
     const size_t tbytes = (size_t)nitems * kSweepWaveTableBytes;
     int table = tbytes <= kSweepWaveTableMax ? 1 : 0;
+    // 32-bit vector indices when the whole level vector lies below 2^31
+    if (table && vn > 0 && vlo + vn < ((int64_t)1 << 31)) table = 2;
     const size_t lds = table ? tbytes : 0;
     if (want == 1 || bar) {
       const int g = std::min(want, device_cus());

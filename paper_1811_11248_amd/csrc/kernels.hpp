@@ -61,7 +61,8 @@ constexpr int kSweepRows = 32;
 // clusters run in workgroups of kSweepWaveThreads threads.
 constexpr int kSweepWaveM = 32;
 constexpr int kSweepWaveThreads = 512;
-constexpr size_t kSweepWaveTableBytes = 56 + 4 * kSweepWaveM;  // per cluster: descriptor + pivots
+constexpr int kSweepWaveVix = 64;  // near-field vector indices staged per cluster
+constexpr size_t kSweepWaveTableBytes = 64 + 4 * kSweepWaveM + 4 * kSweepWaveVix;  // descriptor, pivots, indices
 constexpr size_t kSweepWaveTableMax = 96 * 1024;
 int sweep_units(bool forward, int max_m, int max_acap);
 // The items of one colour (one launch, plus one for the units).
@@ -69,10 +70,12 @@ void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelSt
                 hipStream_t st);
 void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
                 hipStream_t st);
-// A whole level in one persistent launch.
+// A whole level in one persistent launch; [vlo, vlo + vn) is the level's
+// range of the vector buffer (vn = 0: unknown).
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
                               int nitems, int max_items, int max_m, int max_acap, LevelState ls, double* vec,
-                              hipStream_t st, int grid_cap = 0, GridBar* bar = nullptr);
+                              hipStream_t st, int grid_cap = 0, GridBar* bar = nullptr, int64_t vlo = 0,
+                              int64_t vn = 0);
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st);
 // Dense tops of a batch, one workgroup per system (n <= kMaxClusterDofs).
 void launch_top_potrf_batched(const TopD* tops, int ntops, int max_n, hipStream_t st);
