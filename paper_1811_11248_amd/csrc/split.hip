@@ -906,37 +906,45 @@ __global__ void __launch_bounds__(NT) cpqr_kernel(const ItemD* __restrict__ item
 }
 
 // ---------------------------------------------------------------------------
-// C <- U^T C for 64 near-field columns per workgroup; reflectors staged in
-// LDS 16 at a time, four columns per wave in registers.
+// C <- U^T C for kApplyqCols near-field columns per workgroup (one column
+// per wave per pass, R rows per lane in registers); reflectors staged in LDS
+// 16 at a time.
+constexpr int kApplyqCols = 16;
+template <int R>
 __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ items, LevelState ls) {
   extern __shared__ double lds[];
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
-  const int k = min(ls.k[it.s], it.kcap), a = ls.a[it.s];
-  const int c0 = blockIdx.y * 64;
+  const int k = min(gload(ls.k + it.s), it.kcap), a = gload(ls.a + it.s);
+  const int c0 = blockIdx.y * kApplyqCols;
   if (m == 0 || k == 0 || c0 >= a) return;
-  const int c1 = min(a, c0 + 64);
+  const int c1 = min(a, c0 + kApplyqCols);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double* Vs = lds;            // 16 x m
   double* ts = lds + 16 * m;   // 16
+  int* pv = reinterpret_cast<int*>(ts + 16);  // 16
   const double* W = it.P + (size_t)m * (m + a);
   double* C = it.P + (size_t)m * m;
   for (int j0 = 0; j0 < k; j0 += 16) {
     const int nj = min(16, k - j0);
-    __syncthreads();
+    if (j0 > 0) __syncthreads();
+    if (tid < nj) {
+      ts[tid] = gload(it.tau + j0 + tid);
+      pv[tid] = gload(it.piv + j0 + tid);
+    }
+    lds_barrier();
     for (int e = tid; e < nj * m; e += 256) {
       const int jj = e / m, i = e - jj * m, j = j0 + jj;
-      Vs[jj * m + i] = (i == j) ? 1.0 : (i > j ? W[(size_t)m * it.piv[j] + i] : 0.0);
+      Vs[jj * m + i] = (i == j) ? 1.0 : (i > j ? gload(W + (size_t)m * pv[jj] + i) : 0.0);
     }
-    if (tid < nj) ts[tid] = it.tau[j0 + tid];
-    __syncthreads();
+    lds_barrier();
     for (int cb = c0 + wv * 4; cb < c1; cb += 16) {
-      double y[4][kRegRows];
+      double y[4][R];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = cb + q;
 #pragma unroll
-        for (int t = 0; t < kRegRows; ++t) {
+        for (int t = 0; t < R; ++t) {
           const int i = lane + 64 * t;
           y[q][t] = (c < c1 && i < m) ? C[(size_t)m * c + i] : 0.0;
         }
@@ -948,7 +956,7 @@ __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ i
         for (int q = 0; q < 4; ++q) {
           double acc = 0.0;
 #pragma unroll
-          for (int t = 0; t < kRegRows; ++t) {
+          for (int t = 0; t < R; ++t) {
             const int i = lane + 64 * t;
             if (i < m) acc += v[i] * y[q][t];
           }
@@ -957,7 +965,7 @@ __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ i
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int t = 0; t < kRegRows; ++t) {
+          for (int t = 0; t < R; ++t) {
             const int i = lane + 64 * t;
             if (i < m) y[q][t] -= s[q] * v[i];
           }
@@ -967,7 +975,7 @@ __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ i
         const int c = cb + q;
         if (c >= c1) continue;
 #pragma unroll
-        for (int t = 0; t < kRegRows; ++t) {
+        for (int t = 0; t < R; ++t) {
           const int i = lane + 64 * t;
           if (i < m) C[(size_t)m * c + i] = y[q][t];
         }
@@ -1170,8 +1178,12 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
     }
     case kSplitApplyq:
       if (d.max_acap <= 0) break;
-      hipLaunchKernelGGL(applyq_kernel, dim3(nitems, (d.max_acap + 63) / 64), dim3(256),
-                         ((size_t)16 * mm + 16) * 8, st, items, ls);
+      if (mm <= 256)
+        hipLaunchKernelGGL(applyq_kernel<4>, dim3(nitems, (d.max_acap + kApplyqCols - 1) / kApplyqCols), dim3(256),
+                           ((size_t)16 * mm + 24) * 8, st, items, ls);
+      else
+        hipLaunchKernelGGL(applyq_kernel<kRegRows>, dim3(nitems, (d.max_acap + kApplyqCols - 1) / kApplyqCols),
+                           dim3(256), ((size_t)16 * mm + 24) * 8, st, items, ls);
       break;
     case kSplitSchur: {
       if (d.max_acap <= 0) break;
