@@ -98,36 +98,56 @@ __global__ void __launch_bounds__(256) seg_offsets_kernel(const ItemD* __restric
   }
 }
 
+// 32 panel columns per workgroup, eight per wave: the column sources of all
+// eight are looked up together, then their rows (R per lane) are loaded
+// together and stored.
+template <int R>
 __global__ void __launch_bounds__(256) gather_panel_kernel(const ItemD* __restrict__ items,
                                                            LevelState ls) {
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   if (m == 0) return;
-  const int ncols = m + ls.a[it.s] + ls.b[it.s];
+  const int ncols = m + gload(ls.a + it.s) + gload(ls.b + it.s);
   const int c0 = blockIdx.y * 32;
   if (c0 >= ncols) return;
-  const int c1 = min(ncols, c0 + 32);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int c = c0 + wv; c < c1; c += 4) {
-    const double* src;
+  int sg[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int c = c0 + wv + 4 * q;
+    sg[q] = (c >= m && c < ncols) ? gload(it.colseg + (c - m)) : 0;
+  }
+  const double* src[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int c = c0 + wv + 4 * q;
     if (c < m) {
-      src = it.D + (size_t)m * c;
+      src[q] = it.D + (size_t)m * c;
+    } else if (c < ncols) {
+      const double* base = gload(&it.seg[sg[q]].src);
+      src[q] = base + (size_t)m * (c - m - gload(it.segoff + sg[q]));
     } else {
-      const int pc = c - m;
-      const int sg = it.colseg[pc];
-      src = it.seg[sg].src + (size_t)m * (pc - it.segoff[sg]);
+      src[q] = it.D;
     }
+  }
+  double v[8][R];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int c = c0 + wv + 4 * q;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int r = lane + 64 * t;
+      v[q][t] = (c < ncols && r < m) ? gload(src[q] + r) : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int c = c0 + wv + 4 * q;
     double* dst = it.P + (size_t)m * c;
-    double v[kRegRows];
 #pragma unroll
-    for (int t = 0; t < kRegRows; ++t) {
+    for (int t = 0; t < R; ++t) {
       const int r = lane + 64 * t;
-      v[t] = r < m ? src[r] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < kRegRows; ++t) {
-      const int r = lane + 64 * t;
-      if (r < m) dst[r] = v[t];
+      if (c < ncols && r < m) gstore(dst + r, v[q][t]);
     }
   }
 }
@@ -1143,8 +1163,12 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
                          items, ls, level);
       break;
     case kSplitGather:
-      hipLaunchKernelGGL(gather_panel_kernel, dim3(nitems, (mm + d.max_pcap + 31) / 32), dim3(256), 0,
-                         st, items, ls);
+      if (mm <= 256)
+        hipLaunchKernelGGL(gather_panel_kernel<4>, dim3(nitems, (mm + d.max_pcap + 31) / 32), dim3(256), 0, st, items,
+                           ls);
+      else
+        hipLaunchKernelGGL(gather_panel_kernel<kRegRows>, dim3(nitems, (mm + d.max_pcap + 31) / 32), dim3(256), 0, st,
+                           items, ls);
       break;
     case kSplitPotrf:
       if (mm <= kInvMaxDofs)
