@@ -1764,23 +1764,25 @@ __device__ __forceinline__ void gemv_tri(const double* M, int m, bool upper, dou
 
 // Stages reflectors j0..j0+nj-1 of the far-field block Wf (m rows) in LDS as
 // vs[jj*mp + i] (unit leading entry, zeros above).
-__device__ __forceinline__ void stage_reflectors(const ItemD& it, const double* Wf, int m, int mp, int j0, int nj,
-                                 double* vs) {
+// Reflectors j0..j0+nj-1 into vs (rows padded to mp), sixteen loads in
+// flight per thread; pv: their far-field columns (LDS).
+__device__ __forceinline__ void stage_reflectors(const double* Wf, int m, int mp, int j0, int nj,
+                                                 const int* pv, double* vs) {
   const int n = nj * mp;
-  for (int e0 = threadIdx.x; e0 < n; e0 += kThreads * 8) {
-    double v[8];
+  for (int e0 = threadIdx.x; e0 < n; e0 += kThreads * 16) {
+    double v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int e = e0 + u * kThreads;
       const int jj = e / mp, i = e - jj * mp, j = j0 + jj;
       v[u] = 0.0;
       if (e < n && i < m) {
         if (i == j) v[u] = 1.0;
-        else if (i > j) v[u] = Wf[(size_t)m * it.piv[j] + i];
+        else if (i > j) v[u] = gload(Wf + (size_t)m * pv[jj] + i);
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int e = e0 + u * kThreads;
       if (e < n) vs[e] = v[u];
     }
@@ -1808,8 +1810,13 @@ __device__ __forceinline__ void apply_reflectors(const ItemD& it, const double* 
   for (int q = 0; q < nchunk; ++q) {
     const int j0 = fwd ? 16 * q : max(0, k - 16 * (q + 1));
     const int nj = fwd ? min(16, k - j0) : (k - 16 * q) - j0;
-    stage_reflectors(it, Wf, m, mp, j0, nj, vs);
-    for (int jj = tid; jj < nj; jj += kThreads) ts[jj] = it.tau[j0 + jj];
+    int* pv = reinterpret_cast<int*>(ts + 16);
+    if (tid < nj) {
+      ts[tid] = gload(it.tau + j0 + tid);
+      pv[tid] = gload(it.piv + j0 + tid);
+    }
+    lds_barrier();
+    stage_reflectors(Wf, m, mp, j0, nj, pv, vs);
     __syncthreads();
     if (wv == 0) {
       for (int u = 0; u < nj; ++u) {
