@@ -259,8 +259,8 @@ KERNEL_FAMILIES = {
 KERNEL_SYMBOLS = {
     "split_potrf": "void chol_inv_kernel<8>",
     "split_trsm": "trsm_inv_kernel",
-    "split_cpqr": "void cpqr_kernel<4>",
-    "split_applyq": "applyq_kernel",
+    "split_cpqr": "void cpqr_kernel<4, 1024>",
+    "split_applyq": "void applyq_kernel<4>",
     "split_schur": "void schur_kernel<0>",
     "fused": "void slre_level_kernel<false>",
 }

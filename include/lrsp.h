@@ -179,8 +179,8 @@ typedef struct {
   double rank_bytes_worst;    /* the same with worst-case capacities min(m, b) */
   int32_t rank_checks_passed; /* clusters whose rank k <= the predicted k_hat */
   int32_t rank_checks_failed; /* clusters whose QR went on past k_hat */
-  int32_t rank_redo_levels;   /* levels redone with worst-case capacities
-                                 because a rank exceeded its capacity */
+  int32_t rank_redo_levels;   /* levels run again because a rank reached
+                                 its capacity (each level counted once) */
   int32_t reserved3;
 } lrsp_info;
 lrsp_status lrsp_factor_info(const lrsp_factorization* F, lrsp_info* info);
@@ -213,8 +213,10 @@ lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_l
  * capacities, and with them the coarse blocks and panels, are sized
  * ceil(2*k_hat + 4) instead of the worst case min(m, b).  The QR itself
  * is unchanged (it stops at the rank the tolerance sets, so ranks and factor
- * equal rank_mode 0); when a rank exceeds its capacity the level is redone
- * with worst-case capacities.  Parameter vector (fp32, lrsp_mlp_nparams()):
+ * equal rank_mode 0); when a rank reaches a capacity below its worst case
+ * the level runs again from its assembled input, those clusters with the
+ * worst case and the others with their predicted capacities (at most twice;
+ * then every capacity of the level is the worst case).  Parameter vector (fp32, lrsp_mlp_nparams()):
  * mu[12] isd[12] W1[64][12] b1[64] W2[64][64] b2[64] w3[64] b3; the input is
  * (x - mu)*isd.  All arrays of the calls below are device memory. */
 int32_t lrsp_mlp_nparams(void);

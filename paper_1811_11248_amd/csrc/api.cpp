@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <string>
 #include <unordered_map>
@@ -297,9 +298,10 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     if (learned) {
       // level-start features -> predicted ranks -> rank capacities
       if (lrsp_status s = predict_level(L, level, tol, at<float>(d_mlp, 0), st, &L->feat, &L->pred)) return s;
-      const std::vector<int> caps = rank_caps(L->pred);
-      plan_capacities(&L->plan, &caps);
+      L->caps = rank_caps(L->pred);
+      plan_capacities(&L->plan, &L->caps);
       L->capped = true;
+      L->cap_tries = 0;
       if (lrsp_status s = setup_level_b(L, st)) return s;
     }
     if (!reuse) ms_an += ms_since(ta);
@@ -344,11 +346,27 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     L->b.assign(kab.begin() + 2 * M, kab.begin() + 3 * M);
     herr.assign(kab.begin() + 3 * M, kab.end());
     if (herr[0] && herr[3] == kErrCapacity && L->capped) {
-      // a rank exceeded its predicted capacity: redo the level with the
-      // worst-case capacities (the level's input is assembled again)
-      ++cap_redo;
-      plan_capacities(&L->plan, nullptr);
-      L->capped = false;
+      // a rank reached its predicted capacity: the clusters whose QR stopped
+      // at a capacity below their worst case min(m, b) get the worst case,
+      // the others keep theirs, and the level runs again from its assembled
+      // input.  A cluster eliminated after a truncated one can see other
+      // values in the new run, so this repeats, at most kCapRetries times
+      // before every capacity of the level is the worst case.
+      if (L->cap_tries++ == 0) ++cap_redo;
+      bool raised = false;
+      for (int x = 0; x < M; ++x) {
+        const int worst = std::min(p.m[x], p.bcap[x]);
+        if (L->k[x] >= p.kcap[x] && p.kcap[x] < worst) {
+          L->caps[x] = std::numeric_limits<int>::max();
+          raised = true;
+        }
+      }
+      if (raised && L->cap_tries <= kCapRetries) {
+        plan_capacities(&L->plan, &L->caps);
+      } else {
+        plan_capacities(&L->plan, nullptr);
+        L->capped = false;
+      }
       if (lrsp_status s = setup_level_b(L, st)) return s;
       launch_zero(at<double>(L->work, 0), L->plan.work_doubles, st);
       if (level == 0) {

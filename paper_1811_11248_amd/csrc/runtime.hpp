@@ -117,6 +117,8 @@ struct LevelDev {
   bool capped = false;              // rank capacities from predicted ranks
   std::vector<double> feat;         // learned ranks: features [M][12]
   std::vector<float> pred;          // and predicted ranks [M]
+  std::vector<int> caps;            // rank capacities the level runs with
+  int cap_tries = 0;                // runs of the level after a capacity overflow
   void free_all(hipStream_t st) {
     dfree(&work, st); dfree(&wints, st); dfree(&coarse, st); dfree(&fac, st); dfree(&fints, st);
     dfree(&fvidx, st);
@@ -180,6 +182,9 @@ lrsp_status predict_level(LevelDev* L, int level, double tol, const float* d_par
 // Rank capacities from predicted ranks: ceil(kRankCapScale*max(y,0) + kRankCapSlack).
 constexpr double kRankCapScale = 2.0;
 constexpr double kRankCapSlack = 4.0;
+// Targeted runs of a level after a rank overflowed its capacity before every
+// capacity of the level falls back to the worst case.
+constexpr int kCapRetries = 2;
 std::vector<int> rank_caps(const std::vector<float>& pred);
 
 // The cluster tree held by a tree handle.

@@ -161,3 +161,29 @@ def test_tiny_capacities_are_redone(torch, L):
     assert torch.equal(L.apply(F1, b), L.apply(F0, b))
     for li in range(inf["nlevels"]):
         assert F1.level(li)["ranks"].tolist() == F0.level(li)["ranks"].tolist()
+
+
+def test_overflow_rerun_keeps_other_capacities(torch, L):
+    """A constant prediction at the median level-0 rank: about half of the
+    clusters overflow.  Only they move to the worst case, so the ranks and
+    M^{-1} b equal the worst-case factor's while the memory stays below it."""
+    mk, leaf, tol = CASES["slab_aniso"]
+    pr = mk()
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree(pr.grid, leaf)
+    F0 = L.Factor(A, tree, tol)
+    r0 = np.asarray(F0.level(0)["ranks"])
+    T = int(np.median(r0))
+    P = np.zeros(L.mlp_nparams(), np.float32)
+    P[-1] = max(0.0, (T - 4) / 2.0)  # capacity ceil(2 k_hat + 4) = T for every cluster
+    F1 = L.Factor(A, tree, tol, mlp=P)
+    inf = F1.info()
+    _say(f"[overflow rerun] median rank {T}, level-0 ranks above it {int(np.sum(r0 > T))} of {r0.size}, "
+         f"redo {inf['rank_redo_levels']}, bytes {inf['rank_bytes']:.3g} of {inf['rank_bytes_worst']:.3g}")
+    assert np.sum(r0 > T) >= 1
+    assert inf["rank_redo_levels"] >= 1
+    for li in range(inf["nlevels"]):
+        assert F1.level(li)["ranks"].tolist() == F0.level(li)["ranks"].tolist()
+    b = torch.from_numpy(rhs(pr.n, 2)).cuda()
+    assert torch.equal(L.apply(F1, b), L.apply(F0, b))
+    assert inf["rank_bytes"] < inf["rank_bytes_worst"]
