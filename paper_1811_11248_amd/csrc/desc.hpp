@@ -92,7 +92,9 @@ struct LevelState {
   int32_t* a;     // near-field columns
   int32_t* b;     // far-field columns
   int32_t* err;   // [4]: flag, level, cluster, code (then 4 words of grid barrier)
-  int32_t* giok;  // 1: the factorization left G^{-1} in ItemD::Gi (and G^{-T} in GiT)
+  int32_t* giok;  // 1: the factorization left G^{-1} in ItemD::Gi (and G^{-T} in GiT);
+                  // 2: Gi holds W = U^T G^{-1} (k > 0 reflectors folded in, all
+                  //    m x m entries) and GiT holds W^T
 };
 
 // dst[r + dld*c] = trans ? src[c + sld*r] : src[r + sld*c], r < rows, c < cols

@@ -1716,47 +1716,61 @@ __device__ __forceinline__ void trsv_lower_t(const double* G, int ld, int m, dou
   }
 }
 
-// y <- M y for M (m x m, ld m, m <= 256) lower triangular (upper: upper
-// triangular), y in LDS: the 64x64 tiles of the triangle are spread over the
-// waves, each lane one row of a tile with its entries loaded 32 at a time;
-// the partial sums of the column blocks are added in order.  red: 4*256
-// doubles of LDS.
-__device__ __forceinline__ void gemv_tri(const double* M, int m, bool upper, double* y, double* red) {
+// Shapes of the cluster matrix in gemv_blk.
+constexpr int kGemvLower = 0, kGemvUpper = 1, kGemvFull = 2;
+
+// y <- M y for M (m x m, ld m, m <= 256) lower triangular, upper triangular
+// or full, y in LDS: the 64x64 tiles are spread over the waves, each lane one
+// row of a tile with the tile's 64 entries of that row loaded at once; the
+// partial sums of the column blocks are added in order.  With yg, y is first
+// copied from yg (global) into LDS, after the loads of each wave's first tile
+// have been issued, so that the two overlap.  red: 4*256 doubles of LDS.
+__device__ __forceinline__ void gemv_blk(const double* M, int m, int shape, double* y, double* red,
+                                         const double* yg = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = (m + 63) >> 6;
-  const int ntl = nb * (nb + 1) / 2;
-  for (int t = wv; t < ntl; t += kWaves) {
-    int rb = 0;
-    while ((rb + 1) * (rb + 2) / 2 <= t) ++rb;
-    const int cl = t - rb * (rb + 1) / 2;
-    const int ib = upper ? cl : rb, jb = upper ? rb : cl;
+  const int ntl = shape == kGemvFull ? nb * nb : nb * (nb + 1) / 2;
+  double g[64];
+  int ib = 0, jb = 0;
+  auto load_tile = [&](int t) {
+    if (shape == kGemvFull) {
+      ib = t % nb;
+      jb = t / nb;
+    } else {
+      int rb = 0;
+      while ((rb + 1) * (rb + 2) / 2 <= t) ++rb;
+      const int cl = t - rb * (rb + 1) / 2;
+      ib = shape == kGemvUpper ? cl : rb;
+      jb = shape == kGemvUpper ? rb : cl;
+    }
     const int i = 64 * ib + lane;
     const double* Mi = M + min(i, m - 1);
-    double s = 0.0;
-#pragma unroll 1
-    for (int q0 = 0; q0 < 64; q0 += 32) {
-      double g[32];
 #pragma unroll
-      for (int q = 0; q < 32; ++q) {
-        const int j = 64 * jb + q0 + q;
-        const bool ok = i < m && j < m && (upper ? j >= i : j <= i);
-        g[q] = ok ? Mi[(size_t)m * j] : 0.0;
-      }
-#pragma unroll
-      for (int q = 0; q < 32; ++q) s += g[q] * y[min(64 * jb + q0 + q, m - 1)];
-      __builtin_amdgcn_sched_barrier(0);
+    for (int q = 0; q < 64; ++q) {
+      const int j = 64 * jb + q;
+      const bool ok = i < m && j < m && (shape == kGemvFull || (shape == kGemvUpper ? j >= i : j <= i));
+      g[q] = ok ? gload(Mi + (size_t)m * j) : 0.0;
     }
+  };
+  if (wv < ntl) load_tile(wv);
+  if (yg) {
+    for (int i = tid; i < m; i += kThreads) y[i] = gload(yg + i);
+    lds_barrier();
+  }
+  for (int t = wv; t < ntl; t += kWaves) {
+    if (t != wv) load_tile(t);
+    const int i = 64 * ib + lane;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 64; ++q) s += g[q] * y[min(64 * jb + q, m - 1)];
     if (i < m) red[jb * 256 + i] = s;
   }
   __syncthreads();
   for (int i = tid; i < m; i += kThreads) {
     const int ib = i >> 6;
+    const int j0 = shape == kGemvUpper ? ib : 0, j1 = shape == kGemvLower ? ib + 1 : nb;
     double t = 0.0;
-    if (upper) {
-      for (int jb = ib; jb < nb; ++jb) t += red[jb * 256 + i];
-    } else {
-      for (int jb = 0; jb <= ib; ++jb) t += red[jb * 256 + i];
-    }
+    for (int jb = j0; jb < j1; ++jb) t += red[jb * 256 + i];
     y[i] = t;
   }
   __syncthreads();
@@ -1909,11 +1923,16 @@ __device__ __forceinline__ void fwd_item(const ItemD& it, LevelState ls, double*
   double* blk = lds + mp;
   double* vs = blk + 64 * kBlkLd;
   double* yg = vec + it.voff;
-  for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
-  __syncthreads();
-  if (ls.giok[it.s]) gemv_tri(it.Gi, m, false, y, blk);  // G^{-1} formed by the factorization
-  else trsv_lower(it.P, m, m, y, blk);
-  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
+  const int gk = ls.giok[it.s];
+  if (gk == 2) {
+    gemv_blk(it.Gi, m, kGemvFull, y, blk, yg);  // W = U^T G^{-1} formed by the factorization
+  } else {
+    for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
+    __syncthreads();
+    if (gk) gemv_blk(it.Gi, m, kGemvLower, y, blk);  // G^{-1} formed by the factorization
+    else trsv_lower(it.P, m, m, y, blk);
+    apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
+  }
   fwd_near<R>(it, m, k, 0, a, y, vec);
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
   __syncthreads();
@@ -1932,11 +1951,19 @@ __device__ __forceinline__ void fwd_head(const ItemD& it, LevelState ls, double*
   double* blk = lds + mp;
   double* vs = blk + 64 * kBlkLd;
   double* yg = vec + it.voff;
-  for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
-  __syncthreads();
-  if (ls.giok[it.s]) gemv_tri(it.Gi, m, false, y, blk);  // G^{-1} formed by the factorization
-  else trsv_lower(it.P, m, m, y, blk);
-  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
+  const int gk = ls.giok[it.s];
+  if (gk == 2) {
+    gemv_blk(it.Gi, m, kGemvFull, y, blk, yg);  // W = U^T G^{-1} formed by the factorization
+  } else {
+    if (gk) {
+      gemv_blk(it.Gi, m, kGemvLower, y, blk, yg);  // G^{-1} formed by the factorization
+    } else {
+      for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
+      __syncthreads();
+      trsv_lower(it.P, m, m, y, blk);
+    }
+    apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
+  }
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
   __syncthreads();
 }
@@ -2015,11 +2042,16 @@ __device__ __forceinline__ void bwd_tail(const ItemD& it, LevelState ls, double*
   double* blk = lds + mp;
   double* vs = blk + 64 * kBlkLd;
   double* xg = vec + it.voff;
-  for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
-  __syncthreads();
-  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
-  if (ls.giok[it.s]) gemv_tri(it.GiT, m, true, x, blk);  // G^{-T} formed by the factorization
-  else trsv_lower_t<R>(it.P, m, m, x, blk);
+  const int gk = ls.giok[it.s];
+  if (gk == 2) {
+    gemv_blk(it.GiT, m, kGemvFull, x, blk, xg);  // W^T = G^{-T} U formed by the factorization
+  } else {
+    for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
+    __syncthreads();
+    apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
+    if (gk) gemv_blk(it.GiT, m, kGemvUpper, x, blk);  // G^{-T} formed by the factorization
+    else trsv_lower_t<R>(it.P, m, m, x, blk);
+  }
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
 }
@@ -2059,9 +2091,14 @@ __device__ __forceinline__ void bwd_item(const ItemD& it, LevelState ls, double*
     }
   }
   __syncthreads();
-  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
-  if (ls.giok[it.s]) gemv_tri(it.GiT, m, true, x, blk);  // G^{-T} formed by the factorization
-  else trsv_lower_t<R>(it.P, m, m, x, blk);
+  const int gk = ls.giok[it.s];
+  if (gk == 2) {
+    gemv_blk(it.GiT, m, kGemvFull, x, blk);  // W^T = G^{-T} U formed by the factorization
+  } else {
+    apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
+    if (gk) gemv_blk(it.GiT, m, kGemvUpper, x, blk);  // G^{-T} formed by the factorization
+    else trsv_lower_t<R>(it.P, m, m, x, blk);
+  }
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
 }

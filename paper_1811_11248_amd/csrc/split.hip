@@ -928,23 +928,29 @@ __global__ void __launch_bounds__(NT) cpqr_kernel(const ItemD* __restrict__ item
 // ---------------------------------------------------------------------------
 // C <- U^T C for kApplyqCols near-field columns per workgroup (one column
 // per wave per pass, R rows per lane in registers); reflectors staged in LDS
-// 16 at a time.
+// 16 at a time.  The workgroups with blockIdx.y >= ya take the columns of
+// G^{-1} instead (clusters whose inverse was formed, k > 0): W = U^T G^{-1}
+// replaces G^{-1} in Gi and W^T goes to GiT, so that a sweep applies U^T
+// G^{-1} (forward) or G^{-T} U (backward) as one product; the entries of
+// G^{-1} above its diagonal tiles are zeros not stored, read as zeros.
 constexpr int kApplyqCols = 16;
 template <int R>
-__global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ items, LevelState ls) {
+__global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ items, LevelState ls, int ya) {
   extern __shared__ double lds[];
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   const int k = min(gload(ls.k + it.s), it.kcap), a = gload(ls.a + it.s);
-  const int c0 = blockIdx.y * kApplyqCols;
-  if (m == 0 || k == 0 || c0 >= a) return;
-  const int c1 = min(a, c0 + kApplyqCols);
+  const bool winv = (int)blockIdx.y >= ya;
+  const int c0 = (winv ? (int)blockIdx.y - ya : (int)blockIdx.y) * kApplyqCols;
+  if (m == 0 || k == 0 || c0 >= (winv ? m : a)) return;
+  if (winv && (m > kInvMaxDofs || !it.Gi || !it.GiT || gload(ls.giok + it.s) == 0)) return;
+  const int c1 = min(winv ? m : a, c0 + kApplyqCols);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double* Vs = lds;            // 16 x m
   double* ts = lds + 16 * m;   // 16
   int* pv = reinterpret_cast<int*>(ts + 16);  // 16
   const double* W = it.P + (size_t)m * (m + a);
-  double* C = it.P + (size_t)m * m;
+  double* C = winv ? it.Gi : it.P + (size_t)m * m;
   for (int j0 = 0; j0 < k; j0 += 16) {
     const int nj = min(16, k - j0);
     if (j0 > 0) __syncthreads();
@@ -963,10 +969,13 @@ __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ i
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = cb + q;
+        // G^{-1}: rows above the diagonal tile of column c are zeros (first
+        // pass only; later passes read the full column written by the first)
+        const int i0 = (winv && j0 == 0) ? (c & ~15) : 0;
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const int i = lane + 64 * t;
-          y[q][t] = (c < c1 && i < m) ? C[(size_t)m * c + i] : 0.0;
+          y[q][t] = (c < c1 && i >= i0 && i < m) ? C[(size_t)m * c + i] : 0.0;
         }
       }
       for (int jj = 0; jj < nj; ++jj) {
@@ -997,11 +1006,17 @@ __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ i
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const int i = lane + 64 * t;
-          if (i < m) C[(size_t)m * c + i] = y[q][t];
+          if (i < m) {
+            C[(size_t)m * c + i] = y[q][t];
+            if (winv) it.GiT[(size_t)c + (size_t)m * i] = y[q][t];
+          }
         }
       }
     }
   }
+  // read by the sweeps (later kernels); the workgroups of this launch only
+  // test giok for zero
+  if (winv && c0 == 0 && tid == 0) ls.giok[it.s] = 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -1200,15 +1215,17 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
                            level);
       break;
     }
-    case kSplitApplyq:
-      if (d.max_acap <= 0) break;
-      if (mm <= 256)
-        hipLaunchKernelGGL(applyq_kernel<4>, dim3(nitems, (d.max_acap + kApplyqCols - 1) / kApplyqCols), dim3(256),
-                           ((size_t)16 * mm + 24) * 8, st, items, ls);
-      else
-        hipLaunchKernelGGL(applyq_kernel<kRegRows>, dim3(nitems, (d.max_acap + kApplyqCols - 1) / kApplyqCols),
-                           dim3(256), ((size_t)16 * mm + 24) * 8, st, items, ls);
+    case kSplitApplyq: {
+      // near-field columns, then (m <= kInvMaxDofs) the columns of G^{-1}
+      const int ya = ((d.max_acap > 0 ? d.max_acap : 0) + kApplyqCols - 1) / kApplyqCols;
+      if (mm <= kInvMaxDofs)
+        hipLaunchKernelGGL(applyq_kernel<4>, dim3(nitems, ya + (mm + kApplyqCols - 1) / kApplyqCols), dim3(256),
+                           ((size_t)16 * mm + 24) * 8, st, items, ls, ya);
+      else if (ya > 0)
+        hipLaunchKernelGGL(applyq_kernel<kRegRows>, dim3(nitems, ya), dim3(256), ((size_t)16 * mm + 24) * 8, st,
+                           items, ls, ya);
       break;
+    }
     case kSplitSchur: {
       if (d.max_acap <= 0) break;
       const int nt = (d.max_acap + 31) / 32;
