@@ -323,6 +323,7 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
                                                            int level) {
   using Map = InvMap<NW>;
   constexpr int kInvSlots = Map::kSlots;
+  static_assert(NW * 16 * kInvLdP <= 16 * kInvLdX, "staging tiles of the initial load must fit in Ar");
   extern __shared__ double lds[];
   double* Pc = lds;                  // 256 x kInvLdP: tile column p (two buffers
   double* Pc2 = Pc + 256 * kInvLdP;  //   in turn during the Cholesky)
@@ -345,6 +346,10 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
   double* Xg = it.Gi;
   double* XgT = it.GiT;
   if (tid == 0) sbad = 0;
+  // the wave's tiles, loaded with lane l on row l%16 of columns 4v + l/16 (16
+  // consecutive rows of a column per 16 lanes), then turned into the
+  // accumulator layout through a 16 x 17 staging tile of the wave in Ar (free
+  // until the inverse)
   d4_t T[kInvSlots];
 #pragma unroll
   for (int j = 0; j < kInvSlots; ++j) {
@@ -352,10 +357,22 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
     const bool on = Map::slot(w, j, r, c) && r < nt;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int gr = 16 * r + 4 * v + lr, gc = 16 * c + lc;
+      const int gr = 16 * r + lc, gc = 16 * c + 4 * v + lr;
       double x = 0.0;
-      if (on && gc <= gr) x = gr < m ? A[gr + (size_t)m * gc] : (gr == gc ? 1.0 : 0.0);
+      if (on && gc <= gr) x = gr < m ? gload(A + gr + (size_t)m * gc) : (gr == gc ? 1.0 : 0.0);
       T[j][v] = x;
+    }
+  }
+  {
+    double* S = Ar + w * 16 * kInvLdP;
+#pragma unroll
+    for (int j = 0; j < kInvSlots; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S[lc * kInvLdP + 4 * v + lr] = T[j][v];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[j][v] = S[(4 * v + lr) * kInvLdP + lc];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
   }
   // ---- G ----
