@@ -237,7 +237,8 @@ def run_learned(args):
         if "mlp" in kw:
             rec.update(rank_bytes=inf["rank_bytes"], rank_bytes_worst=inf["rank_bytes_worst"],
                        rank_checks_passed=inf["rank_checks_passed"],
-                       rank_checks_failed=inf["rank_checks_failed"], rank_redo_levels=inf["rank_redo_levels"])
+                       rank_checks_failed=inf["rank_checks_failed"], rank_redo_levels=inf["rank_redo_levels"],
+                       rank_reruns=inf["rank_reruns"])
         out[name] = {k: (round(v, 4) if isinstance(v, float) and k != "relres" else v) for k, v in rec.items()}
         log(f"[learned {name}] {out[name]}")
         del F, tree

@@ -181,7 +181,7 @@ typedef struct {
   int32_t rank_checks_failed; /* clusters whose QR went on past k_hat */
   int32_t rank_redo_levels;   /* levels run again because a rank reached
                                  its capacity (each level counted once) */
-  int32_t reserved3;
+  int32_t rank_reruns;        /* runs of levels after the first, in all */
 } lrsp_info;
 lrsp_status lrsp_factor_info(const lrsp_factorization* F, lrsp_info* info);
 

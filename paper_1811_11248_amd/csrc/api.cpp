@@ -38,6 +38,7 @@ struct TreeCache {
     for (auto& L : levels)
       if (L) L->free_all(stream);
     (void)hipStreamSynchronize(stream);
+    pool_trim();
   }
 };
 
@@ -92,6 +93,7 @@ struct lrsp_factorization {
     dfree(&top, stream); dfree(&top_gidx, stream); dfree(&perm, stream); dfree(&vec, stream);
     dfree(&scratch, stream);
     (void)hipStreamSynchronize(stream);
+    pool_trim();
   }
 };
 
@@ -235,7 +237,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     if (lrsp_status s = upload(&d_mlp, o.mlp_weights, sizeof(float) * kMlpParams, st)) return s;
   }
   double cap_bytes = 0.0, worst_bytes = 0.0;
-  int checks_pass = 0, checks_fail = 0, cap_redo = 0;
+  int checks_pass = 0, checks_fail = 0, cap_redo = 0, cap_reruns = 0;
   while (true) {
     const int M = (int)sizes.size();
     if (M == 1 || complete_graph(adj)) break;
@@ -353,6 +355,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       // values in the new run, so this repeats, at most kCapRetries times
       // before every capacity of the level is the worst case.
       if (L->cap_tries++ == 0) ++cap_redo;
+      ++cap_reruns;
       bool raised = false;
       for (int x = 0; x < M; ++x) {
         const int worst = std::min(p.m[x], p.bcap[x]);
@@ -498,6 +501,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   inf.rank_checks_passed = checks_pass;
   inf.rank_checks_failed = checks_fail;
   inf.rank_redo_levels = cap_redo;
+  inf.rank_reruns = cap_reruns;
   int64_t held = 0;
   for (auto& L : F->levels) held += L->held_bytes();
   inf.peak_bytes = held + (int64_t)(F->top.bytes + F->vec.bytes + F->perm.bytes);

@@ -67,6 +67,13 @@ hipError_t dalloc(DevBuf* b, size_t bytes, hipStream_t st) {
   return hipMallocAsync(&b->p, std::max<size_t>(bytes, 256), st);
 }
 
+void pool_trim() {
+  int dev = 0;
+  hipMemPool_t pool;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
+    (void)hipMemPoolTrimTo(pool, kPoolKeepBytes);
+}
+
 void dfree(DevBuf* b, hipStream_t st) {
   if (b->p) (void)hipFreeAsync(b->p, st);
   b->p = nullptr;

@@ -70,6 +70,12 @@ struct DevBuf {
   size_t bytes = 0;
 };
 hipError_t dalloc(DevBuf* b, size_t bytes, hipStream_t st);
+// Unused device memory the default pool keeps once a factorization or a
+// tree has been released (and its stream synchronized); the rest goes back to
+// the device, so that one very large factorization does not leave the next
+// one of another shape to allocate around its free blocks.
+constexpr size_t kPoolKeepBytes = (size_t)16 << 30;
+void pool_trim();
 void dfree(DevBuf* b, hipStream_t st);
 
 template <class T>

@@ -54,7 +54,7 @@ class Info(C.Structure):
                 ("levels_reused", C.c_int32), ("reserved2", C.c_int32),
                 ("rank_bytes", C.c_double), ("rank_bytes_worst", C.c_double),
                 ("rank_checks_passed", C.c_int32), ("rank_checks_failed", C.c_int32),
-                ("rank_redo_levels", C.c_int32), ("reserved3", C.c_int32)]
+                ("rank_redo_levels", C.c_int32), ("rank_reruns", C.c_int32)]
 
 
 class LevelView(C.Structure):
@@ -243,7 +243,7 @@ class Factor:
                 "levels_reused": i.levels_reused, "peak_bytes": i.peak_bytes,
                 "rank_bytes": i.rank_bytes, "rank_bytes_worst": i.rank_bytes_worst,
                 "rank_checks_passed": i.rank_checks_passed, "rank_checks_failed": i.rank_checks_failed,
-                "rank_redo_levels": i.rank_redo_levels}
+                "rank_redo_levels": i.rank_redo_levels, "rank_reruns": i.rank_reruns}
 
     def rank_features(self, lev: int):
         """(features [M, 12], predicted ranks [M]) of a level (rank_mode 1)."""
