@@ -269,13 +269,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "slab64_traffic.md")
 
 
 def kernel_sources_hash():
-    """sha256 over the kernel and runtime sources (file names and contents in
-    name order): the counters in the traffic table hold for this hash only."""
+    """sha256 over the device code (the HIP sources with their kernels and
+    launches, and the headers they include; file names and contents in name
+    order): the counters in the traffic table hold for this hash only."""
     import hashlib
     d = os.path.join(ROOT, "paper_1811_11248_amd", "csrc")
+    device_headers = ("desc.hpp", "devutil.hpp", "kernels.hpp", "learned.hpp")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
+        if f.endswith(".hip") or f in device_headers:
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
