@@ -24,30 +24,34 @@ using namespace lrsp::rt;
 
 namespace {
 
-// Analysis of the last pattern factored with a tree, and level workspaces
-// returned by freed factors.
+// Analysis of the last pattern factored with a tree (with a copy of that
+// pattern to recognise it), and level workspaces returned by freed factors.
 struct TreeCache {
   bool have = false;
-  uint64_t hash = 0;
+  uint64_t gen = 0;  // advanced whenever the analysed pattern changes
   int64_t nnz = -1;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> cl;
   std::vector<std::vector<int>> adj0;
   std::unordered_map<uint64_t, std::vector<uint64_t>> z0;
   std::vector<std::unique_ptr<LevelDev>> levels;
   hipStream_t stream = nullptr;
   ~TreeCache() {
+    int64_t held = 0;
     for (auto& L : levels)
-      if (L) L->free_all(stream);
+      if (L) {
+        held += L->held_bytes();
+        L->free_all(stream);
+      }
     (void)hipStreamSynchronize(stream);
-    pool_trim();
+    if (held > (int64_t)kPoolKeepBytes) pool_trim();
+  }
+  bool same_pattern(const int64_t* r, const int32_t* c, int64_t n, int64_t z) const {
+    return have && nnz == z && (int64_t)rp.size() == n + 1 &&
+           std::memcmp(rp.data(), r, sizeof(int64_t) * (size_t)(n + 1)) == 0 &&
+           std::memcmp(cl.data(), c, sizeof(int32_t) * (size_t)z) == 0;
   }
 };
-
-uint64_t pattern_hash(const int64_t* rp, const int32_t* cl, int64_t n, int64_t nnz) {
-  uint64_t h = 1469598103934665603ull ^ (uint64_t)n ^ ((uint64_t)nnz << 32);
-  for (int64_t i = 0; i <= n; ++i) h = (h ^ (uint64_t)rp[i]) * 1099511628211ull;
-  for (int64_t e = 0; e < nnz; ++e) h = (h ^ (uint32_t)cl[e]) * 1099511628211ull;
-  return h;
-}
 
 }  // namespace
 
@@ -75,10 +79,10 @@ struct lrsp_factorization {
   lrsp_info info{};
   hipStream_t stream = nullptr;
   std::weak_ptr<TreeCache> cache;
-  uint64_t pattern = 0;
+  uint64_t pattern = 0;  // TreeCache::gen of the pattern factored
   ~lrsp_factorization() {
     std::shared_ptr<TreeCache> c = cache.lock();
-    const bool give = c && c->have && c->hash == pattern;
+    const bool give = c && c->have && c->gen == pattern;
     for (size_t l = 0; l < levels.size(); ++l) {
       if (!levels[l]) continue;
       if (give) {
@@ -93,7 +97,7 @@ struct lrsp_factorization {
     dfree(&top, stream); dfree(&top_gidx, stream); dfree(&perm, stream); dfree(&vec, stream);
     dfree(&scratch, stream);
     (void)hipStreamSynchronize(stream);
-    pool_trim();
+    if (!give && info.peak_bytes > (int64_t)kPoolKeepBytes) pool_trim();
   }
 };
 
@@ -194,9 +198,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   std::vector<int> sizes(tr.leaf_ptr.size() - 1);
   for (size_t c = 0; c + 1 < tr.leaf_ptr.size(); ++c)
     sizes[c] = (int)(tr.leaf_ptr[c + 1] - tr.leaf_ptr[c]);
-  const uint64_t ph = pattern_hash(rp, cl, A->n, A->nnz);
-  F->pattern = ph;
-  if (!(cache->have && cache->hash == ph && cache->nnz == A->nnz)) {
+  if (!cache->same_pattern(rp, cl, A->n, A->nnz)) {
     const auto ta = tick();
     for (auto& Lc : cache->levels)
       if (Lc) Lc->free_all(st);
@@ -218,11 +220,14 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
         b[lj >> 6] |= 1ull << (lj & 63);
       }
     }
+    cache->rp.assign(rp, rp + A->n + 1);
+    cache->cl.assign(cl, cl + A->nnz);
     cache->have = true;
-    cache->hash = ph;
+    ++cache->gen;
     cache->nnz = A->nnz;
     ms_an += ms_since(ta);
   }
+  F->pattern = cache->gen;
   std::vector<std::vector<int>> adj = cache->adj0;
   int reused = 0;
   HIPCHK(dalloc(&F->perm, sizeof(int64_t) * tr.n, st));
