@@ -35,6 +35,7 @@ struct TreeCache {
   std::vector<std::vector<int>> adj0;
   std::unordered_map<uint64_t, std::vector<uint64_t>> z0;
   std::vector<std::unique_ptr<LevelDev>> levels;
+  DevBuf perm;  // the tree's DoF permutation on the device, returned by freed factors
   hipStream_t stream = nullptr;
   ~TreeCache() {
     int64_t held = 0;
@@ -43,6 +44,7 @@ struct TreeCache {
         held += L->held_bytes();
         L->free_all(stream);
       }
+    dfree(&perm, stream);
     (void)hipStreamSynchronize(stream);
     if (held > (int64_t)kPoolKeepBytes) pool_trim();
   }
@@ -93,6 +95,12 @@ struct lrsp_factorization {
       } else {
         levels[l]->free_all(stream);
       }
+    }
+    if (c && perm.p) {  // the permutation belongs to the tree: back to its cache
+      dfree(&c->perm, stream);
+      c->perm = perm;
+      c->stream = stream;
+      perm = DevBuf{};
     }
     dfree(&top, stream); dfree(&top_gidx, stream); dfree(&perm, stream); dfree(&vec, stream);
     dfree(&scratch, stream);
@@ -230,8 +238,13 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   F->pattern = cache->gen;
   std::vector<std::vector<int>> adj = cache->adj0;
   int reused = 0;
-  HIPCHK(dalloc(&F->perm, sizeof(int64_t) * tr.n, st));
-  HIPCHK(hipMemcpyAsync(F->perm.p, tr.perm.data(), sizeof(int64_t) * tr.n, hipMemcpyHostToDevice, st));
+  if (cache->perm.p) {  // uploaded by an earlier factorization with this tree
+    F->perm = cache->perm;
+    cache->perm = DevBuf{};
+  } else {
+    HIPCHK(dalloc(&F->perm, sizeof(int64_t) * tr.n, st));
+    HIPCHK(hipMemcpyAsync(F->perm.p, tr.perm.data(), sizeof(int64_t) * tr.n, hipMemcpyHostToDevice, st));
+  }
   double flops[6] = {0, 0, 0, 0, 0, 0};
   int64_t vbase = 0;
   int level = 0;
