@@ -53,8 +53,12 @@ typedef struct {
 /* Sparse SPD matrix in CSR with the FULL symmetric pattern and sorted
  * column indices.  rowptr/col/val are DEVICE pointers.  h_rowptr/h_col are
  * optional HOST copies of the pattern used by the symbolic analysis; when
- * NULL the library copies the pattern from the device.  The caller owns all
- * arrays and keeps them alive for the duration of a call. */
+ * NULL the library copies the pattern from the device.  pattern_id: 0, or a
+ * nonzero number the caller gives to this exact pattern; a factorization
+ * whose tree last analysed a pattern of the same nonzero id reuses that
+ * analysis without comparing the patterns entry by entry (the caller must
+ * never give one id to two different patterns).  The caller owns all arrays
+ * and keeps them alive for the duration of a call. */
 typedef struct {
   int64_t n;
   int64_t nnz;
@@ -63,6 +67,7 @@ typedef struct {
   const double* val;
   const int64_t* h_rowptr;
   const int32_t* h_col;
+  uint64_t pattern_id;
 } lrsp_csr;
 
 typedef struct lrsp_tree lrsp_tree;

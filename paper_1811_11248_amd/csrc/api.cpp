@@ -29,6 +29,7 @@ namespace {
 struct TreeCache {
   bool have = false;
   uint64_t gen = 0;  // advanced whenever the analysed pattern changes
+  uint64_t id = 0;   // the caller's pattern id of that pattern (0: none)
   int64_t nnz = -1;
   std::vector<int64_t> rp;
   std::vector<int32_t> cl;
@@ -48,9 +49,10 @@ struct TreeCache {
     (void)hipStreamSynchronize(stream);
     if (held > (int64_t)kPoolKeepBytes) pool_trim();
   }
-  bool same_pattern(const int64_t* r, const int32_t* c, int64_t n, int64_t z) const {
-    return have && nnz == z && (int64_t)rp.size() == n + 1 &&
-           std::memcmp(rp.data(), r, sizeof(int64_t) * (size_t)(n + 1)) == 0 &&
+  bool same_pattern(const int64_t* r, const int32_t* c, int64_t n, int64_t z, uint64_t pid) const {
+    if (!have || nnz != z || (int64_t)rp.size() != n + 1) return false;
+    if (pid != 0 && pid == id) return true;
+    return std::memcmp(rp.data(), r, sizeof(int64_t) * (size_t)(n + 1)) == 0 &&
            std::memcmp(cl.data(), c, sizeof(int32_t) * (size_t)z) == 0;
   }
 };
@@ -206,7 +208,9 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   std::vector<int> sizes(tr.leaf_ptr.size() - 1);
   for (size_t c = 0; c + 1 < tr.leaf_ptr.size(); ++c)
     sizes[c] = (int)(tr.leaf_ptr[c + 1] - tr.leaf_ptr[c]);
-  if (!cache->same_pattern(rp, cl, A->n, A->nnz)) {
+  if (cache->same_pattern(rp, cl, A->n, A->nnz, A->pattern_id)) {
+    cache->id = A->pattern_id;
+  } else {
     const auto ta = tick();
     for (auto& Lc : cache->levels)
       if (Lc) Lc->free_all(st);
@@ -231,6 +235,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     cache->rp.assign(rp, rp + A->n + 1);
     cache->cl.assign(cl, cl + A->nnz);
     cache->have = true;
+    cache->id = A->pattern_id;
     ++cache->gen;
     cache->nnz = A->nnz;
     ms_an += ms_since(ta);

@@ -8,6 +8,7 @@ device memory and the stream.
 from __future__ import annotations
 
 import ctypes as C
+import itertools
 import os
 
 import numpy as np
@@ -33,7 +34,8 @@ class Grid(C.Structure):
 
 class CSR(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p), ("col", C.c_void_p),
-                ("val", C.c_void_p), ("h_rowptr", C.c_void_p), ("h_col", C.c_void_p)]
+                ("val", C.c_void_p), ("h_rowptr", C.c_void_p), ("h_col", C.c_void_p),
+                ("pattern_id", C.c_uint64)]
 
 
 class Opts(C.Structure):
@@ -182,15 +184,23 @@ class Tree:
             self.handle = None
 
 
+_pattern_ids = itertools.count(1)
+
+
 class DeviceMatrix:
-    """CSR matrix resident in device memory (torch tensors) plus the host pattern."""
+    """CSR matrix resident in device memory (torch tensors) plus the host
+    pattern.  The pattern arrays are private copies named by a pattern id of
+    this process, so that a tree recognises them without comparing them."""
 
     def __init__(self, rowptr, col, val, device="cuda"):
         import torch
-        self.h_rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
-        self.h_col = np.ascontiguousarray(col, dtype=np.int32)
+        self.h_rowptr = np.array(rowptr, dtype=np.int64, copy=True, order="C")
+        self.h_col = np.array(col, dtype=np.int32, copy=True, order="C")
+        self.pattern_id = next(_pattern_ids)
         self.rowptr = torch.from_numpy(self.h_rowptr).to(device)
         self.col = torch.from_numpy(self.h_col).to(device)
+        self.h_rowptr.setflags(write=False)
+        self.h_col.setflags(write=False)
         self.val = torch.as_tensor(np.asarray(val, dtype=np.float64)).to(device)
         self.n = int(self.h_rowptr.shape[0] - 1)
         self.nnz = int(self.h_col.shape[0])
@@ -201,7 +211,7 @@ class DeviceMatrix:
 
     def csr(self) -> CSR:
         return CSR(self.n, self.nnz, self.rowptr.data_ptr(), self.col.data_ptr(),
-                   self.val.data_ptr(), self.h_rowptr.ctypes.data, self.h_col.ctypes.data)
+                   self.val.data_ptr(), self.h_rowptr.ctypes.data, self.h_col.ctypes.data, self.pattern_id)
 
 
 class Factor:
