@@ -30,6 +30,9 @@ struct TreeCache {
   bool have = false;
   uint64_t gen = 0;  // advanced whenever the analysed pattern changes
   uint64_t id = 0;   // the caller's pattern id of that pattern (0: none)
+  // the last factorization reused every level and found the ranks (k, a, b)
+  // of the one before: the next one may assume them (spec_ok)
+  bool spec_ok = false;
   int64_t nnz = -1;
   std::vector<int64_t> rp;
   std::vector<int32_t> cl;
@@ -160,8 +163,11 @@ lrsp_status lrsp_factor_free(lrsp_factorization* F) {
   return LRSP_OK;
 }
 
+// *retry: set when a level assumed the ranks of the previous factorization
+// wrongly; the caller then runs factor_impl again, which no longer assumes.
 static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, const lrsp_opts* opts,
-                               void* stream, lrsp_factorization** out) {
+                               void* stream, lrsp_factorization** out, bool* retry) {
+  *retry = false;
   if (!A || !T || !out) return fail(LRSP_ERR_ARG, "null argument");
   *out = nullptr;
   const TreeH& tr = T->t;
@@ -261,6 +267,43 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   }
   double cap_bytes = 0.0, worst_bytes = 0.0;
   int checks_pass = 0, checks_fail = 0, cap_redo = 0, cap_reruns = 0;
+  // With spec, a reused level assumes the k, a, b of the previous
+  // factorization of this pattern (held by its workspace) instead of waiting
+  // for them: its read-back goes to pinned memory and is compared after the
+  // last kernel; a difference runs the whole factorization again without
+  // assuming.  The host then queues level after level while the GPU works.
+  const bool spec_on = !learned && cache->spec_ok;
+  std::vector<LevelDev*> specs;
+  bool same_ranks = true;  // every level reused, read-back k, a, b as assumed
+  // Checks the levels that assumed their ranks, in level order, once the
+  // stream has been synchronized: a level's error words are its own (the
+  // levels below it were checked first), then its ranks.  1: ranks differ,
+  // run again; 0: all as assumed.
+  auto check_specs = [&](lrsp_status* err) -> int {
+    *err = LRSP_OK;
+    for (LevelDev* Ls : specs) {
+      const int Ms = Ls->plan.M;
+      const int32_t* h = Ls->h_kab;
+      const int32_t* e = h + 3 * Ms;
+      if (e[0]) {
+        if (e[3] == kErrNotSPD)
+          *err = fail(LRSP_ERR_NOT_SPD, "non-positive pivot in the diagonal block of cluster " +
+                                            std::to_string(e[2]) + " at level " + std::to_string(e[1]));
+        else
+          *err = fail(LRSP_ERR_INTERNAL, "device check failed (code " + std::to_string(e[3]) + ") at level " +
+                                             std::to_string(e[1]) + " cluster " + std::to_string(e[2]));
+        return 0;
+      }
+      if (!std::equal(Ls->k.begin(), Ls->k.end(), h) || !std::equal(Ls->a.begin(), Ls->a.end(), h + Ms) ||
+          !std::equal(Ls->b.begin(), Ls->b.end(), h + 2 * Ms)) {
+        cache->spec_ok = false;
+        *retry = true;
+        return 1;
+      }
+    }
+    specs.clear();
+    return 0;
+  };
   while (true) {
     const int M = (int)sizes.size();
     if (M == 1 || complete_graph(adj)) break;
@@ -363,13 +406,41 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     }
     HIPCHK(hipGetLastError());
     // k, a, b and the error words lie back to back in the state buffer: one copy
-    std::vector<int32_t> kab(3 * (size_t)M + 4);
-    HIPCHK(hipMemcpyAsync(kab.data(), L->ls.k, 4 * kab.size(), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    L->k.assign(kab.begin(), kab.begin() + M);
-    L->a.assign(kab.begin() + M, kab.begin() + 2 * M);
-    L->b.assign(kab.begin() + 2 * M, kab.begin() + 3 * M);
-    herr.assign(kab.begin() + 3 * M, kab.end());
+    const size_t nkab = 3 * (size_t)M + 4;
+    const bool spec = spec_on && reuse && L->k.size() == (size_t)M && L->a.size() == (size_t)M &&
+                      L->b.size() == (size_t)M;
+    if (spec) {
+      if (L->h_kab_n < nkab) {
+        if (L->h_kab) {
+          HIPCHK(hipStreamSynchronize(st));
+          HIPCHK(hipHostFree(L->h_kab));
+          L->h_kab = nullptr;
+          L->h_kab_n = 0;
+        }
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&L->h_kab), 4 * nkab, hipHostMallocDefault));
+        L->h_kab_n = nkab;
+      }
+      HIPCHK(hipMemcpyAsync(L->h_kab, L->ls.k, 4 * nkab, hipMemcpyDeviceToHost, st));
+      specs.push_back(L);
+      herr.assign(4, 0);
+    } else {
+      std::vector<int32_t> kab(nkab);
+      HIPCHK(hipMemcpyAsync(kab.data(), L->ls.k, 4 * kab.size(), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (!specs.empty()) {  // this level's input rests on the assumed ranks below it
+        lrsp_status e;
+        if (check_specs(&e)) return LRSP_ERR_INTERNAL;
+        if (e) return e;
+      }
+      if (!reuse || L->k.size() != (size_t)M || !std::equal(L->k.begin(), L->k.end(), kab.begin()) ||
+          !std::equal(L->a.begin(), L->a.end(), kab.begin() + M) ||
+          !std::equal(L->b.begin(), L->b.end(), kab.begin() + 2 * M))
+        same_ranks = false;
+      L->k.assign(kab.begin(), kab.begin() + M);
+      L->a.assign(kab.begin() + M, kab.begin() + 2 * M);
+      L->b.assign(kab.begin() + 2 * M, kab.begin() + 3 * M);
+      herr.assign(kab.begin() + 3 * M, kab.end());
+    }
     if (herr[0] && herr[3] == kErrCapacity && L->capped) {
       // a rank reached its predicted capacity: the clusters whose QR stopped
       // at a capacity below their worst case min(m, b) get the worst case,
@@ -500,6 +571,14 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   HIPCHK(hipMemcpyAsync(herr.data(), terr.p, 16, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   dfree(&terr, st);
+  {  // the levels that assumed their ranks
+    lrsp_status e;
+    if (check_specs(&e)) return LRSP_ERR_INTERNAL;
+    if (e) return e;
+  }
+  // every level reused and every rank as the workspace held it (the assumed
+  // ones were just checked): the next factorization may assume them
+  cache->spec_ok = !learned && level > 0 && reused == level && same_ranks;
   if (herr[0]) return fail(LRSP_ERR_NOT_SPD, "non-positive pivot in the dense top factorization");
   flops[5] = (double)ntop * ntop * ntop / 3.0;
   F->top_vbase = vbase;
@@ -535,7 +614,9 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
 lrsp_status lrsp_factor(const lrsp_csr* A, lrsp_tree* T, double tol, const lrsp_opts* opts,
                         void* stream, lrsp_factorization** out) {
   try {
-    return factor_impl(A, T, tol, opts, stream, out);
+    bool retry = false;
+    const lrsp_status s = factor_impl(A, T, tol, opts, stream, out, &retry);
+    return retry ? factor_impl(A, T, tol, opts, stream, out, &retry) : s;
   } catch (const std::bad_alloc&) {
     return fail(LRSP_ERR_OOM, "host allocation failed");
   } catch (const std::exception& e) {

@@ -125,10 +125,18 @@ struct LevelDev {
   std::vector<float> pred;          // and predicted ranks [M]
   std::vector<int> caps;            // rank capacities the level runs with
   int cap_tries = 0;                // runs of the level after a capacity overflow
+  int32_t* h_kab = nullptr;         // pinned host copy of k, a, b and the error words
+  size_t h_kab_n = 0;
   void free_all(hipStream_t st) {
     dfree(&work, st); dfree(&wints, st); dfree(&coarse, st); dfree(&fac, st); dfree(&fints, st);
     dfree(&fvidx, st);
     dfree(&desc, st); dfree(&state, st); dfree(&gidx, st); dfree(&vals_off, st); dfree(&tasks, st);
+    if (h_kab) {
+      (void)hipStreamSynchronize(st);
+      (void)hipHostFree(h_kab);
+    }
+    h_kab = nullptr;
+    h_kab_n = 0;
   }
   int64_t held_bytes() const {
     return (int64_t)(work.bytes + wints.bytes + coarse.bytes + fac.bytes + fints.bytes + fvidx.bytes + desc.bytes +

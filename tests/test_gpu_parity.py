@@ -200,3 +200,27 @@ def test_analysis_reuse_gives_identical_factor(torch, L):
     x5 = L.apply(F5, torch.from_numpy(bb).cuda()).cpu().numpy()
     xo = oracle.solve(Fo, bb)
     assert np.linalg.norm(x5 - xo) <= APPLY_TOL * np.linalg.norm(xo)
+
+
+def test_assumed_ranks_match_or_rerun(torch, L):
+    # after two factorizations of one pattern with the same ranks, the next
+    # one queues its levels assuming those ranks and checks them at the end;
+    # a tolerance that changes the ranks must be caught and factored again
+    pr = config("slab64")
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree(pr.grid, pr.leaf)
+    b = torch.from_numpy(rhs(pr.n, 5)).cuda()
+    ref = {}
+    for tol in (pr.tol, 1e-3):
+        Ff = L.Factor(A, L.Tree(pr.grid, pr.leaf), tol)  # fresh tree: nothing assumed
+        ref[tol] = (L.apply(Ff, b).clone(), [Ff.level(li)["ranks"].tolist() for li in range(Ff.info()["nlevels"])])
+        del Ff
+    seq = [pr.tol, pr.tol, pr.tol, pr.tol, 1e-3, 1e-3, 1e-3, pr.tol]
+    for i, tol in enumerate(seq):
+        F = L.Factor(A, tree, tol)
+        x = L.apply(F, b)
+        ranks = [F.level(li)["ranks"].tolist() for li in range(F.info()["nlevels"])]
+        _say(f"[assumed ranks] run {i} tol {tol}: levels reused {F.info()['levels_reused']}")
+        assert ranks == ref[tol][1], f"run {i}"
+        assert torch.equal(x, ref[tol][0]), f"run {i}"
+        del F
