@@ -137,6 +137,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1811_11248_amd.build`")
+        # torch first: its HIP runtime is then the one the library binds to
+        # (loading the library first would bring a second runtime into the
+        # process, and the two disagree about the devices)
+        import torch  # noqa: F401
         h = C.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             f = getattr(h, name)
