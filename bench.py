@@ -10,7 +10,11 @@ diffusion (vertical/horizontal 1e4 times a log-normal field, sigma 1,
 correlation 8 cells, seed 1), horizontal-only cluster tree with leaf 256,
 tolerance 1e-2, N(0,1) right-hand side from seed 0.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: the metric and step time, the factor/PCG split, the
+roofline of the kernel family with the most GPU time (event-timed launches,
+algorithmic work, HBM traffic from the committed counter table), the oracle's
+time on the host for the same step, and the precision, batching and
+learned-rank forms.
 """
 from __future__ import annotations
 
