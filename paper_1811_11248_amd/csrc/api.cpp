@@ -273,6 +273,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   // last kernel; a difference runs the whole factorization again without
   // assuming.  The host then queues level after level while the GPU works.
   const bool spec_on = !learned && cache->spec_ok;
+  cache->spec_ok = false;  // set again only by a factorization that completes
   std::vector<LevelDev*> specs;
   bool same_ranks = true;  // every level reused, read-back k, a, b as assumed
   // Checks the levels that assumed their ranks, in level order, once the
