@@ -12,9 +12,11 @@ tolerance 1e-2, N(0,1) right-hand side from seed 0.
 
 Prints one JSON line: the metric and step time, the factor/PCG split, the
 roofline of the kernel family with the most GPU time (event-timed launches,
-algorithmic work, HBM traffic from the committed counter table), the oracle's
-time on the host for the same step, and the precision, batching and
-learned-rank forms.
+algorithmic work, HBM traffic from the committed counter table), the HBM
+rooflines of the substitution sweeps and of the sparse product, a step whose
+matrix values change every step, the oracle's time on the host for the same
+step, and the precision (on the 128x128x20 two-component workload), batching
+and learned-rank forms.
 """
 from __future__ import annotations
 
@@ -73,49 +75,154 @@ def run_gpu(args):
     analysis_ms = (time.perf_counter() - t0) * 1e3
     analysis_info = F0.info()
     del F0
-    for prec in ["f64"] + ([] if args.no_mixed else ["f32", "bf16"]):
-        nsteps = args.steps if prec == "f64" else max(1, min(args.steps, 3))
-        for _ in range(args.warmup):
-            step(prec)
-        torch.cuda.synchronize()
-        if prec == "f64":
-            # breakdown by kernel family from one untimed step with events
-            # around every launch; it names the dominant single kernel, whose
-            # launches alone carry events in the timed steps
-            lrsp.timing_reset()
-            lrsp.timing_families(None)
-            lrsp.timing_enable(True)
-            step(prec)
-            torch.cuda.synchronize()
-            lrsp.timing_enable(False)
-            timing = {f: lrsp.timing_read(f) for f in lrsp.TIMING_FAMILIES}
-            fam = dominant_family(timing)
-            lrsp.timing_reset()
-            lrsp.timing_families([fam])
-            lrsp.timing_enable(True)
-        t0 = time.perf_counter()
-        recs = [step(prec) for _ in range(nsteps)]
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        if prec == "f64":
-            lrsp.timing_enable(False)
-            lrsp.timing_families(None)
-            timing["roofline_" + fam] = lrsp.timing_read(fam)
-        info = recs[-1][0]
-        fl = sum(info["flops"].values())
-        fms = [r[1].elapsed_time(r[2]) for r in recs]
-        pms = [r[2].elapsed_time(r[3]) for r in recs]
-        results[prec] = dict(
-            ms_per_step=(t1 - t0) * 1e3 / nsteps,
-            factor_ms=float(np.median(fms)), pcg_ms=float(np.median(pms)),
-            iters=recs[-1][4], relres=recs[-1][5], factor_gflops=fl / (np.median(fms) * 1e-3) / 1e9,
-            flops=info["flops"], levels=info["nlevels"], top_n=info["top_n"],
-            factor_bytes=info["bytes_factor"], levels_reused=info["levels_reused"],
-            ms_analysis_in_step=info["ms_analysis"])
-        log(f"[{prec}] {results[prec]}")
+    prec = "f64"
+    nsteps = args.steps
+    for _ in range(args.warmup):
+        step(prec)
+    torch.cuda.synchronize()
+    # breakdown by kernel family from one untimed step with events around
+    # every launch; it names the dominant single kernel, whose launches alone
+    # carry events in the timed steps
+    lrsp.timing_reset()
+    lrsp.timing_families(None)
+    lrsp.timing_enable(True)
+    step(prec)
+    torch.cuda.synchronize()
+    lrsp.timing_enable(False)
+    timing = {f: lrsp.timing_read(f) for f in lrsp.TIMING_FAMILIES}
+    fam = dominant_family(timing)
+    lrsp.timing_reset()
+    lrsp.timing_families([fam])
+    lrsp.timing_enable(True)
+    t0 = time.perf_counter()
+    recs = [step(prec) for _ in range(nsteps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lrsp.timing_enable(False)
+    lrsp.timing_families(None)
+    timing["roofline_" + fam] = lrsp.timing_read(fam)
+    info = recs[-1][0]
+    fl = sum(info["flops"].values())
+    fms = [r[1].elapsed_time(r[2]) for r in recs]
+    pms = [r[2].elapsed_time(r[3]) for r in recs]
+    results[prec] = dict(
+        ms_per_step=(t1 - t0) * 1e3 / nsteps,
+        factor_ms=float(np.median(fms)), pcg_ms=float(np.median(pms)),
+        iters=recs[-1][4], relres=recs[-1][5], factor_gflops=fl / (np.median(fms) * 1e-3) / 1e9,
+        flops=info["flops"], levels=info["nlevels"], top_n=info["top_n"],
+        factor_bytes=info["bytes_factor"], levels_reused=info["levels_reused"],
+        ms_analysis_in_step=info["ms_analysis"])
+    log(f"[{prec}] {results[prec]}")
+    if args.changed_values:
+        results["changed_values"] = changed_values_steps(args, pr, tree, b)
     log(f"[timing] {timing}")
     results["analysis"] = dict(first_factor_ms=analysis_ms, host_analysis_ms=analysis_info["ms_analysis"])
     return pr, results, timing
+
+
+def changed_values_steps(args, pr, tree, b):
+    """Steps whose matrix values change every step (as in a Newton or time
+    loop): two matrices with the same pattern and different log-normal
+    fields alternate, so no step can assume the ranks of the one before; the
+    analysis of the pattern is still reused."""
+    import numpy as np
+    import torch
+
+    from paper_1811_11248_amd import lrsp
+    from synth import config_variant
+
+    mats = [lrsp.DeviceMatrix.from_problem(pr), lrsp.DeviceMatrix.from_problem(config_variant(args.workload, 7))]
+    torch.cuda.synchronize()
+    for A in mats:  # warm-up: ranks of both value sets seen once
+        F = lrsp.Factor(A, tree, pr.tol)
+        lrsp.pcg(A, F, b, rtol=1e-8)
+        del F
+    torch.cuda.synchronize()
+    n = max(2, args.steps)
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(n):
+        A = mats[i % 2]
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        F = lrsp.Factor(A, tree, pr.tol)
+        e1.record()
+        _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8)
+        e2.record()
+        recs.append((e0, e1, e2, int(it[0]), float(rr[0]), F.info()["levels_reused"]))
+        del F
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = dict(ms_per_step=(t1 - t0) * 1e3 / n,
+               factor_ms=float(np.median([r[0].elapsed_time(r[1]) for r in recs])),
+               pcg_ms=float(np.median([r[1].elapsed_time(r[2]) for r in recs])),
+               iters_max=max(r[3] for r in recs), relres_max=max(r[4] for r in recs),
+               levels_reused_min=min(r[5] for r in recs), steps=n)
+    log(f"[changed values] {out}")
+    return out
+
+
+def run_mixed(args):
+    """Precision form on its own workload (128x128x20 two-component slab,
+    655,360 DoF): steps with fp64, fp32 and bf16 Schur products, and the
+    difference of M^{-1} b from the fp64 form (whose parity with the fp64
+    oracle at this size is a GPU test)."""
+    import numpy as np
+    import torch
+
+    from paper_1811_11248_amd import lrsp
+    from synth import config, rhs
+
+    t0 = time.perf_counter()
+    pr = config(args.mixed_workload)
+    log(f"[mixed] built {args.mixed_workload} ({pr.n} DoF) in {time.perf_counter() - t0:.1f} s")
+    A = lrsp.DeviceMatrix.from_problem(pr)
+    tree = lrsp.Tree(pr.grid, pr.leaf)
+    b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+    out = {"workload": f"{args.mixed_workload}: {pr.grid[0]}x{pr.grid[1]}x{pr.grid[2]}x{pr.grid[3]}, "
+                       f"{pr.n} DoF, leaf {pr.leaf}, tol {pr.tol}, PCG to 1e-8"}
+    x64 = None
+    t0 = time.perf_counter()
+    F0 = lrsp.Factor(A, tree, pr.tol)
+    torch.cuda.synchronize()
+    out["first_factor_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    out["host_analysis_ms"] = round(F0.info()["ms_analysis"], 2)
+    del F0
+    for prec in ("f64", "f32", "bf16"):
+        recs = []
+        for i in range(args.warmup + args.mixed_steps):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            if i == args.warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            e0.record()
+            F = lrsp.Factor(A, tree, pr.tol, gemm_prec=prec)
+            e1.record()
+            _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8, maxit=1000)
+            e2.record()
+            if i >= args.warmup:
+                recs.append((e0, e1, e2, int(it[0]), float(rr[0])))
+            if i == args.warmup + args.mixed_steps - 1:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                info = F.info()
+                x = lrsp.apply(F, b)
+                if prec == "f64":
+                    x64 = x.clone()
+                diff = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+            del F
+        fms = float(np.median([r[0].elapsed_time(r[1]) for r in recs]))
+        pms = float(np.median([r[1].elapsed_time(r[2]) for r in recs]))
+        fl = sum(info["flops"].values())
+        out[prec] = dict(ms_per_step=round((t1 - t0) * 1e3 / len(recs), 4), factor_ms=round(fms, 4),
+                         pcg_ms=round(pms, 4), iters=recs[-1][3], relres=recs[-1][4],
+                         factor_gflops=round(fl / (fms * 1e-3) / 1e9, 2),
+                         apply_rel_diff_vs_f64=diff, levels=info["nlevels"],
+                         factor_bytes=info["bytes_factor"])
+        log(f"[mixed {prec}] {out[prec]}")
+    for prec in ("f32", "bf16"):
+        out[prec]["speedup_vs_f64"] = round(out["f64"]["ms_per_step"] / out[prec]["ms_per_step"], 4)
+    return out
 
 
 def run_batch(args):
@@ -175,20 +282,29 @@ def run_batch(args):
                          levels=inf["nlevels"])
         log(f"[batch {prec}] {out[prec]}")
         del B
-    # plain GPU form: one system after the other, factor + PCG on 4 columns
-    t0 = time.perf_counter()
+    # plain GPU form, one system after the other (factor + PCG on the 4
+    # columns).  First pass: first factorizations, each with its own host
+    # analysis; second pass: refactorizations reusing every tree's analysis,
+    # which is what the batch's timed step (graph-replayed refactorization)
+    # compares with
     iters = []
-    for i in range(len(probs)):
-        F = lrsp.Factor(mats[i], trees[i], 1e-2)
-        _, it, _ = lrsp.pcg(mats[i], F, torch.from_numpy(rhs[i]).cuda())
-        iters.append(it)
-        del F
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t0) * 1e3
-    out["plain_sequential_ms"] = plain_ms
+    for name in ("first", "refactor"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(len(probs)):
+            F = lrsp.Factor(mats[i], trees[i], 1e-2)
+            _, it, _ = lrsp.pcg(mats[i], F, torch.from_numpy(rhs[i]).cuda())
+            iters.append(it)
+            del F
+        torch.cuda.synchronize()
+        out[f"plain_{name}_ms"] = (time.perf_counter() - t0) * 1e3
     out["plain_iters_max"] = int(np.max(iters))
-    out["speedup_vs_plain"] = plain_ms / out["f64"]["ms_per_step"]
-    log(f"[batch plain] {plain_ms:.1f} ms for one pass, speedup {out['speedup_vs_plain']:.2f}")
+    # like for like: refactor-only on both sides
+    out["speedup_vs_plain"] = out["plain_refactor_ms"] / out["f64"]["ms_per_step"]
+    # first factorizations (host analysis included) on both sides
+    out["speedup_vs_plain_first"] = out["plain_first_ms"] / (out["f64"]["first_factor_ms"] + out["f64"]["pcg_ms"])
+    log(f"[batch plain] first {out['plain_first_ms']:.1f} ms, refactor {out['plain_refactor_ms']:.1f} ms; "
+        f"speedup {out['speedup_vs_plain']:.2f} (refactor), {out['speedup_vs_plain_first']:.2f} (first)")
     return out
 
 
@@ -335,9 +451,38 @@ def roofline(timing, workload):
     return base
 
 
-def run_cpu_baseline(workload):
-    """The oracle, as it stands, on one full step of the same workload."""
-    import numpy as np
+# event-timed families whose algorithmic work is bytes (HBM-bound rows)
+HBM_FAMILIES = {
+    "forward": "forward substitution sweep of a level (fwd/fwd_units/sweep_wave kernels; per level)",
+    "backward": "backward substitution sweep of a level (bwd/bwd_units/sweep_wave kernels; per level)",
+    "spmv": "spmv_kernel (PCG sparse product A p)",
+    "split_gather": "gather_panel_kernel + seg_offsets_kernel (level assembly into the block rows)",
+}
+
+
+def hbm_rooflines(timing):
+    """Achieved bandwidth of the HBM-bound families in the profiled step:
+    algorithmic bytes (every stored factor entry read once per sweep plus the
+    vector entries; 12 nnz + 8 (n+1) + 16 n per sparse product; the gathered
+    block rows read and written) over the summed event time."""
+    out = {}
+    for fam, name in HBM_FAMILIES.items():
+        t = timing.get(fam)
+        if not t or not t["launches"] or t["total_ms"] <= 0:
+            continue
+        ach = t["bytes"] / (t["total_ms"] * 1e-3) / 1e9
+        out[fam] = {"kernel": name, "bound": "hbm", "launches": t["launches"],
+                    "avg_launch_us": round(t["total_ms"] * 1e3 / t["launches"], 2),
+                    "work_per_launch": round(t["bytes"] / t["launches"]), "work_unit": "byte",
+                    "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 6)}
+    return out
+
+
+def _oracle_step(workload, nthreads=None):
+    """One full step of the oracle (factor + PCG), optionally with the BLAS
+    limited to nthreads; returns (seconds factor, seconds pcg, iterations,
+    flops, threads used)."""
     import threadpoolctl
 
     import oracle
@@ -347,17 +492,58 @@ def run_cpu_baseline(workload):
     As = pr.scipy()
     b = rhs(pr.n, 0)
     T = oracle.build_tree(pr.grid, pr.leaf)
-    t0 = time.perf_counter()
-    Fo = oracle.factor(pr.rowptr, pr.col, pr.val, T, pr.tol)
-    t1 = time.perf_counter()
-    _, it, rr, ok = oracle.pcg(lambda v: As @ v, b, lambda r: oracle.solve(Fo, r), 1e-8)
-    t2 = time.perf_counter()
+    with threadpoolctl.threadpool_limits(nthreads):
+        info = threadpoolctl.threadpool_info()
+        cores = max([d.get("num_threads", 1) for d in info if d.get("user_api") == "blas"] or [1])
+        t0 = time.perf_counter()
+        Fo = oracle.factor(pr.rowptr, pr.col, pr.val, T, pr.tol)
+        t1 = time.perf_counter()
+        _, it, rr, ok = oracle.pcg(lambda v: As @ v, b, lambda r: oracle.solve(Fo, r), 1e-8)
+        t2 = time.perf_counter()
+    return t1 - t0, t2 - t1, it, sum(Fo.flops.values()), int(cores)
+
+
+def run_cpu_baseline(workload):
+    """The oracle, as it stands, on one full step of the same workload with
+    every host core, plus one-thread runs of the 64x64 Laplacian and the
+    64x64x16 slab."""
+    import threadpoolctl
+
     info = threadpoolctl.threadpool_info()
-    cores = max([d.get("num_threads", 1) for d in info if d.get("user_api") == "blas"] or [1])
-    return dict(value=(t2 - t0) * 1e3, unit="ms", cores=int(cores), kind="oracle",
-                sample=f"one full step of {workload}: factor {t1 - t0:.1f} s + PCG {t2 - t1:.1f} s "
-                       f"({it} iterations), numpy/OpenBLAS fp64",
-                factor_gflops=sum(Fo.flops.values()) / (t1 - t0) / 1e9)
+    blas = [d for d in info if d.get("user_api") == "blas"]
+    vendor = f"{blas[0].get('internal_api', '?')} {blas[0].get('version', '')}".strip() if blas else "unknown"
+    tf, tp, it, fl, cores = _oracle_step(workload)
+    out = dict(value=(tf + tp) * 1e3, unit="ms", cores=cores, kind="oracle",
+               sample=f"one full step of {workload}: factor {tf:.1f} s + PCG {tp:.1f} s "
+                      f"({it} iterations), numpy with {vendor} BLAS on {cores} threads, fp64",
+               factor_gflops=fl / tf / 1e9, blas=vendor)
+    one = {}
+    for w in ("laplace64", "slab64"):
+        tf1, tp1, it1, fl1, c1 = _oracle_step(w, 1)
+        one[w] = dict(ms=round((tf1 + tp1) * 1e3, 2), factor_ms=round(tf1 * 1e3, 2), pcg_ms=round(tp1 * 1e3, 2),
+                      iters=it1, factor_gflops=round(fl1 / tf1 / 1e9, 3), threads=c1)
+    out["one_thread"] = one
+    log(f"[cpu] {out}")
+    return out
+
+
+def copy_calibration(mib):
+    """A plain elementwise kernel (dst = -src) over mib MiB, three times,
+    from a source that was written long before (cold in the caches): it
+    reads and writes exactly mib MiB, so its FETCH_SIZE and WRITE_SIZE per
+    dispatch calibrate the counters of the other kernels."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    junk = torch.empty(n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        junk.fill_(1.0)  # evicts src from L2 and the memory-side cache
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    log(f"[copy calibration] {mib} MiB read and written three times (neg kernel)")
+    del src, dst, junk
 
 
 def main():
@@ -372,11 +558,22 @@ def main():
     ap.add_argument("--learned-workload", default="stokes256",
                     help="workload of the learned-rank form ('none': skip)")
     ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--mixed-workload", default="stokes128",
+                    help="workload of the precision form ('none': skip)")
+    ap.add_argument("--mixed-steps", type=int, default=3)
+    ap.add_argument("--no-changed-values", dest="changed_values", action="store_false")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB three times (known traffic "
+                         "for the counter calibration of the profiles)")
     args = ap.parse_args()
+    if args.no_mixed:
+        args.mixed_workload = "none"
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the solver runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration_mib > 0:
+        copy_calibration(args.copy_calibration_mib)
     pr, res, timing = run_gpu(args)
     f64 = res["f64"]
     out = {
@@ -406,11 +603,14 @@ def main():
         "one_time_analysis_ms": round(res["analysis"]["host_analysis_ms"], 2),
         "first_factor_ms": round(res["analysis"]["first_factor_ms"], 2),
         "levels_reused": f64["levels_reused"],
-        "mixed": {p: {k: (round(v, 4) if isinstance(v, float) and k != "relres" else v)
-                      for k, v in res[p].items()
-                      if k in ("ms_per_step", "factor_ms", "pcg_ms", "iters", "relres", "factor_gflops")}
-                  for p in res if p not in ("f64", "analysis")},
+        "factor_bytes": f64["factor_bytes"],
+        "roofline_hbm": hbm_rooflines(timing),
     }
+    if "changed_values" in res:
+        out["changed_values"] = {k: (round(v, 4) if isinstance(v, float) and k != "relres_max" else v)
+                                 for k, v in res["changed_values"].items()}
+    if args.mixed_workload != "none":
+        out["mixed"] = run_mixed(args)
     if args.batch > 0:
         out["batch"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in run_batch(args).items()}
     if args.learned_workload != "none":

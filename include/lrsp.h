@@ -54,11 +54,13 @@ typedef struct {
  * column indices.  rowptr/col/val are DEVICE pointers.  h_rowptr/h_col are
  * optional HOST copies of the pattern used by the symbolic analysis; when
  * NULL the library copies the pattern from the device.  pattern_id: 0, or a
- * nonzero number the caller gives to this exact pattern; a factorization
- * whose tree last analysed a pattern of the same nonzero id reuses that
- * analysis without comparing the patterns entry by entry (the caller must
- * never give one id to two different patterns).  The caller owns all arrays
- * and keeps them alive for the duration of a call. */
+ * nonzero number the caller gives to this exact pattern.  Precondition: one
+ * id is never given to two different patterns.  A factorization whose tree
+ * last analysed a pattern of the same nonzero id reuses that analysis after
+ * comparing the row pointers in full and the column indices at up to 4096
+ * evenly spaced entries instead of all of them (id 0: every entry is
+ * compared).  The caller owns all arrays and keeps them alive for the
+ * duration of a call. */
 typedef struct {
   int64_t n;
   int64_t nnz;
@@ -155,7 +157,12 @@ lrsp_status lrsp_apply(const lrsp_factorization* F, const double* b, double* x, 
 
 /* Preconditioned conjugate gradients with M = the factor, x0 = 0, stopping
  * when the recursive residual satisfies ||r||_2 <= rtol*||b||_2 (per column)
- * or after maxit iterations.  b, x: device, n*nrhs column-major.
+ * or after maxit iterations.  This is the Krylov solve of the problem
+ * statement A x = b (section "Improved LoRaSp Solver") with the factor as
+ * preconditioner; the paper wraps the factor in right-preconditioned
+ * GMRES(200) instead (section "Numerical Results", test problems; see
+ * lrsp_gmres), and PCG is used here because the factor is symmetric
+ * positive definite by construction.  b, x: device, n*nrhs column-major.
  * iters[nrhs], relres[nrhs]: host outputs (iteration count = number of
  * matrix-vector products; relres = TRUE ||b - A x||_2/||b||_2).
  * ERR_NO_CONV if some column did not converge (x is still the last iterate). */
@@ -337,8 +344,9 @@ int32_t lrsp_autotune_entries(void);
  * 2 = backward sweep, 3..9 = the split elimination kernels (3 segment
  * offsets + gather [bytes], 4 Cholesky, 5 triangular scaling, 6 pivoted
  * QR, 7 U^T rotation, 8 Schur update, 9 write-back [bytes]), 10 = the
- * one-workgroup-per-cluster elimination kernel.  lrsp_timing_read
- * synchronises the device. */
+ * one-workgroup-per-cluster elimination kernel, 11 = the sparse products
+ * A p of the PCG iterations [bytes: 12 nnz + 8 (n+1) + 16 n each].
+ * lrsp_timing_read synchronises the device. */
 typedef struct {
   int64_t launches;
   double total_ms;

@@ -30,7 +30,7 @@ const char* last_error();
   } while (0)
 
 // Event timing of kernel families (lrsp_timing_*).
-constexpr int kFamilies = 11;
+constexpr int kFamilies = 12;
 struct TimingState {
   bool on = false;
   uint32_t mask = ~0u;  // families that record events

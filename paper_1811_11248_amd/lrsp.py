@@ -471,12 +471,15 @@ def apply(F: Factor, b, x=None, stream=None):
     return out if b.dim() == 1 else out.view(nrhs, -1).t()
 
 
-def pcg(A: DeviceMatrix, F: Factor, b, rtol=1e-8, maxit=1000, stream=None, raise_no_conv=True):
-    """PCG with the factor; returns (x, iters, relres) with per-column numpy arrays."""
+def pcg(A: DeviceMatrix, F: Factor, b, rtol=1e-8, maxit=1000, stream=None, raise_no_conv=True, x=None):
+    """PCG with the factor; returns (x, iters, relres) with per-column numpy arrays.
+
+    x: optional output tensor of the layout of b (for b of shape [n, nrhs],
+    its transpose made contiguous)."""
     import torch
     nrhs = 1 if b.dim() == 1 else b.shape[1]
     bb = b if b.dim() == 1 else b.t().contiguous()
-    x = torch.empty_like(bb)
+    x = torch.empty_like(bb) if x is None else x
     it = (C.c_int32 * nrhs)()
     rr = (C.c_double * nrhs)()
     csr = A.csr()
@@ -490,7 +493,7 @@ def pcg(A: DeviceMatrix, F: Factor, b, rtol=1e-8, maxit=1000, stream=None, raise
 
 TIMING_FAMILIES = {"eliminate": 0, "forward": 1, "backward": 2, "split_gather": 3,
                    "split_potrf": 4, "split_trsm": 5, "split_cpqr": 6, "split_applyq": 7,
-                   "split_schur": 8, "split_writeback": 9, "fused": 10}
+                   "split_schur": 8, "split_writeback": 9, "fused": 10, "spmv": 11}
 
 
 def timing_enable(on: bool = True):

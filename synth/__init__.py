@@ -15,5 +15,6 @@ from .problems import (  # noqa: F401
     batch_system,
     batch_rhs,
     config,
+    config_variant,
     CONFIG_NAMES,
 )

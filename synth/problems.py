@@ -260,3 +260,22 @@ def config(name: str) -> Problem:
         raise ValueError(f"unknown config {name!r}")
     p.name = name
     return p
+
+
+def config_variant(name: str, field_seed: int) -> Problem:
+    """A named workload with another log-normal field seed: the same grid,
+    pattern and parameters, other values (for steps whose values change)."""
+    if name == "slab64":
+        p = slab_scalar(64, 64, 16, 1e4, lognormal_field((64, 64, 16), seed=field_seed))
+    elif name == "stokes256":
+        p = slab_vector(256, 256, 32, 1e4, lognormal_field((256, 256, 32), seed=field_seed))
+    elif name == "stokes128":
+        p = slab_vector(128, 128, 20, 1e4, lognormal_field((128, 128, 20), seed=field_seed))
+    elif name == "laplace64":
+        p = laplace2d(64, eps=float(np.random.default_rng(field_seed).uniform(0.5, 2.0)))
+    else:
+        raise ValueError(f"unknown config {name!r}")
+    base = config(name)
+    p.leaf, p.tol, p.name = base.leaf, base.tol, f"{name}-field{field_seed}"
+    return p
+

@@ -42,11 +42,12 @@ def L():
 
 
 def _problems():
-    """Four of the smallest draws of the many-systems workload, one system
-    whose graph is a single cluster (dense top at level 0) and one with a
-    small leaf (more levels than the others)."""
+    """Four of the smallest draws of the many-systems workload, two draws
+    whose largest leaves hold 275 and 325 DoFs (157 of the 512 systems have
+    leaves above 256), one system whose graph is a single cluster (dense top
+    at level 0) and one with a small leaf (more levels than the others)."""
     P = batch_params()
-    out = [(batch_system(i, P), 256) for i in (196, 456, 7, 22)]
+    out = [(batch_system(i, P), 256) for i in (196, 456, 7, 22, 214, 466)]
     tiny = slab_scalar(4, 4, 8, 1e3, lognormal_field((4, 4, 8), seed=9))
     out.append((tiny, 256))
     deep = slab_scalar(12, 10, 6, 1e4, lognormal_field((10, 12, 6), seed=4))
@@ -107,6 +108,39 @@ def test_batch_matches_single_and_oracle(torch, L):
             xo = oracle.solve(Fo, bs[i][:, c])
             err = np.linalg.norm(xi[:, c] - xo) / np.linalg.norm(xo)
             assert err <= APPLY_TOL, f"sys {i} col {c}: {err:.3e}"
+
+
+@pytest.mark.parametrize("mode", ["split", "colour", "level"])
+def test_batch_forced_schedules(torch, L, mode):
+    """Every level forced to one schedule (several workgroups per cluster,
+    one launch per colour, one persistent launch per level): schedules and
+    ranks equal the oracle's, M^{-1} b matches it to 1e-10 (2-norm and
+    element-wise), including the clusters of more than 256 DoFs."""
+    L.autotune_clear()
+    probs, oracles, mats, trees = _setup(torch, L)
+    _say(f"[batch forced {mode}] {len(probs)} systems, largest leaves "
+         f"{[max(len(d) for d in oracle.build_tree(pr.grid, leaf).leaf_dofs) for pr, leaf in probs]}")
+    B = L.Batch(mats, trees, 1e-2, exec_mode=mode)
+    torch.cuda.synchronize()
+    assert (B.status == 0).all()
+    bs = _packed_rhs(probs, 2)
+    X = B.apply(B.pack(bs)).cpu().numpy()
+    for i, ((pr, leaf), Fo) in enumerate(zip(probs, oracles)):
+        assert B.system_levels(i) == len(Fo.levels)
+        for li, lv in enumerate(Fo.levels):
+            g = B.level(i, li)
+            assert g["order"].tolist() == list(lv.order), f"order sys {i} level {li}"
+            assert g["ranks"].tolist() == list(lv.ranks), f"ranks sys {i} level {li}"
+        xi = X[B.off[i]:B.off[i + 1]]
+        F = L.Factor(mats[i], trees[i], 1e-2, exec_mode=mode)
+        for c in range(2):
+            xo = oracle.solve(Fo, bs[i][:, c])
+            err = np.linalg.norm(xi[:, c] - xo) / np.linalg.norm(xo)
+            erri = np.max(np.abs(xi[:, c] - xo)) / np.max(np.abs(xo))
+            xs = L.apply(F, torch.from_numpy(bs[i][:, c].copy()).cuda()).cpu().numpy()
+            _say(f"  sys {i} col {c}: n={pr.n} err {err:.2e} (element-wise {erri:.2e}), "
+                 f"same bits as the single-system {mode} schedule: {np.array_equal(xs, xi[:, c])}")
+            assert err <= APPLY_TOL and erri <= APPLY_TOL, f"sys {i} col {c}"
 
 
 def test_batch_pcg_four_rhs(torch, L):

@@ -2,8 +2,10 @@
 
 Bars: the cluster tree, level graphs, colouring, elimination order and
 ranks equal the oracle's bit for bit; M^{-1} b matches the oracle's solve to
-relative 1e-10 in fp64; PCG reaches 1e-8 with an iteration count within +-1
-of the oracle's.
+relative 1e-10 in fp64, both in the 2-norm and element by element
+(max |x - x_o| / max |x_o|); PCG reaches 1e-8 with an iteration count within
++-1 of the oracle's.  The precision form is compared with the oracle run in
+the same precision, to a bar derived from the oracle's own fp32 effect.
 """
 import sys
 
@@ -50,6 +52,13 @@ CASES = {
     "slab_split": (lambda: slab_scalar(24, 20, 8, 1e4, lognormal_field((20, 24, 8), seed=7)), 128, 1e-2),
     "vector_split": (lambda: slab_vector(13, 11, 6, 1e3), 120, 1e-2),
     "slab64_full": (lambda: config("slab64"), 256, 1e-2),
+    # leaves of 216..384 DoFs (13x13 columns of 24 cells, leaf target 256):
+    # the largest clusters of the many-systems workload, which take the
+    # m > 256 kernels of the split schedule
+    "slab_large": (lambda: slab_scalar(13, 13, 24, 1e4, lognormal_field((13, 13, 24), seed=8)), 256, 1e-2),
+    # the precision workload's shape: 2 components x 20 layers, 2x2 columns
+    # per leaf = 160 DoFs per cluster
+    "vector_m160": (lambda: slab_vector(16, 16, 20, 1e4), 256, 1e-2),
 }
 # kernel schedules: one workgroup per cluster and one launch per colour; the
 # same in one cooperative launch per level; several workgroups per cluster
@@ -106,15 +115,17 @@ def test_schedule_and_apply(torch, L, name, mode):
         xo = oracle.solve(Fo, b)
         x = L.apply(F, torch.from_numpy(b).cuda()).cpu().numpy()
         err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
-        _say(f"  apply rel err {err:.3e}")
+        erri = np.max(np.abs(x - xo)) / np.max(np.abs(xo))
+        _say(f"  apply rel err {err:.3e} (element-wise {erri:.3e})")
         assert err <= APPLY_TOL
+        assert erri <= APPLY_TOL
     if exact:
         xe = np.linalg.solve(pr.scipy().toarray(), b)
         assert np.linalg.norm(x - xe) <= 1e-10 * np.linalg.norm(xe)
 
 
 @pytest.mark.parametrize("name", ["laplace64", "slab_ragged", "vector_ragged", "slab_aniso", "strip4",
-                                  "slab_split", "slab64_full"])
+                                  "slab_split", "slab64_full", "slab_large", "vector_m160"])
 def test_pcg_iterations(torch, L, name):
     pr, Fo, A, F = _run(torch, L, name)
     b = rhs(pr.n, 0)
@@ -140,22 +151,110 @@ def test_not_spd_is_reported(torch, L):
     assert ex.value.status == L.ERR_NOT_SPD
 
 
+_PREC = {}
+
+
+def _oracle_prec(name, prec):
+    key = (name, prec)
+    if key not in _PREC:
+        mk, leaf, tol = CASES[name]
+        pr, _ = _oracle(name)
+        T = oracle.build_tree(pr.grid, leaf)
+        _PREC[key] = oracle.factor(pr.rowptr, pr.col, pr.val, T, tol, gemm_prec=prec)
+    return _PREC[key]
+
+
+@pytest.mark.parametrize("mode", ["auto", "level"])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_precision_forms_converge(torch, L, prec):
-    pr = config("slab64")
+def test_precision_form_vs_oracle(torch, L, prec, mode):
+    """Schur products with fp32 or bf16 inputs and fp32 accumulation, on
+    clusters of the precision workload's shape (m = 160), against the oracle
+    computing the same form.  Both sides round F identically (fp64 -> fp32
+    -> bf16, nearest even); they differ only in the order of the fp32
+    accumulation, a perturbation of the same kind and size as the effect of
+    fp32 arithmetic in the product itself.  The bar is therefore four times
+    that effect as the oracle measures it (its fp32 form against its fp64
+    form), and never tighter than the fp64 bar.  The error of the form
+    against the fp64 oracle is printed."""
+    name = "vector_m160"
+    pr, Fo64 = _oracle(name)
+    Fo32 = _oracle_prec(name, "f32")
+    Fop = _oracle_prec(name, prec)
+    _say(f"[precision {prec} / {mode}] n={pr.n}")
     A = L.DeviceMatrix.from_problem(pr)
-    tree = L.Tree(pr.grid, 256)
-    F64 = L.Factor(A, tree, 1e-2)
-    Fp = L.Factor(A, tree, 1e-2, gemm_prec=prec)
-    b = torch.from_numpy(rhs(pr.n, 0)).cuda()
-    x64 = L.apply(F64, b)
-    xp = L.apply(Fp, b)
-    err = float(torch.linalg.norm(xp - x64) / torch.linalg.norm(x64))
-    _, it, rr = L.pcg(A, Fp, b, rtol=1e-8)
-    _, it64, _ = L.pcg(A, F64, b, rtol=1e-8)
-    _say(f"  {prec}: apply rel diff vs fp64 {err:.2e}; pcg iters {it[0]} (fp64 {it64[0]}), relres {rr[0]:.1e}")
-    assert rr[0] <= 1e-8
-    assert err < (1e-4 if prec == "f32" else 5e-2)
+    leaf, tol = CASES[name][1], CASES[name][2]
+    F = L.Factor(A, L.Tree(pr.grid, leaf), tol, gemm_prec=prec, exec_mode=mode)
+    assert set(Fo64.levels[0].sizes) == {160}
+    assert F.info()["nlevels"] == len(Fop.levels)
+    for li, lv in enumerate(Fop.levels):
+        assert F.level(li)["ranks"].tolist() == list(lv.ranks), f"ranks level {li}"
+    for seed in (0, 1):
+        b = rhs(pr.n, seed)
+        xo64 = oracle.solve(Fo64, b)
+        xo32 = oracle.solve(Fo32, b)
+        xop = oracle.solve(Fop, b)
+        x = L.apply(F, torch.from_numpy(b).cuda()).cpu().numpy()
+        e32 = np.linalg.norm(xo32 - xo64) / np.linalg.norm(xo64)
+        e32i = np.max(np.abs(xo32 - xo64)) / np.max(np.abs(xo64))
+        err = np.linalg.norm(x - xop) / np.linalg.norm(xop)
+        erri = np.max(np.abs(x - xop)) / np.max(np.abs(xop))
+        e64 = np.linalg.norm(x - xo64) / np.linalg.norm(xo64)
+        eo64 = np.linalg.norm(xop - xo64) / np.linalg.norm(xo64)
+        _say(f"  seed {seed}: vs oracle-{prec} {err:.3e} (element-wise {erri:.3e}), bar {max(APPLY_TOL, 4 * e32):.3e}; "
+             f"vs fp64 oracle: gpu {e64:.3e}, oracle-{prec} {eo64:.3e}")
+        assert err <= max(APPLY_TOL, 4.0 * e32)
+        assert erri <= max(APPLY_TOL, 4.0 * e32i)
+    b = rhs(pr.n, 0)
+    As = pr.scipy()
+    _, ito, _, ok = oracle.pcg(lambda v: As @ v, b, lambda r: oracle.solve(Fop, r), 1e-8)
+    assert ok
+    _, it, rr = L.pcg(A, F, torch.from_numpy(b).cuda(), rtol=1e-8)
+    _say(f"  pcg iters gpu {it[0]} oracle-{prec} {ito}; relres {rr[0]:.2e}")
+    assert abs(int(it[0]) - ito) <= 1 and rr[0] <= 1e-8
+
+
+def test_precision_workload_full_size(torch, L):
+    """The 128x128x20 two-component workload (655,360 DoF) at full size: the
+    fp64 path against the fp64 oracle (schedule and ranks bit for bit, M^{-1} b
+    to 1e-10), then the fp32 and bf16 Schur-product forms, whose error against
+    the fp64 oracle is stated (and bounded by the size the oracle's own
+    reduced-precision forms show on the same cluster shape, with a margin)."""
+    import threadpoolctl
+
+    pr = config("stokes128")
+    T = oracle.build_tree(pr.grid, pr.leaf)
+    _say(f"[stokes128 full size] n={pr.n}, oracle fp64 factor (one BLAS thread)")
+    with threadpoolctl.threadpool_limits(1):
+        Fo = oracle.factor(pr.rowptr, pr.col, pr.val, T, pr.tol,
+                           level_hook=lambda li, *_: _say(f"  oracle level {li}"))
+        b = rhs(pr.n, 0)
+        xo = oracle.solve(Fo, b)
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree(pr.grid, pr.leaf)
+    bd = torch.from_numpy(b).cuda()
+    errs = {}
+    for prec in ("f64", "f32", "bf16"):
+        F = L.Factor(A, tree, pr.tol, gemm_prec=prec)
+        x = L.apply(F, bd).cpu().numpy()
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        erri = np.max(np.abs(x - xo)) / np.max(np.abs(xo))
+        _, it, rr = L.pcg(A, F, bd, rtol=1e-8)
+        errs[prec] = err
+        _say(f"  {prec}: M^-1 b vs fp64 oracle {err:.3e} (element-wise {erri:.3e}); "
+             f"pcg {it[0]} iterations, relres {rr[0]:.2e}")
+        assert rr[0] <= 1e-8
+        if prec == "f64":
+            assert F.info()["nlevels"] == len(Fo.levels)
+            for li, lv in enumerate(Fo.levels):
+                g = F.level(li)
+                assert g["order"].tolist() == list(lv.order), f"order level {li}"
+                assert g["ranks"].tolist() == list(lv.ranks), f"ranks level {li}"
+            assert err <= APPLY_TOL and erri <= APPLY_TOL
+        del F
+    # the reduced forms' error against fp64 at the m = 160 shape is ~4e-10
+    # (fp32) and ~1e-6 (bf16) in the oracle; allow a hundredfold margin
+    assert errs["f32"] <= 1e-7
+    assert errs["bf16"] <= 1e-4
 
 
 def test_analysis_reuse_gives_identical_factor(torch, L):
