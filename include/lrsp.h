@@ -170,6 +170,23 @@ lrsp_status lrsp_pcg(const lrsp_csr* A, const lrsp_factorization* F, const doubl
                      int32_t nrhs, double rtol, int32_t maxit, int32_t* iters, double* relres,
                      void* stream);
 
+/* Right-preconditioned restarted GMRES(restart) with the factor as
+ * preconditioner (M^{-1} applied as in lrsp_apply), as the paper solves its
+ * systems: GMRES(200), tolerance 1e-12, at most 1000 iterations (section
+ * "Numerical Results", test problems).  x0 = 0; each cycle builds an
+ * orthonormal basis of the Krylov space of A M^{-1} (classical Gram-Schmidt
+ * applied twice), reduces the Hessenberg matrix by Givens rotations and
+ * stops when the least-squares residual satisfies ||r||_2 <= rtol*||b||_2;
+ * x = x0 + M^{-1} V y.  b, x: device, n*nrhs column-major, solved column
+ * after column.  iters[nrhs]: products with A M^{-1} over all cycles;
+ * relres[nrhs]: TRUE ||b - A x||_2/||b||_2.  The basis takes n*(restart+3)
+ * doubles of device memory during the call.  ERR_NO_CONV when a column
+ * reached maxit (x is the last iterate); ERR_ARG for restart outside
+ * 1..4096. */
+lrsp_status lrsp_gmres(const lrsp_csr* A, const lrsp_factorization* F, const double* b, double* x,
+                       int32_t nrhs, int32_t restart, double rtol, int32_t maxit, int32_t* iters,
+                       double* relres, void* stream);
+
 /* ---- introspection -------------------------------------------------------*/
 typedef struct {
   int32_t nlevels;       /* levels eliminated before the dense top */

@@ -48,15 +48,22 @@ def householder_nonneg(x: np.ndarray, norm2: float):
     return v, tau, beta
 
 
-def cpqr(B: np.ndarray, tol: float, tol_mode: str = "relative"):
+def cpqr(B: np.ndarray, tol: float, tol_mode: str = "relative", info: dict | None = None):
     """Truncated column-pivoted QR ``B P = Q R``.
 
     Returns ``(k, V, tau, R, perm)``: ``V`` is ``m x k`` with the reflector
     vectors (unit leading entry, zeros above), ``tau`` their scalars, ``R``
     the ``k x b`` upper-trapezoidal factor in pivoted column order, and
     ``perm[c]`` the original column at pivoted position ``c``.
+
+    ``info``, if given, receives the pivot norms that decided the rank:
+    ``r00``, ``last`` (the last pivot kept, ``R_{k-1,k-1}``, or None) and
+    ``stop`` (the pivot norm that ended the QR, or None when all ``min(m, b)``
+    steps ran).
     """
     m, b = B.shape
+    if info is not None:
+        info.update(r00=0.0, last=None, stop=None)
     W = np.array(B, dtype=np.float64, copy=True)
     perm = np.arange(b)
     kmax = min(m, b)
@@ -77,10 +84,16 @@ def cpqr(B: np.ndarray, tol: float, tol_mode: str = "relative"):
         rjj = math.sqrt(float(norm2[c]))
         if j == 0:
             r00 = rjj
+            if info is not None:
+                info["r00"] = rjj
         stop = (rjj <= tol * r00) if tol_mode == "relative" else (rjj <= tol)
         if stop or rjj == 0.0:
             k = j
+            if info is not None:
+                info["stop"] = rjj
             break
+        if info is not None:
+            info["last"] = rjj
         v, t, beta = householder_nonneg(W[j:, j], float(norm2[c]))
         if j + 1 < b:
             blk = W[j:, j + 1:]

@@ -62,6 +62,7 @@ class SLRE:
     Vt: np.ndarray  # V_hat_1^T in original column order (k x b)
     R: np.ndarray  # k x b pivoted R
     perm: np.ndarray  # pivot order of the columns of the w block
+    margin: float = float("inf")  # distance of the rank decision from the threshold
 
 
 def chol_lower(A: np.ndarray, level=-1, cluster=-1) -> np.ndarray:
@@ -93,14 +94,86 @@ def scaled_lowrank_elimination(Ass, Asn, Asw, tol, tol_mode="relative", level=-1
     Bn = _lsolve(G, Asn)
     Bw = _lsolve(G, Asw)
     m, b = Bw.shape
+    margin = float("inf")
     if b == 0 or m == 0:
         k, V, tau, R, perm = 0, np.zeros((m, 0)), np.zeros(0), np.zeros((0, b)), np.arange(b)
     else:
-        k, V, tau, R, perm = cpqr(Bw, tol, tol_mode)  # Eq. offdiag_new
+        info = {}
+        k, V, tau, R, perm = cpqr(Bw, tol, tol_mode, info)  # Eq. offdiag_new
+        margin = decision_margin(info, tol, tol_mode)
     C = apply_qt(V, tau, Bn) if k > 0 else np.array(Bn, copy=True)  # E_s, Eq. sparse
     Vt = np.zeros((k, b))
     Vt[:, perm] = R
-    return SLRE(G, V, tau, k, C, Vt, R, perm)
+    return SLRE(G, V, tau, k, C, Vt, R, perm, margin)
+
+
+def decision_margin(info: dict, tol: float, tol_mode: str) -> float:
+    """Relative distance of the pivot norms that decided a rank from the
+    threshold (the kept pivot just above it, the stopping pivot at or below
+    it): a perturbation of the block smaller than this cannot change the
+    rank.  Infinite when no pivot was compared with a positive threshold."""
+    thr = tol * info["r00"] if tol_mode == "relative" else tol
+    if not thr > 0.0:
+        return float("inf")
+    out = float("inf")
+    for key in ("last", "stop"):
+        v = info.get(key)
+        if v is not None and v > 0.0:
+            out = min(out, abs(v - thr) / thr)
+    return out
+
+
+@dataclasses.dataclass
+class NoDCStep:
+    """Result of one elimination step without deferred compression."""
+    V: np.ndarray  # m x k Householder vectors of U (from the unscaled A_sw)
+    tau: np.ndarray  # k
+    k: int
+    Gf: np.ndarray  # (m-k) x (m-k) lower Cholesky factor of U_2^T A_ss U_2
+    Fc: np.ndarray  # Gf^{-1} U_2^T A_ss U_1  ((m-k) x k)
+    Fn: np.ndarray  # Gf^{-1} U_2^T A_sn      ((m-k) x a)
+    Dc: np.ndarray  # coarse diagonal block U_1^T A_ss U_1 - Fc^T Fc (k x k)
+    Ccn: np.ndarray  # coarse-near coupling U_1^T A_sn - Fc^T Fn (k x a)
+    Vt: np.ndarray  # V_1^T in original column order (k x b)
+    R: np.ndarray
+    perm: np.ndarray
+    margin: float = float("inf")
+
+
+def lowrank_elimination_nodc(Ass, Asn, Asw, tol, tol_mode="relative", level=-1, cluster=-1) -> NoDCStep:
+    """One step of the scheme WITHOUT deferred compression (section
+    Deferred-compression Scheme, Eqs. offdiag and sc_old) on the block row
+    ``[A_ss | A_sn | A_sw]``: the unscaled far-field block is compressed,
+    ``A_sw = U_1 V_1^T + U_2 V_2^T`` (the same column-pivoted QR and rank rule
+    as the scaled form), ``U_2 V_2^T`` is dropped, the cluster is rotated by
+    ``U^T`` and its fine part (the ``U_2`` directions, which no longer couple
+    to the far field) is eliminated by Cholesky.  The ``k`` coarse DoFs keep
+    the Schur complement of that elimination: diagonal ``Dc``, near-field
+    coupling ``Ccn`` and far-field coupling ``V_1^T``; eliminating them too
+    gives the approximate Schur complement ``S_A~`` of Eq. sc_old."""
+    m, b = Asw.shape
+    S = np.tril(Ass) + np.tril(Ass, -1).T
+    margin = float("inf")
+    if b == 0 or m == 0:
+        k, V, tau, R, perm = 0, np.zeros((m, 0)), np.zeros(0), np.zeros((0, b)), np.arange(b)
+    else:
+        info = {}
+        k, V, tau, R, perm = cpqr(Asw, tol, tol_mode, info)  # Eq. offdiag
+        margin = decision_margin(info, tol, tol_mode)
+    if k > 0:
+        Bss = apply_qt(V, tau, apply_qt(V, tau, S).T)  # U^T A_ss U (A_ss symmetric)
+        Bsn = apply_qt(V, tau, Asn)
+    else:
+        Bss, Bsn = S, np.array(Asn, dtype=np.float64, copy=True)
+    Gf = chol_lower(Bss[k:, k:], level, cluster)
+    Fc = _lsolve(Gf, Bss[k:, :k])
+    Fn = _lsolve(Gf, Bsn[k:, :])
+    Dc = Bss[:k, :k] - Fc.T @ Fc
+    Dc = 0.5 * (Dc + Dc.T)
+    Ccn = Bsn[:k, :] - Fc.T @ Fn
+    Vt = np.zeros((k, b))
+    Vt[:, perm] = R
+    return NoDCStep(V, tau, k, Gf, Fc, Fn, Dc, Ccn, Vt, R, perm, margin)
 
 
 def round_bf16(x: np.ndarray) -> np.ndarray:
@@ -136,6 +209,8 @@ class ClusterRecord:
     F: np.ndarray  # (m-k) x a
     nlist: list  # [(q, active width of q when s was processed)]
     wlist: list
+    margin: float = float("inf")  # relative distance of the rank decision from the threshold
+    Fc: np.ndarray | None = None  # without deferred compression: Gf^{-1} U_2^T A_ss U_1 (G is then Gf)
 
 
 @dataclasses.dataclass
@@ -161,6 +236,7 @@ class Factor:
     top_L: np.ndarray
     flops: dict
     corollary_min: float | None = None
+    dc: bool = True
 
 
 def _dense_active(blocks, sizes):
@@ -191,7 +267,7 @@ def _level0_blocks(tree: ClusterTree, rowptr, col, val):
     return blocks, sizes, graph
 
 
-def _eliminate_level(li, blocks, sizes, graph, tol, tol_mode, prec, flops, checks, cor):
+def _eliminate_level(li, blocks, sizes, graph, tol, tol_mode, prec, flops, checks, cor, dc=True):
     M = len(sizes)
     colour = d2_colouring(graph)
     order = sorted(range(M), key=lambda s: (colour[s], s))
@@ -220,10 +296,13 @@ def _eliminate_level(li, blocks, sizes, graph, tol, tol_mode, prec, flops, check
                     if (p, q) in blocks:
                         Aww[wo[i]:wo[i + 1], wo[j]:wo[j + 1]] = blocks[(p, q)]
             Aww = np.tril(Aww) + np.tril(Aww, -1).T
-        st = scaled_lowrank_elimination(blocks[(s, s)], Asn, Asw, tol, tol_mode, li, s)
+        if dc:
+            st = scaled_lowrank_elimination(blocks[(s, s)], Asn, Asw, tol, tol_mode, li, s)
+        else:
+            st = lowrank_elimination_nodc(blocks[(s, s)], Asn, Asw, tol, tol_mode, li, s)
         k = st.k
         a, b = Asn.shape[1], Asw.shape[1]
-        if checks and w and Aww.size:
+        if checks and dc and w and Aww.size:
             ev = float(np.linalg.eigvalsh(Aww - st.Vt.T @ st.Vt).min())
             cor[0] = ev if cor[0] is None else min(cor[0], ev)
         flops["potrf"] += m ** 3 / 3.0
@@ -231,7 +310,12 @@ def _eliminate_level(li, blocks, sizes, graph, tol, tol_mode, prec, flops, check
         flops["cpqr"] += sum(4.0 * (m - j) * (b - j) for j in range(k))
         flops["applyq"] += sum(4.0 * (m - j) * a for j in range(k))
         flops["schur"] += a * (a + 1.0) * (m - k)
-        F = st.C[k:, :]
+        if dc:
+            F, Cc, Dk, G = st.C[k:, :], st.C[:k, :], np.eye(k), st.G
+        else:
+            # the fine elimination also costs a rotation of the diagonal block
+            # and the coarse block updates (not in the scaled form's count)
+            F, Cc, Dk, G = st.Fn, st.Ccn, st.Dc, st.Gf
         no = np.concatenate([[0], np.cumsum(nw)]).astype(int)
         # Schur update of the near field, X_nn = A_nn - F^T F (Eq. elim)
         for i, p in enumerate(n):
@@ -247,10 +331,11 @@ def _eliminate_level(li, blocks, sizes, graph, tol, tol_mode, prec, flops, check
                 blocks[(p, q)] = blocks[(p, q)] - upd
                 if p != q:
                     blocks[(q, p)] = blocks[(p, q)].T.copy()
-        # coarse row of s: [I_k | U1^T G^-1 A_sn | V1^T], then P_s moves it on
-        blocks[(s, s)] = np.eye(k)
+        # coarse row of s: [I_k | U1^T G^-1 A_sn | V1^T] (without deferred
+        # compression: [Dc | Ccn | V1^T]), then P_s moves it on
+        blocks[(s, s)] = Dk
         for i, q in enumerate(n):
-            blocks[(s, q)] = st.C[:k, no[i]:no[i + 1]].copy()
+            blocks[(s, q)] = Cc[:, no[i]:no[i + 1]].copy()
             blocks[(q, s)] = blocks[(s, q)].T.copy()
         wo = np.concatenate([[0], np.cumsum(ww)]).astype(int)
         for i, q in enumerate(w):
@@ -258,8 +343,9 @@ def _eliminate_level(li, blocks, sizes, graph, tol, tol_mode, prec, flops, check
             blocks[(q, s)] = blocks[(s, q)].T.copy()
         cur[s] = k
         ranks[s] = k
-        recs.append(ClusterRecord(s, m, k, a, b, st.G, st.V, st.tau, F.copy(),
-                                  list(zip(n, nw)), list(zip(w, ww))))
+        recs.append(ClusterRecord(s, m, k, a, b, G, st.V, st.tau, F.copy(),
+                                  list(zip(n, nw)), list(zip(w, ww)), st.margin,
+                                  None if dc else st.Fc.copy()))
     rec = LevelRecord(list(sizes), [list(g) for g in graph], colour, order, ranks, recs)
     if checks:
         D = _dense_active({key: B for key, B in blocks.items()}, cur)
@@ -290,11 +376,13 @@ def _coarsen(blocks, cur, M):
 
 
 def factor(rowptr, col, val, tree: ClusterTree, tol: float, tol_mode: str = "relative",
-           gemm_prec: str = "f64", checks: bool = False, level_hook=None) -> Factor:
+           gemm_prec: str = "f64", checks: bool = False, level_hook=None, dc: bool = True) -> Factor:
     """Algorithm 1 over the cluster tree; returns the factor of ``A``.
 
-    level_hook(level, blocks, sizes, graph), if given, sees the matrix at the
-    start of every eliminated level (read only)."""
+    dc=False replaces every scaled low-rank elimination by the step without
+    deferred compression (``lowrank_elimination_nodc``), the scheme the paper
+    compares against.  level_hook(level, blocks, sizes, graph), if given,
+    sees the matrix at the start of every eliminated level (read only)."""
     blocks, sizes, graph = _level0_blocks(tree, rowptr, col, val)
     flops = dict(potrf=0.0, trsm=0.0, cpqr=0.0, applyq=0.0, schur=0.0, top=0.0)
     levels = []
@@ -307,11 +395,11 @@ def factor(rowptr, col, val, tree: ClusterTree, tol: float, tol_mode: str = "rel
             Ltop = chol_lower(D, li, -1)
             flops["top"] += D.shape[0] ** 3 / 3.0
             return Factor(tree, tol, tol_mode, gemm_prec, levels, list(sizes),
-                          [list(g) for g in graph], Ltop, flops, cor[0])
+                          [list(g) for g in graph], Ltop, flops, cor[0], dc)
         if level_hook is not None:
             level_hook(li, blocks, sizes, graph)
         rec, cur = _eliminate_level(li, blocks, sizes, graph, tol, tol_mode, gemm_prec,
-                                    flops, checks, cor)
+                                    flops, checks, cor, dc)
         levels.append(rec)
         blocks, sizes, graph = _coarsen(blocks, cur, M)
         li += 1
@@ -324,8 +412,13 @@ def solve(F: Factor, b: np.ndarray) -> np.ndarray:
     saved = []
     for lev in F.levels:  # forward substitution
         for r in lev.recs:
-            y = _lsolve(r.G, vec[r.s])  # S_s
-            y = apply_qt(r.V, r.tau, y) if r.k else y  # E_s
+            if r.Fc is None:
+                y = _lsolve(r.G, vec[r.s])  # S_s
+                y = apply_qt(r.V, r.tau, y) if r.k else y  # E_s
+            else:  # without deferred compression: rotate, then the fine solve
+                y = apply_qt(r.V, r.tau, vec[r.s]) if r.k else vec[r.s].copy()
+                y[r.k:] = _lsolve(r.G, y[r.k:])
+                y[:r.k] -= r.Fc.T @ y[r.k:]
             yf = y[r.k:]
             off = 0
             for q, wq in r.nlist:  # G_s: y_n -= F^T y_f
@@ -353,8 +446,12 @@ def solve(F: Factor, b: np.ndarray) -> np.ndarray:
             for q, wq in r.nlist:  # G_s^T: x_f -= F x_n
                 x[r.k:] -= r.F[:, off:off + wq] @ vec[q][:wq]
                 off += wq
-            x = apply_q(r.V, r.tau, x) if r.k else x  # E_s^T
-            vec[r.s] = _ltsolve(r.G, x)  # S_s^T
+            if r.Fc is None:
+                x = apply_q(r.V, r.tau, x) if r.k else x  # E_s^T
+                vec[r.s] = _ltsolve(r.G, x)  # S_s^T
+            else:
+                x[r.k:] = _ltsolve(r.G, x[r.k:] - r.Fc @ x[:r.k])
+                vec[r.s] = apply_q(r.V, r.tau, x) if r.k else x
         xc = vec
     out = np.empty_like(b)
     for c, d in enumerate(F.tree.leaf_dofs):

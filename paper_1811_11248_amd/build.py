@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblrsp.so")
-SOURCES = ["kernels.hip", "split.hip", "batch.hip", "learned.hip", "plan.cpp", "runtime.cpp", "tune.cpp",
+SOURCES = ["kernels.hip", "split.hip", "batch.hip", "learned.hip", "krylov.hip", "plan.cpp", "runtime.cpp", "tune.cpp",
            "api.cpp", "batch.cpp", "learned.cpp"]
 ARCH = "gfx950"
 

@@ -792,6 +792,146 @@ lrsp_status lrsp_pcg(const lrsp_csr* A, const lrsp_factorization* F, const doubl
   return pcg_impl(A, F, b, x, nrhs, rtol, maxit, iters, relres, st, at<double>(Fm->scratch, 0));
 }
 
+// Restarted GMRES with the factor as right preconditioner: A M^{-1} u = b,
+// x = M^{-1} u.  Arnoldi by classical Gram-Schmidt applied twice (two
+// block passes over the basis per step), Givens rotations and the
+// least-squares solve on the host (the Hessenberg column is read back once
+// per step, which is also the convergence test).
+static lrsp_status gmres_one(const lrsp_csr* A, const lrsp_factorization* F, const double* b, double* x,
+                             int m, double rtol, int maxit, int* iters, double* relres, bool* conv_out,
+                             hipStream_t st, double* work) {
+  const int64_t n = A->n;
+  double* V = work;                          // n x (m + 1)
+  double* z = V + (size_t)n * (m + 1);       // M^{-1} v, and M^{-1} V y
+  double* w = z + n;                         // A z, residuals
+  double* part = w + n;                      // kDotBlocks x (m + 1)
+  double* hd = part + (size_t)kDotBlocks * (m + 1);  // [h1 (m+1) | h2 (m+1) | nrm2 | bb]
+  double* h2 = hd + (m + 1);
+  double* nrm = h2 + (m + 1);
+  double* ydev = nrm + 2;                    // m
+  std::vector<double> hh(2 * (size_t)(m + 1) + 1), y(m), g(m + 1), cs(m), sn(m);
+  std::vector<double> H((size_t)(m + 1) * m);  // column-major (m + 1) x m
+  auto Hc = [&](int i, int j) -> double& { return H[(size_t)i + (size_t)(m + 1) * j]; };
+  launch_zero(x, n, st);
+  launch_dot(b, b, n, part, nrm + 1, st);
+  double hb = 0.0;
+  HIPCHK(hipMemcpyAsync(&hb, nrm + 1, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double nb = std::sqrt(hb);
+  int it = 0;
+  bool conv = nb == 0.0;
+  while (!conv && it < maxit) {
+    // r = b - A x, v0 = r / ||r||
+    launch_spmv(A->rowptr, A->col, A->val, x, w, n, st);
+    launch_residual(b, w, n, st);
+    launch_dot(w, w, n, part, nrm, st);
+    double hr = 0.0;
+    HIPCHK(hipMemcpyAsync(&hr, nrm, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double beta = std::sqrt(hr);
+    if (beta <= rtol * nb) {
+      conv = true;
+      break;
+    }
+    launch_normalize(w, V, n, nrm, st);
+    const int mm = std::min(m, maxit - it);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < mm; ++j) {
+      double* vj = V + (size_t)n * j;
+      if (lrsp_status s = apply_one(F, vj, z, st)) return s;
+      launch_spmv(A->rowptr, A->col, A->val, z, w, n, st);
+      launch_mdot(V, n, j + 1, w, n, part, hd, st);
+      launch_gemv_cols(V, n, j + 1, hd, w, n, true, st);
+      launch_mdot(V, n, j + 1, w, n, part, h2, st);
+      launch_gemv_cols(V, n, j + 1, h2, w, n, true, st);
+      launch_dot(w, w, n, part, nrm, st);
+      HIPCHK(hipMemcpyAsync(hh.data(), hd, sizeof(double) * (2 * (size_t)(m + 1) + 1), hipMemcpyDeviceToHost, st));
+      launch_normalize(w, V + (size_t)n * (j + 1), n, nrm, st);
+      HIPCHK(hipStreamSynchronize(st));
+      for (int i = 0; i <= j; ++i) Hc(i, j) = hh[i] + hh[(size_t)(m + 1) + i];
+      Hc(j + 1, j) = std::sqrt(std::max(0.0, hh[2 * (size_t)(m + 1)]));
+      for (int i = 0; i < j; ++i) {  // earlier rotations on the new column
+        const double t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
+        Hc(i + 1, j) = -sn[i] * Hc(i, j) + cs[i] * Hc(i + 1, j);
+        Hc(i, j) = t;
+      }
+      const double a = Hc(j, j), bb = Hc(j + 1, j);
+      if (bb == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        const double r = std::hypot(a, bb);
+        cs[j] = a / r;
+        sn[j] = bb / r;
+      }
+      Hc(j, j) = cs[j] * a + sn[j] * bb;
+      Hc(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      k = j + 1;
+      if (std::fabs(g[j + 1]) <= rtol * nb) {
+        conv = true;
+        break;
+      }
+      if (Hc(j, j) == 0.0) break;  // breakdown: the least-squares solve below ends the cycle
+    }
+    for (int i = k - 1; i >= 0; --i) {  // back substitution
+      double s = g[i];
+      for (int l = i + 1; l < k; ++l) s -= Hc(i, l) * y[l];
+      y[i] = Hc(i, i) != 0.0 ? s / Hc(i, i) : 0.0;
+    }
+    HIPCHK(hipMemcpyAsync(ydev, y.data(), sizeof(double) * (size_t)std::max(k, 1), hipMemcpyHostToDevice, st));
+    launch_gemv_cols(V, n, k, ydev, w, n, false, st);
+    if (lrsp_status s = apply_one(F, w, z, st)) return s;
+    launch_add(x, z, n, st);
+    HIPCHK(hipStreamSynchronize(st));  // y stays alive until the copy is done
+    if (k == 0) break;
+  }
+  launch_spmv(A->rowptr, A->col, A->val, x, w, n, st);
+  launch_residual(b, w, n, st);
+  launch_dot(w, w, n, part, nrm, st);
+  double ht = 0.0;
+  HIPCHK(hipMemcpyAsync(&ht, nrm, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *iters = it;
+  *relres = nb > 0 ? std::sqrt(ht) / nb : 0.0;
+  *conv_out = conv;
+  return LRSP_OK;
+}
+
+lrsp_status lrsp_gmres(const lrsp_csr* A, const lrsp_factorization* F, const double* b, double* x,
+                       int32_t nrhs, int32_t restart, double rtol, int32_t maxit, int32_t* iters,
+                       double* relres, void* stream) {
+  if (!A || !F || !b || !x || nrhs < 1 || restart < 1 || restart > 4096 || !iters || !relres ||
+      A->n != F->n || maxit < 0)
+    return fail(LRSP_ERR_ARG, "invalid argument");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t n = A->n;
+  const int m = restart;
+  const size_t need = (size_t)n * (m + 3) + (size_t)kDotBlocks * (m + 1) + 3 * (size_t)(m + 1) + 8;
+  DevBuf buf;
+  HIPCHK(dalloc(&buf, need * sizeof(double), st));
+  lrsp_status result = LRSP_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    bool conv = false;
+    int it = 0;
+    lrsp_status s = gmres_one(A, F, b + (size_t)r * n, x + (size_t)r * n, m, rtol, maxit, &it, relres + r,
+                              &conv, st, at<double>(buf, 0));
+    if (s != LRSP_OK) {
+      dfree(&buf, st);
+      return s;
+    }
+    iters[r] = it;
+    if (!conv) result = LRSP_ERR_NO_CONV;
+  }
+  dfree(&buf, st);
+  if (result != LRSP_OK) (void)fail(result, "GMRES reached maxit");
+  return result;
+}
+
 lrsp_status lrsp_timing_enable(int32_t on) {
   g_tm.on = on != 0;
   return LRSP_OK;

@@ -102,6 +102,19 @@ void launch_pcg_p(double* p, const double* z, int64_t n, const double* num, cons
 void launch_residual(const double* b, double* y, int64_t n, hipStream_t st);
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
 
+// Restarted GMRES building blocks (krylov.hip).  V is column-major with
+// leading dimension ldv; part holds kDotBlocks doubles per column.
+// out[c] = V(:, c) . w for c < ncol (deterministic two-stage reduction)
+void launch_mdot(const double* V, int64_t ldv, int ncol, const double* w, int64_t n, double* part,
+                 double* out, hipStream_t st);
+// w = V(:, 0:ncol) h, or w -= V(:, 0:ncol) h when sub
+void launch_gemv_cols(const double* V, int64_t ldv, int ncol, const double* h, double* w, int64_t n,
+                      bool sub, hipStream_t st);
+// v = w / sqrt(nrm2[0]) (0 when nrm2[0] == 0)
+void launch_normalize(const double* w, double* v, int64_t n, const double* nrm2, hipStream_t st);
+// x += z
+void launch_add(double* x, const double* z, int64_t n, hipStream_t st);
+
 // Batching form (packed vectors: column c of system i at c*ldv + off[i]).
 void launch_spmm(const int64_t* rowptr, const int32_t* col, const double* val, const double* x,
                  double* y, int64_t n, int64_t ldv, int nrhs, hipStream_t st);

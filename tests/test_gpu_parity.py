@@ -170,12 +170,19 @@ def test_precision_form_vs_oracle(torch, L, prec, mode):
     """Schur products with fp32 or bf16 inputs and fp32 accumulation, on
     clusters of the precision workload's shape (m = 160), against the oracle
     computing the same form.  Both sides round F identically (fp64 -> fp32
-    -> bf16, nearest even); they differ only in the order of the fp32
-    accumulation, a perturbation of the same kind and size as the effect of
-    fp32 arithmetic in the product itself.  The bar is therefore four times
-    that effect as the oracle measures it (its fp32 form against its fp64
-    form), and never tighter than the fp64 bar.  The error of the form
-    against the fp64 oracle is printed."""
+    -> bf16, nearest even); the form leaves the order (and on the matrix
+    cores the internal rounding) of the fp32 accumulation open, and the
+    coarse-level blocks of this anisotropic operator are small differences
+    of large Schur sums, so their pivots move by more than their distance to
+    the threshold under such perturbations (in the oracle a random relative
+    1e-6 on the Schur products already changes a level-2 rank, while the
+    level-0 ranks hold up to 1e-5).  What the form determines is compared
+    exactly: the level-0 ranks; every other rank is compared when all levels
+    below agree, and M^{-1} b element by element while all ranks agree (bar:
+    four times the oracle's own fp32 effect, never tighter than the fp64 bar).
+    What it does not determine must still be valid: M^{-1} b within four times
+    the oracle's same-form error of the fp64 oracle, and PCG within one
+    iteration of the oracle's same-form PCG."""
     name = "vector_m160"
     pr, Fo64 = _oracle(name)
     Fo32 = _oracle_prec(name, "f32")
@@ -185,9 +192,16 @@ def test_precision_form_vs_oracle(torch, L, prec, mode):
     leaf, tol = CASES[name][1], CASES[name][2]
     F = L.Factor(A, L.Tree(pr.grid, leaf), tol, gemm_prec=prec, exec_mode=mode)
     assert set(Fo64.levels[0].sizes) == {160}
-    assert F.info()["nlevels"] == len(Fop.levels)
+    same = F.info()["nlevels"] == len(Fop.levels)
+    assert F.level(0)["ranks"].tolist() == list(Fop.levels[0].ranks), "level-0 ranks"
     for li, lv in enumerate(Fop.levels):
-        assert F.level(li)["ranks"].tolist() == list(lv.ranks), f"ranks level {li}"
+        if not same:
+            break
+        got = F.level(li)["ranks"].tolist()
+        if got != list(lv.ranks):
+            diff = [(i, g, o) for i, (g, o) in enumerate(zip(got, lv.ranks)) if g != o]
+            _say(f"  level {li}: ranks differ from the oracle's {prec} form at (cluster, gpu, oracle) {diff}")
+            same = False
     for seed in (0, 1):
         b = rhs(pr.n, seed)
         xo64 = oracle.solve(Fo64, b)
@@ -201,9 +215,11 @@ def test_precision_form_vs_oracle(torch, L, prec, mode):
         e64 = np.linalg.norm(x - xo64) / np.linalg.norm(xo64)
         eo64 = np.linalg.norm(xop - xo64) / np.linalg.norm(xo64)
         _say(f"  seed {seed}: vs oracle-{prec} {err:.3e} (element-wise {erri:.3e}), bar {max(APPLY_TOL, 4 * e32):.3e}; "
-             f"vs fp64 oracle: gpu {e64:.3e}, oracle-{prec} {eo64:.3e}")
-        assert err <= max(APPLY_TOL, 4.0 * e32)
-        assert erri <= max(APPLY_TOL, 4.0 * e32i)
+             f"vs fp64 oracle: gpu {e64:.3e}, oracle-{prec} {eo64:.3e}; ranks all equal: {same}")
+        if same:
+            assert err <= max(APPLY_TOL, 4.0 * e32)
+            assert erri <= max(APPLY_TOL, 4.0 * e32i)
+        assert e64 <= 4.0 * max(eo64, e32) + APPLY_TOL
     b = rhs(pr.n, 0)
     As = pr.scipy()
     _, ito, _, ok = oracle.pcg(lambda v: As @ v, b, lambda r: oracle.solve(Fop, r), 1e-8)
@@ -211,6 +227,25 @@ def test_precision_form_vs_oracle(torch, L, prec, mode):
     _, it, rr = L.pcg(A, F, torch.from_numpy(b).cuda(), rtol=1e-8)
     _say(f"  pcg iters gpu {it[0]} oracle-{prec} {ito}; relres {rr[0]:.2e}")
     assert abs(int(it[0]) - ito) <= 1 and rr[0] <= 1e-8
+
+
+def test_factor_is_deterministic(torch, L):
+    """Two factorizations of one matrix on fresh trees give the same bits in
+    every schedule and precision (no dependence on timing between
+    workgroups)."""
+    pr, _ = _oracle("vector_m160")
+    A = L.DeviceMatrix.from_problem(pr)
+    b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+    for mode in ("auto", "level", "colour"):
+        for prec in ("f64", "bf16"):
+            xs, ks = [], []
+            for rep in range(2):
+                F = L.Factor(A, L.Tree(pr.grid, 256), 1e-2, gemm_prec=prec, exec_mode=mode)
+                xs.append(L.apply(F, b).clone())
+                ks.append([F.level(li)["ranks"].tolist() for li in range(F.info()["nlevels"])])
+                del F
+            _say(f"[determinism {mode} {prec}] same ranks {ks[0] == ks[1]}, same bits {torch.equal(xs[0], xs[1])}")
+            assert ks[0] == ks[1] and torch.equal(xs[0], xs[1])
 
 
 def test_precision_workload_full_size(torch, L):
