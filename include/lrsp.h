@@ -187,6 +187,22 @@ lrsp_status lrsp_gmres(const lrsp_csr* A, const lrsp_factorization* F, const dou
                        int32_t nrhs, int32_t restart, double rtol, int32_t maxit, int32_t* iters,
                        double* relres, void* stream);
 
+/* lrsp_pcg without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the same iteration, results and errors as lrsp_pcg, with its
+ * work vectors (4 n + 528 doubles) in a static device array of the library
+ * instead of memory held by F.  Limit: n <= LRSP_PCG_NOALLOC_MAX_N, else
+ * ERR_ARG and nothing is launched.  The array is one per GPU, is held from
+ * the loading of the library until the process ends, and keeps what the last
+ * call left in it (every call initialises what it reads); calls that overlap
+ * on one GPU (other threads, other streams) race on it and must not be made.
+ * The preconditioner application inside allocates nothing either: it uses
+ * the level vectors that F owns. */
+#define LRSP_PCG_NOALLOC_MAX_N 1048576
+lrsp_status lrsp_pcg_noalloc(const lrsp_csr* A, const lrsp_factorization* F, const double* b,
+                             double* x, int32_t nrhs, double rtol, int32_t maxit, int32_t* iters,
+                             double* relres, void* stream);
+
 /* ---- introspection -------------------------------------------------------*/
 typedef struct {
   int32_t nlevels;       /* levels eliminated before the dense top */

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -790,6 +791,46 @@ lrsp_status lrsp_pcg(const lrsp_csr* A, const lrsp_factorization* F, const doubl
     Fm->scratch_n = need;
   }
   return pcg_impl(A, F, b, x, nrhs, rtol, maxit, iters, relres, st, at<double>(Fm->scratch, 0));
+}
+
+// Work vectors of lrsp_pcg_noalloc: one array per GPU, resident from the
+// loading of the library until the process ends (33.6 MB).
+static __device__ __align__(256) double scratch[4 * (size_t)LRSP_PCG_NOALLOC_MAX_N + kDotBlocks + 16];
+
+// Device address of `scratch` on each GPU, looked up once per device with
+// that device current (the host-side name of the array is not a device
+// address and must not be handed to kernels or copies).
+static double* scratch_ptr(hipError_t* err) {
+  static std::mutex mu;
+  static std::unordered_map<int, double*> ptrs;
+  int dev = -1;
+  if ((*err = hipGetDevice(&dev)) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = ptrs.find(dev);
+  if (it != ptrs.end()) return it->second;
+  void* p = nullptr;
+  if ((*err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess || !p) {
+    if (*err == hipSuccess) *err = hipErrorInvalidSymbol;
+    return nullptr;
+  }
+  ptrs[dev] = static_cast<double*>(p);
+  return static_cast<double*>(p);
+}
+
+lrsp_status lrsp_pcg_noalloc(const lrsp_csr* A, const lrsp_factorization* F, const double* b, double* x,
+                             int32_t nrhs, double rtol, int32_t maxit, int32_t* iters, double* relres,
+                             void* stream) {
+  if (!A || !F || !b || !x || nrhs < 1 || !iters || !relres || maxit < 0)
+    return fail(LRSP_ERR_ARG, "invalid argument");
+  if (A->n > LRSP_PCG_NOALLOC_MAX_N)
+    return fail(LRSP_ERR_ARG, "lrsp_pcg_noalloc: n = " + std::to_string(A->n) +
+                                  " exceeds the static work area (n <= " +
+                                  std::to_string(LRSP_PCG_NOALLOC_MAX_N) + "); use lrsp_pcg");
+  if (A->n != F->n) return fail(LRSP_ERR_ARG, "invalid argument");
+  hipError_t e = hipSuccess;
+  double* work = scratch_ptr(&e);
+  if (!work) return fail(LRSP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  return pcg_impl(A, F, b, x, nrhs, rtol, maxit, iters, relres, reinterpret_cast<hipStream_t>(stream), work);
 }
 
 // Restarted GMRES with the factor as right preconditioner: A M^{-1} u = b,

@@ -92,6 +92,9 @@ SIGNATURES = [
     ("lrsp_pcg", C.c_int, [C.POINTER(CSR), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                            C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                            C.c_void_p]),
+    ("lrsp_pcg_noalloc", C.c_int, [C.POINTER(CSR), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                   C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                   C.c_void_p]),
     ("lrsp_gmres", C.c_int, [C.POINTER(CSR), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                              C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                              C.c_void_p]),
@@ -474,11 +477,16 @@ def apply(F: Factor, b, x=None, stream=None):
     return out if b.dim() == 1 else out.view(nrhs, -1).t()
 
 
-def pcg(A: DeviceMatrix, F: Factor, b, rtol=1e-8, maxit=1000, stream=None, raise_no_conv=True, x=None):
+PCG_NOALLOC_MAX_N = 1048576
+
+
+def pcg(A: DeviceMatrix, F: Factor, b, rtol=1e-8, maxit=1000, stream=None, raise_no_conv=True,
+        noalloc=False, x=None):
     """PCG with the factor; returns (x, iters, relres) with per-column numpy arrays.
 
-    x: optional output tensor of the layout of b (for b of shape [n, nrhs],
-    its transpose made contiguous)."""
+    noalloc: call lrsp_pcg_noalloc (work vectors in the library's static
+    device array, n <= PCG_NOALLOC_MAX_N); x: optional output tensor of the
+    layout of b (for b of shape [n, nrhs], its transpose made contiguous)."""
     import torch
     nrhs = 1 if b.dim() == 1 else b.shape[1]
     bb = b if b.dim() == 1 else b.t().contiguous()
@@ -486,8 +494,9 @@ def pcg(A: DeviceMatrix, F: Factor, b, rtol=1e-8, maxit=1000, stream=None, raise
     it = (C.c_int32 * nrhs)()
     rr = (C.c_double * nrhs)()
     csr = A.csr()
-    st = lib().lrsp_pcg(C.byref(csr), F.handle, bb.data_ptr(), x.data_ptr(), nrhs, float(rtol),
-                        int(maxit), it, rr, _stream(stream))
+    fn = lib().lrsp_pcg_noalloc if noalloc else lib().lrsp_pcg
+    st = fn(C.byref(csr), F.handle, bb.data_ptr(), x.data_ptr(), nrhs, float(rtol),
+            int(maxit), it, rr, _stream(stream))
     if st != ERR_NO_CONV or raise_no_conv:
         _check(st)
     xo = x if b.dim() == 1 else x.view(nrhs, -1).t()
