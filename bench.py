@@ -251,6 +251,64 @@ def run_mixed(args):
     return out
 
 
+def run_scaling(args):
+    """Scaling study (Complexity Analysis, Theorem 1: with ranks bounded per
+    level, factorization and solve cost grow like N): the 16-layer anisotropic
+    slab of the main workload at growing horizontal size, one first
+    factorization (analysis) and one timed factorization + PCG each, with the
+    per-level flops, ranks, factor and sweep times."""
+    import torch
+
+    from paper_1811_11248_amd import lrsp
+    from synth import lognormal_field, rhs, slab_scalar
+
+    out = {"workload": "nh x nh x 16 slab, ratio 1e4 x log-normal (sigma 1, seed 1), leaf 256, tol 1e-2, "
+                       "PCG to 1e-8", "runs": []}
+    for nh in [int(v) for v in args.scaling.split(",")]:
+        pr = slab_scalar(nh, nh, 16, 1e4, lognormal_field((nh, nh, 16), seed=1))
+        A = lrsp.DeviceMatrix.from_problem(pr)
+        tree = lrsp.Tree(pr.grid, 256)
+        b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+        for _ in range(2):  # analysis, then a warm factorization
+            F = lrsp.Factor(A, tree, 1e-2)
+            del F
+        torch.cuda.synchronize()
+        lrsp.timing_reset()
+        lrsp.timing_families([])  # only the per-level events
+        lrsp.timing_enable(True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        F = lrsp.Factor(A, tree, 1e-2)
+        e1.record()
+        _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8)
+        e2.record()
+        torch.cuda.synchronize()
+        lrsp.timing_enable(False)
+        lrsp.timing_families(None)
+        inf = F.info()
+        levels = []
+        for li in range(inf["nlevels"] + 1):
+            st = F.level_stats(li)
+            levels.append(dict(level=li if li < inf["nlevels"] else "top", dofs=st["dofs"],
+                               clusters=st["nclusters"], mean_rank=round(st["coarse"] / max(1, st["nclusters"]), 2),
+                               gflop=round(st["flops"] / 1e9, 4), factor_ms=round(st["factor_ms"], 4),
+                               solve_ms_per_apply=round(st["solve_ms"] / max(1, st["applies"]), 4),
+                               sweep_mb=round(st["sweep_bytes"] / 1e6, 3)))
+        fl = sum(inf["flops"].values())
+        fms, pms = e0.elapsed_time(e1), e1.elapsed_time(e2)
+        rec = dict(nh=nh, n=pr.n, nnz=pr.nnz, levels=inf["nlevels"], factor_ms=round(fms, 4),
+                   pcg_ms=round(pms, 4), iters=int(it[0]), relres=float(rr[0]),
+                   factor_ns_per_dof=round(fms * 1e6 / pr.n, 2), flops_per_dof=round(fl / pr.n, 1),
+                   factor_bytes_per_dof=round(inf["bytes_factor"] / pr.n, 1),
+                   sweep_bytes_per_dof=round(sum(lv["sweep_mb"] for lv in levels) * 1e6 / pr.n, 1),
+                   factor_gflops=round(fl / (fms * 1e-3) / 1e9, 2), per_level=levels)
+        out["runs"].append(rec)
+        log(f"[scaling] {rec}")
+        del F, A, tree
+        torch.cuda.synchronize()
+    return out
+
+
 def run_batch(args):
     """Batching form: all systems of the many-systems workload factored per
     level in one launch (schedules from the autotuner), refactored by graph
@@ -588,6 +646,8 @@ def main():
                     help="workload of the precision form ('none': skip)")
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--no-changed-values", dest="changed_values", action="store_false")
+    ap.add_argument("--scaling", default="32,64,128,256",
+                    help="horizontal sizes of the scaling study ('none': skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (known traffic "
                          "for the counter calibration of the profiles)")
@@ -640,6 +700,8 @@ def main():
                                  for k, v in res["changed_values"].items()}
     if args.mixed_workload != "none":
         out["mixed"] = run_mixed(args)
+    if args.scaling != "none":
+        out["scaling"] = run_scaling(args)
     if args.batch > 0:
         out["batch"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in run_batch(args).items()}
     if args.learned_workload != "none":

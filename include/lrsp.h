@@ -110,6 +110,24 @@ typedef struct {
  * ERR_ARG if leaf_size < nz*ncomp or a split would have to cut a column.
  * The tree is allocated by the library; free it with lrsp_tree_free. */
 lrsp_status lrsp_tree_build(const lrsp_grid* g, int32_t leaf_size, lrsp_tree** out);
+
+/* Extruded partitioning of an unstructured extruded mesh (same section: one
+ * layer partitioned by a graph partitioner, the parts extruded through all
+ * layers).  The layer is the graph of ncols vertical columns: adj_ptr
+ * [ncols+1] and adj (host arrays, CSR, symmetric, without self loops; the
+ * caller keeps ownership).  Column v holds global DoFs
+ * c + ncomp*(z + nz*v).  The column set is bisected L times (L as above) by
+ * level-structure bisection, which uses the graph alone: a breadth-first
+ * search from the smallest column finds the column farthest from it (ties:
+ * smallest id), a breadth-first search from that column (neighbours in
+ * increasing id, restarting at the smallest unvisited column when a
+ * component is exhausted) orders the set, and the first floor(|S|/2)
+ * columns of that order form the left child.  Children left, right; a
+ * leaf's DoFs sorted by global id.  ERR_ARG for leaf_size < nz*ncomp, an
+ * index out of range or a self loop, or a part of one column that would
+ * have to be split. */
+lrsp_status lrsp_tree_build_graph(int64_t ncols, const int64_t* adj_ptr, const int32_t* adj, int32_t nz,
+                                  int32_t ncomp, int32_t leaf_size, lrsp_tree** out);
 lrsp_status lrsp_tree_free(lrsp_tree* t);
 
 /* Read-only view of the level-0 clustering.  The arrays are owned by the
@@ -246,6 +264,31 @@ typedef struct {
   const int32_t* adj;
 } lrsp_level_view;
 lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_level_view* v);
+
+/* Per-level measurements for scaling studies (Complexity Analysis: O(N)
+ * work and memory with ranks bounded per level; the paper's per-level
+ * breakdown of factor and solve time).  level == nlevels is the dense top.
+ * flops: algorithmic flops of the level (the lrsp_info model); sweep_bytes:
+ * factor and vector bytes one sweep of the level reads and writes; dofs,
+ * coarse: unknowns at level start and kept after it; factor_ms: GPU time
+ * from the start of the level's work to the start of the next level's
+ * (top: its Cholesky), and solve_ms: GPU time of the level's forward plus
+ * backward sweeps summed over the `applies` preconditioner applications
+ * (lrsp_apply, and those inside lrsp_pcg / lrsp_gmres) -- both 0 unless
+ * timing (lrsp_timing_enable) was on during lrsp_factor and during the
+ * applications.  Synchronises the device. */
+typedef struct {
+  double flops;
+  double sweep_bytes;
+  double factor_ms;
+  double solve_ms;
+  int64_t applies;
+  int64_t dofs;
+  int64_t coarse;
+  int32_t nclusters;
+  int32_t reserved;
+} lrsp_level_stats;
+lrsp_status lrsp_factor_level_stats(const lrsp_factorization* F, int32_t level, lrsp_level_stats* out);
 
 /* ---- learned ranks ---------------------------------------------------------
  * rank_mode 1: before a level is eliminated, every cluster gets 12 features:

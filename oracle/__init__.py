@@ -27,7 +27,8 @@ the compressed factor as a whole at tol > 0, whose values the paper does not
 print ("parity unpinned" beyond the invariants the tests check: exactness at
 tol = 0, the no-fill strip, Proposition 2 identities and the Corollary).
 """
-from .tree import ClusterTree, build_tree, level0_graph, coarsen_square, d2_colouring  # noqa: F401
+from .tree import (ClusterTree, build_tree, build_tree_graph, level0_graph, coarsen_square,  # noqa: F401
+                   d2_colouring)
 from .cpqr import cpqr, householder_nonneg, apply_qt, apply_q  # noqa: F401
 from .hsolver import (  # noqa: F401
     NotSPDError,

@@ -17,6 +17,9 @@ Reading used here (the paper does not fix the partitioner's rule):
   order and a cluster's DoFs are sorted by global id; the level-``l``
   cluster ``c`` is the parent of level-``(l-1)`` clusters ``2c`` and ``2c+1``.
 
+For unstructured extruded meshes ``build_tree_graph`` partitions the layer
+graph instead (level-structure bisection, the graph alone).
+
 Two clusters are neighbours when their block of the current matrix is
 structurally nonzero (section "Scaled Low-rank Elimination").
 """
@@ -88,6 +91,85 @@ def build_tree(grid, leaf: int) -> ClusterTree:
                 ids.extend(range(base, base + col))
         leaf_dofs.append(np.array(sorted(ids), dtype=np.int64))
     return ClusterTree((nx, ny, nz, nc), leaf, L, boxes, leaf_dofs)
+
+
+def _bfs_order(S: list, adj_ptr, adj, start: int) -> tuple:
+    """Breadth-first order of the vertex set S (ascending list) from start,
+    over the subgraph S induces, neighbours taken in increasing id; when the
+    queue empties the search restarts at the smallest unvisited vertex of S.
+    Returns (order, distance of each vertex of start's component)."""
+    inside = set(S)
+    seen = {start}
+    order = [start]
+    dist = {start: 0}
+    head = 0
+    first_comp = True
+    nxt_unvisited = 0
+    while len(order) < len(S):
+        if head == len(order):
+            # restart at the smallest unvisited vertex (another component)
+            while S[nxt_unvisited] in seen:
+                nxt_unvisited += 1
+            v = S[nxt_unvisited]
+            seen.add(v)
+            order.append(v)
+            first_comp = False
+        u = order[head]
+        head += 1
+        for e in range(adj_ptr[u], adj_ptr[u + 1]):
+            w = int(adj[e])
+            if w in inside and w not in seen:
+                seen.add(w)
+                order.append(w)
+                if first_comp and u in dist:
+                    dist[w] = dist[u] + 1
+    return order, dist
+
+
+def graph_bisect(S: list, adj_ptr, adj) -> tuple:
+    """Level-structure bisection of the vertex set S (ascending list): a
+    breadth-first search from the smallest vertex finds a far vertex r (the
+    largest distance in its component, ties: smallest id); the breadth-first
+    order from r is cut in the middle.  Returns (left, right), each
+    ascending; left holds the first floor(|S|/2) vertices of that order."""
+    _, dist = _bfs_order(S, adj_ptr, adj, S[0])
+    far = max(dist.values())
+    r = min(v for v, d in dist.items() if d == far)
+    order, _ = _bfs_order(S, adj_ptr, adj, r)
+    h = len(S) // 2
+    return sorted(order[:h]), sorted(order[h:])
+
+
+def build_tree_graph(adj_ptr, adj, nz: int, nc: int, leaf: int) -> ClusterTree:
+    """Extruded partitioning of an unstructured extruded mesh (section
+    "Extruded Partitioning for Ice Sheets": partition one layer with a graph
+    partitioner, then extrude every part through all layers).
+
+    The layer is the graph of the ``ncols = len(adj_ptr) - 1`` vertical
+    columns (CSR, symmetric, sorted, no self loops); global DoF id of
+    component c at layer z of column v is ``c + nc (z + nz v)``.  The column
+    set is bisected ``L`` times (``L`` as for the grid tree) by
+    ``graph_bisect``, which uses the graph only (no coordinates); children
+    are ordered left, right and a leaf's DoFs sorted by global id."""
+    adj_ptr = np.asarray(adj_ptr, dtype=np.int64)
+    adj = np.asarray(adj, dtype=np.int64)
+    ncols = len(adj_ptr) - 1
+    col = nz * nc
+    if leaf < col or ncols < 1:
+        raise ValueError("leaf size smaller than one vertical column")
+    n = ncols * col
+    L = num_levels(n, leaf)
+    sets = [list(range(ncols))]
+    for _ in range(L):
+        nxt = []
+        for S in sets:
+            if len(S) < 2:
+                raise ValueError("a part would have to split a single column")
+            left, right = graph_bisect(S, adj_ptr, adj)
+            nxt += [left, right]
+        sets = nxt
+    leaf_dofs = [np.concatenate([np.arange(v * col, (v + 1) * col, dtype=np.int64) for v in S]) for S in sets]
+    return ClusterTree((ncols, 1, nz, nc), leaf, L, [], leaf_dofs)
 
 
 def level0_graph(tree: ClusterTree, rowptr, col) -> list:

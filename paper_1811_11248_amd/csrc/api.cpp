@@ -97,7 +97,27 @@ struct lrsp_factorization {
   hipStream_t stream = nullptr;
   std::weak_ptr<TreeCache> cache;
   uint64_t pattern = 0;  // TreeCache::gen of the pattern factored
+  // Per-level statistics (lrsp_factor_level_stats).  With timing on, an
+  // event at the start of every level, one before and one after the dense
+  // top, and one pair around each level's forward and backward sweep of
+  // every apply.
+  std::vector<double> lev_flops, lev_sweep_bytes;
+  std::vector<hipEvent_t> lev_ev;
+  mutable std::vector<std::vector<std::pair<hipEvent_t, hipEvent_t>>> sweep_ev;
+  mutable int64_t timed_applies = 0;
+  hipEvent_t new_event() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
   ~lrsp_factorization() {
+    for (hipEvent_t e : lev_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& v : sweep_ev)
+      for (auto& pr : v) {
+        if (pr.first) (void)hipEventDestroy(pr.first);
+        if (pr.second) (void)hipEventDestroy(pr.second);
+      }
     std::shared_ptr<TreeCache> c = cache.lock();
     const bool give = c && c->have && c->gen == pattern;
     for (size_t l = 0; l < levels.size(); ++l) {
@@ -149,6 +169,18 @@ lrsp_status lrsp_tree_build(const lrsp_grid* g, int32_t leaf_size, lrsp_tree** o
   auto t = std::make_unique<lrsp_tree>();
   if (build_tree(g->nx, g->ny, g->nz, g->ncomp, leaf_size, &t->t) != 0)
     return fail(LRSP_ERR_ARG, "invalid grid/leaf size (leaf < nz*ncomp or a column would be split)");
+  *out = t.release();
+  return LRSP_OK;
+}
+
+lrsp_status lrsp_tree_build_graph(int64_t ncols, const int64_t* adj_ptr, const int32_t* adj, int32_t nz,
+                                  int32_t ncomp, int32_t leaf_size, lrsp_tree** out) {
+  if (!out || !adj_ptr) return fail(LRSP_ERR_ARG, "null argument");
+  auto t = std::make_unique<lrsp_tree>();
+  if (build_tree_graph(ncols, adj_ptr, adj, nz, ncomp, leaf_size, &t->t) != 0)
+    return fail(LRSP_ERR_ARG,
+                "invalid layer graph or leaf size (leaf < nz*ncomp, an index out of range, a self loop, "
+                "or a part that would have to split a column)");
   *out = t.release();
   return LRSP_OK;
 }
@@ -348,6 +380,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     }
     LevelDev* L = Lp.get();
     vbase += L->nvec;
+    if (g_tm.on) {  // start of this level's GPU work (its assembly included)
+      hipEvent_t e = F->new_event();
+      if (e) (void)hipEventRecord(e, st);
+      F->lev_ev.push_back(e);
+    }
     // assemble the level's matrix
     if (level == 0 && L->vals_off.p) {
       launch_scatter_vals(A->val, at<int64_t>(L->vals_off, 0), A->nnz, at<double>(L->work, 0), st);
@@ -522,6 +559,12 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       g_tm.flops[0] += lvl_flops;
       if (!L->split) g_tm.flops[10] += lvl_flops;
     }
+    F->lev_flops.push_back(lvl_flops);
+    {
+      double by = 0.0;
+      for (double v : L->sweep_bytes) by += v;
+      F->lev_sweep_bytes.push_back(by);
+    }
     // next level
     std::vector<int> nsz(M / 2);
     for (int P = 0; P < M / 2; ++P) nsz[P] = L->k[2 * P] + L->k[2 * P + 1];
@@ -536,6 +579,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     ++level;
   }
   // dense top
+  if (g_tm.on) {
+    hipEvent_t e = F->new_event();
+    if (e) (void)hipEventRecord(e, st);
+    F->lev_ev.push_back(e);
+  }
   const int M = (int)sizes.size();
   int ntop = 0;
   std::vector<int64_t> toff(M + 1, 0);
@@ -579,6 +627,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   launch_zero_i32(at<int32_t>(terr, 0), 4, st);
   launch_top_potrf(Tm, ntop, at<int32_t>(terr, 0), st);
   HIPCHK(hipGetLastError());
+  if (g_tm.on) {
+    hipEvent_t e = F->new_event();
+    if (e) (void)hipEventRecord(e, st);
+    F->lev_ev.push_back(e);
+  }
   HIPCHK(hipMemcpyAsync(herr.data(), terr.p, 16, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   dfree(&terr, st);
@@ -641,9 +694,22 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
   const int nl = (int)F->levels.size();
   double* v0 = V + (nl ? F->levels[0]->vbase : F->top_vbase);
   launch_gather(b, at<int64_t>(F->perm, 0), v0, n, st);
+  const bool lev_t = g_tm.on;
+  if (lev_t) {
+    if (F->sweep_ev.size() < (size_t)nl + 1) F->sweep_ev.resize(nl + 1);
+    ++F->timed_applies;
+  }
+  auto lev_event = [&](int l) -> hipEvent_t {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    (void)hipEventRecord(e, st);
+    (void)l;
+    return e;
+  };
   for (int l = 0; l < nl; ++l) {
     const LevelDev& L = *F->levels[l];
     const LevelPlan& p = L.plan;
+    hipEvent_t fa = lev_t ? lev_event(l) : nullptr;
     {
       TimedLaunch tl(1, st);
       // levels with split clusters run one launch per colour (plus its units)
@@ -658,6 +724,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
       if (g_tm.on)
         for (double by : L.sweep_bytes) g_tm.bytes[1] += by;
     }
+    if (lev_t) F->sweep_ev[l].push_back({fa, lev_event(l)});
     if (l + 1 < nl) {
       const LevelDev& N = *F->levels[l + 1];
       launch_gather(V, at<int64_t>(N.gidx, 0), V + N.vbase, N.nvec, st);
@@ -665,7 +732,11 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
       launch_gather(V, at<int64_t>(F->top_gidx, 0), V + F->top_vbase, F->top_n, st);
     }
   }
-  launch_top_solve(at<double>(F->top, 0), F->top_n, V + F->top_vbase, st);
+  {
+    hipEvent_t ta = lev_t ? lev_event(nl) : nullptr;
+    launch_top_solve(at<double>(F->top, 0), F->top_n, V + F->top_vbase, st);
+    if (lev_t) F->sweep_ev[nl].push_back({ta, lev_event(nl)});
+  }
   for (int l = nl - 1; l >= 0; --l) {
     const LevelDev& L = *F->levels[l];
     const LevelPlan& p = L.plan;
@@ -675,6 +746,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
     } else {
       launch_scatter(V + F->top_vbase, at<int64_t>(F->top_gidx, 0), V, F->top_n, st);
     }
+    hipEvent_t ba = lev_t ? lev_event(l) : nullptr;
     {
       TimedLaunch tl(2, st);
       const bool per_colour = F->exec_mode == 1 || sweep_units(false, L.max_m, L.max_acap) > 0;
@@ -688,6 +760,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
       if (g_tm.on)
         for (double by : L.sweep_bytes) g_tm.bytes[2] += by;
     }
+    if (lev_t) F->sweep_ev[l].push_back({ba, lev_event(l)});
   }
   launch_scatter(v0, at<int64_t>(F->perm, 0), x, n, st);
   HIPCHK(hipGetLastError());
@@ -1015,6 +1088,47 @@ lrsp_status lrsp_factor_rank_features(const lrsp_factorization* F, int32_t level
   if (L.feat.empty()) return fail(LRSP_ERR_ARG, "the factor was not computed with learned ranks");
   if (feat) std::copy(L.feat.begin(), L.feat.end(), feat);
   if (pred) std::copy(L.pred.begin(), L.pred.end(), pred);
+  return LRSP_OK;
+}
+
+lrsp_status lrsp_factor_level_stats(const lrsp_factorization* F, int32_t level, lrsp_level_stats* out) {
+  if (!F || !out || level < 0 || level > (int)F->levels.size())
+    return fail(LRSP_ERR_ARG, "invalid level");
+  const int nl = (int)F->levels.size();
+  lrsp_level_stats r{};
+  if (level < nl) {
+    r.flops = F->lev_flops[level];
+    r.sweep_bytes = F->lev_sweep_bytes[level];
+    const LevelDev& L = *F->levels[level];
+    for (int x = 0; x < L.plan.M; ++x) {
+      r.dofs += L.plan.m[x];
+      r.coarse += L.k[x];
+    }
+    r.nclusters = L.plan.M;
+  } else {
+    r.flops = F->info.flops[5];
+    r.dofs = F->top_n;
+    r.nclusters = (int32_t)F->top_sizes.size();
+  }
+  // factor time: from the start of this level to the start of the next
+  // (the top: its factorization alone)
+  if ((int)F->lev_ev.size() == nl + 2) {
+    HIPCHK(hipEventSynchronize(F->lev_ev[nl + 1]));
+    float ms = 0.f;
+    if (F->lev_ev[level] && F->lev_ev[level + 1] &&
+        hipEventElapsedTime(&ms, F->lev_ev[level], F->lev_ev[level + 1]) == hipSuccess)
+      r.factor_ms = ms;
+  }
+  if ((size_t)level < F->sweep_ev.size()) {
+    for (auto& pr : F->sweep_ev[level]) {
+      float ms = 0.f;
+      if (!pr.first || !pr.second) continue;
+      HIPCHK(hipEventSynchronize(pr.second));
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) r.solve_ms += ms;
+    }
+    r.applies = F->timed_applies;
+  }
+  *out = r;
   return LRSP_OK;
 }
 

@@ -2,6 +2,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <set>
 
 namespace lrsp {
@@ -51,6 +52,110 @@ int build_tree(int nx, int ny, int nz, int nc, int leaf, TreeH* t) {
           t->dof_cluster[base + z] = (int32_t)c;
           t->dof_local[base + z] = loc++;
         }
+      }
+    t->leaf_ptr.push_back((int64_t)t->perm.size());
+  }
+  return 0;
+}
+
+// Breadth-first order of the ascending vertex set S over the subgraph it
+// induces (neighbours in increasing id, restarts at the smallest unvisited
+// vertex of S when the queue empties).  mark[v] == tag marks v in S and is
+// set to tag + 1 once v is visited; dist (optional) receives the distances
+// within start's component (-1 elsewhere).
+static void bfs_order(const std::vector<int32_t>& S, const int64_t* adj_ptr, const int32_t* adj,
+                      int32_t start, std::vector<int32_t>& mark, int32_t tag, std::vector<int32_t>* order,
+                      std::vector<int32_t>* dist) {
+  order->clear();
+  order->reserve(S.size());
+  mark[start] = tag + 1;
+  order->push_back(start);
+  if (dist) (*dist)[start] = 0;
+  size_t head = 0, next_unvisited = 0;
+  bool first_comp = true;
+  while (order->size() < S.size()) {
+    if (head == order->size()) {
+      while (mark[S[next_unvisited]] != tag) ++next_unvisited;
+      const int32_t v = S[next_unvisited];
+      mark[v] = tag + 1;
+      order->push_back(v);
+      first_comp = false;
+    }
+    const int32_t u = (*order)[head++];
+    for (int64_t e = adj_ptr[u]; e < adj_ptr[u + 1]; ++e) {
+      const int32_t w = adj[e];
+      if (mark[w] != tag) continue;
+      mark[w] = tag + 1;
+      order->push_back(w);
+      if (dist && first_comp && (*dist)[u] >= 0) (*dist)[w] = (*dist)[u] + 1;
+    }
+  }
+}
+
+int build_tree_graph(int64_t ncols, const int64_t* adj_ptr, const int32_t* adj, int nz, int nc, int leaf,
+                     TreeH* t) {
+  if (ncols <= 0 || nz <= 0 || nc <= 0 || leaf <= 0 || !adj_ptr || (!adj && adj_ptr[ncols] > 0)) return -1;
+  const int64_t col = (int64_t)nz * nc;
+  if (leaf < col || ncols > INT32_MAX) return -1;
+  for (int64_t v = 0; v < ncols; ++v) {
+    if (adj_ptr[v + 1] < adj_ptr[v]) return -1;
+    for (int64_t e = adj_ptr[v]; e < adj_ptr[v + 1]; ++e)
+      if (adj[e] < 0 || adj[e] >= ncols || adj[e] == v) return -1;
+  }
+  const int64_t n = ncols * col;
+  int L = 0;
+  while (((int64_t)leaf << L) < n) ++L;
+  std::vector<std::vector<int32_t>> sets(1);
+  sets[0].resize(ncols);
+  for (int64_t v = 0; v < ncols; ++v) sets[0][v] = (int32_t)v;
+  // mark[v]: the tag of the set being split (even), +1 once visited
+  std::vector<int32_t> mark(ncols, -2), dist(ncols, -1), order;
+  int32_t tag = 0;
+  for (int d = 0; d < L; ++d) {
+    std::vector<std::vector<int32_t>> nxt;
+    nxt.reserve(sets.size() * 2);
+    for (const auto& S : sets) {
+      if (S.size() < 2) return -1;
+      // search 1 from the smallest vertex: the far vertex of its component
+      tag += 2;
+      for (int32_t v : S) {
+        mark[v] = tag;
+        dist[v] = -1;
+      }
+      bfs_order(S, adj_ptr, adj, S[0], mark, tag, &order, &dist);
+      int32_t far = -1, r = S[0];
+      for (int32_t v : S)  // ascending ids: the first of the largest distance
+        if (dist[v] > far) {
+          far = dist[v];
+          r = v;
+        }
+      // search 2 from it; cut its order in the middle
+      tag += 2;
+      for (int32_t v : S) mark[v] = tag;
+      bfs_order(S, adj_ptr, adj, r, mark, tag, &order, nullptr);
+      const size_t h = S.size() / 2;
+      std::vector<int32_t> left(order.begin(), order.begin() + h), right(order.begin() + h, order.end());
+      std::sort(left.begin(), left.end());
+      std::sort(right.begin(), right.end());
+      nxt.push_back(std::move(left));
+      nxt.push_back(std::move(right));
+    }
+    sets.swap(nxt);
+  }
+  t->nx = (int)ncols; t->ny = 1; t->nz = nz; t->nc = nc; t->leaf = leaf; t->L = L; t->n = n;
+  t->perm.clear();
+  t->perm.reserve(n);
+  t->leaf_ptr.assign(1, 0);
+  t->dof_cluster.assign(n, -1);
+  t->dof_local.assign(n, -1);
+  for (size_t c = 0; c < sets.size(); ++c) {
+    int loc = 0;
+    for (int32_t v : sets[c])
+      for (int64_t z = 0; z < col; ++z) {
+        const int64_t g = col * (int64_t)v + z;
+        t->perm.push_back(g);
+        t->dof_cluster[g] = (int32_t)c;
+        t->dof_local[g] = loc++;
       }
     t->leaf_ptr.push_back((int64_t)t->perm.size());
   }

@@ -29,6 +29,12 @@ struct TreeH {
 
 // Returns 0 on success, -1 on invalid arguments.
 int build_tree(int nx, int ny, int nz, int nc, int leaf, TreeH* t);
+// Extruded partitioning of an unstructured layer: the graph of the ncols
+// vertical columns (CSR, symmetric, no self loops) is bisected L times by
+// level-structure bisection (breadth-first order from a far vertex, cut in
+// the middle); column v holds DoFs v*nz*nc .. (v+1)*nz*nc - 1.
+int build_tree_graph(int64_t ncols, const int64_t* adj_ptr, const int32_t* adj, int nz, int nc, int leaf,
+                     TreeH* t);
 
 inline uint64_t pkey(int p, int q) { return ((uint64_t)(uint32_t)p << 32) | (uint32_t)q; }
 

@@ -66,6 +66,12 @@ class LevelView(C.Structure):
                 ("adj_ptr", C.POINTER(C.c_int32)), ("adj", C.POINTER(C.c_int32))]
 
 
+class LevelStats(C.Structure):
+    _fields_ = [("flops", C.c_double), ("sweep_bytes", C.c_double), ("factor_ms", C.c_double),
+                ("solve_ms", C.c_double), ("applies", C.c_int64), ("dofs", C.c_int64), ("coarse", C.c_int64),
+                ("nclusters", C.c_int32), ("reserved", C.c_int32)]
+
+
 class BatchInfo(C.Structure):
     _fields_ = [("nsys", C.c_int32), ("nlevels", C.c_int32), ("ntot", C.c_int64),
                 ("flops", C.c_double * 6), ("ms_factor", C.c_double), ("ms_analysis", C.c_double),
@@ -83,6 +89,8 @@ class Timing(C.Structure):
 # (name, restype, argtypes) of every symbol declared in include/lrsp.h
 SIGNATURES = [
     ("lrsp_tree_build", C.c_int, [C.POINTER(Grid), C.c_int32, C.POINTER(C.c_void_p)]),
+    ("lrsp_tree_build_graph", C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_void_p)]),
     ("lrsp_tree_free", C.c_int, [C.c_void_p]),
     ("lrsp_tree_export", C.c_int, [C.c_void_p, C.POINTER(TreeView)]),
     ("lrsp_factor", C.c_int, [C.POINTER(CSR), C.c_void_p, C.c_double, C.POINTER(Opts), C.c_void_p,
@@ -100,6 +108,7 @@ SIGNATURES = [
                              C.c_void_p]),
     ("lrsp_factor_info", C.c_int, [C.c_void_p, C.POINTER(Info)]),
     ("lrsp_factor_level", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(LevelView)]),
+    ("lrsp_factor_level_stats", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(LevelStats)]),
     ("lrsp_factor_batched", C.c_int, [C.c_int32, C.POINTER(CSR), C.POINTER(C.c_void_p), C.c_double,
                                       C.POINTER(Opts), C.c_void_p, C.POINTER(C.c_void_p),
                                       C.POINTER(C.c_int32)]),
@@ -179,6 +188,20 @@ class Tree:
         self.handle = h
         self.grid = tuple(grid)
         self.leaf = leaf
+
+    @classmethod
+    def from_graph(cls, adj_ptr, adj, nz: int, ncomp: int, leaf: int):
+        """Extruded tree of an unstructured layer (lrsp_tree_build_graph)."""
+        ap = np.ascontiguousarray(adj_ptr, dtype=np.int64)
+        aj = np.ascontiguousarray(adj, dtype=np.int32)
+        h = C.c_void_p()
+        _check(lib().lrsp_tree_build_graph(int(ap.shape[0] - 1), ap.ctypes.data, aj.ctypes.data if aj.size else None,
+                                           int(nz), int(ncomp), int(leaf), C.byref(h)))
+        t = cls.__new__(cls)
+        t.handle = h
+        t.grid = (int(ap.shape[0] - 1), 1, int(nz), int(ncomp))
+        t.leaf = leaf
+        return t
 
     def export(self):
         v = TreeView()
@@ -278,6 +301,13 @@ class Factor:
         v = LevelView()
         _check(lib().lrsp_factor_level(self.handle, int(lev), C.byref(v)))
         return _level_dict(v)
+
+    def level_stats(self, lev: int) -> dict:
+        """Per-level flops, sweep bytes, sizes and (with timing on) GPU times;
+        lev == info()['nlevels'] is the dense top."""
+        r = LevelStats()
+        _check(lib().lrsp_factor_level_stats(self.handle, int(lev), C.byref(r)))
+        return {f: getattr(r, f) for f, _ in LevelStats._fields_ if f != "reserved"}
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -9,6 +9,9 @@ from .problems import (  # noqa: F401
     laplace2d,
     slab_scalar,
     slab_vector,
+    slab_icesheet,
+    layer_mesh,
+    extruded_mesh,
     lognormal_field,
     rhs,
     batch_params,

@@ -195,6 +195,136 @@ def slab_vector(nx: int, ny: int, nz: int, ratio: float, kappa=None,
                    params={"ratio": ratio, "coupling": coupling})
 
 
+def slab_icesheet(nx: int, ny: int, nz: int, ratio: float, kappa=None, shelf_frac: float = 0.5,
+                  beta: float = 1e2, coupling: float = 0.3) -> Problem:
+    """Two-component extruded slab with the ice sheet's boundary types.
+
+    The boundary conditions of the first-order Stokes model in the paper's
+    Ice Sheet Model section: homogeneous Neumann on the top surface and on
+    the lateral (open-ocean) boundary, and a Robin (basal sliding) condition
+    on the bottom whose coefficient is ``beta`` where the ice is grounded
+    (``x < (1 - shelf_frac) nx``) and zero under the floating shelf.  With a
+    floating part the operator is anchored only through the grounded bed, so
+    its diagonal blocks are far more ill-conditioned than with Dirichlet
+    faces.  Interior faces and coupling matrices as in ``slab_vector``; the
+    bottom face term is the series of the half cell (``2 ratio kappa``) and
+    the Robin resistance ``1 / beta``.
+    """
+    if kappa is None:
+        kappa = np.ones((ny, nx, nz))
+    M = coupling_mats(coupling)
+    inner, _ = _faces(nx, ny, nz, kappa, ratio)
+    cell = lambda y, x, z: z + nz * (x + nx * y)  # noqa: E731
+    Y, X, Z = np.meshgrid(np.arange(ny), np.arange(nx), np.arange(nz), indexing="ij")
+    sl = (slice(None), slice(None), 0)
+    grounded = X[sl] < (1.0 - shelf_frac) * nx
+    kb = kappa[sl]
+    tb = np.where(grounded, 1.0 / (1.0 / (2.0 * ratio * kb) + 1.0 / beta), 0.0)
+    bnd = [(cell(Y[sl], X[sl], Z[sl]).ravel(), tb.ravel(), 2)]
+    n = 2 * nx * ny * nz
+    rows, cols, vals = [], [], []
+    for a, b, t, d in inner:
+        for ci in range(2):
+            for cj in range(2):
+                tv = t * M[d][ci, cj]
+                ai, aj = 2 * a + ci, 2 * a + cj
+                bi, bj = 2 * b + ci, 2 * b + cj
+                rows += [ai, bi, ai, bi]
+                cols += [aj, bj, bj, aj]
+                vals += [tv, tv, -tv, -tv]
+    for a, t, d in bnd:
+        for ci in range(2):
+            for cj in range(2):
+                rows.append(2 * a + ci)
+                cols.append(2 * a + cj)
+                vals.append(t * M[d][ci, cj])
+    rp, c, v = _to_csr(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), n)
+    return Problem("slab_icesheet", (nx, ny, nz, 2), rp, c, v,
+                   params={"ratio": ratio, "shelf_frac": shelf_frac, "beta": beta, "coupling": coupling})
+
+
+def layer_mesh(npts: int, seed: int = 0):
+    """Unstructured horizontal layer: ``npts`` random points in an irregular
+    sheet-like region (a disk with a bay cut out), numbered in the order they
+    were drawn, and the edges of their Delaunay triangulation.  Returns
+    ``(xy [npts, 2], adj_ptr, adj)`` with the symmetric, sorted adjacency."""
+    import scipy.spatial
+
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < npts:
+        p = rng.uniform(-1.0, 1.0, size=2)
+        r = math.hypot(p[0], p[1])
+        bay = math.hypot(p[0] - 0.75, p[1] - 0.1) < 0.45
+        if r <= 1.0 and not bay:
+            pts.append(p)
+    xy = np.array(pts)
+    tri = scipy.spatial.Delaunay(xy).simplices
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    e = np.concatenate([e, e[:, ::-1]])
+    g = sp.coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(npts, npts)).tocsr()
+    g.sum_duplicates()
+    g.sort_indices()
+    return xy, g.indptr.astype(np.int64), g.indices.astype(np.int32)
+
+
+def extruded_mesh(npts: int, nz: int, ratio: float, seed: int = 0, beta: float = 1e2,
+                  coupling: float = 0.3) -> Problem:
+    """Two-component operator on an unstructured extruded mesh: the layer of
+    ``layer_mesh`` repeated over ``nz`` layers.  Horizontal couplings along
+    the layer's edges (transmissibility = harmonic mean of a log-normal
+    coefficient, times the horizontal 2x2 coupling matrix), vertical
+    couplings ``ratio`` times that, Neumann on top and sides and a Robin bed
+    with coefficient ``beta`` (grounded everywhere, so the operator is SPD).
+    DoF id ``c + 2 (z + nz v)`` for column v.  The layer's graph is returned
+    in ``params`` (``layer_adj_ptr``, ``layer_adj``) for the extruded tree."""
+    xy, ap, aj = layer_mesh(npts, seed)
+    rng = np.random.default_rng(seed + 1)
+    # smooth log-normal coefficient: a few Fourier modes in (x, y), a linear
+    # trend in z, per-cell noise
+    a = rng.standard_normal((3, 2))
+    zz = np.arange(nz) / max(1, nz - 1)
+    g = (a[0, 0] * np.sin(2.0 * xy[:, 0] + a[0, 1]) + a[1, 0] * np.cos(3.0 * xy[:, 1] + a[1, 1]))[:, None] \
+        + a[2, 0] * zz[None, :] + 0.3 * rng.standard_normal((npts, nz))
+    kappa = np.exp(g)  # [column, layer]
+    Mh = np.array([[1.5, coupling], [coupling, 1.5]])
+    Mz = coupling_mats(coupling)[2]
+    col = lambda v, z: z + nz * v  # noqa: E731
+    rows, cols, vals = [], [], []
+
+    def add(ia, ib, t, M):
+        for ci in range(2):
+            for cj in range(2):
+                tv = t * M[ci, cj]
+                rows.extend([2 * ia + ci, 2 * ib + ci, 2 * ia + ci, 2 * ib + ci])
+                cols.extend([2 * ia + cj, 2 * ib + cj, 2 * ib + cj, 2 * ia + cj])
+                vals.extend([tv, tv, -tv, -tv])
+
+    hm = lambda p, q: 2.0 * p * q / (p + q)  # noqa: E731
+    src = np.repeat(np.arange(npts), np.diff(ap))
+    up = src < aj  # each edge once
+    va, vb = src[up], aj[up].astype(np.int64)
+    for z in range(nz):
+        add(col(va, z), col(vb, z), hm(kappa[va, z], kappa[vb, z]), Mh)
+    for z in range(nz - 1):
+        v = np.arange(npts)
+        add(col(v, z), col(v, z + 1), ratio * hm(kappa[:, z], kappa[:, z + 1]), Mz)
+    tb = 1.0 / (1.0 / (2.0 * ratio * kappa[:, 0]) + 1.0 / beta)
+    cb = col(np.arange(npts), 0)
+    for ci in range(2):
+        for cj in range(2):
+            rows.append(2 * cb + ci)
+            cols.append(2 * cb + cj)
+            vals.append(tb * Mz[ci, cj])
+    n = 2 * npts * nz
+    rows = [np.asarray(r).ravel() for r in rows]
+    cols = [np.asarray(c).ravel() for c in cols]
+    vals = [np.asarray(v, dtype=np.float64).ravel() for v in vals]
+    rp, c, v = _to_csr(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), n)
+    return Problem("extruded_mesh", (npts, 1, nz, 2), rp, c, v,
+                   params={"ratio": ratio, "beta": beta, "layer_adj_ptr": ap, "layer_adj": aj, "xy": xy})
+
+
 def rhs(n: int, seed: int = 0) -> np.ndarray:
     """i.i.d. N(0,1) right-hand side."""
     return np.random.default_rng(seed).standard_normal(n)

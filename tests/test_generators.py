@@ -81,3 +81,36 @@ def test_batch_params_ranges():
         assert 1e2 <= p["ratio"] <= 1e5
     ns = [p["nx"] * p["ny"] * p["nz"] for p in ps]
     assert min(ns) >= 2048 and max(ns) <= 55296
+
+
+def test_icesheet_slab_boundary_types():
+    # homogeneous Neumann on top and lateral faces and a Robin bed that is
+    # zero under the floating shelf: constant fields are in the kernel of
+    # every row except those of grounded bottom cells, whose row sums are the
+    # Robin face term times the vertical coupling matrix
+    from synth import slab_icesheet
+    from synth.problems import coupling_mats
+    nx, ny, nz, ratio, beta = 6, 5, 4, 1e3, 50.0
+    kap = lognormal_field((ny, nx, nz), seed=3)
+    pr = slab_icesheet(nx, ny, nz, ratio, kap, shelf_frac=0.5, beta=beta)
+    A = pr.scipy()
+    assert abs(A - A.T).max() == 0.0
+    Mz = coupling_mats()[2]
+    for comp in range(2):
+        e = np.zeros(pr.n)
+        e[comp::2] = 1.0
+        r = A @ e
+        for y in range(ny):
+            for x in range(nx):
+                for z in range(nz):
+                    cid = z + nz * (x + nx * y)
+                    want = np.zeros(2)
+                    if z == 0 and x < 0.5 * nx:
+                        tb = 1.0 / (1.0 / (2.0 * ratio * kap[y, x, 0]) + 1.0 / beta)
+                        want = tb * Mz[:, comp]
+                    np.testing.assert_allclose(r[2 * cid:2 * cid + 2], want, atol=1e-9 * ratio)
+    # SPD, and far more ill-conditioned than the Dirichlet slab
+    ev = np.linalg.eigvalsh(A.toarray())
+    assert ev.min() > 0
+    evd = np.linalg.eigvalsh(slab_vector(nx, ny, nz, ratio, kap).scipy().toarray())
+    assert ev.max() / ev.min() > 10 * evd.max() / evd.min()

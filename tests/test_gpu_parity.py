@@ -140,6 +140,46 @@ def test_pcg_iterations(torch, L, name):
     assert np.linalg.norm(b - As @ xr) <= 1.01e-8 * np.linalg.norm(b) or rr[0] <= 1e-8
 
 
+_MESH = {}
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_unstructured_extruded_mesh(torch, L, mode):
+    """An unstructured extruded mesh (Delaunay layer of 1,500 columns, 12
+    layers, 2 components, 36,000 DoF) with the graph-partitioned extruded
+    tree: schedule and ranks bit for bit, M^{-1} b to 1e-10 and PCG within one
+    iteration of the oracle's."""
+    from synth import extruded_mesh
+    if "p" not in _MESH:
+        pr = extruded_mesh(1500, 12, 1e3, seed=5)
+        T = oracle.build_tree_graph(pr.params["layer_adj_ptr"], pr.params["layer_adj"], 12, 2, 200)
+        _MESH["p"] = (pr, oracle.factor(pr.rowptr, pr.col, pr.val, T, 1e-2))
+    pr, Fo = _MESH["p"]
+    _say(f"[unstructured mesh / {mode}] n={pr.n}, {len(Fo.levels)} levels, leaves "
+         f"{min(Fo.levels[0].sizes)}..{max(Fo.levels[0].sizes)} DoFs")
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree.from_graph(pr.params["layer_adj_ptr"], pr.params["layer_adj"], 12, 2, 200)
+    F = L.Factor(A, tree, 1e-2, exec_mode=mode)
+    assert F.info()["nlevels"] == len(Fo.levels)
+    for li, lv in enumerate(Fo.levels):
+        g = F.level(li)
+        assert g["sizes"].tolist() == list(lv.sizes), f"sizes level {li}"
+        assert g["graph"] == [list(x) for x in lv.graph], f"graph level {li}"
+        assert g["order"].tolist() == list(lv.order), f"order level {li}"
+        assert g["ranks"].tolist() == list(lv.ranks), f"ranks level {li}"
+    b = rhs(pr.n, 0)
+    xo = oracle.solve(Fo, b)
+    x = L.apply(F, torch.from_numpy(b).cuda()).cpu().numpy()
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    erri = np.max(np.abs(x - xo)) / np.max(np.abs(xo))
+    As = pr.scipy()
+    _, ito, _, ok = oracle.pcg(lambda v: As @ v, b, lambda r: oracle.solve(Fo, r), 1e-8)
+    _, it, rr = L.pcg(A, F, torch.from_numpy(b).cuda(), rtol=1e-8)
+    _say(f"  apply rel err {err:.3e} (element-wise {erri:.3e}); pcg iters gpu {it[0]} oracle {ito}")
+    assert err <= APPLY_TOL and erri <= APPLY_TOL
+    assert ok and abs(int(it[0]) - ito) <= 1 and rr[0] <= 1e-8
+
+
 def test_not_spd_is_reported(torch, L):
     pr = laplace2d(16)
     val = pr.val.copy()
@@ -290,6 +330,43 @@ def test_precision_workload_full_size(torch, L):
     # (fp32) and ~1e-6 (bf16) in the oracle; allow a hundredfold margin
     assert errs["f32"] <= 1e-7
     assert errs["bf16"] <= 1e-4
+
+
+def test_level_stats(torch, L):
+    """Per-level measurements of the scaling study: sizes and kept unknowns
+    equal the oracle's levels, the level flops add up to the factor's, and
+    with timing on every level has a factor time and a sweep time for each
+    application."""
+    pr, Fo = _oracle("slab_aniso")
+    mk, leaf, tol = CASES["slab_aniso"]
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree(pr.grid, leaf)
+    b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+    L.timing_reset()
+    L.timing_families([])
+    L.timing_enable(True)
+    try:
+        F = L.Factor(A, tree, tol)
+        L.apply(F, b)
+        L.apply(F, b)
+    finally:
+        L.timing_enable(False)
+        L.timing_families(None)
+    inf = F.info()
+    nl = inf["nlevels"]
+    assert nl == len(Fo.levels)
+    stats = [F.level_stats(li) for li in range(nl + 1)]
+    _say(f"[level stats] {[(s['dofs'], s['coarse'], round(s['factor_ms'], 3), round(s['solve_ms'], 3)) for s in stats]}")
+    for li, lv in enumerate(Fo.levels):
+        st = stats[li]
+        assert st["dofs"] == sum(lv.sizes) and st["coarse"] == sum(lv.ranks) and st["nclusters"] == len(lv.sizes)
+        assert st["factor_ms"] > 0 and st["solve_ms"] > 0 and st["applies"] == 2 and st["sweep_bytes"] > 0
+    assert stats[nl]["dofs"] == sum(Fo.top_sizes) and stats[nl]["factor_ms"] > 0
+    tot = sum(st["flops"] for st in stats)
+    assert abs(tot - sum(inf["flops"].values())) <= 1e-9 * tot
+    # without timing the times stay zero
+    F2 = L.Factor(A, tree, tol)
+    assert F2.level_stats(0)["factor_ms"] == 0.0 and F2.level_stats(0)["flops"] == stats[0]["flops"]
 
 
 def test_analysis_reuse_gives_identical_factor(torch, L):
