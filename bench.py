@@ -32,6 +32,9 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-1e-8 residual (factor+PCG) & factor GFLOP/s, plain FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
+# the dense top takes over at the first level with at most this many
+# unknowns (Algorithm 1: "small enough"; set by --top-dense)
+TOP_DENSE = 768
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -52,12 +55,12 @@ def run_gpu(args):
     b = torch.from_numpy(rhs(pr.n, 0)).cuda()
     torch.cuda.synchronize()
 
-    def step(prec):
+    def step(prec, top=None, tr=None):
         # one factorization + PCG solve; the factor is released at the end of
         # the step, which hands its level workspaces back to the tree
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
-        F = lrsp.Factor(A, tree, pr.tol, gemm_prec=prec)
+        F = lrsp.Factor(A, tr or tree, pr.tol, gemm_prec=prec, top_dense=TOP_DENSE if top is None else top)
         e1.record()
         _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8, maxit=1000)
         e2.record()
@@ -70,7 +73,7 @@ def run_gpu(args):
     analysis = {}
     # one-time host analysis of the pattern (reported, not part of a step)
     t0 = time.perf_counter()
-    F0 = lrsp.Factor(A, tree, pr.tol)
+    F0 = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE)
     torch.cuda.synchronize()
     analysis_ms = (time.perf_counter() - t0) * 1e3
     analysis_info = F0.info()
@@ -113,6 +116,23 @@ def run_gpu(args):
         factor_bytes=info["bytes_factor"], levels_reused=info["levels_reused"],
         ms_analysis_in_step=info["ms_analysis"])
     log(f"[{prec}] {results[prec]}")
+    if TOP_DENSE > 0:
+        # the same step with the recursion stopping only at a complete level
+        # graph (its own tree, so that each keeps its analysis)
+        tree0 = lrsp.Tree(pr.grid, pr.leaf)
+        for _ in range(max(2, args.warmup)):
+            step(prec, 0, tree0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r0 = [step(prec, 0, tree0) for _ in range(nsteps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        results["complete_graph_stop"] = dict(
+            ms_per_step=(t1 - t0) * 1e3 / nsteps, levels=r0[-1][0]["nlevels"], top_n=r0[-1][0]["top_n"],
+            factor_ms=float(np.median([r[1].elapsed_time(r[2]) for r in r0])),
+            pcg_ms=float(np.median([r[2].elapsed_time(r[3]) for r in r0])), iters=r0[-1][4])
+        log(f"[complete-graph stop] {results['complete_graph_stop']}")
+        del tree0
     if args.changed_values:
         results["changed_values"] = changed_values_steps(args, pr, tree, b)
     results["gmres"] = gmres_solves(pr, A, tree, b)
@@ -129,7 +149,7 @@ def gmres_solves(pr, A, tree, b, reps=3):
 
     from paper_1811_11248_amd import lrsp
 
-    F = lrsp.Factor(A, tree, pr.tol)
+    F = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE)
     ms, its, rrs = [], [], []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -160,7 +180,7 @@ def changed_values_steps(args, pr, tree, b):
     mats = [lrsp.DeviceMatrix.from_problem(pr), lrsp.DeviceMatrix.from_problem(config_variant(args.workload, 7))]
     torch.cuda.synchronize()
     for A in mats:  # warm-up: ranks of both value sets seen once
-        F = lrsp.Factor(A, tree, pr.tol)
+        F = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE)
         lrsp.pcg(A, F, b, rtol=1e-8)
         del F
     torch.cuda.synchronize()
@@ -171,7 +191,7 @@ def changed_values_steps(args, pr, tree, b):
         A = mats[i % 2]
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
-        F = lrsp.Factor(A, tree, pr.tol)
+        F = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE)
         e1.record()
         _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8)
         e2.record()
@@ -209,7 +229,7 @@ def run_mixed(args):
                        f"{pr.n} DoF, leaf {pr.leaf}, tol {pr.tol}, PCG to 1e-8"}
     x64 = None
     t0 = time.perf_counter()
-    F0 = lrsp.Factor(A, tree, pr.tol)
+    F0 = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE)
     torch.cuda.synchronize()
     out["first_factor_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
     out["host_analysis_ms"] = round(F0.info()["ms_analysis"], 2)
@@ -222,7 +242,7 @@ def run_mixed(args):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
             e0.record()
-            F = lrsp.Factor(A, tree, pr.tol, gemm_prec=prec)
+            F = lrsp.Factor(A, tree, pr.tol, gemm_prec=prec, top_dense=TOP_DENSE)
             e1.record()
             _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8, maxit=1000)
             e2.record()
@@ -270,7 +290,7 @@ def run_scaling(args):
         tree = lrsp.Tree(pr.grid, 256)
         b = torch.from_numpy(rhs(pr.n, 0)).cuda()
         for _ in range(2):  # analysis, then a warm factorization
-            F = lrsp.Factor(A, tree, 1e-2)
+            F = lrsp.Factor(A, tree, 1e-2, top_dense=TOP_DENSE)
             del F
         torch.cuda.synchronize()
         lrsp.timing_reset()
@@ -278,7 +298,7 @@ def run_scaling(args):
         lrsp.timing_enable(True)
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
-        F = lrsp.Factor(A, tree, 1e-2)
+        F = lrsp.Factor(A, tree, 1e-2, top_dense=TOP_DENSE)
         e1.record()
         _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8)
         e2.record()
@@ -332,7 +352,7 @@ def run_batch(args):
     out = {"systems": len(probs), "dof": int(sum(p.n for p in probs)), "nrhs": 4}
     for prec in ("f64", "f32"):
         t0 = time.perf_counter()
-        B = lrsp.Batch(mats, trees, 1e-2, gemm_prec=prec, autotune=(prec == "f64"))
+        B = lrsp.Batch(mats, trees, 1e-2, gemm_prec=prec, autotune=(prec == "f64"), top_dense=TOP_DENSE)
         torch.cuda.synchronize()
         first_ms = (time.perf_counter() - t0) * 1e3
         Bt = B.pack(rhs)
@@ -376,7 +396,7 @@ def run_batch(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(len(probs)):
-            F = lrsp.Factor(mats[i], trees[i], 1e-2)
+            F = lrsp.Factor(mats[i], trees[i], 1e-2, top_dense=TOP_DENSE)
             _, it, _ = lrsp.pcg(mats[i], F, torch.from_numpy(rhs[i]).cuda())
             iters.append(it)
             del F
@@ -428,7 +448,7 @@ def run_learned(args):
         tree = lrsp.Tree(pr.grid, pr.leaf)  # fresh tree: nothing reused
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        F = lrsp.Factor(A, tree, pr.tol, **kw)
+        F = lrsp.Factor(A, tree, pr.tol, **kw, top_dense=TOP_DENSE)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8, maxit=1000)
@@ -646,6 +666,9 @@ def main():
                     help="workload of the precision form ('none': skip)")
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--no-changed-values", dest="changed_values", action="store_false")
+    ap.add_argument("--top-dense", type=int, default=768,
+                    help="dense top at the first level with at most this many unknowns (0: only at a "
+                         "complete level graph)")
     ap.add_argument("--scaling", default="32,64,128,256",
                     help="horizontal sizes of the scaling study ('none': skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -658,6 +681,8 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the solver runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
+    global TOP_DENSE
+    TOP_DENSE = args.top_dense
     if args.copy_calibration_mib > 0:
         copy_calibration(args.copy_calibration_mib)
     pr, res, timing = run_gpu(args)
@@ -677,7 +702,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {pr.grid[0]}x{pr.grid[1]}x{pr.grid[2]} slab, "
                                f"{pr.n} DoF, leaf {pr.leaf}, tol {pr.tol}, PCG to 1e-8",
-                   "n": pr.n, "nnz": pr.nnz, "leaf": pr.leaf, "tol": pr.tol},
+                   "n": pr.n, "nnz": pr.nnz, "leaf": pr.leaf, "tol": pr.tol, "top_dense_threshold": TOP_DENSE},
         "factor_ms": round(f64["factor_ms"], 4),
         "pcg_ms": round(f64["pcg_ms"], 4),
         "pcg_iters": f64["iters"],
@@ -692,6 +717,11 @@ def main():
         "factor_bytes": f64["factor_bytes"],
         "roofline_hbm": hbm_rooflines(timing),
     }
+    if "complete_graph_stop" in res:
+        out["complete_graph_stop"] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                      for k, v in res["complete_graph_stop"].items()}
+    out["levels"] = f64["levels"]
+    out["top_n"] = f64["top_n"]
     if "gmres" in res:
         g = res["gmres"]
         out["gmres"] = dict(g, ms=round(g["ms"], 4), time_to_1e12_ms=round(f64["factor_ms"] + g["ms"], 4))

@@ -97,7 +97,12 @@ typedef struct {
                          level now and record the fastest in the autotuner
                          table; 0 = use the table's entry for the level's
                          shape if there is one, else the default schedule */
-  int32_t reserved32;
+  int32_t top_dense_threshold; /* 0: the recursion stops at the first level
+                         whose cluster graph is complete or has one cluster;
+                         T > 0: also at the first level whose unknowns number
+                         at most T (Algorithm 1: "small enough" to factor
+                         directly), which is then factored by the dense top
+                         Cholesky.  0 <= T <= 768 (ERR_ARG otherwise). */
   int64_t reserved[5];
 } lrsp_opts;
 

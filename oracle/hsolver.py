@@ -376,13 +376,18 @@ def _coarsen(blocks, cur, M):
 
 
 def factor(rowptr, col, val, tree: ClusterTree, tol: float, tol_mode: str = "relative",
-           gemm_prec: str = "f64", checks: bool = False, level_hook=None, dc: bool = True) -> Factor:
+           gemm_prec: str = "f64", checks: bool = False, level_hook=None, dc: bool = True,
+           top_dense: int = 0) -> Factor:
     """Algorithm 1 over the cluster tree; returns the factor of ``A``.
 
-    dc=False replaces every scaled low-rank elimination by the step without
-    deferred compression (``lowrank_elimination_nodc``), the scheme the paper
-    compares against.  level_hook(level, blocks, sizes, graph), if given,
-    sees the matrix at the start of every eliminated level (read only)."""
+    The recursion stops at the first level whose cluster graph is complete or
+    has one cluster, and, with ``top_dense`` > 0, also at the first level with
+    at most ``top_dense`` unknowns ("small enough" to factor directly); the
+    rest is one dense Cholesky in cluster order.  dc=False replaces every
+    scaled low-rank elimination by the step without deferred compression
+    (``lowrank_elimination_nodc``), the scheme the paper compares against.
+    level_hook(level, blocks, sizes, graph), if given, sees the matrix at the
+    start of every eliminated level (read only)."""
     blocks, sizes, graph = _level0_blocks(tree, rowptr, col, val)
     flops = dict(potrf=0.0, trsm=0.0, cpqr=0.0, applyq=0.0, schur=0.0, top=0.0)
     levels = []
@@ -390,7 +395,8 @@ def factor(rowptr, col, val, tree: ClusterTree, tol: float, tol_mode: str = "rel
     li = 0
     while True:
         M = len(sizes)
-        if M == 1 or all(len(graph[p]) == M - 1 for p in range(M)):
+        small = top_dense > 0 and sum(sizes) <= top_dense
+        if M == 1 or small or all(len(graph[p]) == M - 1 for p in range(M)):
             D = _dense_active(blocks, sizes)
             Ltop = chol_lower(D, li, -1)
             flops["top"] += D.shape[0] ** 3 / 3.0

@@ -219,7 +219,8 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   lrsp_opts o{};
   if (opts) o = *opts;
   if (o.gemm_prec < 0 || o.gemm_prec > 2 || o.tol_mode < 0 || o.tol_mode > 1 || o.exec_mode < 0 ||
-      o.exec_mode > 3 || o.rank_mode < 0 || o.rank_mode > 1 || o.autotune < 0 || o.autotune > 1)
+      o.exec_mode > 3 || o.rank_mode < 0 || o.rank_mode > 1 || o.autotune < 0 || o.autotune > 1 ||
+      o.top_dense_threshold < 0 || o.top_dense_threshold > kMaxClusterDofs)
     return fail(LRSP_ERR_ARG, "invalid option");
   const bool learned = o.rank_mode == 1;
   if (learned && !o.mlp_weights) return fail(LRSP_ERR_ARG, "rank_mode 1 needs mlp_weights");
@@ -350,6 +351,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   while (true) {
     const int M = (int)sizes.size();
     if (M == 1 || complete_graph(adj)) break;
+    if (o.top_dense_threshold > 0) {  // "small enough": the dense top takes the rest
+      int64_t tot = 0;
+      for (int x : sizes) tot += x;
+      if (tot <= o.top_dense_threshold) break;
+    }
     std::unique_ptr<LevelDev> Lp;
     bool reuse = false;
     if (!learned && (int)cache->levels.size() > level && cache->levels[level] &&

@@ -277,7 +277,8 @@ lrsp_status autotune_level(const BLevel& B, int level, double tol, const lrsp_op
 
 lrsp_status check_opts(const lrsp_opts& o) {
   if (o.gemm_prec < 0 || o.gemm_prec > 2 || o.tol_mode < 0 || o.tol_mode > 1 || o.exec_mode < 0 ||
-      o.exec_mode > 3 || o.autotune < 0 || o.autotune > 1)
+      o.exec_mode > 3 || o.autotune < 0 || o.autotune > 1 || o.top_dense_threshold < 0 ||
+      o.top_dense_threshold > kMaxClusterDofs)
     return fail(LRSP_ERR_ARG, "invalid option");
   if (o.rank_mode != 0) return fail(LRSP_ERR_ARG, "batched factorizations use rank_mode 0");
   return LRSP_OK;
@@ -378,7 +379,11 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
     for (int i = 0; i < nsys; ++i) {
       BSys& S = F->sys[i];
       if (S.stopped) continue;
-      if (S.sizes.size() == 1 || complete_graph(S.adj)) B.stop.push_back(i);
+      int64_t tot = 0;
+      for (int x : S.sizes) tot += x;
+      if (S.sizes.size() == 1 || complete_graph(S.adj) ||
+          (F->o.top_dense_threshold > 0 && tot <= F->o.top_dense_threshold))
+        B.stop.push_back(i);
       else B.sys.push_back(i);
     }
     if (B.sys.empty() && B.stop.empty()) break;

@@ -41,7 +41,7 @@ class CSR(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("tol_mode", C.c_int32), ("gemm_prec", C.c_int32), ("rank_mode", C.c_int32),
                 ("exec_mode", C.c_int32), ("mlp_weights", C.c_void_p),
-                ("autotune", C.c_int32), ("reserved32", C.c_int32), ("reserved", C.c_int64 * 5)]
+                ("autotune", C.c_int32), ("top_dense_threshold", C.c_int32), ("reserved", C.c_int64 * 5)]
 
 
 class TreeView(C.Structure):
@@ -255,12 +255,14 @@ class Factor:
     learned ranks (rank_mode 1)."""
 
     def __init__(self, A: DeviceMatrix, tree: Tree, tol: float, tol_mode="relative",
-                 gemm_prec="f64", exec_mode="auto", stream=None, mlp=None, autotune=False):
+                 gemm_prec="f64", exec_mode="auto", stream=None, mlp=None, autotune=False,
+                 top_dense=0):
         o = Opts()
         o.tol_mode = TOL_MODE[tol_mode]
         o.gemm_prec = PREC[gemm_prec]
         o.exec_mode = EXEC_MODE[exec_mode]
         o.autotune = 1 if autotune else 0
+        o.top_dense_threshold = int(top_dense)
         self._mlp = None
         if mlp is not None:
             w = mlp.detach().cpu().numpy() if hasattr(mlp, "detach") else np.asarray(mlp)
@@ -339,12 +341,13 @@ class Batch:
     """
 
     def __init__(self, mats, trees, tol: float, tol_mode="relative", gemm_prec="f64",
-                 exec_mode="auto", autotune=False, stream=None, raise_not_spd=True):
+                 exec_mode="auto", autotune=False, stream=None, raise_not_spd=True, top_dense=0):
         o = Opts()
         o.tol_mode = TOL_MODE[tol_mode]
         o.gemm_prec = PREC[gemm_prec]
         o.exec_mode = EXEC_MODE[exec_mode]
         o.autotune = 1 if autotune else 0
+        o.top_dense_threshold = int(top_dense)
         self.mats = list(mats)
         self.trees = list(trees)
         n = len(self.mats)

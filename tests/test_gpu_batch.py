@@ -143,6 +143,29 @@ def test_batch_forced_schedules(torch, L, mode):
             assert err <= APPLY_TOL and erri <= APPLY_TOL, f"sys {i} col {c}"
 
 
+def test_batch_top_dense_threshold(torch, L):
+    """The size threshold of the dense top in the batch: every system stops
+    where its own factorization with the same option stops (same bits as
+    the single-system path, one persistent launch per level), and matches
+    the oracle with that threshold."""
+    L.autotune_clear()
+    probs, oracles, mats, trees = _setup(torch, L)
+    thr = 400
+    B = L.Batch(mats, trees, 1e-2, top_dense=thr)
+    bs = _packed_rhs(probs, 1)
+    X = B.apply(B.pack(bs)).cpu().numpy()
+    for i, (pr, leaf) in enumerate(probs):
+        Fo = oracle.factor(pr.rowptr, pr.col, pr.val, oracle.build_tree(pr.grid, leaf), 1e-2, top_dense=thr)
+        assert B.system_levels(i) == len(Fo.levels)
+        assert B.level(i, len(Fo.levels))["sizes"].tolist() == list(Fo.top_sizes)
+        xi = X[B.off[i]:B.off[i + 1], 0]
+        F = L.Factor(mats[i], trees[i], 1e-2, exec_mode="level", top_dense=thr)
+        xs = L.apply(F, torch.from_numpy(bs[i][:, 0].copy()).cuda()).cpu().numpy()
+        assert np.array_equal(xs, xi), f"sys {i}"
+        xo = oracle.solve(Fo, bs[i][:, 0])
+        assert np.linalg.norm(xi - xo) <= APPLY_TOL * np.linalg.norm(xo)
+
+
 def test_batch_pcg_four_rhs(torch, L):
     L.autotune_clear()
     probs, oracles, mats, trees = _setup(torch, L)

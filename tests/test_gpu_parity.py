@@ -191,6 +191,39 @@ def test_not_spd_is_reported(torch, L):
     assert ex.value.status == L.ERR_NOT_SPD
 
 
+@pytest.mark.parametrize("name,thr", [("slab64_full", 768), ("laplace64", 300), ("vector_m160", 500)])
+@pytest.mark.parametrize("mode", MODES)
+def test_top_dense_threshold(torch, L, name, thr, mode):
+    """The recursion also stops at the first level with at most thr unknowns
+    (Algorithm 1's "small enough"): schedule and ranks of the levels still
+    eliminated, the top sizes, M^{-1} b and PCG against the oracle with the
+    same threshold."""
+    mk, leaf, tol = CASES[name]
+    pr, _ = _oracle(name)
+    key = ("top", name, thr)
+    if key not in _ORACLE:
+        _ORACLE[key] = oracle.factor(pr.rowptr, pr.col, pr.val, oracle.build_tree(pr.grid, leaf), tol, top_dense=thr)
+    Fo = _ORACLE[key]
+    A = L.DeviceMatrix.from_problem(pr)
+    F = L.Factor(A, L.Tree(pr.grid, leaf), tol, exec_mode=mode, top_dense=thr)
+    _say(f"[top dense {name} <= {thr} / {mode}] levels {len(Fo.levels)}, top {sum(Fo.top_sizes)}")
+    assert F.info()["nlevels"] == len(Fo.levels) and F.info()["top_n"] == sum(Fo.top_sizes)
+    for li, lv in enumerate(Fo.levels):
+        g = F.level(li)
+        assert g["order"].tolist() == list(lv.order) and g["ranks"].tolist() == list(lv.ranks), f"level {li}"
+    b = rhs(pr.n, 0)
+    xo = oracle.solve(Fo, b)
+    x = L.apply(F, torch.from_numpy(b).cuda()).cpu().numpy()
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    erri = np.max(np.abs(x - xo)) / np.max(np.abs(xo))
+    _say(f"  apply rel err {err:.3e} (element-wise {erri:.3e})")
+    assert err <= APPLY_TOL and erri <= APPLY_TOL
+    As = pr.scipy()
+    _, ito, _, ok = oracle.pcg(lambda v: As @ v, b, lambda r: oracle.solve(Fo, r), 1e-8)
+    _, it, rr = L.pcg(A, F, torch.from_numpy(b).cuda(), rtol=1e-8)
+    assert ok and abs(int(it[0]) - ito) <= 1 and rr[0] <= 1e-8
+
+
 _PREC = {}
 
 

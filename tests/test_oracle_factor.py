@@ -94,3 +94,23 @@ def test_pcg_textbook_cases():
     scipy.sparse.linalg.cg(A, bb, rtol=1e-8, maxiter=1000,
                            callback=lambda xk: count.__setitem__(0, count[0] + 1))
     assert ok and abs(it - count[0]) <= 1
+
+
+def test_top_dense_threshold():
+    # "small enough" as a size: the recursion stops at the first level with at
+    # most top_dense unknowns; that remainder is factored exactly, so with a
+    # threshold covering everything the factor is plain Cholesky (a dense
+    # solve at any tol), and a smaller threshold only cuts levels off the end
+    pr = slab_scalar(8, 8, 4, 1e3, lognormal_field((8, 8, 4), seed=3))
+    T = build_tree(pr.grid, 16)
+    b = rhs(pr.n, 1)
+    xe = np.linalg.solve(pr.scipy().toarray(), b)
+    F = factor(pr.rowptr, pr.col, pr.val, T, 0.5, top_dense=pr.n)
+    assert len(F.levels) == 0 and F.top_sizes == [16] * 16
+    assert np.linalg.norm(solve(F, b) - xe) <= 1e-10 * np.linalg.norm(xe)
+    F0 = factor(pr.rowptr, pr.col, pr.val, T, 1e-1)
+    sizes = [sum(lv.sizes) for lv in F0.levels]
+    thr = sizes[1]  # the unknowns at the start of level 1
+    F1 = factor(pr.rowptr, pr.col, pr.val, T, 1e-1, top_dense=thr)
+    assert len(F1.levels) == 1 and sum(F1.top_sizes) == thr
+    assert F1.levels[0].ranks == F0.levels[0].ranks
