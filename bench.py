@@ -34,7 +34,7 @@ METRIC = "time-to-1e-8 residual (factor+PCG) & factor GFLOP/s, plain FP64 vs mix
 HBM_PEAK_GBS = 8000.0
 # the dense top takes over at the first level with at most this many
 # unknowns (Algorithm 1: "small enough"; set by --top-dense)
-TOP_DENSE = 768
+TOP_DENSE = 512
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -666,7 +666,7 @@ def main():
                     help="workload of the precision form ('none': skip)")
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--no-changed-values", dest="changed_values", action="store_false")
-    ap.add_argument("--top-dense", type=int, default=768,
+    ap.add_argument("--top-dense", type=int, default=512,
                     help="dense top at the first level with at most this many unknowns (0: only at a "
                          "complete level graph)")
     ap.add_argument("--scaling", default="32,64,128,256",

@@ -631,7 +631,8 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   DevBuf terr;
   HIPCHK(dalloc(&terr, 16, st));
   launch_zero_i32(at<int32_t>(terr, 0), 4, st);
-  launch_top_potrf(Tm, ntop, at<int32_t>(terr, 0), st);
+  if (ntop >= 64 && ntop <= kSplitMaxDofs) launch_top_potrf_wg(Tm, ntop, at<int32_t>(terr, 0), st);
+  else launch_top_potrf(Tm, ntop, at<int32_t>(terr, 0), st);
   HIPCHK(hipGetLastError());
   if (g_tm.on) {
     hipEvent_t e = F->new_event();

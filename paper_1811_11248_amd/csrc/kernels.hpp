@@ -77,6 +77,9 @@ hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* c
                               hipStream_t st, int grid_cap = 0, GridBar* bar = nullptr, int64_t vlo = 0,
                               int64_t vn = 0);
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st);
+// Dense top by the blocked MFMA Cholesky of the split kernels (one
+// workgroup of 512 threads, n <= kSplitMaxDofs).
+void launch_top_potrf_wg(double* A, int n, int32_t* err, hipStream_t st);
 // Dense tops of a batch, one workgroup per system (n <= kMaxClusterDofs).
 void launch_top_potrf_batched(const TopD* tops, int ntops, int max_n, hipStream_t st);
 void launch_top_solve_batched(const TopD* tops, int ntops, int max_n, double* vec, hipStream_t st);

@@ -276,6 +276,29 @@ __global__ void __launch_bounds__(512) potrf_kernel(const ItemD* __restrict__ it
   if (sbad && threadIdx.x == 0) item_error(it, ls.err, level, kErrNotSPD);
 }
 
+// Dense top of the factorization (n <= kSplitMaxDofs): the same blocked
+// Cholesky by one workgroup of 512 threads, the trailing updates on MFMA.
+__global__ void __launch_bounds__(512) top_potrf_wg_kernel(double* A, int n, int32_t* err) {
+  extern __shared__ double lds[];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  potrf_wg<512>(A, n, n, lds, &sbad);
+  __syncthreads();
+  if (sbad && threadIdx.x == 0) set_error(err, -1, -1, kErrNotSPD);
+}
+
+void launch_top_potrf_wg(double* A, int n, int32_t* err, hipStream_t st) {
+  if (n <= 0) return;
+  static bool lds_set = false;
+  if (!lds_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(top_potrf_wg_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    lds_set = true;
+  }
+  hipLaunchKernelGGL(top_potrf_wg_kernel, dim3(1), dim3(512), (size_t)n * 33 * 8, st, A, n, err);
+}
+
 // ---------------------------------------------------------------------------
 // Cholesky factor G and explicit inverse G^{-1} of the diagonal block of a
 // cluster of at most kInvMaxDofs DoFs by one workgroup of 1024 threads, the
