@@ -2665,7 +2665,9 @@ __global__ void __launch_bounds__(kThreads) top_potrf_batched_kernel(const TopD*
   extern __shared__ double lds[];
   __shared__ int sbad;
   const TopD t = tops[blockIdx.x];
-  if (t.n <= 0) return;
+  // tops of 64..512 unknowns take the blocked MFMA Cholesky (as a single
+  // system's top does, so that each system's factor is the same bits)
+  if (t.n <= 0 || (t.n >= 64 && t.n <= kSplitMaxDofs)) return;
   if (threadIdx.x == 0) sbad = 0;
   __syncthreads();
   chol_solve(t.L, t.n, t.n, nullptr, 0, lds, &sbad);
@@ -2679,6 +2681,7 @@ void launch_top_potrf_batched(const TopD* tops, int ntops, int max_n, hipStream_
   allow_lds(reinterpret_cast<const void*>(top_potrf_batched_kernel), &lds_ok);
   size_t lds = ((size_t)max_n * kNB + kNB * kNB + kNB * 256) * sizeof(double);
   hipLaunchKernelGGL(top_potrf_batched_kernel, dim3(ntops), dim3(kThreads), lds, st, tops);
+  if (max_n >= 64) launch_top_potrf_wg_batched(tops, ntops, std::min(max_n, kSplitMaxDofs), st);
 }
 
 __global__ void __launch_bounds__(kThreads) top_solve_batched_kernel(const TopD* __restrict__ tops,

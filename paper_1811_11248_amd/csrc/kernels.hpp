@@ -80,6 +80,9 @@ void launch_top_solve(const double* L, int n, double* y, hipStream_t st);
 // Dense top by the blocked MFMA Cholesky of the split kernels (one
 // workgroup of 512 threads, n <= kSplitMaxDofs).
 void launch_top_potrf_wg(double* A, int n, int32_t* err, hipStream_t st);
+// The tops of a batch with 64..kSplitMaxDofs unknowns by the same kernel
+// (the others are skipped); max_n: their largest size.
+void launch_top_potrf_wg_batched(const TopD* tops, int ntops, int max_n, hipStream_t st);
 // Dense tops of a batch, one workgroup per system (n <= kMaxClusterDofs).
 void launch_top_potrf_batched(const TopD* tops, int ntops, int max_n, hipStream_t st);
 void launch_top_solve_batched(const TopD* tops, int ntops, int max_n, double* vec, hipStream_t st);

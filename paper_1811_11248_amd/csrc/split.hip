@@ -299,6 +299,31 @@ void launch_top_potrf_wg(double* A, int n, int32_t* err, hipStream_t st) {
   hipLaunchKernelGGL(top_potrf_wg_kernel, dim3(1), dim3(512), (size_t)n * 33 * 8, st, A, n, err);
 }
 
+// The same for the tops of a batch with 64..512 unknowns, one workgroup per
+// top (the others are factored by top_potrf_batched_kernel).
+__global__ void __launch_bounds__(512) top_potrf_wg_batched_kernel(const TopD* __restrict__ tops) {
+  extern __shared__ double lds[];
+  __shared__ int sbad;
+  const TopD t = tops[blockIdx.x];
+  if (t.n < 64 || t.n > kSplitMaxDofs) return;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  potrf_wg<512>(t.L, t.n, t.n, lds, &sbad);
+  __syncthreads();
+  if (sbad && threadIdx.x == 0) atomicOr(t.err, 1 << kErrNotSPD);
+}
+
+void launch_top_potrf_wg_batched(const TopD* tops, int ntops, int max_n, hipStream_t st) {
+  if (ntops <= 0 || max_n < 64) return;
+  static bool lds_set = false;
+  if (!lds_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(top_potrf_wg_batched_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    lds_set = true;
+  }
+  hipLaunchKernelGGL(top_potrf_wg_batched_kernel, dim3(ntops), dim3(512), (size_t)max_n * 33 * 8, st, tops);
+}
+
 // ---------------------------------------------------------------------------
 // Cholesky factor G and explicit inverse G^{-1} of the diagonal block of a
 // cluster of at most kInvMaxDofs DoFs by one workgroup of 1024 threads, the
