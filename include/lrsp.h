@@ -397,6 +397,8 @@ typedef struct {
   int32_t graph_timeouts;   /* graph runs redone eagerly because a grid barrier gave up */
   int32_t sched[16];        /* schedule of levels 0..15 (0 persistent, 1 per colour, 2 split) */
   int32_t grid_cap[16];     /* persistent grid cap of levels 0..15 (0 = full occupancy) */
+  int32_t tile[16];         /* split schedule: column tile of the scaling step of
+                               levels 0..15 (0: 32 columns per workgroup, 1: 16) */
 } lrsp_batch_info;
 lrsp_status lrsp_batch_info_get(const lrsp_batch* F, lrsp_batch_info* info);
 
@@ -406,8 +408,12 @@ lrsp_status lrsp_batch_level(const lrsp_batch* F, int32_t sys, int32_t level, lr
 lrsp_status lrsp_batch_system_levels(const lrsp_batch* F, int32_t sys, int32_t* nlevels);
 
 /* ---- autotuner table -----------------------------------------------------
- * Schedules chosen by timing (opts.autotune = 1), keyed by level shape,
- * shared by all factorizations of the process; saved and loaded as JSON. */
+ * Schedules and tile shapes chosen by timing (opts.autotune = 1): for every
+ * level the batch times one persistent launch (full grid and one workgroup
+ * per CU), one launch per colour, and the split schedule with either column
+ * tile of its scaling step, and keeps the fastest; keyed by level shape,
+ * shared by all factorizations of the process; saved and loaded as JSON
+ * ({"key", "sched", "grid_cap", "tile", "ms"} per entry). */
 lrsp_status lrsp_autotune_save(const char* path);
 lrsp_status lrsp_autotune_load(const char* path);
 lrsp_status lrsp_autotune_clear(void);

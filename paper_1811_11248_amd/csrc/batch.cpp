@@ -223,7 +223,7 @@ lrsp_status eliminate(const BLevel& B, int level, double tol, const lrsp_opts& o
     for (int col = 0; col < B.ncolours; ++col)
       for (int step = 0; step < kSplitSteps; ++step)
         launch_split_step(step, B.d_items + B.cstart[col], B.cstart[col + 1] - B.cstart[col],
-                          B.cdims[col], B.ls, level, tol, o.tol_mode, o.gemm_prec, st);
+                          B.cdims[col], B.ls, level, tol, o.tol_mode, o.gemm_prec, st, c.tile);
   } else {
     TimedLaunch tf(10, st);
     for (int col = 0; col < B.ncolours; ++col)
@@ -243,7 +243,10 @@ lrsp_status autotune_level(const BLevel& B, int level, double tol, const lrsp_op
   const int occ = slre_level_occupancy(B.max_m, B.max_nseg);
   if (occ > 1) cand.push_back({tune::kSchedPersistent, device_cus(), 0.0});
   cand.push_back({tune::kSchedPerColour, 0, 0.0});
-  if (B.max_m >= kSplitMinDofs && B.max_m <= kSplitMaxDofs) cand.push_back({tune::kSchedSplit, 0, 0.0});
+  if (B.max_m >= kSplitMinDofs && B.max_m <= kSplitMaxDofs) {
+    cand.push_back({tune::kSchedSplit, 0, 0.0, kTileWide});
+    if (B.max_m <= 256) cand.push_back({tune::kSchedSplit, 0, 0.0, kTileNarrow});
+  }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -637,6 +640,7 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
   for (size_t l = 0; l < F->lv.size() && l < 16; ++l) {
     inf.sched[l] = F->lv[l].sched.sched;
     inf.grid_cap[l] = F->lv[l].sched.grid_cap;
+    inf.tile[l] = F->lv[l].sched.tile;
   }
   int64_t held = 0;
   for (auto& S : F->sys) {

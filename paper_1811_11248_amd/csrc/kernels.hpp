@@ -45,8 +45,12 @@ enum SplitStep {
   kSplitOffsets = 0, kSplitGather, kSplitPotrf, kSplitTrsm, kSplitCpqr, kSplitApplyq, kSplitSchur,
   kSplitWriteback, kSplitSteps
 };
+// Column tiles of the scaling step (G^{-1} [A_sn | A_sw] on MFMA): 32
+// columns per workgroup (default) or 16 (twice the workgroups); the results
+// are the same bits either way.
+constexpr int kTileWide = 0, kTileNarrow = 1;
 void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims& d, LevelState ls,
-                       int level, double tol, int tol_mode, int prec, hipStream_t st);
+                       int level, double tol, int tol_mode, int prec, hipStream_t st, int tile = kTileWide);
 
 // Dense Cholesky of the top system (lower, in place).
 void launch_top_potrf(double* A, int n, int32_t* err, hipStream_t st);

@@ -628,20 +628,25 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
 constexpr int kTrsmInvLdB = 33;
 constexpr size_t kTrsmInvLds = (size_t)(256 * kTrsmInvLdB + 16 * 32) * sizeof(double);
 
+// NC = 32 or 16 columns per workgroup (the autotuner's tile choice): every
+// column goes through the same MFMA sequence and norm sums either way, so
+// the results do not depend on NC.
+template <int NC>
 __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__ items, LevelState ls,
                                                        int level) {
+  static_assert(NC == 16 || NC == 32, "column tile");
   extern __shared__ double lds[];
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   if (m == 0) return;
   const int a = ls.a[it.s], nb = a + ls.b[it.s];
-  const int c0 = blockIdx.y * 32;
+  const int c0 = blockIdx.y * NC;
   if (c0 >= nb) return;
   if (m > kInvMaxDofs || !it.Gi) {
     if (threadIdx.x == 0) item_error(it, ls.err, level, kErrTooLarge);
     return;
   }
-  const int wc = min(32, nb - c0);
+  const int wc = min(NC, nb - c0);
   const int nt = (m + 15) >> 4;
   const int nr = 16 * nt;
   double* Bs = lds;                          // nr x kTrsmInvLdB
@@ -651,7 +656,7 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
   double* B = it.P + (size_t)m * (m + c0);
   const double* Gi = it.Gi;
   {
-    const int n = nr * 32;
+    const int n = nr * NC;
     for (int e0 = tid; e0 < n; e0 += 512 * 8) {
       double v[8];
 #pragma unroll
@@ -691,7 +696,8 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
         for (int s4 = 0; s4 < 4; ++s4) {
           const double* br = Bs + (16 * (k0 + kk) + 4 * s4 + lr) * kTrsmInvLdB;
           acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk][s4], br[lc], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk][s4], br[16 + lc], acc1, 0, 0, 0);
+          if constexpr (NC == 32)
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk][s4], br[16 + lc], acc1, 0, 0, 0);
         }
       }
     }
@@ -701,9 +707,11 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
       const int r = 16 * i + 4 * v + lr;
       if (r < m) {
         if (lc < wc) B[r + (size_t)m * lc] = acc0[v];
-        if (16 + lc < wc) B[r + (size_t)m * (16 + lc)] = acc1[v];
         s0 += acc0[v] * acc0[v];
-        s1 += acc1[v] * acc1[v];
+        if constexpr (NC == 32) {
+          if (16 + lc < wc) B[r + (size_t)m * (16 + lc)] = acc1[v];
+          s1 += acc1[v] * acc1[v];
+        }
       }
     }
     s0 += __shfl_xor(s0, 16, 64);
@@ -712,7 +720,7 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
     s1 += __shfl_xor(s1, 32, 64);
     if (lr == 0) {
       red[i * 32 + lc] = s0;
-      red[i * 32 + 16 + lc] = s1;
+      if constexpr (NC == 32) red[i * 32 + 16 + lc] = s1;
     }
   }
   lds_barrier();
@@ -1220,7 +1228,7 @@ __global__ void __launch_bounds__(256) writeback_kernel(const ItemD* __restrict_
 
 // ---------------------------------------------------------------------------
 void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims& d, LevelState ls,
-                       int level, double tol, int tol_mode, int prec, hipStream_t st) {
+                       int level, double tol, int tol_mode, int prec, hipStream_t st, int tile) {
   if (nitems <= 0) return;
   static bool lds_set = false;
   if (!lds_set) {
@@ -1232,7 +1240,9 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
                               hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(chol_inv_kernel<kInvWaves>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInvLds);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(trsm_inv_kernel),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(trsm_inv_kernel<32>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsmInvLds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(trsm_inv_kernel<16>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsmInvLds);
     lds_set = true;
   }
@@ -1260,8 +1270,11 @@ void launch_split_step(int step, const ItemD* items, int nitems, const SplitDims
       break;
     case kSplitTrsm:
       if (d.max_pcap <= 0) break;
-      if (mm <= kInvMaxDofs)
-        hipLaunchKernelGGL(trsm_inv_kernel, dim3(nitems, (d.max_pcap + 31) / 32), dim3(512), kTrsmInvLds, st,
+      if (mm <= kInvMaxDofs && tile == kTileNarrow)
+        hipLaunchKernelGGL(trsm_inv_kernel<16>, dim3(nitems, (d.max_pcap + 15) / 16), dim3(512), kTrsmInvLds, st,
+                           items, ls, level);
+      else if (mm <= kInvMaxDofs)
+        hipLaunchKernelGGL(trsm_inv_kernel<32>, dim3(nitems, (d.max_pcap + 31) / 32), dim3(512), kTrsmInvLds, st,
                            items, ls, level);
       else if (mm <= 256)
         hipLaunchKernelGGL(trsm_kernel<32>, dim3(nitems, (d.max_pcap + 31) / 32), dim3(256),

@@ -53,7 +53,7 @@ void clear() {
   g_table.clear();
 }
 
-// {"version": 1, "entries": [{"key": "...", "sched": s, "grid_cap": g, "ms": t}, ...]}
+// {"version": 1, "entries": [{"key": "...", "sched": s, "grid_cap": g, "tile": t, "ms": ms}, ...]}
 lrsp_status save(const char* path) {
   if (!path) return rt::fail(LRSP_ERR_ARG, "null path");
   std::lock_guard<std::mutex> g(g_mu);
@@ -62,8 +62,9 @@ lrsp_status save(const char* path) {
   std::fprintf(f, "{\"version\": 1, \"entries\": [");
   bool first = true;
   for (auto& kv : g_table) {
-    std::fprintf(f, "%s\n  {\"key\": \"%s\", \"sched\": %d, \"grid_cap\": %d, \"ms\": %.6g}",
-                 first ? "" : ",", kv.first.c_str(), kv.second.sched, kv.second.grid_cap, kv.second.ms);
+    std::fprintf(f, "%s\n  {\"key\": \"%s\", \"sched\": %d, \"grid_cap\": %d, \"tile\": %d, \"ms\": %.6g}",
+                 first ? "" : ",", kv.first.c_str(), kv.second.sched, kv.second.grid_cap, kv.second.tile,
+                 kv.second.ms);
     first = false;
   }
   std::fprintf(f, "\n]}\n");
@@ -102,8 +103,12 @@ lrsp_status load(const char* path) {
     if (!field("\"sched\"", &s) || !field("\"grid_cap\"", &g) || !field("\"ms\"", &ms))
       return rt::fail(LRSP_ERR_ARG, "malformed autotune entry " + k);
     if (s < 0 || s > 2) return rt::fail(LRSP_ERR_ARG, "invalid schedule in autotune entry " + k);
+    double t = 0;  // optional (files without tiles: the default tile)
+    if (field("\"tile\"", &t) && (t < 0 || t > 1))
+      return rt::fail(LRSP_ERR_ARG, "invalid tile in autotune entry " + k);
     c.sched = (int)s;
     c.grid_cap = (int)g;
+    c.tile = (int)t;
     c.ms = ms;
     parsed[k] = c;
     pos = end;

@@ -7,7 +7,8 @@
 //                     colours); `grid_cap` > 0 limits the resident grid
 //   kSchedPerColour   one launch per colour, one workgroup per cluster
 //   kSchedSplit       per colour, one launch per elimination step with
-//                     several workgroups per cluster (96..512 DoFs)
+//                     several workgroups per cluster (96..512 DoFs); `tile`
+//                     picks the column tile of the scaling step
 // The tuner times the candidates on the level itself and records the
 // fastest under a key made of the level's shape.  The table persists as a
 // small JSON file (lrsp_autotune_save / lrsp_autotune_load).
@@ -26,6 +27,7 @@ struct Choice {
   int sched = kSchedPersistent;
   int grid_cap = 0;
   double ms = 0.0;
+  int tile = 0;  // kSchedSplit: column tile of the scaling step (kTileWide / kTileNarrow)
 };
 
 // Key of a level: batched or not, largest cluster (rounded up to 32),

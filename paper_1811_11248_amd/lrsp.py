@@ -78,7 +78,7 @@ class BatchInfo(C.Structure):
                 ("peak_bytes", C.c_int64), ("graph_factor", C.c_int32), ("graph_pcg", C.c_int32),
                 ("coop_in_graph", C.c_int32), ("refactor_fallbacks", C.c_int32),
                 ("tuned_levels", C.c_int32), ("graph_timeouts", C.c_int32),
-                ("sched", C.c_int32 * 16), ("grid_cap", C.c_int32 * 16)]
+                ("sched", C.c_int32 * 16), ("grid_cap", C.c_int32 * 16), ("tile", C.c_int32 * 16)]
 
 
 class Timing(C.Structure):
@@ -384,7 +384,8 @@ class Batch:
                 "refactor_fallbacks": i.refactor_fallbacks, "tuned_levels": i.tuned_levels,
                 "graph_timeouts": i.graph_timeouts,
                 "sched": [SCHED.get(i.sched[l], "?") for l in range(nl)],
-                "grid_cap": list(i.grid_cap[:nl])}
+                "grid_cap": list(i.grid_cap[:nl]),
+                "tile": [32 if i.tile[l] == 0 else 16 for l in range(nl)]}
 
     def system_levels(self, sys: int) -> int:
         n = C.c_int32()

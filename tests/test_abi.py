@@ -71,6 +71,17 @@ def test_autotune_table_round_trip(tmp_path):
     lrsp.autotune_load(str(q))
     assert lrsp.autotune_entries() == 2
     assert "batch/m256/n1024/c8" in q.read_text()
+    # tiles: optional on load, kept through a save
+    r = tmp_path / "r.json"
+    r.write_text('{"entries": [{"key": "batch/m160/n64/c8", "sched": 2, "grid_cap": 0, "tile": 1, "ms": 2}]}')
+    lrsp.autotune_clear()
+    lrsp.autotune_load(str(r))
+    lrsp.autotune_save(str(q))
+    assert '"tile": 1' in q.read_text()
+    badt = tmp_path / "badt.json"
+    badt.write_text('{"entries": [{"key": "x", "sched": 2, "grid_cap": 0, "tile": 5, "ms": 1}]}')
+    with pytest.raises(lrsp.LrspError):
+        lrsp.autotune_load(str(badt))
     bad = tmp_path / "bad.json"
     bad.write_text('{"entries": [{"key": "x", "sched": 7, "grid_cap": 0, "ms": 1}]}')
     with pytest.raises(lrsp.LrspError):

@@ -278,6 +278,45 @@ def test_autotune_records_and_keeps_parity(torch, L):
     L.autotune_clear()
 
 
+def test_autotune_tile_shapes_keep_bits(torch, L):
+    """The tuner's tile choice for the split schedule (16 or 32 columns per
+    workgroup in the scaling step) changes the launch, not the arithmetic:
+    with every level forced to the split schedule through the table, both
+    tiles give the same bits, and the batch reports the tile it used."""
+    import re
+    L.autotune_clear()
+    probs, oracles, mats, trees = _setup(torch, L)
+    B = L.Batch(mats, trees, 1e-2, autotune=True)
+    inf = B.info()
+    _say(f"[autotune tiles] sched {inf['sched']} tiles {inf['tile']}")
+    Bt = B.pack(_packed_rhs(probs, 1))
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        L.autotune_save(path)
+        text = open(path).read()
+        assert '"tile"' in text
+        X = {}
+        for tile in (1, 0):
+            t2 = re.sub(r'"sched": \d+', '"sched": 2', text)
+            t2 = re.sub(r'"tile": \d+', f'"tile": {tile}', t2)
+            with open(path, "w") as f:
+                f.write(t2)
+            L.autotune_clear()
+            L.autotune_load(path)
+            Bf = L.Batch(mats, trees, 1e-2)  # schedules and tiles from the table
+            fi = Bf.info()
+            assert all(sc == "split" for sc in fi["sched"][:fi["nlevels"]])
+            assert all(t == (16 if tile else 32) for t in fi["tile"][:fi["nlevels"]])
+            X[tile] = Bf.apply(Bt).clone()
+    L.autotune_clear()
+    assert torch.equal(X[0], X[1])
+    Xn = X[1].cpu().numpy()
+    for i, Fo in enumerate(oracles):
+        xo = oracle.solve(Fo, _packed_rhs(probs, 1)[i][:, 0])
+        xi = Xn[B.off[i]:B.off[i + 1]]
+        assert np.linalg.norm(xi - xo) <= APPLY_TOL * np.linalg.norm(xo)
+
+
 def test_not_spd_system_is_reported(torch, L):
     L.autotune_clear()
     probs, oracles, mats, trees = _setup(torch, L)
