@@ -313,7 +313,7 @@ def test_autotune_tile_shapes_keep_bits(torch, L):
     Xn = X[1].cpu().numpy()
     for i, Fo in enumerate(oracles):
         xo = oracle.solve(Fo, _packed_rhs(probs, 1)[i][:, 0])
-        xi = Xn[B.off[i]:B.off[i + 1]]
+        xi = Xn[B.off[i]:B.off[i + 1]].ravel()
         assert np.linalg.norm(xi - xo) <= APPLY_TOL * np.linalg.norm(xo)
 
 
