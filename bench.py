@@ -329,6 +329,58 @@ def run_scaling(args):
     return out
 
 
+def run_dc_sweep(args):
+    """With and without deferred compression (section Deferred-compression
+    Scheme and its table of iteration counts): the ice-sheet analogue (thin
+    two-component slab of 9 layers with a floating shelf over half of the
+    bed, Neumann top and sides, coupling ratio 1e4 x log-normal),
+    clusters of about 128 unknowns, tolerances 1e-1..1e-4; per run the
+    factorization time, GMRES(200) to 1e-12 and PCG to 1e-8 with the factor
+    (iterations and time), the mean coarse rank per level and the factor's
+    size."""
+    import torch
+
+    from paper_1811_11248_amd import lrsp
+    from synth import lognormal_field, rhs, slab_icesheet
+
+    out = {"workload": "slab_icesheet nh x nh x 9, ratio 1e4 x log-normal (seed 1), leaf 128, rhs seed 0",
+           "runs": []}
+    for nh in [int(v) for v in args.dc_sweep.split(",")]:
+        pr = slab_icesheet(nh, nh, 9, 1e4, lognormal_field((nh, nh, 9), seed=1))
+        A = lrsp.DeviceMatrix.from_problem(pr)
+        tree = lrsp.Tree(pr.grid, 128)
+        b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+        for tol in (1e-1, 1e-2, 1e-3, 1e-4):
+            for dc in (True, False):
+                F = lrsp.Factor(A, tree, tol, dc=dc)  # analysis
+                del F
+                torch.cuda.synchronize()
+                e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+                e0.record()
+                F = lrsp.Factor(A, tree, tol, dc=dc)
+                e1.record()
+                _, itg, rrg = lrsp.gmres(A, F, b, rtol=1e-12, restart=200, maxit=1000, raise_no_conv=False)
+                e2.record()
+                _, itp, rrp = lrsp.pcg(A, F, b, rtol=1e-8, raise_no_conv=False)
+                e3.record()
+                torch.cuda.synchronize()
+                inf = F.info()
+                ranks = []
+                for li in range(inf["nlevels"]):
+                    st = F.level_stats(li)
+                    ranks.append(round(st["coarse"] / max(1, st["nclusters"]), 2))
+                rec = dict(nh=nh, n=pr.n, tol=tol, dc=dc, factor_ms=round(e0.elapsed_time(e1), 4),
+                           gmres_iters=int(itg[0]), gmres_relres=float(rrg[0]), gmres_ms=round(e1.elapsed_time(e2), 4),
+                           pcg_iters=int(itp[0]), pcg_relres=float(rrp[0]), pcg_ms=round(e2.elapsed_time(e3), 4),
+                           ranks_mean=ranks, factor_bytes=inf["bytes_factor"])
+                out["runs"].append(rec)
+                log(f"[dc sweep] {rec}")
+                del F
+        del A, tree
+        torch.cuda.synchronize()
+    return out
+
+
 def run_batch(args):
     """Batching form: all systems of the many-systems workload factored per
     level in one launch (schedules from the autotuner), refactored by graph
@@ -687,6 +739,8 @@ def main():
                          "complete level graph)")
     ap.add_argument("--scaling", default="32,64,128,256",
                     help="horizontal sizes of the scaling study ('none': skip)")
+    ap.add_argument("--dc-sweep", default="48,96",
+                    help="horizontal sizes of the sweep with and without deferred compression ('none': skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (known traffic "
                          "for the counter calibration of the profiles)")
@@ -748,6 +802,8 @@ def main():
         out["mixed"] = run_mixed(args)
     if args.scaling != "none":
         out["scaling"] = run_scaling(args)
+    if args.dc_sweep != "none":
+        out["dc_sweep"] = run_dc_sweep(args)
     if args.batch > 0:
         out["batch"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in run_batch(args).items()}
     if args.learned_workload != "none":

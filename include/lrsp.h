@@ -103,7 +103,20 @@ typedef struct {
                          at most T (Algorithm 1: "small enough" to factor
                          directly), which is then factored by the dense top
                          Cholesky.  0 <= T <= 768 (ERR_ARG otherwise). */
-  int64_t reserved[5];
+  int32_t scheme;     /* 0: deferred compression (the scaled low-rank
+                         elimination); 1: without it, the scheme the paper
+                         compares against (section "Deferred-compression
+                         Scheme", Eqs. offdiag and sc_old): the unscaled
+                         far-field block is compressed, the cluster rotated by
+                         U^T on both sides and its fine part eliminated by
+                         Cholesky; the coarse unknowns keep that Schur
+                         complement as their diagonal block.  Scheme 1 runs
+                         one workgroup per cluster (exec_mode 1 or 2; auto
+                         and 3 become 2) with the sweeps one launch per
+                         colour, fp64 or reduced Schur products; not with
+                         rank_mode 1 or the batching form (ERR_ARG). */
+  int32_t reserved32b;
+  int64_t reserved[4];
 } lrsp_opts;
 
 /* ---- cluster tree ------------------------------------------------------

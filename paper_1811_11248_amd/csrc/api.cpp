@@ -80,6 +80,7 @@ struct lrsp_tree {
 struct lrsp_factorization {
   int64_t n = 0;
   int exec_mode = 0;  // 1: the sweeps too run one launch per colour
+  bool nodc = false;  // eliminated without deferred compression (sweeps per colour)
   std::vector<std::unique_ptr<LevelDev>> levels;
   // dense top
   int top_n = 0;
@@ -220,10 +221,12 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   if (opts) o = *opts;
   if (o.gemm_prec < 0 || o.gemm_prec > 2 || o.tol_mode < 0 || o.tol_mode > 1 || o.exec_mode < 0 ||
       o.exec_mode > 3 || o.rank_mode < 0 || o.rank_mode > 1 || o.autotune < 0 || o.autotune > 1 ||
-      o.top_dense_threshold < 0 || o.top_dense_threshold > kMaxClusterDofs)
+      o.top_dense_threshold < 0 || o.top_dense_threshold > kMaxClusterDofs || o.scheme < 0 || o.scheme > 1)
     return fail(LRSP_ERR_ARG, "invalid option");
   const bool learned = o.rank_mode == 1;
   if (learned && !o.mlp_weights) return fail(LRSP_ERR_ARG, "rank_mode 1 needs mlp_weights");
+  const bool nodc = o.scheme == 1;
+  if (nodc && learned) return fail(LRSP_ERR_ARG, "scheme 1 (no deferred compression) with rank_mode 1");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
   // host copy of the pattern
@@ -245,6 +248,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   auto F = std::make_unique<lrsp_factorization>();
   F->n = A->n;
   F->exec_mode = o.exec_mode;
+  F->nodc = nodc;
   F->stream = st;
   double ms_an = 0.0;
   auto tick = [] { return std::chrono::steady_clock::now(); };
@@ -429,8 +433,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     if (!reuse) ms_an += ms_since(ta);
     // eliminate the clusters colour by colour
     const LevelPlan& p = L->plan;
-    const int mode = o.exec_mode == 0 ? 3 : o.exec_mode;
+    // without deferred compression: one workgroup per cluster (the fused
+    // kernels), persistent unless one launch per colour was asked for
+    const int mode = nodc ? (o.exec_mode == 1 ? 1 : 2) : (o.exec_mode == 0 ? 3 : o.exec_mode);
     L->split = mode == 3 && L->max_m >= kSplitMinDofs && L->max_m <= kSplitMaxDofs;
+    L->ls.nodc = nodc ? 1 : 0;
   eliminate_level:
     bool done = false;
     if (L->split) {
@@ -720,7 +727,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
     {
       TimedLaunch tl(1, st);
       // levels with split clusters run one launch per colour (plus its units)
-      const bool per_colour = F->exec_mode == 1 || sweep_units(true, L.max_m, L.max_acap) > 0;
+      const bool per_colour = F->exec_mode == 1 || F->nodc || sweep_units(true, L.max_m, L.max_acap) > 0;
       if (per_colour ||
           launch_sweep_level(true, L.d_items, L.d_cstart, p.ncolours, p.cstart.back(), L.max_items, L.max_m, L.max_acap, L.ls, V,
                              st, 0, nullptr, L.vbase, L.nvec) != hipSuccess) {
@@ -756,7 +763,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
     hipEvent_t ba = lev_t ? lev_event(l) : nullptr;
     {
       TimedLaunch tl(2, st);
-      const bool per_colour = F->exec_mode == 1 || sweep_units(false, L.max_m, L.max_acap) > 0;
+      const bool per_colour = F->exec_mode == 1 || F->nodc || sweep_units(false, L.max_m, L.max_acap) > 0;
       if (per_colour ||
           launch_sweep_level(false, L.d_items, L.d_cstart, p.ncolours, p.cstart.back(), L.max_items, L.max_m, L.max_acap, L.ls, V,
                              st, 0, nullptr, L.vbase, L.nvec) != hipSuccess) {

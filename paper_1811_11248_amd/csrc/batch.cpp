@@ -280,7 +280,7 @@ lrsp_status autotune_level(const BLevel& B, int level, double tol, const lrsp_op
 
 lrsp_status check_opts(const lrsp_opts& o) {
   if (o.gemm_prec < 0 || o.gemm_prec > 2 || o.tol_mode < 0 || o.tol_mode > 1 || o.exec_mode < 0 ||
-      o.exec_mode > 3 || o.autotune < 0 || o.autotune > 1 || o.top_dense_threshold < 0 ||
+      o.exec_mode > 3 || o.autotune < 0 || o.autotune > 1 || o.scheme != 0 || o.top_dense_threshold < 0 ||
       o.top_dense_threshold > kMaxClusterDofs)
     return fail(LRSP_ERR_ARG, "invalid option");
   if (o.rank_mode != 0) return fail(LRSP_ERR_ARG, "batched factorizations use rank_mode 0");

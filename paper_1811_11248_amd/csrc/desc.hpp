@@ -94,7 +94,11 @@ struct LevelState {
   int32_t* err;   // [4]: flag, level, cluster, code (then 4 words of grid barrier)
   int32_t* giok;  // 1: the factorization left G^{-1} in ItemD::Gi (and G^{-T} in GiT);
                   // 2: Gi holds W = U^T G^{-1} (k > 0 reflectors folded in, all
-                  //    m x m entries) and GiT holds W^T
+                  //    m x m entries) and GiT holds W^T;
+                  // 3: eliminated without deferred compression (the panel holds
+                  //    the reflectors of U, the fine factor G_f in rows/columns
+                  //    k.. of the diagonal block, F_c in its columns ..k and F_n)
+  int32_t nodc = 0;  // 1: eliminate without deferred compression (fused kernels)
 };
 
 // dst[r + dld*c] = trans ? src[c + sld*r] : src[r + sld*c], r < rows, c < cols

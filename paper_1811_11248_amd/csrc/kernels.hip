@@ -32,7 +32,18 @@ __device__ __forceinline__ int block_min_int(int v, int* sh) { return group_min_
 // (ld), fused with the triangular solve B <- G^{-1} B of the nb columns B
 // (same ld).  Pivots that are not > 0 raise *bad and are replaced by 1 so
 // that the sweep stays finite.  LDS: m*kNB + kNB*kNB + kNB*256 doubles.
-__device__ __forceinline__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* lds, int* bad) {
+// TWO: the right-hand side is B (nb columns) followed by B2 (nb2 columns),
+// two separate column ranges of the same ld.
+template <bool TWO = false>
+__device__ __forceinline__ void chol_solve(double* A, int ld, int m, double* B, int nb, double* lds, int* bad,
+                                           double* B2 = nullptr, int nb2 = 0) {
+  auto colp = [&](int c) -> double* {
+    if constexpr (TWO) {
+      if (c >= nb) return B2 + (size_t)ld * (c - nb);
+    }
+    return B + (size_t)ld * c;
+  };
+  const int nbt = TWO ? nb + nb2 : nb;
   double* Lp = lds;                // (m) x kNB, row-major
   double* Dg = Lp + (size_t)m * kNB;  // kNB x kNB, row-major
   double* Bb = Dg + kNB * kNB;     // kNB x 256, row-major
@@ -98,12 +109,13 @@ __device__ __forceinline__ void chol_solve(double* A, int ld, int m, double* B, 
     }
     __syncthreads();
     // (c) right-hand block: rows jb..jb+w of B, then the rows below
-    for (int c0 = 0; c0 < nb; c0 += 256) {
+    for (int c0 = 0; c0 < nbt; c0 += 256) {
       const int c = c0 + tid;
-      if (c < nb) {
+      if (c < nbt) {
+        double* Bc = colp(c);
         double x[kNB];
 #pragma unroll
-        for (int u = 0; u < kNB; ++u) x[u] = (u < w) ? B[(size_t)(jb + u) + (size_t)ld * c] : 0.0;
+        for (int u = 0; u < kNB; ++u) x[u] = (u < w) ? Bc[jb + u] : 0.0;
 #pragma unroll
         for (int u = 0; u < kNB; ++u) {
           if (u < w) {
@@ -116,14 +128,14 @@ __device__ __forceinline__ void chol_solve(double* A, int ld, int m, double* B, 
 #pragma unroll
         for (int u = 0; u < kNB; ++u) {
           Bb[u * 256 + tid] = x[u];
-          if (u < w) B[(size_t)(jb + u) + (size_t)ld * c] = x[u];
+          if (u < w) Bc[jb + u] = x[u];
         }
       } else {
 #pragma unroll
         for (int u = 0; u < kNB; ++u) Bb[u * 256 + tid] = 0.0;
       }
       __syncthreads();
-      const int ncol = min(256, nb - c0);
+      const int ncol = min(256, nbt - c0);
       const int nR = (rem + 3) >> 2, nC = (ncol + 3) >> 2;
       for (int idx = tid; idx < nR * nC; idx += kThreads) {
         const int R = idx % nR, C = idx / nR;
@@ -147,9 +159,10 @@ __device__ __forceinline__ void chol_solve(double* A, int ld, int m, double* B, 
         for (int q = 0; q < 4; ++q) {
           const int cc = c0 + 4 * C + q;
           if (4 * C + q < ncol) {
+            double* Bc = colp(cc);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (4 * R + r < rem) B[(size_t)(jb + w + 4 * R + r) + (size_t)ld * cc] -= acc[r][q];
+              if (4 * R + r < rem) Bc[jb + w + 4 * R + r] -= acc[r][q];
           }
         }
       }
@@ -1306,7 +1319,93 @@ __device__ __forceinline__ void slre_tiny(const ItemD& it, LevelState ls, int le
   __syncthreads();
 }
 
-// One scaled low-rank elimination W_s = P_s G_s E_s S_s by one workgroup.
+// Elimination of one cluster without deferred compression (section
+// "Deferred-compression Scheme", Eqs. offdiag and sc_old) on the gathered
+// panel P = [A_ss | A_sn | A_sw] (ld m).  The unscaled far-field block is
+// compressed by the same column-pivoted QR and rank rule as the scaled form,
+// A_sw ~ U_1 V_1^T; A_ss is rotated by U on both sides and A_sn by U^T; the
+// fine part of the rotated diagonal block is factored, X_ff = G_f G_f^T, and
+// F_c = G_f^{-1} X_fc, F_n = G_f^{-1} (U^T A_sn)_f; the coarse unknowns keep
+// D_c = X_cc - F_c^T F_c (its two triangles averaged) and C_cn = (U^T A_sn)_c
+// - F_c^T F_n.  On return the panel holds the reflectors of U in A_sw's
+// columns, G_f in rows and columns k.. of the diagonal block, F_c below D_c
+// in columns ..k, C_cn over F_n in A_sn's columns; returns k.
+__device__ __forceinline__ int slre_nodc_core(const ItemD& it, LevelState ls, int level, double tol, int tol_mode,
+                                              double* lds, int a, int b, double* shd, int* shi, int* sbad) {
+  const int tid = threadIdx.x;
+  const int m = it.m;
+  double* P = it.P;
+  const size_t ld = (size_t)m;
+  const size_t scr = (size_t)m * kNB + kNB * kNB + kNB * 256;
+  // the assembled diagonal block is valid in its lower triangle: mirror it
+  for (int e = tid; e < m * m; e += kThreads) {
+    const int r = e % m, c = e / m;
+    if (r < c) P[(size_t)r + ld * c] = P[(size_t)c + ld * r];
+  }
+  if (tid == 0) *sbad = 0;
+  __syncthreads();
+  double* Wf = P + ld * (m + a);
+  int k = 0;
+  bool over = false;
+  if (b > 0 && m > 0)
+    k = cpqr(Wf, m, m, b, tol, tol_mode, it.kcap, it.piv, it.stepof, it.tau, it.norms, shd, shi, &over);
+  if (over || k > it.kcap) {
+    if (tid == 0) item_error(it, ls.err, level, kErrCapacity);
+    k = min(k, it.kcap);
+  }
+  __syncthreads();
+  if (k > 0) {
+    apply_qt_cols(P, m, m, m + a, Wf, it.piv, it.tau, k, lds, scr);  // U^T [A_ss | A_sn]
+    __syncthreads();
+    for (int e = tid; e < m * m; e += kThreads) {  // (U^T A_ss)^T = A_ss U
+      const int r = e % m, c = e / m;
+      if (r < c) {
+        const double x = P[(size_t)r + ld * c];
+        P[(size_t)r + ld * c] = P[(size_t)c + ld * r];
+        P[(size_t)c + ld * r] = x;
+      }
+    }
+    __syncthreads();
+    apply_qt_cols(P, m, m, m, Wf, it.piv, it.tau, k, lds, scr);  // X = U^T A_ss U
+    __syncthreads();
+  }
+  // G_f, F_n and F_c in one fused factor-and-solve
+  chol_solve<true>(P + k + ld * k, m, m - k, P + k + ld * m, a, lds, sbad, P + k, k);
+  __syncthreads();
+  if (*sbad && tid == 0) item_error(it, ls.err, level, kErrNotSPD);
+  // rows ..k of the columns of X_cc and of (U^T A_sn): minus F_c^T times the
+  // column's rows k.. (F_c, F_n), sixteen rows at a time
+  for (int c = tid; c < k + a; c += kThreads) {
+    double* col = c < k ? P + ld * c : P + ld * (m + c - k);
+    for (int r0 = 0; r0 < k; r0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+      for (int i = k; i < m; ++i) {
+        const double f = col[i];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] += P[(size_t)i + ld * min(r0 + t, k - 1)] * f;
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (r0 + t < k) col[r0 + t] -= acc[t];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += kThreads) {
+    const int r = e % k, c = e / k;
+    if (r > c) {
+      const double v = 0.5 * (P[(size_t)r + ld * c] + P[(size_t)c + ld * r]);
+      P[(size_t)r + ld * c] = v;
+      P[(size_t)c + ld * r] = v;
+    }
+  }
+  __syncthreads();
+  return k;
+}
+
+// One scaled low-rank elimination W_s = P_s G_s E_s S_s by one workgroup
+// (with ls.nodc, the step without deferred compression instead).
 // lds: slre_scratch(m) doubles, then nseg+1 ints.
 __device__ __forceinline__ void slre_item(const ItemD& it, LevelState ls, int level, double tol, int tol_mode,
                           int prec, double* lds, int* soff) {
@@ -1326,7 +1425,7 @@ __device__ __forceinline__ void slre_item(const ItemD& it, LevelState ls, int le
     }
     return;
   }
-  if (tiny_fits(m, a, b, it.nseg, it.nsegn)) {
+  if (!ls.nodc && tiny_fits(m, a, b, it.nseg, it.nsegn)) {
     slre_tiny(it, ls, level, tol, tol_mode, prec, reinterpret_cast<char*>(lds), soff, a, b);
     return;
   }
@@ -1417,28 +1516,33 @@ __device__ __forceinline__ void slre_item(const ItemD& it, LevelState ls, int le
       if (r < m) P[ld * c + r] = v[t];
     }
   }
-  if (tid == 0) sbad = 0;
-  __syncthreads();
-  // S_s: Cholesky of A_ss and scaling of the block row
-  chol_solve(P, m, m, P + ld * m, a + b, lds, &sbad);
-  __syncthreads();
-  if (sbad && tid == 0) item_error(it, ls.err, level, kErrNotSPD);
-  // compression of the scaled far field G^{-1} A_sw
-  double* Wf = P + ld * (m + a);
-  int k = 0;
-  bool over = false;
-  if (b > 0 && m > 0)
-    k = cpqr(Wf, m, m, b, tol, tol_mode, it.kcap, it.piv, it.stepof, it.tau, it.norms, shd, shi, &over);
-  if (over || k > it.kcap) {
-    if (tid == 0) item_error(it, ls.err, level, kErrCapacity);
-    k = min(k, it.kcap);
-  }
-  __syncthreads();
-  // E_s: rotate the near-field columns, C = U^T G^{-1} A_sn
   double* C = P + ld * m;
-  if (k > 0) apply_qt_cols(C, m, m, a, Wf, it.piv, it.tau, k, lds, (size_t)m * kNB + kNB * kNB + kNB * 256);
-  __syncthreads();
-  // G_s: eliminate the fine DoFs, X_nn -= F^T F
+  int k = 0;
+  if (ls.nodc) {
+    if (!table) __syncthreads();
+    k = slre_nodc_core(it, ls, level, tol, tol_mode, lds, a, b, shd, shi, &sbad);
+  } else {
+    if (tid == 0) sbad = 0;
+    __syncthreads();
+    // S_s: Cholesky of A_ss and scaling of the block row
+    chol_solve(P, m, m, P + ld * m, a + b, lds, &sbad);
+    __syncthreads();
+    if (sbad && tid == 0) item_error(it, ls.err, level, kErrNotSPD);
+    // compression of the scaled far field G^{-1} A_sw
+    double* Wf = P + ld * (m + a);
+    bool over = false;
+    if (b > 0 && m > 0)
+      k = cpqr(Wf, m, m, b, tol, tol_mode, it.kcap, it.piv, it.stepof, it.tau, it.norms, shd, shi, &over);
+    if (over || k > it.kcap) {
+      if (tid == 0) item_error(it, ls.err, level, kErrCapacity);
+      k = min(k, it.kcap);
+    }
+    __syncthreads();
+    // E_s: rotate the near-field columns, C = U^T G^{-1} A_sn
+    if (k > 0) apply_qt_cols(C, m, m, a, Wf, it.piv, it.tau, k, lds, (size_t)m * kNB + kNB * kNB + kNB * 256);
+    __syncthreads();
+  }
+  // G_s: eliminate the fine DoFs, X_nn -= F^T F (F = rows k.. of C)
   if (m > k && a > 0 &&
       !schur_scatter_staged(it, C, m, m, k, a, prec, ls.err, level, lds, (size_t)m * kNB + kNB * kNB + kNB * 256))
     schur_scatter(it, C, m, m, k, a, prec, ls.err, level);
@@ -1459,15 +1563,17 @@ __device__ __forceinline__ void slre_item(const ItemD& it, LevelState ls, int le
     }
     t.dst[(size_t)row + (size_t)t.ld * col] = v;
   }
+  // diagonal block of the coarse unknowns: I_k (without deferred
+  // compression D_c)
   for (int e = tid; e < k * k; e += kThreads) {
     const int r = e % k, c = e / k;
-    it.D[(size_t)r + ld * c] = (r == c) ? 1.0 : 0.0;
+    it.D[(size_t)r + ld * c] = ls.nodc ? P[(size_t)r + ld * c] : ((r == c) ? 1.0 : 0.0);
   }
   if (tid == 0) {
     ls.k[it.s] = k;
     ls.a[it.s] = a;
     ls.b[it.s] = b;
-    ls.giok[it.s] = 0;
+    ls.giok[it.s] = ls.nodc ? 3 : 0;
   }
   __syncthreads();
 }
@@ -1906,6 +2012,50 @@ __device__ __forceinline__ void fwd_near(const ItemD& it, int m, int k, int c0, 
   }
 }
 
+// Without deferred compression (giok 3): y_c -= F_c^T y_f, F_c = rows k.. of
+// the panel's columns ..k (ld m), y in LDS; one wave per coarse entry.
+__device__ __forceinline__ void nodc_fc_t(const double* P, int m, int k, double* y) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int r = wv; r < k; r += kWaves) {
+    const double* f = P + (size_t)m * r;
+    double s = 0.0;
+    for (int i = k + lane; i < m; i += 64) s += f[i] * y[i];
+    s = wave_sum(s);
+    if (lane == 0) y[r] -= s;
+  }
+  __syncthreads();
+}
+
+// Without deferred compression: x_f -= F_c x_c, one thread per fine row.
+__device__ __forceinline__ void nodc_fc(const double* P, int m, int k, double* x) {
+  for (int i = k + threadIdx.x; i < m; i += kThreads) {
+    double s = 0.0;
+    for (int r = 0; r < k; ++r) s += P[(size_t)i + (size_t)m * r] * x[r];
+    x[i] -= s;
+  }
+  __syncthreads();
+}
+
+// Without deferred compression, forward part of the cluster itself:
+// y <- U^T y, y_f <- G_f^{-1} y_f, y_c -= F_c^T y_f (y in LDS).
+template <int R>
+__device__ __forceinline__ void nodc_fwd(const ItemD& it, int m, int k, int a, int mp, double* y, double* blk,
+                                         double* vs) {
+  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
+  trsv_lower(it.P + k + (size_t)m * k, m, m - k, y + k, blk);
+  nodc_fc_t(it.P, m, k, y);
+}
+
+// Without deferred compression, backward part of the cluster itself (after
+// x_f -= F_n x_n): x_f <- G_f^{-T} (x_f - F_c x_c), x <- U x.
+template <int R>
+__device__ __forceinline__ void nodc_bwd(const ItemD& it, int m, int k, int a, int mp, double* x, double* blk,
+                                         double* vs) {
+  nodc_fc(it.P, m, k, x);
+  trsv_lower_t<R>(it.P + k + (size_t)m * k, m, m - k, x + k, blk);
+  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
+}
+
 }  // namespace
 
 namespace {
@@ -1929,9 +2079,13 @@ __device__ __forceinline__ void fwd_item(const ItemD& it, LevelState ls, double*
   } else {
     for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
     __syncthreads();
-    if (gk) gemv_blk(it.Gi, m, kGemvLower, y, blk);  // G^{-1} formed by the factorization
-    else trsv_lower(it.P, m, m, y, blk);
-    apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
+    if (gk == 3) {
+      nodc_fwd<R>(it, m, k, a, mp, y, blk, vs);
+    } else {
+      if (gk) gemv_blk(it.Gi, m, kGemvLower, y, blk);  // G^{-1} formed by the factorization
+      else trsv_lower(it.P, m, m, y, blk);
+      apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
+    }
   }
   fwd_near<R>(it, m, k, 0, a, y, vec);
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
@@ -1954,8 +2108,12 @@ __device__ __forceinline__ void fwd_head(const ItemD& it, LevelState ls, double*
   const int gk = ls.giok[it.s];
   if (gk == 2) {
     gemv_blk(it.Gi, m, kGemvFull, y, blk, yg);  // W = U^T G^{-1} formed by the factorization
+  } else if (gk == 3) {
+    for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
+    __syncthreads();
+    nodc_fwd<R>(it, m, k, a, mp, y, blk, vs);
   } else {
-    if (gk) {
+    if (gk == 1) {
       gemv_blk(it.Gi, m, kGemvLower, y, blk, yg);  // G^{-1} formed by the factorization
     } else {
       for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
@@ -2048,9 +2206,13 @@ __device__ __forceinline__ void bwd_tail(const ItemD& it, LevelState ls, double*
   } else {
     for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
     __syncthreads();
-    apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
-    if (gk) gemv_blk(it.GiT, m, kGemvUpper, x, blk);  // G^{-T} formed by the factorization
-    else trsv_lower_t<R>(it.P, m, m, x, blk);
+    if (gk == 3) {
+      nodc_bwd<R>(it, m, k, a, mp, x, blk, vs);
+    } else {
+      apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
+      if (gk) gemv_blk(it.GiT, m, kGemvUpper, x, blk);  // G^{-T} formed by the factorization
+      else trsv_lower_t<R>(it.P, m, m, x, blk);
+    }
   }
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
@@ -2094,6 +2256,8 @@ __device__ __forceinline__ void bwd_item(const ItemD& it, LevelState ls, double*
   const int gk = ls.giok[it.s];
   if (gk == 2) {
     gemv_blk(it.GiT, m, kGemvFull, x, blk);  // W^T = G^{-T} U formed by the factorization
+  } else if (gk == 3) {
+    nodc_bwd<R>(it, m, k, a, mp, x, blk, vs);
   } else {
     apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
     if (gk) gemv_blk(it.GiT, m, kGemvUpper, x, blk);  // G^{-T} formed by the factorization
@@ -2407,7 +2571,7 @@ __global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const Ite
 // Clusters of at most kSweepWaveM DoFs run the wave form in wave 0 whatever
 // the schedule, so that every schedule gives the same bits.
 __device__ __forceinline__ void fwd_any(const ItemD& it, bool split, LevelState ls, double* vec, double* lds) {
-  if (it.m <= kSweepWaveM) {
+  if (it.m <= kSweepWaveM && !ls.nodc) {
     if (threadIdx.x < 64) {
       const WaveItem wi = wave_item(it, ls);
       LRSP_WAVE_DISPATCH(fwd_wave, wi, vec);
@@ -2421,7 +2585,7 @@ __device__ __forceinline__ void fwd_any(const ItemD& it, bool split, LevelState 
 }
 
 __device__ __forceinline__ void bwd_any(const ItemD& it, bool split, LevelState ls, double* vec, double* lds) {
-  if (it.m <= kSweepWaveM) {
+  if (it.m <= kSweepWaveM && !ls.nodc) {
     if (threadIdx.x < 64) {
       const WaveItem wi = wave_item(it, ls);
       LRSP_WAVE_DISPATCH(bwd_wave, wi, vec);

@@ -41,7 +41,8 @@ class CSR(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("tol_mode", C.c_int32), ("gemm_prec", C.c_int32), ("rank_mode", C.c_int32),
                 ("exec_mode", C.c_int32), ("mlp_weights", C.c_void_p),
-                ("autotune", C.c_int32), ("top_dense_threshold", C.c_int32), ("reserved", C.c_int64 * 5)]
+                ("autotune", C.c_int32), ("top_dense_threshold", C.c_int32), ("scheme", C.c_int32),
+                ("reserved32b", C.c_int32), ("reserved", C.c_int64 * 4)]
 
 
 class TreeView(C.Structure):
@@ -256,8 +257,9 @@ class Factor:
 
     def __init__(self, A: DeviceMatrix, tree: Tree, tol: float, tol_mode="relative",
                  gemm_prec="f64", exec_mode="auto", stream=None, mlp=None, autotune=False,
-                 top_dense=0):
+                 top_dense=0, dc=True):
         o = Opts()
+        o.scheme = 0 if dc else 1
         o.tol_mode = TOL_MODE[tol_mode]
         o.gemm_prec = PREC[gemm_prec]
         o.exec_mode = EXEC_MODE[exec_mode]

@@ -89,3 +89,30 @@ def test_autotune_table_round_trip(tmp_path):
     with pytest.raises(lrsp.LrspError):
         lrsp.autotune_load(str(tmp_path / "missing.json"))
     lrsp.autotune_clear()
+
+
+def test_struct_layouts_match_the_header(L, tmp_path):
+    # every struct of the header: size and field offsets as the C compiler
+    # lays them out equal the binding's ctypes layout
+    import ctypes as C
+    import subprocess
+    pairs = [("lrsp_grid", L.Grid), ("lrsp_csr", L.CSR), ("lrsp_opts", L.Opts), ("lrsp_tree_view", L.TreeView),
+             ("lrsp_info", L.Info), ("lrsp_level_view", L.LevelView), ("lrsp_level_stats", L.LevelStats),
+             ("lrsp_batch_info", L.BatchInfo), ("lrsp_timing", L.Timing)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{os.path.join(ROOT, "include", "lrsp.h")}"',
+             "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname}.{f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                  text=True).stdout.splitlines())
+    for cname, py in pairs:
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f in py._fields_:
+            assert int(got[f"{cname}.{f[0]}"]) == getattr(py, f[0]).offset, f"{cname}.{f[0]}"
