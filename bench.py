@@ -116,6 +116,18 @@ def run_gpu(args):
         factor_bytes=info["bytes_factor"], levels_reused=info["levels_reused"],
         ms_analysis_in_step=info["ms_analysis"])
     log(f"[{prec}] {results[prec]}")
+    # memory of the factor, level by level (an untimed factorization)
+    F = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE)
+    inf = F.info()
+    per = []
+    for li in range(inf["nlevels"] + 1):
+        st = F.level_stats(li)
+        per.append(dict(level=li if li < inf["nlevels"] else "top", dofs=st["dofs"],
+                        factor_mb=round(st["factor_bytes"] / 1e6, 3), held_mb=round(st["held_bytes"] / 1e6, 3)))
+    results["memory"] = dict(factor_bytes=inf["bytes_factor"], factor_bytes_per_dof=round(inf["bytes_factor"] / pr.n, 1),
+                             peak_bytes=inf["peak_bytes"], per_level=per)
+    log(f"[memory] {results['memory']}")
+    del F
     if TOP_DENSE > 0:
         # the same step with the recursion stopping only at a complete level
         # graph (its own tree, so that each keeps its analysis)
@@ -790,6 +802,7 @@ def main():
     if "complete_graph_stop" in res:
         out["complete_graph_stop"] = {k: (round(v, 4) if isinstance(v, float) else v)
                                       for k, v in res["complete_graph_stop"].items()}
+    out["memory"] = res["memory"]
     out["levels"] = f64["levels"]
     out["top_n"] = f64["top_n"]
     if "gmres" in res:

@@ -294,7 +294,10 @@ lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_l
  * backward sweeps summed over the `applies` preconditioner applications
  * (lrsp_apply, and those inside lrsp_pcg / lrsp_gmres) -- both 0 unless
  * timing (lrsp_timing_enable) was on during lrsp_factor and during the
- * applications.  Synchronises the device. */
+ * applications.  factor_bytes: device bytes of the level's part of the
+ * factor (what the sweeps read, with the panels the level is eliminated in);
+ * held_bytes: all device bytes the level holds (its work arenas too), the
+ * dense top's for level == nlevels.  Synchronises the device. */
 typedef struct {
   double flops;
   double sweep_bytes;
@@ -305,6 +308,8 @@ typedef struct {
   int64_t coarse;
   int32_t nclusters;
   int32_t reserved;
+  int64_t factor_bytes;
+  int64_t held_bytes;
 } lrsp_level_stats;
 lrsp_status lrsp_factor_level_stats(const lrsp_factorization* F, int32_t level, lrsp_level_stats* out);
 

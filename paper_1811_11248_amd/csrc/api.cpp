@@ -362,8 +362,10 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     }
     std::unique_ptr<LevelDev> Lp;
     bool reuse = false;
+    // the split schedule (auto or forced) needs room for explicit inverses
+    const bool want_gi = !nodc && (o.exec_mode == 0 || o.exec_mode == 3);
     if (!learned && (int)cache->levels.size() > level && cache->levels[level] &&
-        !cache->levels[level]->capped &&
+        !cache->levels[level]->capped && (cache->levels[level]->want_gi || !want_gi) &&
         cache->levels[level]->plan.m == sizes && cache->levels[level]->vbase == vbase) {
       Lp = std::move(cache->levels[level]);
       reuse = true;
@@ -372,6 +374,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     const auto ta = tick();
     if (!reuse) {
       Lp = std::make_unique<LevelDev>();
+      Lp->want_gi = want_gi;
       Lp->plan.M = M;
       Lp->plan.m = sizes;
       Lp->plan.adj = adj;
@@ -553,6 +556,14 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
         else ++checks_fail;
       }
     }
+    {  // what the sweeps read, into the clusters' factor stores
+      bool changed = false;
+      if (lrsp_status s = plan_stores(L, st, &changed)) return s;
+      if (changed)
+        HIPCHK(hipMemcpyAsync(L->d_items, L->h_items.data(), sizeof(ItemD) * (size_t)M, hipMemcpyHostToDevice, st));
+      TimedLaunch tall(0, st);
+      launch_compact(L->d_items, M, L->ls, st);
+    }
     double f[5];
     level_stats(L, f);
     double lvl_flops = 0.0;
@@ -671,7 +682,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   inf.top_clusters = M;
   for (int i = 0; i < 6; ++i) inf.flops[i] = flops[i];
   double fb = 8.0 * ntop * ntop;
-  for (auto& L : F->levels) fb += (double)L->fac.bytes;
+  for (auto& L : F->levels) fb += (double)L->factor_bytes();
   inf.bytes_factor = fb;
   inf.ms_levels = std::chrono::duration<double, std::milli>(t1 - t0).count();
   inf.ms_analysis = ms_an;
@@ -1119,10 +1130,14 @@ lrsp_status lrsp_factor_level_stats(const lrsp_factorization* F, int32_t level, 
       r.coarse += L.k[x];
     }
     r.nclusters = L.plan.M;
+    r.factor_bytes = L.factor_bytes();
+    r.held_bytes = L.held_bytes();
   } else {
     r.flops = F->info.flops[5];
     r.dofs = F->top_n;
     r.nclusters = (int32_t)F->top_sizes.size();
+    r.factor_bytes = (int64_t)F->top.bytes;
+    r.held_bytes = (int64_t)F->top.bytes;
   }
   // factor time: from the start of this level to the start of the next
   // (the top: its factorization alone)

@@ -76,6 +76,12 @@ struct BSys {
   std::vector<int> top_sizes, top_adj_ptr, top_adj;
 };
 
+// Items of colour c of a system's level, in processing order.
+void append_colour(const LevelDev& L, int c, std::vector<ItemD>* items) {
+  const LevelPlan& p = L.plan;
+  items->insert(items->end(), L.h_items.begin() + p.cstart[c], L.h_items.begin() + p.cstart[c + 1]);
+}
+
 struct BLevel {
   std::vector<int> sys;    // systems eliminated at this level
   std::vector<int> stop;   // systems whose dense top starts at this level
@@ -528,7 +534,7 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
         for (auto& L : Ls) {
           const LevelPlan& p = L->plan;
           if (c >= p.ncolours) continue;
-          items.insert(items.end(), L->h_items.begin() + p.cstart[c], L->h_items.begin() + p.cstart[c + 1]);
+          append_colour(*L, c, &items);
           SplitDims& d = B.cdims[c];
           const SplitDims& e = L->cdims[c];
           d.max_m = std::max(d.max_m, e.max_m);
@@ -587,12 +593,23 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
         L.k.assign(kab.begin() + sbase[j], kab.begin() + sbase[j] + M);
         L.a.assign(kab.begin() + B.Mtot + sbase[j], kab.begin() + B.Mtot + sbase[j] + M);
         L.b.assign(kab.begin() + 2 * B.Mtot + sbase[j], kab.begin() + 2 * B.Mtot + sbase[j] + M);
+        bool changed = false;
+        if (lrsp_status s = plan_stores(&L, st, &changed)) return s;
         double f[5];
         level_stats(&L, f);
         for (int q = 0; q < 5; ++q) flops[q] += f[q];
         if (B.sweep_bytes.size() < L.sweep_bytes.size()) B.sweep_bytes.resize(L.sweep_bytes.size(), 0.0);
         for (size_t c = 0; c < L.sweep_bytes.size(); ++c) B.sweep_bytes[c] += L.sweep_bytes[c];
       }
+      // the merged work list again, now pointing at the factor stores, and
+      // what the sweeps read copied into them
+      std::vector<ItemD> items;
+      for (int c = 0; c < B.ncolours; ++c)
+        for (auto& L : Ls)
+          if (c < L->plan.ncolours) append_colour(*L, c, &items);
+      HIPCHK(hipMemcpyAsync(B.d_items, items.data(), sizeof(ItemD) * items.size(), hipMemcpyHostToDevice, st));
+      launch_compact(B.d_items, (int)items.size(), B.ls, st);
+      HIPCHK(hipStreamSynchronize(st));
     }
     // next level of every eliminated system; the stopped ones are done
     for (size_t j = 0; j < B.sys.size(); ++j) {
@@ -669,6 +686,7 @@ lrsp_status numeric_phase(lrsp_batch* F, bool graph, hipStream_t st) {
     const BLevel& B = F->lv[l];
     assemble(B, st);
     if (lrsp_status s = eliminate(B, (int)l, F->tol, F->o, B.sched, graph, st)) return s;
+    if (B.Mtot > 0) launch_compact(B.d_items, B.cstart.back(), B.ls, st);
   }
   launch_top_potrf_batched(at<TopD>(F->tops, 0), F->nsys, F->max_top, st);
   HIPCHK(hipGetLastError());

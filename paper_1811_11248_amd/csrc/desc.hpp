@@ -71,8 +71,11 @@ struct ItemD {
   const WbD* wb;
   double* D;        // m x m
   double* P;        // m x (m + pcap)
-  double* Gi;       // m x m, G^{-1} (lower) for m <= kInvMaxDofs, else null
-  double* GiT;      // m x m, G^{-T} (upper), same condition
+  double* Gi;       // m x m, G^{-1} (lower) for m <= kInvMaxDofs on levels that
+                    // may take the split schedule, else null
+  double* S;        // factor store read by the sweeps: [M0 (m x m) | C (m x sa)
+                    // | V (m x sk) | tau (sk)], ld m, filled after the level
+  int32_t sa, sk;   // near-field columns and rank the store holds room for
   int32_t* colseg;  // [pcap] segment of each panel column
   int32_t* colnat;  // [pcap] natural index of each panel column
   int64_t* vidx;    // [pcap] level-vector index of each near-field column
@@ -92,9 +95,9 @@ struct LevelState {
   int32_t* a;     // near-field columns
   int32_t* b;     // far-field columns
   int32_t* err;   // [4]: flag, level, cluster, code (then 4 words of grid barrier)
-  int32_t* giok;  // 1: the factorization left G^{-1} in ItemD::Gi (and G^{-T} in GiT);
+  int32_t* giok;  // 1: the factorization left G^{-1} in ItemD::Gi;
                   // 2: Gi holds W = U^T G^{-1} (k > 0 reflectors folded in, all
-                  //    m x m entries) and GiT holds W^T;
+                  //    m x m entries); the backward sweep applies its transpose;
                   // 3: eliminated without deferred compression (the panel holds
                   //    the reflectors of U, the fine factor G_f in rows/columns
                   //    k.. of the diagonal block, F_c in its columns ..k and F_n)

@@ -1823,10 +1823,9 @@ __device__ __forceinline__ void trsv_lower_t(const double* G, int ld, int m, dou
 }
 
 // Shapes of the cluster matrix in gemv_blk.
-constexpr int kGemvLower = 0, kGemvUpper = 1, kGemvFull = 2;
+constexpr int kGemvLower = 0, kGemvFull = 2;
 
-// y <- M y for M (m x m, ld m, m <= 256) lower triangular, upper triangular
-// or full, y in LDS: the 64x64 tiles are spread over the waves, each lane one
+// y <- M y for M (m x m, ld m, m <= 256) lower triangular or full, y in LDS: the 64x64 tiles are spread over the waves, each lane one
 // row of a tile with the tile's 64 entries of that row loaded at once; the
 // partial sums of the column blocks are added in order.  With yg, y is first
 // copied from yg (global) into LDS, after the loads of each wave's first tile
@@ -1846,15 +1845,15 @@ __device__ __forceinline__ void gemv_blk(const double* M, int m, int shape, doub
       int rb = 0;
       while ((rb + 1) * (rb + 2) / 2 <= t) ++rb;
       const int cl = t - rb * (rb + 1) / 2;
-      ib = shape == kGemvUpper ? cl : rb;
-      jb = shape == kGemvUpper ? rb : cl;
+      ib = rb;
+      jb = cl;
     }
     const int i = 64 * ib + lane;
     const double* Mi = M + min(i, m - 1);
 #pragma unroll
     for (int q = 0; q < 64; ++q) {
       const int j = 64 * jb + q;
-      const bool ok = i < m && j < m && (shape == kGemvFull || (shape == kGemvUpper ? j >= i : j <= i));
+      const bool ok = i < m && j < m && (shape == kGemvFull || j <= i);
       g[q] = ok ? gload(Mi + (size_t)m * j) : 0.0;
     }
   };
@@ -1874,20 +1873,57 @@ __device__ __forceinline__ void gemv_blk(const double* M, int m, int shape, doub
   __syncthreads();
   for (int i = tid; i < m; i += kThreads) {
     const int ib = i >> 6;
-    const int j0 = shape == kGemvUpper ? ib : 0, j1 = shape == kGemvLower ? ib + 1 : nb;
+    const int j1 = shape == kGemvLower ? ib + 1 : nb;
     double t = 0.0;
-    for (int jb = j0; jb < j1; ++jb) t += red[jb * 256 + i];
+    for (int jb = 0; jb < j1; ++jb) t += red[jb * 256 + i];
     y[i] = t;
   }
   __syncthreads();
 }
 
-// Stages reflectors j0..j0+nj-1 of the far-field block Wf (m rows) in LDS as
-// vs[jj*mp + i] (unit leading entry, zeros above).
-// Reflectors j0..j0+nj-1 into vs (rows padded to mp), sixteen loads in
-// flight per thread; pv: their far-field columns (LDS).
-__device__ __forceinline__ void stage_reflectors(const double* Wf, int m, int mp, int j0, int nj,
-                                                 const int* pv, double* vs) {
+// y <- M^T y for M (m x m, ld m, m <= 64 R) lower triangular (lower) or full,
+// y in LDS: one wave per column of M, four columns in flight, each column's
+// dot product with y summed across the wave; the results pass through red (m
+// doubles of LDS) so that no wave overwrites y while another still reads it.
+template <int R>
+__device__ __forceinline__ void gemv_t(const double* M, int m, bool lower, double* y, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double yr[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int i = lane + 64 * t;
+    yr[t] = i < m ? y[i] : 0.0;
+  }
+  for (int cb = wv * 4; cb < m; cb += kWaves * 4) {
+    double g[4][R];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = min(cb + q, m - 1);
+      const double* col = M + (size_t)m * c;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = lane + 64 * t;
+        g[q][t] = (cb + q < m && i < m && (!lower || i >= c)) ? gload(col + i) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) acc += g[q][t] * yr[t];
+      acc = wave_sum(acc);
+      if (lane == q && cb + q < m) red[cb + q] = acc;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += kThreads) y[i] = red[i];
+  __syncthreads();
+}
+
+// Stages reflectors j0..j0+nj-1 (column j of V, m rows) in LDS as
+// vs[jj*mp + i] (unit leading entry, zeros above; rows padded to mp),
+// sixteen loads in flight per thread.
+__device__ __forceinline__ void stage_reflectors(const double* V, int m, int mp, int j0, int nj, double* vs) {
   const int n = nj * mp;
   for (int e0 = threadIdx.x; e0 < n; e0 += kThreads * 16) {
     double v[16];
@@ -1898,7 +1934,7 @@ __device__ __forceinline__ void stage_reflectors(const double* Wf, int m, int mp
       v[u] = 0.0;
       if (e < n && i < m) {
         if (i == j) v[u] = 1.0;
-        else if (i > j) v[u] = gload(Wf + (size_t)m * pv[jj] + i);
+        else if (i > j) v[u] = gload(V + (size_t)m * j + i);
       }
     }
 #pragma unroll
@@ -1910,12 +1946,13 @@ __device__ __forceinline__ void stage_reflectors(const double* Wf, int m, int mp
 }
 
 // y <- H_{k-1} ... H_0 y (forward: H_0 first) or y <- H_0 ... H_{k-1} y
-// (backward: H_{k-1} first) for the k reflectors of the far-field block Wf,
-// y in LDS (m).  Reflectors and their tau pass through LDS (vs, ts) sixteen
-// at a time; wave 0 applies them with y in registers and wave reductions.
+// (backward: H_{k-1} first) for the k reflectors V (column j = reflector j)
+// with factors tau, y in LDS (m).  Reflectors and their tau pass through LDS
+// (vs, ts) sixteen at a time; wave 0 applies them with y in registers and
+// wave reductions.
 template <int R>
-__device__ __forceinline__ void apply_reflectors(const ItemD& it, const double* Wf, int m, int mp, int k, bool fwd,
-                                 double* y, double* vs, double* ts) {
+__device__ __forceinline__ void apply_reflectors(const double* V, const double* tau, int m, int mp, int k,
+                                                 bool fwd, double* y, double* vs, double* ts) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nt = (m + 63) >> 6;
   double yr[R];
@@ -1930,13 +1967,9 @@ __device__ __forceinline__ void apply_reflectors(const ItemD& it, const double* 
   for (int q = 0; q < nchunk; ++q) {
     const int j0 = fwd ? 16 * q : max(0, k - 16 * (q + 1));
     const int nj = fwd ? min(16, k - j0) : (k - 16 * q) - j0;
-    int* pv = reinterpret_cast<int*>(ts + 16);
-    if (tid < nj) {
-      ts[tid] = gload(it.tau + j0 + tid);
-      pv[tid] = gload(it.piv + j0 + tid);
-    }
+    if (tid < nj) ts[tid] = gload(tau + j0 + tid);
     lds_barrier();
-    stage_reflectors(Wf, m, mp, j0, nj, pv, vs);
+    stage_reflectors(V, m, mp, j0, nj, vs);
     __syncthreads();
     if (wv == 0) {
       for (int u = 0; u < nj; ++u) {
@@ -1971,8 +2004,8 @@ __device__ __forceinline__ void apply_reflectors(const ItemD& it, const double* 
 }
 
 // y_n -= F^T y_f over the columns [c0, c1) of F = C[k:m, :] (C = U^T G^{-1}
-// A_sn, ld m): one wave per column, four columns in flight.  y (m entries)
-// may be in LDS or global memory.
+// A_sn in the factor store, ld m): one wave per column, four columns in
+// flight.  y (m entries) may be in LDS or global memory.
 template <int R>
 __device__ __forceinline__ void fwd_near(const ItemD& it, int m, int k, int c0, int c1, const double* y, double* vec) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1982,7 +2015,7 @@ __device__ __forceinline__ void fwd_near(const ItemD& it, int m, int k, int c0, 
     const int i = lane + 64 * t;
     yr[t] = (i >= k && i < m) ? y[i] : 0.0;
   }
-  const double* C = it.P + (size_t)m * m;
+  const double* C = it.S + (size_t)m * m;
   for (int cb = c0 + wv * 4; cb < c1; cb += kWaves * 4) {
     double g[4][R];
 #pragma unroll
@@ -2037,28 +2070,77 @@ __device__ __forceinline__ void nodc_fc(const double* P, int m, int k, double* x
 }
 
 // Without deferred compression, forward part of the cluster itself:
-// y <- U^T y, y_f <- G_f^{-1} y_f, y_c -= F_c^T y_f (y in LDS).
+// y <- U^T y, y_f <- G_f^{-1} y_f, y_c -= F_c^T y_f (y in LDS; S the
+// cluster's factor store).
 template <int R>
-__device__ __forceinline__ void nodc_fwd(const ItemD& it, int m, int k, int a, int mp, double* y, double* blk,
+__device__ __forceinline__ void nodc_fwd(const double* S, int m, int k, int a, int mp, double* y, double* blk,
                                          double* vs) {
-  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
-  trsv_lower(it.P + k + (size_t)m * k, m, m - k, y + k, blk);
-  nodc_fc_t(it.P, m, k, y);
+  const double* V = S + (size_t)m * (m + a);
+  apply_reflectors<R>(V, V + (size_t)m * k, m, mp, k, true, y, vs, blk);
+  trsv_lower(S + k + (size_t)m * k, m, m - k, y + k, blk);
+  nodc_fc_t(S, m, k, y);
 }
 
 // Without deferred compression, backward part of the cluster itself (after
 // x_f -= F_n x_n): x_f <- G_f^{-T} (x_f - F_c x_c), x <- U x.
 template <int R>
-__device__ __forceinline__ void nodc_bwd(const ItemD& it, int m, int k, int a, int mp, double* x, double* blk,
+__device__ __forceinline__ void nodc_bwd(const double* S, int m, int k, int a, int mp, double* x, double* blk,
                                          double* vs) {
-  nodc_fc(it.P, m, k, x);
-  trsv_lower_t<R>(it.P + k + (size_t)m * k, m, m - k, x + k, blk);
-  apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
+  const double* V = S + (size_t)m * (m + a);
+  nodc_fc(S, m, k, x);
+  trsv_lower_t<R>(S + k + (size_t)m * k, m, m - k, x + k, blk);
+  apply_reflectors<R>(V, V + (size_t)m * k, m, mp, k, false, x, vs, blk);
 }
 
 }  // namespace
 
 namespace {
+
+// The cluster's own part of the forward sweep, y <- U^T G^{-1} y (without
+// deferred compression the rotation, fine solve and coarse update), from the
+// factor store S: gk 2: one product with W = U^T G^{-1} (first copying y from
+// yg when yg is given); gk 1: G^{-1} then the reflectors; gk 0: a triangular
+// solve with G then the reflectors; gk 3: nodc_fwd.  y in LDS (loaded from yg
+// unless yg is null).
+template <int R>
+__device__ __forceinline__ void own_fwd(const double* S, int gk, int m, int k, int a, int mp, double* y,
+                                        const double* yg, double* blk, double* vs) {
+  if (gk == 2) {
+    gemv_blk(S, m, kGemvFull, y, blk, yg);
+    return;
+  }
+  if (yg) {
+    for (int i = threadIdx.x; i < m; i += kThreads) y[i] = yg[i];
+    __syncthreads();
+  }
+  if (gk == 3) {
+    nodc_fwd<R>(S, m, k, a, mp, y, blk, vs);
+    return;
+  }
+  if (gk == 1) gemv_blk(S, m, kGemvLower, y, blk);
+  else trsv_lower(S, m, m, y, blk);
+  const double* V = S + (size_t)m * (m + a);
+  apply_reflectors<R>(V, V + (size_t)m * k, m, mp, k, true, y, vs, blk);
+}
+
+// The cluster's own part of the backward sweep, x <- G^{-T} U x (the
+// transposes of own_fwd), x in LDS.
+template <int R>
+__device__ __forceinline__ void own_bwd(const double* S, int gk, int m, int k, int a, int mp, double* x,
+                                        double* blk, double* vs) {
+  if (gk == 2) {
+    gemv_t<R>(S, m, false, x, blk);  // W^T = G^{-T} U
+    return;
+  }
+  if (gk == 3) {
+    nodc_bwd<R>(S, m, k, a, mp, x, blk, vs);
+    return;
+  }
+  const double* V = S + (size_t)m * (m + a);
+  apply_reflectors<R>(V, V + (size_t)m * k, m, mp, k, false, x, vs, blk);
+  if (gk == 1) gemv_t<R>(S, m, true, x, blk);  // G^{-T} = (G^{-1})^T
+  else trsv_lower_t<R>(S, m, m, x, blk);
+}
 
 // Forward substitution of one cluster: y_s <- U^T G^{-1} y_s, y_n -= F^T y_f.
 // lds: mp (y) + 64*65 (diagonal block) + 16*mp (reflectors) doubles.
@@ -2073,20 +2155,7 @@ __device__ __forceinline__ void fwd_item(const ItemD& it, LevelState ls, double*
   double* blk = lds + mp;
   double* vs = blk + 64 * kBlkLd;
   double* yg = vec + it.voff;
-  const int gk = ls.giok[it.s];
-  if (gk == 2) {
-    gemv_blk(it.Gi, m, kGemvFull, y, blk, yg);  // W = U^T G^{-1} formed by the factorization
-  } else {
-    for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
-    __syncthreads();
-    if (gk == 3) {
-      nodc_fwd<R>(it, m, k, a, mp, y, blk, vs);
-    } else {
-      if (gk) gemv_blk(it.Gi, m, kGemvLower, y, blk);  // G^{-1} formed by the factorization
-      else trsv_lower(it.P, m, m, y, blk);
-      apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
-    }
-  }
+  own_fwd<R>(it.S, ls.giok[it.s], m, k, a, mp, y, yg, blk, vs);
   fwd_near<R>(it, m, k, 0, a, y, vec);
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
   __syncthreads();
@@ -2105,23 +2174,7 @@ __device__ __forceinline__ void fwd_head(const ItemD& it, LevelState ls, double*
   double* blk = lds + mp;
   double* vs = blk + 64 * kBlkLd;
   double* yg = vec + it.voff;
-  const int gk = ls.giok[it.s];
-  if (gk == 2) {
-    gemv_blk(it.Gi, m, kGemvFull, y, blk, yg);  // W = U^T G^{-1} formed by the factorization
-  } else if (gk == 3) {
-    for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
-    __syncthreads();
-    nodc_fwd<R>(it, m, k, a, mp, y, blk, vs);
-  } else {
-    if (gk == 1) {
-      gemv_blk(it.Gi, m, kGemvLower, y, blk, yg);  // G^{-1} formed by the factorization
-    } else {
-      for (int i = tid; i < m; i += kThreads) y[i] = yg[i];
-      __syncthreads();
-      trsv_lower(it.P, m, m, y, blk);
-    }
-    apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, true, y, vs, blk);
-  }
+  own_fwd<R>(it.S, ls.giok[it.s], m, k, a, mp, y, yg, blk, vs);
   for (int i = tid; i < m; i += kThreads) yg[i] = y[i];
   __syncthreads();
 }
@@ -2152,7 +2205,7 @@ __device__ __forceinline__ void bwd_unit(const ItemD& it, int part, LevelState l
   const bool act = row >= k && row < m;
   double* xn = lds;
   double* red = lds + 1024;
-  const double* C = it.P + (size_t)m * m;
+  const double* C = it.S + (size_t)m * m;
   double s = 0.0;
   for (int c0 = 0; c0 < a; c0 += 1024) {
     const int nc = min(1024, a - c0);
@@ -2200,20 +2253,9 @@ __device__ __forceinline__ void bwd_tail(const ItemD& it, LevelState ls, double*
   double* blk = lds + mp;
   double* vs = blk + 64 * kBlkLd;
   double* xg = vec + it.voff;
-  const int gk = ls.giok[it.s];
-  if (gk == 2) {
-    gemv_blk(it.GiT, m, kGemvFull, x, blk, xg);  // W^T = G^{-T} U formed by the factorization
-  } else {
-    for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
-    __syncthreads();
-    if (gk == 3) {
-      nodc_bwd<R>(it, m, k, a, mp, x, blk, vs);
-    } else {
-      apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
-      if (gk) gemv_blk(it.GiT, m, kGemvUpper, x, blk);  // G^{-T} formed by the factorization
-      else trsv_lower_t<R>(it.P, m, m, x, blk);
-    }
-  }
+  for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
+  __syncthreads();
+  own_bwd<R>(it.S, ls.giok[it.s], m, k, a, mp, x, blk, vs);
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
 }
@@ -2233,7 +2275,7 @@ __device__ __forceinline__ void bwd_item(const ItemD& it, LevelState ls, double*
   double* xn = vs + 16 * mp;  // 1024-column chunks of x_n
   double* xg = vec + it.voff;
   for (int i = tid; i < m; i += kThreads) x[i] = xg[i];
-  const double* C = it.P + (size_t)m * m;
+  const double* C = it.S + (size_t)m * m;
   for (int c0 = 0; c0 < a; c0 += 1024) {
     const int nc = min(1024, a - c0);
     __syncthreads();
@@ -2253,16 +2295,7 @@ __device__ __forceinline__ void bwd_item(const ItemD& it, LevelState ls, double*
     }
   }
   __syncthreads();
-  const int gk = ls.giok[it.s];
-  if (gk == 2) {
-    gemv_blk(it.GiT, m, kGemvFull, x, blk);  // W^T = G^{-T} U formed by the factorization
-  } else if (gk == 3) {
-    nodc_bwd<R>(it, m, k, a, mp, x, blk, vs);
-  } else {
-    apply_reflectors<R>(it, it.P + (size_t)m * (m + a), m, mp, k, false, x, vs, blk);
-    if (gk) gemv_blk(it.GiT, m, kGemvUpper, x, blk);  // G^{-T} formed by the factorization
-    else trsv_lower_t<R>(it.P, m, m, x, blk);
-  }
+  own_bwd<R>(it.S, ls.giok[it.s], m, k, a, mp, x, blk, vs);
   for (int i = tid; i < m; i += kThreads) xg[i] = x[i];
   __syncthreads();
 }
@@ -2280,22 +2313,22 @@ size_t sweep_lds(int max_m) {
 // readlane, the near-field products run one lane per column (forward) or
 // per row (backward).  MB >= m bounds the row slots kept in registers.
 
-// What a wave needs of a small cluster in the sweeps (piv may point to an
-// LDS copy).
+// What a wave needs of a small cluster in the sweeps: its factor store S
+// ([G | C | V], ld m) and the reflector factors tau behind it.
 struct WaveItem {
-  const double* P;
+  const double* S;
   const double* tau;
   const int64_t* vidx;
-  const int32_t* piv;
   const int32_t* vix;  // LDS copy of the first kSweepWaveVix entries of vidx, or null
   int64_t voff;
   int32_t m, k, a, pad;
 };
 
-static_assert(sizeof(WaveItem) + 4 * kSweepWaveM + 4 * kSweepWaveVix <= kSweepWaveTableBytes, "wave table entry");
+static_assert(sizeof(WaveItem) + 4 * kSweepWaveVix <= kSweepWaveTableBytes, "wave table entry");
 
 __device__ __forceinline__ WaveItem wave_item(const ItemD& it, LevelState ls) {
-  return WaveItem{it.P, it.tau, it.vidx, it.piv, nullptr, it.voff, it.m, ls.k[it.s], ls.a[it.s], 0};
+  const int m = it.m, k = ls.k[it.s], a = ls.a[it.s];
+  return WaveItem{it.S, it.S + (size_t)m * (m + a + k), it.vidx, nullptr, it.voff, m, k, a, 0};
 }
 
 // y_s <- U^T G^{-1} y_s; y_n -= F^T y_f.  For MB <= 32 every load that does
@@ -2309,14 +2342,13 @@ __device__ __forceinline__ void fwd_wave(const WaveItem& wi, double* vec) {
   if (m == 0) return;
   const int k = wi.k, a = wi.a;
   const bool on = lane < m;
-  const double* G = wi.P;
-  const double* Wf = wi.P + (size_t)m * (m + a);
-  const double* C = wi.P + (size_t)m * m;
+  const double* G = wi.S;
+  const double* V = wi.S + (size_t)m * (m + a);
+  const double* C = wi.S + (size_t)m * m;
   double g[MB];  // row `lane` of G, columns < lane
 #pragma unroll
   for (int j = 0; j < MB; ++j) g[j] = (on && j < lane) ? G[lane + (size_t)m * j] : 0.0;
   const double gd = on ? G[lane + (size_t)m * lane] : 1.0;
-  const int pv = lane < k ? wi.piv[lane] : 0;
   const double tv = lane < k ? wi.tau[lane] : 0.0;
   double* yg = vec + wi.voff;
   double y = on ? yg[lane] : 0.0;
@@ -2326,10 +2358,8 @@ __device__ __forceinline__ void fwd_wave(const WaveItem& wi, double* vec) {
   const bool cv0 = lane < a;
   if constexpr (PF) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int pj = __builtin_amdgcn_readlane(pv, j);
-      vr[j] = (j < k) ? (lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0)) : 0.0;
-    }
+    for (int j = 0; j < 16; ++j)
+      vr[j] = (j < k) ? (lane == j ? 1.0 : ((on && lane > j) ? V[lane + (size_t)m * j] : 0.0)) : 0.0;
     const double* Cc = C + (size_t)m * (cv0 ? lane : 0);
 #pragma unroll
     for (int i = 0; i < MB; ++i) f0[i] = (cv0 && i >= k && i < m) ? Cc[i] : 0.0;
@@ -2359,8 +2389,7 @@ __device__ __forceinline__ void fwd_wave(const WaveItem& wi, double* vec) {
   }
   {
     for (int j = j1; j < k; ++j) {
-      const int pj = __builtin_amdgcn_readlane(pv, j);
-      const double v = lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0);
+      const double v = lane == j ? 1.0 : ((on && lane > j) ? V[lane + (size_t)m * j] : 0.0);
       const double sj = wave_sum(v * y);
       y -= (readlane_d(tv, j) * sj) * v;
     }
@@ -2409,12 +2438,11 @@ __device__ __forceinline__ void bwd_wave(const WaveItem& wi, double* vec) {
   if (m == 0) return;
   const int k = wi.k, a = wi.a;
   const bool on = lane < m;
-  const double* G = wi.P;
-  const double* Wf = wi.P + (size_t)m * (m + a);
-  const double* C = wi.P + (size_t)m * m;
+  const double* G = wi.S;
+  const double* V = wi.S + (size_t)m * (m + a);
+  const double* C = wi.S + (size_t)m * m;
   const bool fine = on && lane >= k;
   const double gd = on ? G[lane + (size_t)m * lane] : 1.0;
-  const int pv = lane < k ? wi.piv[lane] : 0;
   const double tv = lane < k ? wi.tau[lane] : 0.0;
   double* xg = vec + wi.voff;
   double x = on ? xg[lane] : 0.0;
@@ -2427,10 +2455,8 @@ __device__ __forceinline__ void bwd_wave(const WaveItem& wi, double* vec) {
   const int nc0 = min(32, a);
   if constexpr (PF) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int pj = __builtin_amdgcn_readlane(pv, j);
-      vr[j] = (j < k) ? (lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0)) : 0.0;
-    }
+    for (int j = 0; j < 16; ++j)
+      vr[j] = (j < k) ? (lane == j ? 1.0 : ((on && lane > j) ? V[lane + (size_t)m * j] : 0.0)) : 0.0;
     const double* Cr = C + (size_t)(fine ? lane : 0);
 #pragma unroll
     for (int q = 0; q < 32; ++q) f0[q] = (fine && q < nc0) ? Cr[(size_t)m * q] : 0.0;
@@ -2466,8 +2492,7 @@ __device__ __forceinline__ void bwd_wave(const WaveItem& wi, double* vec) {
   if (fine) x -= s;
   // U: reflectors k-1..0 (the first 16 prefetched)
   for (int j = k - 1; j >= (PF ? 16 : 0); --j) {
-    const int pj = __builtin_amdgcn_readlane(pv, j);
-    const double v = lane == j ? 1.0 : ((on && lane > j) ? Wf[lane + (size_t)m * pj] : 0.0);
+    const double v = lane == j ? 1.0 : ((on && lane > j) ? V[lane + (size_t)m * j] : 0.0);
     const double sj = wave_sum(v * x);
     x -= (readlane_d(tv, j) * sj) * v;
   }
@@ -2501,7 +2526,7 @@ __device__ __forceinline__ void bwd_wave(const WaveItem& wi, double* vec) {
 // One launch per level and sweep direction for levels whose clusters all
 // have at most kSweepWaveM DoFs: every wave takes a cluster of the colour;
 // one workgroup needs no grid barrier between colours.  With table != 0 the
-// descriptors, ranks and pivots of all the level's clusters are first copied
+// descriptors and ranks of all the level's clusters are first copied
 // to LDS (kSweepWaveTableBytes per cluster), which takes their loads off the
 // path of every colour; with table == 2 also the level-vector indices of the
 // first kSweepWaveVix near-field columns (32-bit), so that the vector loads
@@ -2515,26 +2540,20 @@ __global__ void __launch_bounds__(kSweepWaveThreads) sweep_wave_kernel(const Ite
   const int wv = threadIdx.x >> 6, nw = kSweepWaveThreads / 64;
   const int ni = cstart[ncolours];
   WaveItem* tab = reinterpret_cast<WaveItem*>(dlds);
-  int32_t* pvs = reinterpret_cast<int32_t*>(tab + (table ? ni : 0));
-  int32_t* vxs = pvs + (table ? (size_t)ni * kSweepWaveM : 0);
+  int32_t* vxs = reinterpret_cast<int32_t*>(tab + (table ? ni : 0));
   if (table) {
     for (int i = threadIdx.x; i < ni; i += kSweepWaveThreads) tab[i] = wave_item(items[i], ls);
     __syncthreads();
-    for (int e = threadIdx.x; e < ni * kSweepWaveM; e += kSweepWaveThreads) {
-      const int i = e / kSweepWaveM, j = e - i * kSweepWaveM;
-      pvs[e] = j < tab[i].k ? tab[i].piv[j] : 0;
-    }
     if (table > 1)
       for (int e = threadIdx.x; e < ni * kSweepWaveVix; e += kSweepWaveThreads) {
         const int i = e / kSweepWaveVix, j = e - i * kSweepWaveVix;
         vxs[e] = j < tab[i].a ? (int32_t)tab[i].vidx[j] : 0;
       }
     __syncthreads();
-    for (int i = threadIdx.x; i < ni; i += kSweepWaveThreads) {
-      tab[i].piv = pvs + (size_t)kSweepWaveM * i;
-      if (table > 1) tab[i].vix = vxs + (size_t)kSweepWaveVix * i;
+    if (table > 1) {
+      for (int i = threadIdx.x; i < ni; i += kSweepWaveThreads) tab[i].vix = vxs + (size_t)kSweepWaveVix * i;
+      __syncthreads();
     }
-    __syncthreads();
   }
   for (int q = 0; q < ncolours; ++q) {
     const int c = FWD ? q : ncolours - 1 - q;
@@ -2884,9 +2903,55 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
     p[i] = 0;
 }
 
+// Factor store of one cluster after its level (one workgroup per cluster):
+// S = [M0 | C | V | tau] with M0 the m x m diagonal-block factor (W = U^T
+// G^{-1} or G^{-1} when the factorization formed them, else the panel's
+// diagonal block: G, or without deferred compression G_f with F_c and D_c),
+// C the panel's a near-field columns, V the k reflectors in step order
+// (column j = the far-field column of pivot j) and tau their factors.  A
+// cluster whose k or a exceed the store's capacities (ranks other than the
+// layout was planned for, which the host detects and answers by a new
+// factorization) is left alone.
+__global__ void __launch_bounds__(256) compact_kernel(const ItemD* __restrict__ items, LevelState ls) {
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  if (m == 0 || !it.S) return;
+  const int k = ls.k[it.s], a = ls.a[it.s], gk = ls.giok[it.s];
+  if (k > it.sk || a > it.sa) return;
+  const size_t mm = (size_t)m * m;
+  const double* M0 = (gk == 1 || gk == 2) ? it.Gi : it.P;
+  double* S = it.S;
+  const size_t n0 = mm + (size_t)m * a, nv = (size_t)m * k;
+  for (size_t e0 = threadIdx.x; e0 < n0; e0 += 256 * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const size_t e = e0 + (size_t)u * 256;
+      v[u] = e < n0 ? (e < mm ? M0[e] : it.P[e]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const size_t e = e0 + (size_t)u * 256;
+      if (e < n0) S[e] = v[u];
+    }
+  }
+  const double* Wf = it.P + (size_t)m * (m + a);
+  double* V = S + n0;
+  for (size_t e = threadIdx.x; e < nv; e += 256) {
+    const int j = (int)(e / m), i = (int)(e - (size_t)j * m);
+    V[e] = Wf[(size_t)m * it.piv[j] + i];
+  }
+  for (int j = threadIdx.x; j < k; j += 256) V[nv + j] = it.tau[j];
+}
+
 static int grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   return (int)(g < 8192 ? (g > 0 ? g : 1) : 8192);
+}
+
+void launch_compact(const ItemD* items, int nitems, LevelState ls, hipStream_t st) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(compact_kernel, dim3(nitems), dim3(256), 0, st, items, ls);
 }
 
 void launch_zero(double* p, int64_t n, hipStream_t st) {

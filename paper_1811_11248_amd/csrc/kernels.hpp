@@ -9,6 +9,9 @@ namespace lrsp {
 // Fill n doubles with zero (a kernel, so that it can be graph-captured).
 void launch_zero(double* p, int64_t n, hipStream_t st);
 void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
+// Copies what the sweeps read of every cluster of a level (nitems items)
+// from its panel into its factor store ItemD::S.
+void launch_compact(const ItemD* items, int nitems, LevelState ls, hipStream_t st);
 
 // base[off[e]] = val[e] for every e with off[e] >= 0.
 void launch_scatter_vals(const double* val, const int64_t* off, int64_t nnz, double* base,
@@ -66,7 +69,7 @@ constexpr int kSweepRows = 32;
 constexpr int kSweepWaveM = 32;
 constexpr int kSweepWaveThreads = 512;
 constexpr int kSweepWaveVix = 64;  // near-field vector indices staged per cluster
-constexpr size_t kSweepWaveTableBytes = 64 + 4 * kSweepWaveM + 4 * kSweepWaveVix;  // descriptor, pivots, indices
+constexpr size_t kSweepWaveTableBytes = 64 + 4 * kSweepWaveVix;  // descriptor, indices
 constexpr size_t kSweepWaveTableMax = 96 * 1024;
 int sweep_units(bool forward, int max_m, int max_acap);
 // The items of one colour (one launch, plus one for the units).

@@ -199,6 +199,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
   HIPCHK(dalloc(&L->coarse, sizeof(double) * p.coarse_doubles, st));
   launch_zero(at<double>(L->coarse, 0), p.coarse_doubles, st);
   // factor arenas
+  const bool want_gi = L->want_gi;
   int64_t fd = 0, fi = 0, fv = 0;
   std::vector<int64_t> poff(M), toff(M), noff(M), csoff(M), cnoff(M), stoff(M), pvoff(M),
       sgoff(M), vxoff(M), gioff(M, -1);
@@ -209,9 +210,9 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     poff[s] = fd; fd += al((int64_t)p.m[s] * (p.m[s] + pc));
     toff[s] = fd; fd += al(p.kcap[s]);
     noff[s] = fd; fd += al(pc);
-    if (p.m[s] > 0 && p.m[s] <= kInvMaxDofs) {
+    if (want_gi && p.m[s] > 0 && p.m[s] <= kInvMaxDofs) {
       gioff[s] = fd;
-      fd += 2 * al((int64_t)p.m[s] * p.m[s]);
+      fd += al((int64_t)p.m[s] * p.m[s]);
     }
     csoff[s] = fi; fi += al(pc);
     cnoff[s] = fi; fi += al(pc);
@@ -346,7 +347,6 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     it.D = W + p.d_off[s];
     it.P = F + poff[s];
     it.Gi = gioff[s] >= 0 ? F + gioff[s] : nullptr;
-    it.GiT = gioff[s] >= 0 ? F + gioff[s] + al((int64_t)p.m[s] * p.m[s]) : nullptr;
     it.tau = F + toff[s];
     it.norms = F + noff[s];
     it.colseg = FI + csoff[s];
@@ -388,6 +388,8 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
   // hipMemcpyAsync from pageable memory may return before the copy is done
   HIPCHK(hipStreamSynchronize(st));
   L->h_items = std::move(items);
+  L->sol_k.clear();  // the new items carry no stores yet
+  L->sol_a.clear();
   // export copies
   L->sizes_i = p.m;
   L->colour_i = p.colour;
@@ -398,6 +400,36 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     L->adj.insert(L->adj.end(), p.adj[x].begin(), p.adj[x].end());
     L->adj_ptr.push_back((int)L->adj.size());
   }
+  return LRSP_OK;
+}
+
+lrsp_status plan_stores(LevelDev* L, hipStream_t st, bool* changed) {
+  *changed = false;
+  const LevelPlan& p = L->plan;
+  const int M = p.M;
+  if (L->sol.p && L->sol_k == L->k && L->sol_a == L->a) return LRSP_OK;
+  auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
+  std::vector<int64_t> off(M);
+  int64_t tot = 0;
+  for (int idx = 0; idx < M; ++idx) {
+    const int s = p.order[idx];
+    const int64_t m = p.m[s], a = L->a[s], k = L->k[s];
+    off[idx] = tot;
+    tot += al(m * (m + a + k) + k);
+  }
+  dfree(&L->sol, st);
+  HIPCHK(dalloc(&L->sol, sizeof(double) * (size_t)std::max<int64_t>(tot, 1), st));
+  double* base = at<double>(L->sol, 0);
+  for (int idx = 0; idx < M; ++idx) {
+    const int s = p.order[idx];
+    ItemD& it = L->h_items[idx];
+    it.S = base + off[idx];
+    it.sa = L->a[s];
+    it.sk = L->k[s];
+  }
+  L->sol_k = L->k;
+  L->sol_a = L->a;
+  *changed = true;
   return LRSP_OK;
 }
 

@@ -93,7 +93,9 @@ struct LevelDev {
   int max_m = 0;
   DevBuf work, wints;      // D / fine halves; posmaps and column lists
   DevBuf coarse;           // coarse halves (sized by the rank capacities)
-  DevBuf fac;              // panels, tau, norms (doubles)
+  DevBuf fac;              // panels, inverses, tau, norms (doubles): the level's workspace
+  DevBuf sol;              // factor stores (ItemD::S) of the clusters: what the sweeps read
+  std::vector<int> sol_k, sol_a;  // ranks and near-field widths the stores are laid out for
   DevBuf fints;            // colseg, colnat, stepof, piv, segoff (int32)
   DevBuf fvidx;            // vidx (int64)
   DevBuf desc;             // SegD / PairD / WbD / ItemD
@@ -114,6 +116,7 @@ struct LevelDev {
   int max_acap = 0;                 // widest near field (capacity)
   int max_nseg = 0;
   bool split = false;               // several workgroups per cluster
+  bool want_gi = true;              // room for the explicit inverses (split schedule)
   const int32_t* d_cstart = nullptr;
   DevBuf vals_off;                  // level 0: CSR entry -> work-arena offset
   DevBuf tasks;                     // level >= 1: assembly copy tasks
@@ -129,7 +132,7 @@ struct LevelDev {
   size_t h_kab_n = 0;
   void free_all(hipStream_t st) {
     dfree(&work, st); dfree(&wints, st); dfree(&coarse, st); dfree(&fac, st); dfree(&fints, st);
-    dfree(&fvidx, st);
+    dfree(&fvidx, st); dfree(&sol, st);
     dfree(&desc, st); dfree(&state, st); dfree(&gidx, st); dfree(&vals_off, st); dfree(&tasks, st);
     if (h_kab) {
       (void)hipStreamSynchronize(st);
@@ -139,10 +142,18 @@ struct LevelDev {
     h_kab_n = 0;
   }
   int64_t held_bytes() const {
-    return (int64_t)(work.bytes + wints.bytes + coarse.bytes + fac.bytes + fints.bytes + fvidx.bytes + desc.bytes +
+    return (int64_t)(work.bytes + wints.bytes + coarse.bytes + fac.bytes + sol.bytes + fints.bytes + fvidx.bytes + desc.bytes +
                      state.bytes + gidx.bytes + vals_off.bytes + tasks.bytes);
   }
+  // bytes of the level's part of the factor: the stores and the vector indices
+  int64_t factor_bytes() const { return (int64_t)(sol.bytes + fvidx.bytes); }
 };
+
+// Lays out the factor stores of a finished level for its ranks L->k and
+// near-field widths L->a (host copies), allocates them and points the host
+// items at them; *changed tells whether the device items must be uploaded
+// again (false when the stores already have this layout).
+lrsp_status plan_stores(LevelDev* L, hipStream_t st, bool* changed);
 
 // Coupling c(x,y) between the coarse DoFs of two linked clusters of a
 // finished level: the source block and whether it is transposed.

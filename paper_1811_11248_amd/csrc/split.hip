@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   if (m == 0) return;
-  if (m > kInvMaxDofs || !it.Gi || !it.GiT) {
+  if (m > kInvMaxDofs || !it.Gi) {
     if (threadIdx.x == 0) item_error(it, ls.err, level, kErrTooLarge);
     return;
   }
@@ -392,7 +392,6 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
   const int nt = (m + 15) >> 4;
   double* A = it.P;
   double* Xg = it.Gi;
-  double* XgT = it.GiT;
   if (tid == 0) sbad = 0;
   // the wave's tiles, loaded with lane l on row l%16 of columns 4v + l/16 (16
   // consecutive rows of a column per 16 lanes), then turned into the
@@ -591,10 +590,7 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
       for (int v = 0; v < 4; ++v) {
         if (jt < p) Xr[(4 * v + lr) * kInvLdX + 16 * jt + lc] = x[v];
         const int gr = 16 * p + 4 * v + lr, gc = 16 * jt + lc;
-        if (gr < m && gc < m) {
-          Xg[gr + (size_t)m * gc] = x[v];
-          XgT[gc + (size_t)m * gr] = x[v];
-        }
+        if (gr < m && gc < m) Xg[gr + (size_t)m * gc] = x[v];
       }
     }
     lds_barrier();
@@ -1003,8 +999,8 @@ __global__ void __launch_bounds__(NT) cpqr_kernel(const ItemD* __restrict__ item
 // per wave per pass, R rows per lane in registers); reflectors staged in LDS
 // 16 at a time.  The workgroups with blockIdx.y >= ya take the columns of
 // G^{-1} instead (clusters whose inverse was formed, k > 0): W = U^T G^{-1}
-// replaces G^{-1} in Gi and W^T goes to GiT, so that a sweep applies U^T
-// G^{-1} (forward) or G^{-T} U (backward) as one product; the entries of
+// replaces G^{-1} in Gi, so that a sweep applies U^T G^{-1} (forward) or its
+// transpose G^{-T} U (backward) as one product; the entries of
 // G^{-1} above its diagonal tiles are zeros not stored, read as zeros.
 constexpr int kApplyqCols = 16;
 template <int R>
@@ -1016,7 +1012,7 @@ __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ i
   const bool winv = (int)blockIdx.y >= ya;
   const int c0 = (winv ? (int)blockIdx.y - ya : (int)blockIdx.y) * kApplyqCols;
   if (m == 0 || k == 0 || c0 >= (winv ? m : a)) return;
-  if (winv && (m > kInvMaxDofs || !it.Gi || !it.GiT || gload(ls.giok + it.s) == 0)) return;
+  if (winv && (m > kInvMaxDofs || !it.Gi || gload(ls.giok + it.s) == 0)) return;
   const int c1 = min(winv ? m : a, c0 + kApplyqCols);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double* Vs = lds;            // 16 x m
@@ -1079,10 +1075,7 @@ __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ i
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const int i = lane + 64 * t;
-          if (i < m) {
-            C[(size_t)m * c + i] = y[q][t];
-            if (winv) it.GiT[(size_t)c + (size_t)m * i] = y[q][t];
-          }
+          if (i < m) C[(size_t)m * c + i] = y[q][t];
         }
       }
     }
