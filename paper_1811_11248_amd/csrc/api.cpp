@@ -41,6 +41,7 @@ struct TreeCache {
   std::unordered_map<uint64_t, std::vector<uint64_t>> z0;
   std::vector<std::unique_ptr<LevelDev>> levels;
   DevBuf perm;  // the tree's DoF permutation on the device, returned by freed factors
+  PanelArena arena;  // panel workspace shared by the levels
   hipStream_t stream = nullptr;
   ~TreeCache() {
     int64_t held = 0;
@@ -50,6 +51,9 @@ struct TreeCache {
         L->free_all(stream);
       }
     dfree(&perm, stream);
+    if (arena.used && arena.stream != stream) (void)hipStreamSynchronize(arena.stream);
+    held += (int64_t)arena.buf.bytes;
+    dfree(&arena.buf, stream);
     (void)hipStreamSynchronize(stream);
     if (held > (int64_t)kPoolKeepBytes) pool_trim();
   }
@@ -383,13 +387,20 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       if (learned) {
         // what the worst-case capacities min(m, b) would allocate
         worst_bytes += 8.0 * (double)(Lp->plan.coarse_doubles + plan_panel_doubles(Lp->plan));
-      } else if (lrsp_status s = setup_level_b(Lp.get(), st)) {
+      } else if (lrsp_status s = setup_level_b(Lp.get(), st, 0, nullptr, nullptr, &cache->arena)) {
         return s;
       }
     } else {
       launch_zero(at<double>(Lp->work, 0), Lp->plan.work_doubles, st);
       launch_zero(at<double>(Lp->coarse, 0), Lp->plan.coarse_doubles, st);
       launch_zero_i32(at<int32_t>(Lp->state, 0), 4 * (int64_t)M + 8, st);
+      // the shared panel arena may have been allocated anew since the level
+      // last ran
+      if (Lp->arena_gen != cache->arena.gen) {
+        if (lrsp_status s = rebind_panels(Lp.get(), st, &cache->arena)) return s;
+      } else {
+        arena_use(&cache->arena, st);
+      }
     }
     LevelDev* L = Lp.get();
     vbase += L->nvec;
@@ -431,7 +442,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       plan_capacities(&L->plan, &L->caps);
       L->capped = true;
       L->cap_tries = 0;
-      if (lrsp_status s = setup_level_b(L, st)) return s;
+      if (lrsp_status s = setup_level_b(L, st, 0, nullptr, nullptr, &cache->arena)) return s;
     }
     if (!reuse) ms_an += ms_since(ta);
     // eliminate the clusters colour by colour
@@ -528,7 +539,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
         plan_capacities(&L->plan, nullptr);
         L->capped = false;
       }
-      if (lrsp_status s = setup_level_b(L, st)) return s;
+      if (lrsp_status s = setup_level_b(L, st, 0, nullptr, nullptr, &cache->arena)) return s;
       launch_zero(at<double>(L->work, 0), L->plan.work_doubles, st);
       if (level == 0) {
         launch_scatter_vals(A->val, at<int64_t>(L->vals_off, 0), A->nnz, at<double>(L->work, 0), st);
@@ -695,7 +706,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   inf.rank_reruns = cap_reruns;
   int64_t held = 0;
   for (auto& L : F->levels) held += L->held_bytes();
-  inf.peak_bytes = held + (int64_t)(F->top.bytes + F->vec.bytes + F->perm.bytes);
+  inf.peak_bytes = held + (int64_t)(F->top.bytes + F->vec.bytes + F->perm.bytes + cache->arena.buf.bytes);
   *out = F.release();
   return LRSP_OK;
 }

@@ -124,6 +124,7 @@ struct lrsp_batch {
   hipStream_t cap = nullptr;       // private stream on which graphs are recorded
   std::vector<BSys> sys;
   std::vector<BLevel> lv;          // vector blocks 0..nb-1
+  PanelArena arena;                // panel workspace: the systems of a level side by side
   int nlevels = 0;                 // blocks with eliminations
   DevBuf perm;                     // packed index -> block-0 index
   DevBuf offs;                     // [nsys+1] packed offsets
@@ -176,6 +177,7 @@ struct lrsp_batch {
     }
     for (auto& B : lv) B.free_all(stream);
     lv.clear();
+    dfree(&arena.buf, stream);
     dfree(&perm, stream); dfree(&offs, stream); dfree(&rowsys, stream); dfree(&serr, stream);
     dfree(&tops, stream); dfree(&bars, stream); dfree(&vec, stream); dfree(&mrowptr, stream); dfree(&mcol, stream);
     dfree(&mval, stream); dfree(&mtasks, stream); dfree(&pcg, stream);
@@ -440,9 +442,18 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
       B.ls = LevelState{sb, sb + B.Mtot, sb + 2 * B.Mtot, sb + 3 * B.Mtot, sb + 3 * B.Mtot + 8};
       launch_zero_i32(sb, 4 * (int64_t)B.Mtot + 8, st);
     }
+    {  // the systems' panels side by side in the shared arena
+      int64_t off = 0;
+      for (auto& L : Ls) {
+        L->arena_off = off;
+        off += panel_doubles(*L);
+      }
+      if (lrsp_status s = arena_reserve(&F->arena, off, st)) return s;
+    }
     for (size_t j = 0; j < B.sys.size(); ++j) {
       const int i = B.sys[j];
-      if (lrsp_status s = setup_level(Ls[j].get(), st, vb[i], sbase[j], &B.ls, at<int32_t>(F->serr, i)))
+      if (lrsp_status s = setup_level(Ls[j].get(), st, vb[i], sbase[j], &B.ls, at<int32_t>(F->serr, i),
+                                      &F->arena))
         return s;
     }
     // assembly of the block's input
@@ -628,6 +639,27 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
     if (B.Mtot > 0) F->nlevels = l + 1;
     F->lv.push_back(std::move(B));
   }
+  // levels set up before the arena last grew: their items to the new buffer
+  for (size_t l = 0; l < F->lv.size(); ++l) {
+    BLevel& B = F->lv[l];
+    if (B.Mtot == 0) continue;
+    std::vector<LevelDev*> Ls;
+    bool stale = false;
+    for (int i : B.sys) {
+      LevelDev* L = F->sys[i].levels[l].get();
+      Ls.push_back(L);
+      stale = stale || L->arena_gen != F->arena.gen;
+    }
+    if (!stale) continue;
+    for (LevelDev* L : Ls)
+      if (lrsp_status s = rebind_panels(L, st, &F->arena)) return s;
+    std::vector<ItemD> items;
+    for (int c = 0; c < B.ncolours; ++c)
+      for (LevelDev* L : Ls)
+        if (c < L->plan.ncolours) append_colour(*L, c, &items);
+    HIPCHK(hipMemcpyAsync(B.d_items, items.data(), sizeof(ItemD) * items.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   // dense tops
   std::vector<TopD> tops(nsys);
   for (int i = 0; i < nsys; ++i) {
@@ -666,7 +698,7 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
   }
   for (auto& B : F->lv)
     held += (int64_t)(B.state.bytes + B.desc.bytes + B.zero.bytes + B.scat.bytes + B.tasks.bytes + B.gidx.bytes);
-  inf.peak_bytes = held;
+  inf.peak_bytes = held + (int64_t)F->arena.buf.bytes;
   lrsp_status rs = LRSP_OK;
   for (int i = 0; i < nsys; ++i) {
     const bool notspd = (se[i] & (1 << kErrNotSPD)) != 0;

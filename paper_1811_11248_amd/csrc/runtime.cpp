@@ -148,9 +148,9 @@ lrsp_status upload(DevBuf* b, const void* src, size_t bytes, hipStream_t st) {
 }
 
 lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase,
-                        const LevelState* shared, int32_t* serr) {
+                        const LevelState* shared, int32_t* serr, PanelArena* arena) {
   if (lrsp_status s = setup_level_a(L, st, vbase)) return s;
-  return setup_level_b(L, st, sbase, shared, serr);
+  return setup_level_b(L, st, sbase, shared, serr, arena);
 }
 
 lrsp_status setup_level_a(LevelDev* L, hipStream_t st, int64_t vbase) {
@@ -185,35 +185,120 @@ lrsp_status setup_level_a(LevelDev* L, hipStream_t st, int64_t vbase) {
   return LRSP_OK;
 }
 
+namespace {
+
+int64_t al32(int64_t v) { return (v + 31) & ~(int64_t)31; }
+
+// Panel workspace of a level (doubles): panel, tau, norms and, where the
+// split schedule may form it, the inverse of every cluster; returns the
+// total.
+struct PanelLayout {
+  std::vector<int64_t> poff, toff, noff, gioff;
+};
+int64_t panel_layout(const LevelPlan& p, bool want_gi, PanelLayout* o) {
+  const int M = p.M;
+  o->poff.assign(M, 0);
+  o->toff.assign(M, 0);
+  o->noff.assign(M, 0);
+  o->gioff.assign(M, -1);
+  int64_t fd = 0;
+  for (int s = 0; s < M; ++s) {
+    const int64_t pc = p.acap[s] + p.bcap[s];
+    o->poff[s] = fd; fd += al32((int64_t)p.m[s] * (p.m[s] + pc));
+    o->toff[s] = fd; fd += al32(p.kcap[s]);
+    o->noff[s] = fd; fd += al32(pc);
+    if (want_gi && p.m[s] > 0 && p.m[s] <= kInvMaxDofs) {
+      o->gioff[s] = fd;
+      fd += al32((int64_t)p.m[s] * p.m[s]);
+    }
+  }
+  return fd;
+}
+
+// The panel workspace of a level: its own buffer, or the start of the
+// shared arena (grown when too small; a user on another stream is waited
+// for first).
+lrsp_status panel_base(LevelDev* L, int64_t fd, hipStream_t st, PanelArena* arena, double** base) {
+  dfree(&L->fac, st);
+  if (!arena) {
+    HIPCHK(dalloc(&L->fac, sizeof(double) * (size_t)fd, st));
+    *base = at<double>(L->fac, 0);
+    return LRSP_OK;
+  }
+  if (lrsp_status s = arena_reserve(arena, L->arena_off + fd, st)) return s;
+  L->arena_gen = arena->gen;
+  L->arena_doubles = fd;
+  *base = at<double>(arena->buf, 0) + L->arena_off;
+  return LRSP_OK;
+}
+
+void point_items(const LevelPlan& p, const PanelLayout& lay, double* F, std::vector<ItemD>* items) {
+  for (int idx = 0; idx < p.M; ++idx) {
+    const int s = p.order[idx];
+    ItemD& it = (*items)[idx];
+    it.P = F + lay.poff[s];
+    it.Gi = lay.gioff[s] >= 0 ? F + lay.gioff[s] : nullptr;
+    it.tau = F + lay.toff[s];
+    it.norms = F + lay.noff[s];
+  }
+}
+
+}  // namespace
+
+void arena_use(PanelArena* arena, hipStream_t st) {
+  if (arena->used && arena->stream != st) (void)hipStreamSynchronize(arena->stream);
+  arena->stream = st;
+  arena->used = true;
+}
+
+lrsp_status arena_reserve(PanelArena* arena, int64_t doubles, hipStream_t st) {
+  arena_use(arena, st);
+  if (arena->buf.bytes < sizeof(double) * (size_t)doubles) {
+    dfree(&arena->buf, st);
+    HIPCHK(dalloc(&arena->buf, sizeof(double) * (size_t)doubles, st));
+    ++arena->gen;
+  }
+  return LRSP_OK;
+}
+
+int64_t panel_doubles(const LevelDev& L) {
+  PanelLayout lay;
+  return panel_layout(L.plan, L.want_gi, &lay);
+}
+
+lrsp_status rebind_panels(LevelDev* L, hipStream_t st, PanelArena* arena) {
+  PanelLayout lay;
+  const int64_t fd = panel_layout(L->plan, L->want_gi, &lay);
+  double* F = nullptr;
+  if (lrsp_status s = panel_base(L, fd, st, arena, &F)) return s;
+  point_items(L->plan, lay, F, &L->h_items);
+  HIPCHK(hipMemcpyAsync(L->d_items, L->h_items.data(), sizeof(ItemD) * (size_t)L->plan.M, hipMemcpyHostToDevice,
+                        st));
+  return LRSP_OK;
+}
+
 lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelState* shared,
-                          int32_t* serr) {
+                          int32_t* serr, PanelArena* arena) {
   LevelPlan& p = L->plan;
   const int M = p.M;
   // coarse halves (layout from the current rank capacities)
   plan_layout(&p);
   dfree(&L->coarse, st);
-  dfree(&L->fac, st);
   dfree(&L->fints, st);
   dfree(&L->fvidx, st);
   dfree(&L->desc, st);
   HIPCHK(dalloc(&L->coarse, sizeof(double) * p.coarse_doubles, st));
   launch_zero(at<double>(L->coarse, 0), p.coarse_doubles, st);
-  // factor arenas
-  const bool want_gi = L->want_gi;
-  int64_t fd = 0, fi = 0, fv = 0;
-  std::vector<int64_t> poff(M), toff(M), noff(M), csoff(M), cnoff(M), stoff(M), pvoff(M),
-      sgoff(M), vxoff(M), gioff(M, -1);
-  auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
+  // panel workspace and index arenas
+  PanelLayout lay;
+  double* F = nullptr;
+  if (lrsp_status s = panel_base(L, panel_layout(p, L->want_gi, &lay), st, arena, &F)) return s;
+  int64_t fi = 0, fv = 0;
+  std::vector<int64_t> csoff(M), cnoff(M), stoff(M), pvoff(M), sgoff(M), vxoff(M);
+  auto al = al32;
   for (int s = 0; s < M; ++s) {
     const int64_t pc = p.acap[s] + p.bcap[s];
     const int nseg = (int)(p.nlist[s].size() + p.wlist[s].size());
-    poff[s] = fd; fd += al((int64_t)p.m[s] * (p.m[s] + pc));
-    toff[s] = fd; fd += al(p.kcap[s]);
-    noff[s] = fd; fd += al(pc);
-    if (want_gi && p.m[s] > 0 && p.m[s] <= kInvMaxDofs) {
-      gioff[s] = fd;
-      fd += al((int64_t)p.m[s] * p.m[s]);
-    }
     csoff[s] = fi; fi += al(pc);
     cnoff[s] = fi; fi += al(pc);
     stoff[s] = fi; fi += al(pc);
@@ -221,7 +306,6 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     sgoff[s] = fi; fi += al(nseg + 1);
     vxoff[s] = fv; fv += al(pc);
   }
-  HIPCHK(dalloc(&L->fac, sizeof(double) * fd, st));
   HIPCHK(dalloc(&L->fints, sizeof(int32_t) * fi, st));
   HIPCHK(dalloc(&L->fvidx, sizeof(int64_t) * fv, st));
   L->sbase = sbase;
@@ -328,7 +412,6 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
                o3 = o2 + ((bw + 255) & ~(size_t)255), o4 = o3 + ((bi + 255) & ~(size_t)255);
   HIPCHK(dalloc(&L->desc, o4 + bc, st));
   char* db = reinterpret_cast<char*>(L->desc.p);
-  double* F = at<double>(L->fac, 0);
   int32_t* FI = at<int32_t>(L->fints, 0);
   int64_t* FV = at<int64_t>(L->fvidx, 0);
   for (int idx = 0; idx < M; ++idx) {
@@ -345,10 +428,6 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     it.pair = reinterpret_cast<const PairD*>(db + o1) + pair0[s];
     it.wb = reinterpret_cast<const WbD*>(db + o2) + wb0[s];
     it.D = W + p.d_off[s];
-    it.P = F + poff[s];
-    it.Gi = gioff[s] >= 0 ? F + gioff[s] : nullptr;
-    it.tau = F + toff[s];
-    it.norms = F + noff[s];
     it.colseg = FI + csoff[s];
     it.colnat = FI + cnoff[s];
     it.stepof = FI + stoff[s];
@@ -357,6 +436,7 @@ lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase, const LevelSta
     it.vidx = FV + vxoff[s];
     it.voff = L->voff[s];
   }
+  point_items(p, lay, F, &items);
   std::vector<char> blob(o4 + bc, 0);
   if (bs) std::memcpy(blob.data(), segs.data(), bs);
   if (bp) std::memcpy(blob.data() + o1, pairs.data(), bp);

@@ -85,6 +85,23 @@ T* at(const DevBuf& b, int64_t off) {
 
 uint64_t next_level_id();
 
+// Workspace of the panels (with the inverses, tau and norms) shared by the
+// levels of one tree's factorizations: a level needs its panels only while it
+// is eliminated (the sweeps read the factor stores), so every level lays them
+// out from the arena's start.
+struct PanelArena {
+  DevBuf buf;
+  uint64_t gen = 0;              // advanced whenever buf is allocated anew
+  hipStream_t stream = nullptr;  // stream of the last user
+  bool used = false;
+};
+// Before a factorization on stream st works in the arena: waits for the
+// last user's stream when it is another.
+void arena_use(PanelArena* arena, hipStream_t st);
+// Makes the arena hold at least `doubles` (allocated anew, with a new
+// generation, when it is smaller); includes arena_use.
+lrsp_status arena_reserve(PanelArena* arena, int64_t doubles, hipStream_t st);
+
 // Device storage, descriptors and results of one planned tree level.
 struct LevelDev {
   const uint64_t id = next_level_id();  // unique per workspace
@@ -94,6 +111,10 @@ struct LevelDev {
   DevBuf work, wints;      // D / fine halves; posmaps and column lists
   DevBuf coarse;           // coarse halves (sized by the rank capacities)
   DevBuf fac;              // panels, inverses, tau, norms (doubles): the level's workspace
+                           // (empty when the level uses a shared arena)
+  uint64_t arena_gen = 0;  // generation of the shared arena the items point into
+  int64_t arena_off = 0;   // where in the arena the level's panels start (doubles)
+  int64_t arena_doubles = 0;
   DevBuf sol;              // factor stores (ItemD::S) of the clusters: what the sweeps read
   std::vector<int> sol_k, sol_a;  // ranks and near-field widths the stores are laid out for
   DevBuf fints;            // colseg, colnat, stepof, piv, segoff (int32)
@@ -175,7 +196,10 @@ lrsp_status upload(DevBuf* b, const void* src, size_t bytes, hipStream_t st);
 // sbase.. (items and segments carry the shifted ids) and items report their
 // errors also to *serr.
 lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase = 0,
-                        const LevelState* shared = nullptr, int32_t* serr = nullptr);
+                        const LevelState* shared = nullptr, int32_t* serr = nullptr,
+                        PanelArena* arena = nullptr);
+// Doubles of the panel workspace of a planned level (at its capacities).
+int64_t panel_doubles(const LevelDev& L);
 // The two phases of setup_level.  A: layout, work arena (diagonal blocks and
 // fine halves, cleared), column lists, vector offsets -- everything the
 // level's assembly needs, independent of the rank capacities.  B: coarse
@@ -183,7 +207,13 @@ lrsp_status setup_level(LevelDev* L, hipStream_t st, int64_t vbase, int sbase = 
 // may be called again after the capacities change.
 lrsp_status setup_level_a(LevelDev* L, hipStream_t st, int64_t vbase);
 lrsp_status setup_level_b(LevelDev* L, hipStream_t st, int sbase = 0,
-                          const LevelState* shared = nullptr, int32_t* serr = nullptr);
+                          const LevelState* shared = nullptr, int32_t* serr = nullptr,
+                          PanelArena* arena = nullptr);
+// Points the items of a level that uses the shared arena at its current
+// buffer (after the arena was allocated anew; the level's panels at
+// arena_off, which the caller has reserved) and uploads them to the level's
+// own item array.
+lrsp_status rebind_panels(LevelDev* L, hipStream_t st, PanelArena* arena);
 
 bool complete_graph(const std::vector<std::vector<int>>& adj);
 
