@@ -123,9 +123,12 @@ def run_gpu(args):
     for li in range(inf["nlevels"] + 1):
         st = F.level_stats(li)
         per.append(dict(level=li if li < inf["nlevels"] else "top", dofs=st["dofs"],
-                        factor_mb=round(st["factor_bytes"] / 1e6, 3), held_mb=round(st["held_bytes"] / 1e6, 3)))
+                        factor_mb=round(st["factor_bytes"] / 1e6, 3), held_mb=round(st["held_bytes"] / 1e6, 3),
+                        work_mb=round(st["work_bytes"] / 1e6, 3), coarse_mb=round(st["coarse_bytes"] / 1e6, 3),
+                        panel_mb=round(st["panel_bytes"] / 1e6, 3)))
     results["memory"] = dict(factor_bytes=inf["bytes_factor"], factor_bytes_per_dof=round(inf["bytes_factor"] / pr.n, 1),
-                             peak_bytes=inf["peak_bytes"], per_level=per)
+                             peak_bytes=inf["peak_bytes"], first_factor_peak_bytes=analysis_info["peak_bytes"],
+                             per_level=per)
     log(f"[memory] {results['memory']}")
     del F
     if TOP_DENSE > 0:
@@ -541,6 +544,38 @@ def run_learned(args):
                        rank_reruns=inf["rank_reruns"])
         out[name] = {k: (round(v, 4) if isinstance(v, float) and k != "relres" else v) for k, v in rec.items()}
         log(f"[learned {name}] {out[name]}")
+        if name == "plain_f64":
+            # refactorizations of the same pattern: the tree's cache sizes
+            # every level from the ranks it found before (the first of them
+            # lays the levels out again), the second is the steady state
+            for rep in range(2):
+                del F
+                torch.cuda.synchronize()
+                lrsp.timing_reset()
+                lrsp.timing_families(["eliminate"])
+                lrsp.timing_enable(True)
+                t0 = time.perf_counter()
+                F = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                lrsp.timing_enable(False)
+                lrsp.timing_families(None)
+                inf = F.info()
+            tot = {key: 0 for key in ("factor_bytes", "work_bytes", "coarse_bytes", "panel_bytes")}
+            pmax = 0
+            for li in range(inf["nlevels"]):
+                st = F.level_stats(li)
+                for key in ("factor_bytes", "work_bytes", "coarse_bytes"):
+                    tot[key] += st[key]
+                pmax = max(pmax, st["panel_bytes"])
+            tot["panel_bytes"] = pmax
+            out["plain_f64_refactor_bytes"] = tot
+            out["plain_f64_refactor"] = dict(factor_ms=round((t1 - t0) * 1e3, 4),
+                                             eliminate_gpu_ms=round(lrsp.timing_read("eliminate")["total_ms"], 4),
+                                             peak_bytes=inf["peak_bytes"], factor_bytes=inf["bytes_factor"],
+                                             levels_reused=inf["levels_reused"],
+                                             rank_redo_levels=inf["rank_redo_levels"])
+            log(f"[learned plain_f64_refactor] {out['plain_f64_refactor']}")
         del F, tree
         torch.cuda.synchronize()
     # like for like (same fp32 Schur products): whole first factorization +

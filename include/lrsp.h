@@ -248,7 +248,9 @@ typedef struct {
   double flops[6];       /* algorithmic flops: potrf, trsm, cpqr, applyq, schur, top */
   double bytes_factor;   /* bytes of the stored factor */
   double ms_levels;      /* wall time of lrsp_factor (host clock, ms) */
-  int64_t peak_bytes;    /* device bytes held by the factor */
+  int64_t peak_bytes;    /* device bytes held while the factorization ran:
+                            the factor, the tree's cached level workspaces
+                            and the panel arena */
   double ms_analysis;    /* host time spent on symbolic analysis and setup
                             (zero for levels whose analysis was reused) */
   int32_t levels_reused; /* levels whose analysis and workspace came from the
@@ -260,6 +262,9 @@ typedef struct {
   double rank_bytes_worst;    /* the same with worst-case capacities min(m, b) */
   int32_t rank_checks_passed; /* clusters whose rank k <= the predicted k_hat */
   int32_t rank_checks_failed; /* clusters whose QR went on past k_hat */
+  /* any rank_mode: a level the tree's cache held is sized from the ranks it
+   * found before (k + max(2, k/4)); a rank that reaches such a capacity, or
+   * a predicted one, makes the level run again with more room: */
   int32_t rank_redo_levels;   /* levels run again because a rank reached
                                  its capacity (each level counted once) */
   int32_t rank_reruns;        /* runs of levels after the first, in all */
@@ -295,9 +300,13 @@ lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_l
  * (lrsp_apply, and those inside lrsp_pcg / lrsp_gmres) -- both 0 unless
  * timing (lrsp_timing_enable) was on during lrsp_factor and during the
  * applications.  factor_bytes: device bytes of the level's part of the
- * factor (what the sweeps read, with the panels the level is eliminated in);
- * held_bytes: all device bytes the level holds (its work arenas too), the
- * dense top's for level == nlevels.  Synchronises the device. */
+ * factor (the factor stores the sweeps read and the vector indices);
+ * held_bytes: all device bytes the level holds (its workspaces too), the
+ * dense top's for level == nlevels; of those, work_bytes: the level-start
+ * blocks (diagonal blocks and fine halves), coarse_bytes: the coarse halves
+ * (sized by the rank capacities); panel_bytes: the level's share of the
+ * panel workspace while it is eliminated (held in the tree's arena, not in
+ * held_bytes).  Synchronises the device. */
 typedef struct {
   double flops;
   double sweep_bytes;
@@ -310,6 +319,9 @@ typedef struct {
   int32_t reserved;
   int64_t factor_bytes;
   int64_t held_bytes;
+  int64_t work_bytes;
+  int64_t coarse_bytes;
+  int64_t panel_bytes;
 } lrsp_level_stats;
 lrsp_status lrsp_factor_level_stats(const lrsp_factorization* F, int32_t level, lrsp_level_stats* out);
 

@@ -210,6 +210,14 @@ lrsp_status lrsp_factor_free(lrsp_factorization* F) {
   return LRSP_OK;
 }
 
+// Rank capacities of a level from the ranks k a previous factorization of the
+// same pattern found: k plus a quarter, at least 2 more.
+static std::vector<int> reuse_caps(const std::vector<int>& k) {
+  std::vector<int> c(k.size());
+  for (size_t i = 0; i < k.size(); ++i) c[i] = k[i] + std::max(2, k[i] / 4);
+  return c;
+}
+
 // *retry: set when a level assumed the ranks of the previous factorization
 // wrongly; the caller then runs factor_impl again, which no longer assumes.
 static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, const lrsp_opts* opts,
@@ -337,6 +345,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       const int Ms = Ls->plan.M;
       const int32_t* h = Ls->h_kab;
       const int32_t* e = h + 3 * Ms;
+      if (e[0] && e[3] == kErrCapacity) {  // a rank outgrew a capacity: run again, per level
+        cache->spec_ok = false;
+        *retry = true;
+        return 1;
+      }
       if (e[0]) {
         if (e[3] == kErrNotSPD)
           *err = fail(LRSP_ERR_NOT_SPD, "non-positive pivot in the diagonal block of cluster " +
@@ -356,6 +369,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     specs.clear();
     return 0;
   };
+  // a level whose coarse halves were allocated anew: the assembly tasks of
+  // the next level, which copy from them, are built again
+  auto next_level_tasks_stale = [&](int l) {
+    if ((int)cache->levels.size() > l + 1 && cache->levels[l + 1]) cache->levels[l + 1]->tasks_src = 0;
+  };
   while (true) {
     const int M = (int)sizes.size();
     if (M == 1 || complete_graph(adj)) break;
@@ -369,7 +387,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     // the split schedule (auto or forced) needs room for explicit inverses
     const bool want_gi = !nodc && (o.exec_mode == 0 || o.exec_mode == 3);
     if (!learned && (int)cache->levels.size() > level && cache->levels[level] &&
-        !cache->levels[level]->capped && (cache->levels[level]->want_gi || !want_gi) &&
+        (cache->levels[level]->want_gi || !want_gi) &&
         cache->levels[level]->plan.m == sizes && cache->levels[level]->vbase == vbase) {
       Lp = std::move(cache->levels[level]);
       reuse = true;
@@ -394,9 +412,19 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       launch_zero(at<double>(Lp->work, 0), Lp->plan.work_doubles, st);
       launch_zero(at<double>(Lp->coarse, 0), Lp->plan.coarse_doubles, st);
       launch_zero_i32(at<int32_t>(Lp->state, 0), 4 * (int64_t)M + 8, st);
-      // the shared panel arena may have been allocated anew since the level
-      // last ran
-      if (Lp->arena_gen != cache->arena.gen) {
+      if (!Lp->capped && (int)Lp->k.size() == M) {
+        // the level ran before with the worst-case rank capacities: from now
+        // on the ranks it found, with some room, size its coarse halves and
+        // panels (a rank that outgrows them makes the level run again with
+        // more room, as with learned ranks)
+        Lp->caps = reuse_caps(Lp->k);
+        plan_capacities(&Lp->plan, &Lp->caps);
+        Lp->capped = true;
+        Lp->cap_tries = 0;
+        if (lrsp_status s = setup_level_b(Lp.get(), st, 0, nullptr, nullptr, &cache->arena)) return s;
+        next_level_tasks_stale(level);
+      } else if (Lp->arena_gen != cache->arena.gen) {
+        // the shared panel arena was allocated anew since the level last ran
         if (lrsp_status s = rebind_panels(Lp.get(), st, &cache->arena)) return s;
       } else {
         arena_use(&cache->arena, st);
@@ -517,8 +545,9 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
       herr.assign(kab.begin() + 3 * M, kab.end());
     }
     if (herr[0] && herr[3] == kErrCapacity && L->capped) {
-      // a rank reached its predicted capacity: the clusters whose QR stopped
-      // at a capacity below their worst case min(m, b) get the worst case,
+      // a rank reached its capacity (predicted, or from the ranks found
+      // before): the clusters whose QR stopped at a capacity below their
+      // worst case min(m, b) get the worst case,
       // the others keep theirs, and the level runs again from its assembled
       // input.  A cluster eliminated after a truncated one can see other
       // values in the new run, so this repeats, at most kCapRetries times
@@ -540,6 +569,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
         L->capped = false;
       }
       if (lrsp_status s = setup_level_b(L, st, 0, nullptr, nullptr, &cache->arena)) return s;
+      next_level_tasks_stale(level);
       launch_zero(at<double>(L->work, 0), L->plan.work_doubles, st);
       if (level == 0) {
         launch_scatter_vals(A->val, at<int64_t>(L->vals_off, 0), A->nnz, at<double>(L->work, 0), st);
@@ -679,6 +709,17 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   // every level reused and every rank as the workspace held it (the assumed
   // ones were just checked): the next factorization may assume them
   cache->spec_ok = !learned && level > 0 && reused == level && same_ranks;
+  const size_t arena_held = cache->arena.buf.bytes;  // held while the levels ran
+  {  // an arena far larger than this factorization's levels needed (sized by
+     // worst-case capacities before) is given back; the next factorization
+     // allocates what it needs
+    int64_t need = 0;
+    for (auto& L : F->levels) need = std::max(need, L->arena_off + L->arena_doubles);
+    if (cache->arena.buf.bytes > sizeof(double) * (size_t)need + (sizeof(double) * (size_t)need) / 2) {
+      dfree(&cache->arena.buf, st);
+      ++cache->arena.gen;
+    }
+  }
   if (herr[0]) return fail(LRSP_ERR_NOT_SPD, "non-positive pivot in the dense top factorization");
   flops[5] = (double)ntop * ntop * ntop / 3.0;
   F->top_vbase = vbase;
@@ -706,7 +747,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   inf.rank_reruns = cap_reruns;
   int64_t held = 0;
   for (auto& L : F->levels) held += L->held_bytes();
-  inf.peak_bytes = held + (int64_t)(F->top.bytes + F->vec.bytes + F->perm.bytes + cache->arena.buf.bytes);
+  inf.peak_bytes = held + (int64_t)(F->top.bytes + F->vec.bytes + F->perm.bytes + arena_held);
   *out = F.release();
   return LRSP_OK;
 }
@@ -1143,6 +1184,9 @@ lrsp_status lrsp_factor_level_stats(const lrsp_factorization* F, int32_t level, 
     r.nclusters = L.plan.M;
     r.factor_bytes = L.factor_bytes();
     r.held_bytes = L.held_bytes();
+    r.work_bytes = (int64_t)(L.work.bytes + L.wints.bytes);
+    r.coarse_bytes = (int64_t)L.coarse.bytes;
+    r.panel_bytes = L.fac.p ? (int64_t)L.fac.bytes : 8 * L.arena_doubles;
   } else {
     r.flops = F->info.flops[5];
     r.dofs = F->top_n;

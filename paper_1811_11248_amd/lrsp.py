@@ -71,7 +71,8 @@ class LevelStats(C.Structure):
     _fields_ = [("flops", C.c_double), ("sweep_bytes", C.c_double), ("factor_ms", C.c_double),
                 ("solve_ms", C.c_double), ("applies", C.c_int64), ("dofs", C.c_int64), ("coarse", C.c_int64),
                 ("nclusters", C.c_int32), ("reserved", C.c_int32), ("factor_bytes", C.c_int64),
-                ("held_bytes", C.c_int64)]
+                ("held_bytes", C.c_int64), ("work_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
+                ("panel_bytes", C.c_int64)]
 
 
 class BatchInfo(C.Structure):

@@ -321,6 +321,37 @@ def test_factor_is_deterministic(torch, L):
             assert ks[0] == ks[1] and torch.equal(xs[0], xs[1])
 
 
+def test_factor_store_and_panel_arena(torch, L):
+    """The factor keeps per cluster only what the sweeps read (its bytes are
+    the levels' store bytes plus the dense top, below what the levels hold
+    while they are factored); the panel workspace is one arena per tree, so
+    that factorizations of one tree on two streams, one after the other and
+    then a third while the first two are alive, all give the oracle's
+    preconditioner and the same bits."""
+    pr, Fo = _oracle("slab_split")
+    A = L.DeviceMatrix.from_problem(pr)
+    tree = L.Tree(pr.grid, 128)
+    b = torch.from_numpy(rhs(pr.n, 0)).cuda()
+    xo = oracle.solve(Fo, rhs(pr.n, 0))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    F1 = L.Factor(A, tree, 1e-2, stream=s1)
+    F2 = L.Factor(A, tree, 1e-2, stream=s2)
+    F3 = L.Factor(A, tree, 1e-2, stream=s1)
+    xs = [L.apply(F, b, stream=st) for F, st in ((F1, s1), (F2, s2), (F3, s1))]
+    torch.cuda.synchronize()
+    for x in xs:
+        assert torch.equal(x, xs[0])
+    x = xs[0].cpu().numpy()
+    assert np.linalg.norm(x - xo) <= APPLY_TOL * np.linalg.norm(xo)
+    inf = F1.info()
+    st = [F1.level_stats(li) for li in range(inf["nlevels"] + 1)]
+    assert inf["bytes_factor"] == sum(q["factor_bytes"] for q in st[:-1]) + 8 * inf["top_n"] ** 2
+    for q in st[:-1]:
+        assert 0 < q["factor_bytes"] < q["held_bytes"]
+    _say(f"[factor store] {inf['bytes_factor'] / pr.n:.0f} bytes per DoF, peak {inf['peak_bytes'] / pr.n:.0f}")
+
+
 def test_precision_workload_full_size(torch, L):
     """The 128x128x20 two-component workload (655,360 DoF) at full size: the
     fp64 path against the fp64 oracle (schedule and ranks bit for bit, M^{-1} b
