@@ -274,8 +274,10 @@ lrsp_status lrsp_factor_info(const lrsp_factorization* F, lrsp_info* info);
 /* Per-level schedule and ranks (host arrays owned by F, valid until freed):
  * nclusters, sizes[c] (DoFs at level start), colour[c], order[i] (the i-th
  * processed cluster), ranks[c] (coarse DoFs kept), and the level graph in
- * CSR form (adj_ptr[nclusters+1], adj[]).  level == nlevels describes the
- * dense top (colour/order/ranks NULL). */
+ * CSR form (adj_ptr[nclusters+1], adj[]); near[c] and far[c]: the columns
+ * of cluster c's near- and far-field blocks when it was eliminated (a and
+ * b, structurally nonzero columns only).  level == nlevels describes the
+ * dense top (colour/order/ranks/near/far NULL). */
 typedef struct {
   int32_t nclusters;
   int32_t ncolours;
@@ -285,6 +287,8 @@ typedef struct {
   const int32_t* ranks;
   const int32_t* adj_ptr;
   const int32_t* adj;
+  const int32_t* near;
+  const int32_t* far;
 } lrsp_level_view;
 lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_level_view* v);
 

@@ -1228,6 +1228,8 @@ lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_l
     v->ranks = nullptr;
     v->adj_ptr = F->top_adj_ptr.data();
     v->adj = F->top_adj.data();
+    v->near = nullptr;
+    v->far = nullptr;
     return LRSP_OK;
   }
   const LevelDev& L = *F->levels[level];
@@ -1239,6 +1241,8 @@ lrsp_status lrsp_factor_level(const lrsp_factorization* F, int32_t level, lrsp_l
   v->ranks = L.k.data();
   v->adj_ptr = L.adj_ptr.data();
   v->adj = L.adj.data();
+  v->near = L.a.data();
+  v->far = L.b.data();
   return LRSP_OK;
 }
 

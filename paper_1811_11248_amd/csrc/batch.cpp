@@ -1161,6 +1161,8 @@ lrsp_status lrsp_batch_level(const lrsp_batch* F, int32_t sys, int32_t level, lr
     v->ranks = nullptr;
     v->adj_ptr = S.top_adj_ptr.data();
     v->adj = S.top_adj.data();
+    v->near = nullptr;
+    v->far = nullptr;
     return LRSP_OK;
   }
   const LevelDev& L = *S.levels[level];
@@ -1172,6 +1174,8 @@ lrsp_status lrsp_batch_level(const lrsp_batch* F, int32_t sys, int32_t level, lr
   v->ranks = L.k.data();
   v->adj_ptr = L.adj_ptr.data();
   v->adj = L.adj.data();
+  v->near = L.a.data();
+  v->far = L.b.data();
   return LRSP_OK;
 }
 

@@ -64,7 +64,8 @@ class LevelView(C.Structure):
     _fields_ = [("nclusters", C.c_int32), ("ncolours", C.c_int32),
                 ("sizes", C.POINTER(C.c_int32)), ("colour", C.POINTER(C.c_int32)),
                 ("order", C.POINTER(C.c_int32)), ("ranks", C.POINTER(C.c_int32)),
-                ("adj_ptr", C.POINTER(C.c_int32)), ("adj", C.POINTER(C.c_int32))]
+                ("adj_ptr", C.POINTER(C.c_int32)), ("adj", C.POINTER(C.c_int32)),
+                ("near", C.POINTER(C.c_int32)), ("far", C.POINTER(C.c_int32))]
 
 
 class LevelStats(C.Structure):
@@ -332,6 +333,8 @@ def _level_dict(v: LevelView) -> dict:
            "graph": [adj[ptr[c]:ptr[c + 1]].tolist() for c in range(M)]}
     if v.colour:
         out.update(colour=arr(v.colour, M), order=arr(v.order, M), ranks=arr(v.ranks, M))
+    if v.near:
+        out.update(near=arr(v.near, M), far=arr(v.far, M))
     return out
 
 
