@@ -233,7 +233,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   if (opts) o = *opts;
   if (o.gemm_prec < 0 || o.gemm_prec > 2 || o.tol_mode < 0 || o.tol_mode > 1 || o.exec_mode < 0 ||
       o.exec_mode > 3 || o.rank_mode < 0 || o.rank_mode > 1 || o.autotune < 0 || o.autotune > 1 ||
-      o.top_dense_threshold < 0 || o.top_dense_threshold > kMaxClusterDofs || o.scheme < 0 || o.scheme > 1)
+      o.top_dense_threshold < 0 || o.top_dense_threshold > kTopMaxDofs || o.scheme < 0 || o.scheme > 1)
     return fail(LRSP_ERR_ARG, "invalid option");
   const bool learned = o.rank_mode == 1;
   if (learned && !o.mlp_weights) return fail(LRSP_ERR_ARG, "rank_mode 1 needs mlp_weights");
@@ -654,8 +654,8 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   std::vector<int64_t> toff(M + 1, 0);
   for (int x = 0; x < M; ++x) toff[x + 1] = toff[x] + sizes[x];
   ntop = (int)toff[M];
-  if (ntop > kMaxClusterDofs)
-    return fail(LRSP_ERR_ARG, "dense top system larger than " + std::to_string(kMaxClusterDofs));
+  if (ntop > kTopMaxDofs)
+    return fail(LRSP_ERR_ARG, "dense top system larger than " + std::to_string(kTopMaxDofs));
   F->top_n = ntop;
   F->top_level = level;
   F->top_sizes = sizes;
@@ -664,7 +664,9 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     F->top_adj.insert(F->top_adj.end(), adj[x].begin(), adj[x].end());
     F->top_adj_ptr.push_back((int)F->top_adj.size());
   }
-  HIPCHK(dalloc(&F->top, sizeof(double) * std::max<int64_t>(1, (int64_t)ntop * ntop), st));
+  // n x (n + 64): the blocked Cholesky of large tops forms its diagonal
+  // blocks' inverses in the last 64 columns
+  HIPCHK(dalloc(&F->top, sizeof(double) * std::max<int64_t>(1, (int64_t)ntop * (ntop + 64)), st));
   double* Tm = at<double>(F->top, 0);
   launch_zero(Tm, (int64_t)ntop * ntop, st);
   if (level == 0) {
@@ -691,6 +693,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   HIPCHK(dalloc(&terr, 16, st));
   launch_zero_i32(at<int32_t>(terr, 0), 4, st);
   if (ntop >= 64 && ntop <= kSplitMaxDofs) launch_top_potrf_wg(Tm, ntop, at<int32_t>(terr, 0), st);
+  else if (ntop > kSplitMaxDofs) launch_top_potrf_blocked(Tm, ntop, at<int32_t>(terr, 0), 0, st);
   else launch_top_potrf(Tm, ntop, at<int32_t>(terr, 0), st);
   HIPCHK(hipGetLastError());
   if (g_tm.on) {

@@ -199,6 +199,16 @@ lrsp_status upload_vec(DevBuf* b, const void* src, size_t bytes, hipStream_t st)
   return upload(b, src, bytes, st);
 }
 
+// Tops of more than kSplitMaxDofs unknowns: the blocked Cholesky, system by
+// system (their error bit as the batched kernels report it).
+void top_potrf_large(lrsp_batch* F, hipStream_t st) {
+  for (int i = 0; i < F->nsys; ++i) {
+    BSys& S = F->sys[i];
+    if (S.top_n > kSplitMaxDofs)
+      launch_top_potrf_blocked(at<double>(S.top, 0), S.top_n, at<int32_t>(F->serr, i), 1, st);
+  }
+}
+
 // Clears and assembles the input of block B (levels and tops starting at B).
 void assemble(const BLevel& B, hipStream_t st) {
   if (B.Mtot > 0) launch_zero_i32(B.ls.k, 4 * (int64_t)B.Mtot + 8, st);
@@ -484,7 +494,7 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
         S.top_adj.insert(S.top_adj.end(), S.adj[x].begin(), S.adj[x].end());
         S.top_adj_ptr.push_back((int)S.top_adj.size());
       }
-      HIPCHK(dalloc(&S.top, sizeof(double) * std::max<int64_t>(1, (int64_t)S.top_n * S.top_n), st));
+      HIPCHK(dalloc(&S.top, sizeof(double) * std::max<int64_t>(1, (int64_t)S.top_n * (S.top_n + 64)), st));
       zeros.push_back(SpanD{at<double>(S.top, 0), (int64_t)S.top_n * S.top_n});
       F->max_top = std::max(F->max_top, S.top_n);
       if (l == 0) {
@@ -669,6 +679,7 @@ lrsp_status batch_factor(lrsp_batch* F, const lrsp_csr* A, const TreeH* const* T
   }
   if (lrsp_status s = upload(&F->tops, tops.data(), tops.size() * sizeof(TopD), st)) return s;
   launch_top_potrf_batched(at<TopD>(F->tops, 0), nsys, F->max_top, st);
+  top_potrf_large(F, st);
   HIPCHK(hipGetLastError());
   std::vector<int32_t> se(nsys);
   HIPCHK(hipMemcpyAsync(se.data(), F->serr.p, 4 * (size_t)nsys, hipMemcpyDeviceToHost, st));
@@ -721,6 +732,7 @@ lrsp_status numeric_phase(lrsp_batch* F, bool graph, hipStream_t st) {
     if (B.Mtot > 0) launch_compact(B.d_items, B.cstart.back(), B.ls, st);
   }
   launch_top_potrf_batched(at<TopD>(F->tops, 0), F->nsys, F->max_top, st);
+  top_potrf_large(F, st);
   HIPCHK(hipGetLastError());
   return LRSP_OK;
 }

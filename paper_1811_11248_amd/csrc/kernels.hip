@@ -2835,12 +2835,240 @@ __global__ void __launch_bounds__(kThreads) top_solve_kernel(const double* L, in
   for (int i = threadIdx.x; i < n; i += kThreads) yg[i] = y[i];
 }
 
+// y <- G^{-T} y for G lower (m x m, ld) of any size, y in LDS: from the last
+// 64-row block up, the dot products of the block's columns below the block
+// with y (one wave per column, four columns at a time, y read from LDS),
+// then the diagonal block transposed in wave 0.
+__device__ __forceinline__ void trsv_lower_t_lds(const double* G, int ld, int m, double* y, double* blk) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nblk = (m + 63) / 64;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int jb = bi * 64;
+    const int w = min(64, m - jb);
+    const int r0 = jb + w;
+    load_block_rowmajor<kThreads>(blk, kBlkLd, G + (size_t)jb * ld + jb, (size_t)ld, w, 64,
+                                  [&](int r, int c) { return c < w && c <= r; });
+    for (int t0 = wv * 4; t0 < w; t0 += kWaves * 4) {
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = r0 + lane; i < m; i += 64) {
+        const double yi = y[i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] += G[(size_t)i + (size_t)ld * (jb + min(t0 + q, w - 1))] * yi;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double sq = wave_sum(s[q]);
+        if (lane == 0 && t0 + q < w) y[jb + t0 + q] -= sq;
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const double rd = 1.0 / (lane < w ? blk[lane * kBlkLd + lane] : 1.0);
+      double yl = (lane < w) ? y[jb + lane] : 0.0;
+#pragma unroll 8
+      for (int t = 63; t >= 0; --t) {
+        if (t < w) {
+          const double yt = readlane_d(yl, t) * readlane_d(rd, t);
+          if (lane == t) yl = yt;
+          else if (lane < t) yl -= blk[t * kBlkLd + lane] * yt;
+        }
+      }
+      if (lane < w) y[jb + lane] = yl;
+    }
+    __syncthreads();
+  }
+}
+
+// Tops beyond kMaxClusterDofs unknowns (up to kTopMaxDofs).
+__global__ void __launch_bounds__(kThreads) top_solve_big_kernel(const double* L, int n, double* yg) {
+  extern __shared__ double lds[];
+  double* y = lds;
+  double* blk = lds + ((n + 63) / 64) * 64;  // 64*65 doubles
+  for (int i = threadIdx.x; i < n; i += kThreads) y[i] = yg[i];
+  __syncthreads();
+  trsv_lower(L, n, n, y, blk);
+  trsv_lower_t_lds(L, n, n, y, blk);
+  for (int i = threadIdx.x; i < n; i += kThreads) yg[i] = y[i];
+}
+
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
   if (n <= 0) return;
+  size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * kBlkLd) * sizeof(double);
+  if (n > kMaxClusterDofs) {
+    static bool lds_big = false;
+    allow_lds(reinterpret_cast<const void*>(top_solve_big_kernel), &lds_big);
+    hipLaunchKernelGGL(top_solve_big_kernel, dim3(1), dim3(kThreads), lds, st, L, n, y);
+    return;
+  }
   static bool lds_ok = false;
   allow_lds(reinterpret_cast<const void*>(top_solve_kernel), &lds_ok);
-  size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * kBlkLd) * sizeof(double);
   hipLaunchKernelGGL(top_solve_kernel, dim3(1), dim3(kThreads), lds, st, L, n, y);
+}
+
+
+// ---------------------------------------------------------------------------
+// Dense tops larger than one workgroup's Cholesky (kSplitMaxDofs < n <=
+// kTopMaxDofs): right-looking blocked Cholesky over blocks of kTB columns.
+// Step p: every row tile below the diagonal takes its panel tile L_ip =
+// A_ip L_pp^{-T} (one workgroup each, a 64x64x64 product on MFMA f64 with
+// the inverse of the diagonal block), then every tile of the trailing lower
+// triangle takes A_ij -= L_ip L_jp^T (one workgroup each); the workgroup of
+// tile (p+1, p+1) goes on to factor it and to form its inverse.  The buffer
+// holds n x (n + kTB) doubles (ld n): the last kTB columns receive, in the
+// rows of each diagonal block, that block's inverse.
+constexpr int kTB = 64, kTLd = kTB + 1;
+
+// Row-major kTB x kTB tile (rows r0.., columns c0.. of the column-major A,
+// ld) into LDS with row stride kTLd; entries beyond nr rows or nc columns
+// are zeros.
+__device__ __forceinline__ void load_tile(const double* A, size_t ld, int r0, int c0, int nr, int nc, double* T) {
+  for (int e0 = threadIdx.x; e0 < kTB * kTB; e0 += kThreads * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads, c = e / kTB, r = e - c * kTB;
+      v[u] = (e < kTB * kTB && r < nr && c < nc) ? A[(size_t)(r0 + r) + ld * (size_t)(c0 + c)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads, c = e / kTB, r = e - c * kTB;
+      if (e < kTB * kTB) T[r * kTLd + c] = v[u];
+    }
+  }
+}
+
+// X = As Bs^T for two kTB x kTB tiles in LDS: wave w computes the 32 x 32
+// quadrant (w / 2, w % 2) as 2 x 2 tiles of v_mfma_f64_16x16x4; acc[a][b][v]
+// is X(32 (w/2) + 16 a + 4 v + lane/16, 32 (w%2) + 16 b + lane%16).
+__device__ __forceinline__ void tile_abt(const double* As, const double* Bs, d4_t acc[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int s4 = 0; s4 < kTB / 4; ++s4) {
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = As[(r0 + 16 * a + lc) * kTLd + 4 * s4 + lr];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = Bs[(c0 + 16 * b + lc) * kTLd + 4 * s4 + lr];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+}
+
+// Factor of diagonal block q (lower, in place) and its inverse into the
+// extra columns; one workgroup.  A pivot that is not > 0 is reported in the
+// error words (bits == 0) or as the error bit of a batched system (bits !=
+// 0).  lds: kTB*kNB + kNB*kNB + kNB*256 doubles.
+__device__ __forceinline__ void dense_diag(double* A, int n, int q, double* lds, int32_t* err, int bits) {
+  __shared__ int sbad;
+  const int r0 = q * kTB, w = min(kTB, n - r0);
+  double* B = A + (size_t)n * n + r0;  // rows r0.. of the extra columns
+  for (int e = threadIdx.x; e < w * w; e += kThreads) {
+    const int c = e / w, r = e - c * w;
+    B[(size_t)r + (size_t)n * c] = r == c ? 1.0 : 0.0;
+  }
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  chol_solve(A + r0 + (size_t)n * r0, n, w, B, w, lds, &sbad);
+  __syncthreads();
+  if (sbad && threadIdx.x == 0) {
+    if (bits) atomicOr(err, 1 << kErrNotSPD);
+    else set_error(err, -1, -1, kErrNotSPD);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, int q, int32_t* err, int bits) {
+  extern __shared__ double lds[];
+  dense_diag(A, n, q, lds, err, bits);
+}
+
+// Panel tiles of step p: workgroup b takes row tile i = p + 1 + b.
+__global__ void __launch_bounds__(kThreads) dense_panel_kernel(double* A, int n, int p) {
+  extern __shared__ double lds[];
+  double* As = lds;
+  double* Bs = lds + kTB * kTLd;
+  const int i = p + 1 + blockIdx.x;
+  const int ri = i * kTB, rp = p * kTB;
+  const int ni = min(kTB, n - ri), np = min(kTB, n - rp);
+  load_tile(A, n, ri, rp, ni, np, As);                      // A_ip
+  load_tile(A + (size_t)n * n, n, rp, 0, np, np, Bs);       // L_pp^{-1}
+  __syncthreads();
+  d4_t acc[2][2];
+  tile_abt(As, Bs, acc);  // A_ip L_pp^{-T}
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 32 * (w >> 1) + 16 * a + 4 * v + lr, c = 32 * (w & 1) + 16 * b + lc;
+        if (r < ni && c < np) A[(size_t)(ri + r) + (size_t)n * (rp + c)] = acc[a][b][v];
+      }
+}
+
+// Trailing update of step p: workgroup t takes lower tile (i, j), p < j <= i,
+// in row order of the triangle (t = 0 is (p+1, p+1), which then factors
+// diagonal block p + 1).
+__global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n, int p, int32_t* err, int bits) {
+  extern __shared__ double lds[];
+  double* As = lds;
+  double* Bs = lds + kTB * kTLd;
+  const int t = blockIdx.x;
+  int ii = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+  while (ii * (ii + 1) / 2 > t) --ii;
+  const int jj = t - ii * (ii + 1) / 2;
+  const int i = p + 1 + ii, j = p + 1 + jj;
+  const int ri = i * kTB, rj = j * kTB, rp = p * kTB;
+  const int ni = min(kTB, n - ri), nj = min(kTB, n - rj), np = min(kTB, n - rp);
+  load_tile(A, n, ri, rp, ni, np, As);  // L_ip
+  load_tile(A, n, rj, rp, nj, np, Bs);  // L_jp
+  __syncthreads();
+  d4_t acc[2][2];
+  tile_abt(As, Bs, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 32 * (w >> 1) + 16 * a + 4 * v + lr, c = 32 * (w & 1) + 16 * b + lc;
+        if (r < ni && c < nj && (i != j || r >= c)) {
+          double* x = A + (size_t)(ri + r) + (size_t)n * (rj + c);
+          *x = *x - acc[a][b][v];
+        }
+      }
+  if (t != 0) return;
+  __syncthreads();
+  dense_diag(A, n, p + 1, lds, err, bits);
+}
+
+void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st) {
+  if (n <= 0) return;
+  static bool done[3] = {false, false, false};
+  allow_lds(reinterpret_cast<const void*>(dense_diag_kernel), &done[0]);
+  allow_lds(reinterpret_cast<const void*>(dense_panel_kernel), &done[1]);
+  allow_lds(reinterpret_cast<const void*>(dense_update_kernel), &done[2]);
+  const size_t lds = (size_t)2 * kTB * kTLd * sizeof(double);
+  const size_t ldsd = ((size_t)kTB * kNB + kNB * kNB + kNB * 256) * sizeof(double);
+  const int nt = (n + kTB - 1) / kTB;
+  hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(kThreads), ldsd, st, A, n, 0, err, bits);
+  for (int p = 0; p + 1 < nt; ++p) {
+    const int T = nt - p - 1;
+    hipLaunchKernelGGL(dense_panel_kernel, dim3(T), dim3(kThreads), lds, st, A, n, p);
+    hipLaunchKernelGGL(dense_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), lds, st, A, n, p, err, bits);
+  }
 }
 
 // Dense tops of a batch: one workgroup per system.
@@ -2848,9 +3076,10 @@ __global__ void __launch_bounds__(kThreads) top_potrf_batched_kernel(const TopD*
   extern __shared__ double lds[];
   __shared__ int sbad;
   const TopD t = tops[blockIdx.x];
-  // tops of 64..512 unknowns take the blocked MFMA Cholesky (as a single
-  // system's top does, so that each system's factor is the same bits)
-  if (t.n <= 0 || (t.n >= 64 && t.n <= kSplitMaxDofs)) return;
+  // tops of 64..512 unknowns take the MFMA Cholesky of one workgroup, larger
+  // ones the blocked Cholesky over several (as a single system's top does,
+  // so that each system's factor is the same bits)
+  if (t.n <= 0 || t.n >= 64) return;
   if (threadIdx.x == 0) sbad = 0;
   __syncthreads();
   chol_solve(t.L, t.n, t.n, nullptr, 0, lds, &sbad);

@@ -87,6 +87,12 @@ void launch_top_solve(const double* L, int n, double* y, hipStream_t st);
 // Dense top by the blocked MFMA Cholesky of the split kernels (one
 // workgroup of 512 threads, n <= kSplitMaxDofs).
 void launch_top_potrf_wg(double* A, int n, int32_t* err, hipStream_t st);
+// Dense tops of kSplitMaxDofs < n <= kTopMaxDofs unknowns: blocked Cholesky
+// over several workgroups (A: n x (n + 64) doubles, ld n; the last 64
+// columns are workspace).  A non-positive pivot sets the error words (bits ==
+// 0) or the bit kErrNotSPD of *err (bits != 0, a batched system).
+constexpr int kTopMaxDofs = 4096;
+void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st);
 // The tops of a batch with 64..kSplitMaxDofs unknowns by the same kernel
 // (the others are skipped); max_n: their largest size.
 void launch_top_potrf_wg_batched(const TopD* tops, int ntops, int max_n, hipStream_t st);

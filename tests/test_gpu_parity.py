@@ -191,7 +191,12 @@ def test_not_spd_is_reported(torch, L):
     assert ex.value.status == L.ERR_NOT_SPD
 
 
-@pytest.mark.parametrize("name,thr", [("slab64_full", 768), ("laplace64", 300), ("vector_m160", 500)])
+@pytest.mark.parametrize("name,thr", [("slab64_full", 768), ("laplace64", 300), ("vector_m160", 500),
+                                      # tops beyond one workgroup (blocked Cholesky over several): 953
+                                      # unknowns, a ragged 715 (a partial last tile), the whole 4096-
+                                      # unknown Laplacian (the largest top), a two-component top
+                                      ("slab64_full", 2000), ("slab_ragged", 715), ("laplace64", 4096),
+                                      ("vector_m160", 1500)])
 @pytest.mark.parametrize("mode", MODES)
 def test_top_dense_threshold(torch, L, name, thr, mode):
     """The recursion also stops at the first level with at most thr unknowns
