@@ -2835,69 +2835,13 @@ __global__ void __launch_bounds__(kThreads) top_solve_kernel(const double* L, in
   for (int i = threadIdx.x; i < n; i += kThreads) yg[i] = y[i];
 }
 
-// y <- G^{-T} y for G lower (m x m, ld) of any size, y in LDS: from the last
-// 64-row block up, the dot products of the block's columns below the block
-// with y (one wave per column, four columns at a time, y read from LDS),
-// then the diagonal block transposed in wave 0.
-__device__ __forceinline__ void trsv_lower_t_lds(const double* G, int ld, int m, double* y, double* blk) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nblk = (m + 63) / 64;
-  for (int bi = nblk - 1; bi >= 0; --bi) {
-    const int jb = bi * 64;
-    const int w = min(64, m - jb);
-    const int r0 = jb + w;
-    load_block_rowmajor<kThreads>(blk, kBlkLd, G + (size_t)jb * ld + jb, (size_t)ld, w, 64,
-                                  [&](int r, int c) { return c < w && c <= r; });
-    for (int t0 = wv * 4; t0 < w; t0 += kWaves * 4) {
-      double s[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int i = r0 + lane; i < m; i += 64) {
-        const double yi = y[i];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] += G[(size_t)i + (size_t)ld * (jb + min(t0 + q, w - 1))] * yi;
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double sq = wave_sum(s[q]);
-        if (lane == 0 && t0 + q < w) y[jb + t0 + q] -= sq;
-      }
-    }
-    __syncthreads();
-    if (tid < 64) {
-      const double rd = 1.0 / (lane < w ? blk[lane * kBlkLd + lane] : 1.0);
-      double yl = (lane < w) ? y[jb + lane] : 0.0;
-#pragma unroll 8
-      for (int t = 63; t >= 0; --t) {
-        if (t < w) {
-          const double yt = readlane_d(yl, t) * readlane_d(rd, t);
-          if (lane == t) yl = yt;
-          else if (lane < t) yl -= blk[t * kBlkLd + lane] * yt;
-        }
-      }
-      if (lane < w) y[jb + lane] = yl;
-    }
-    __syncthreads();
-  }
-}
-
-// Tops beyond kMaxClusterDofs unknowns (up to kTopMaxDofs).
-__global__ void __launch_bounds__(kThreads) top_solve_big_kernel(const double* L, int n, double* yg) {
-  extern __shared__ double lds[];
-  double* y = lds;
-  double* blk = lds + ((n + 63) / 64) * 64;  // 64*65 doubles
-  for (int i = threadIdx.x; i < n; i += kThreads) y[i] = yg[i];
-  __syncthreads();
-  trsv_lower(L, n, n, y, blk);
-  trsv_lower_t_lds(L, n, n, y, blk);
-  for (int i = threadIdx.x; i < n; i += kThreads) yg[i] = y[i];
-}
+void launch_top_solve_coop(const double* L, int n, double* y, hipStream_t st);
 
 void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
   if (n <= 0) return;
   size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * kBlkLd) * sizeof(double);
   if (n > kMaxClusterDofs) {
-    static bool lds_big = false;
-    allow_lds(reinterpret_cast<const void*>(top_solve_big_kernel), &lds_big);
-    hipLaunchKernelGGL(top_solve_big_kernel, dim3(1), dim3(kThreads), lds, st, L, n, y);
+    launch_top_solve_coop(L, n, y, st);
     return;
   }
   static bool lds_ok = false;
@@ -2908,14 +2852,13 @@ void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // Dense tops larger than one workgroup's Cholesky (kSplitMaxDofs < n <=
-// kTopMaxDofs): right-looking blocked Cholesky over blocks of kTB columns.
-// Step p: every row tile below the diagonal takes its panel tile L_ip =
-// A_ip L_pp^{-T} (one workgroup each, a 64x64x64 product on MFMA f64 with
-// the inverse of the diagonal block), then every tile of the trailing lower
-// triangle takes A_ij -= L_ip L_jp^T (one workgroup each); the workgroup of
-// tile (p+1, p+1) goes on to factor it and to form its inverse.  The buffer
-// holds n x (n + kTB) doubles (ld n): the last kTB columns receive, in the
-// rows of each diagonal block, that block's inverse.
+// kTopMaxDofs): right-looking blocked Cholesky over blocks of kTB columns,
+// three launches per block: the diagonal block factored and inverted by one
+// wave in registers; every row tile below it, L_ip = A_ip L_pp^{-T} on MFMA
+// f64 (one workgroup each); every tile of the trailing lower triangle, A_ij
+// -= L_ip L_jp^T on MFMA f64 (one workgroup each).  The buffer holds n x (n
+// + kTB) doubles (ld n): the last kTB columns receive, in the rows of each
+// diagonal block, its inverse (read by the panel and by the solve).
 constexpr int kTB = 64, kTLd = kTB + 1;
 
 // Row-major kTB x kTB tile (rows r0.., columns c0.. of the column-major A,
@@ -2937,9 +2880,10 @@ __device__ __forceinline__ void load_tile(const double* A, size_t ld, int r0, in
   }
 }
 
-// X = As Bs^T for two kTB x kTB tiles in LDS: wave w computes the 32 x 32
-// quadrant (w / 2, w % 2) as 2 x 2 tiles of v_mfma_f64_16x16x4; acc[a][b][v]
-// is X(32 (w/2) + 16 a + 4 v + lane/16, 32 (w%2) + 16 b + lane%16).
+// X = As Bs^T for two kTB x kTB tiles in LDS (row stride kTLd): wave w
+// computes the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 tiles of
+// v_mfma_f64_16x16x4; acc[a][b][v] is X(32 (w/2) + 16 a + 4 v + lane/16,
+// 32 (w%2) + 16 b + lane%16).
 __device__ __forceinline__ void tile_abt(const double* As, const double* Bs, d4_t acc[2][2]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane >> 4, lc = lane & 15;
@@ -2962,46 +2906,11 @@ __device__ __forceinline__ void tile_abt(const double* As, const double* Bs, d4_
   }
 }
 
-// Factor of diagonal block q (lower, in place) and its inverse into the
-// extra columns; one workgroup.  A pivot that is not > 0 is reported in the
-// error words (bits == 0) or as the error bit of a batched system (bits !=
-// 0).  lds: kTB*kNB + kNB*kNB + kNB*256 doubles.
-__device__ __forceinline__ void dense_diag(double* A, int n, int q, double* lds, int32_t* err, int bits) {
-  __shared__ int sbad;
-  const int r0 = q * kTB, w = min(kTB, n - r0);
-  double* B = A + (size_t)n * n + r0;  // rows r0.. of the extra columns
-  for (int e = threadIdx.x; e < w * w; e += kThreads) {
-    const int c = e / w, r = e - c * w;
-    B[(size_t)r + (size_t)n * c] = r == c ? 1.0 : 0.0;
-  }
-  if (threadIdx.x == 0) sbad = 0;
-  __syncthreads();
-  chol_solve(A + r0 + (size_t)n * r0, n, w, B, w, lds, &sbad);
-  __syncthreads();
-  if (sbad && threadIdx.x == 0) {
-    if (bits) atomicOr(err, 1 << kErrNotSPD);
-    else set_error(err, -1, -1, kErrNotSPD);
-  }
-}
-
-__global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, int q, int32_t* err, int bits) {
-  extern __shared__ double lds[];
-  dense_diag(A, n, q, lds, err, bits);
-}
-
-// Panel tiles of step p: workgroup b takes row tile i = p + 1 + b.
-__global__ void __launch_bounds__(kThreads) dense_panel_kernel(double* A, int n, int p) {
-  extern __shared__ double lds[];
-  double* As = lds;
-  double* Bs = lds + kTB * kTLd;
-  const int i = p + 1 + blockIdx.x;
-  const int ri = i * kTB, rp = p * kTB;
-  const int ni = min(kTB, n - ri), np = min(kTB, n - rp);
-  load_tile(A, n, ri, rp, ni, np, As);                      // A_ip
-  load_tile(A + (size_t)n * n, n, rp, 0, np, np, Bs);       // L_pp^{-1}
-  __syncthreads();
-  d4_t acc[2][2];
-  tile_abt(As, Bs, acc);  // A_ip L_pp^{-T}
+// Stores acc (the tile_abt layout) into rows r0.., columns c0.. of A (ld):
+// op 0 stores, op 1 subtracts; rows >= nr, columns >= nc and, with lower,
+// entries above the diagonal are left alone.
+__device__ __forceinline__ void store_tile(double* A, size_t ld, int r0, int c0, int nr, int nc, bool lower, int op,
+                                           const d4_t acc[2][2]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane >> 4, lc = lane & 15;
 #pragma unroll
@@ -3011,14 +2920,89 @@ __global__ void __launch_bounds__(kThreads) dense_panel_kernel(double* A, int n,
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 32 * (w >> 1) + 16 * a + 4 * v + lr, c = 32 * (w & 1) + 16 * b + lc;
-        if (r < ni && c < np) A[(size_t)(ri + r) + (size_t)n * (rp + c)] = acc[a][b][v];
+        if (r < nr && c < nc && (!lower || r >= c)) {
+          double* x = A + (size_t)(r0 + r) + ld * (size_t)(c0 + c);
+          *x = op ? *x - acc[a][b][v] : acc[a][b][v];
+        }
       }
 }
 
-// Trailing update of step p: workgroup t takes lower tile (i, j), p < j <= i,
-// in row order of the triangle (t = 0 is (p+1, p+1), which then factors
-// diagonal block p + 1).
-__global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n, int p, int32_t* err, int bits) {
+// Diagonal block p of a large top in one wave: lane r holds row r of the
+// block (64 registers), column j of the Cholesky factor is formed with the
+// pivot and the multipliers broadcast by readlane; then lane c forms column
+// c of the inverse by forward substitution, the rows of the factor again
+// broadcast by readlane.  Stores L_pp (lower) in place and L_pp^{-1} in the
+// extra columns.  A pivot that is not > 0 is replaced by 1 and reported in
+// the error words (bits == 0) or as the error bit of a batched system.
+// (About 65 us per block: the serial part of the blocked factorization.)
+__global__ void __launch_bounds__(64) dense_diag_kernel(double* A, int n, int p, int32_t* err, int bits) {
+  const int lane = threadIdx.x;
+  const int rp = p * kTB, np = min(kTB, n - rp);
+  const bool on = lane < np;
+  double a[kTB];
+#pragma unroll
+  for (int c = 0; c < kTB; ++c)
+    a[c] = (on && c <= lane && c < np) ? A[(size_t)(rp + lane) + (size_t)n * (rp + c)] : (c == lane ? 1.0 : 0.0);
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < kTB; ++j) {
+    double d = readlane_d(a[j], j);
+    if (!(d > 0.0)) {
+      bad = bad || j < np;
+      d = 1.0;
+    }
+    const double piv = sqrt(d);
+    const double rs = 1.0 / piv;
+    a[j] = lane == j ? piv : (lane > j ? a[j] * rs : a[j]);
+#pragma unroll
+    for (int c = j + 1; c < kTB; ++c) {
+      const double lcj = readlane_d(a[j], c);
+      if (lane >= c) a[c] -= a[j] * lcj;
+    }
+  }
+  // column `lane` of L^{-1}: y[r] for r >= lane
+  double y[kTB];
+#pragma unroll
+  for (int r = 0; r < kTB; ++r) {
+    double s = r == lane ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < r; ++k) s -= readlane_d(a[k], r) * y[k];
+    y[r] = r >= lane ? s / readlane_d(a[r], r) : 0.0;
+  }
+  if (on) {
+#pragma unroll
+    for (int c = 0; c < kTB; ++c)
+      if (c <= lane) A[(size_t)(rp + lane) + (size_t)n * (rp + c)] = a[c];
+#pragma unroll
+    for (int r = 0; r < kTB; ++r)
+      if (r < np) A[(size_t)n * n + (size_t)(rp + r) + (size_t)n * lane] = y[r];
+  }
+  if (bad && lane == 0) {
+    if (bits) atomicOr(err, 1 << kErrNotSPD);
+    else set_error(err, -1, -1, kErrNotSPD);
+  }
+}
+
+// Panel launch of step p: workgroup b takes row tile i = p + 1 + b, L_ip =
+// A_ip L_pp^{-T} with the inverse from dense_diag_kernel.
+__global__ void __launch_bounds__(kThreads) dense_panel_kernel(double* A, int n, int p) {
+  extern __shared__ double lds[];
+  double* As = lds;
+  double* Bs = lds + kTB * kTLd;
+  const int i = p + 1 + blockIdx.x;
+  const int ri = i * kTB, rp = p * kTB;
+  const int ni = min(kTB, n - ri), np = min(kTB, n - rp);
+  load_tile(A, n, ri, rp, ni, np, As);                 // A_ip
+  load_tile(A + (size_t)n * n, n, rp, 0, np, np, Bs);  // L_pp^{-1}
+  __syncthreads();
+  d4_t acc[2][2];
+  tile_abt(As, Bs, acc);  // A_ip L_pp^{-T}
+  store_tile(A, n, ri, rp, ni, np, false, 0, acc);
+}
+
+// Update launch of step p: workgroup t takes lower tile (i, j), p < j <= i,
+// in row order of the triangle.
+__global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n, int p) {
   extern __shared__ double lds[];
   double* As = lds;
   double* Bs = lds + kTB * kTLd;
@@ -3035,40 +3019,110 @@ __global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n
   __syncthreads();
   d4_t acc[2][2];
   tile_abt(As, Bs, acc);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int lr = lane >> 4, lc = lane & 15;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 32 * (w >> 1) + 16 * a + 4 * v + lr, c = 32 * (w & 1) + 16 * b + lc;
-        if (r < ni && c < nj && (i != j || r >= c)) {
-          double* x = A + (size_t)(ri + r) + (size_t)n * (rj + c);
-          *x = *x - acc[a][b][v];
-        }
-      }
-  if (t != 0) return;
-  __syncthreads();
-  dense_diag(A, n, p + 1, lds, err, bits);
+  store_tile(A, n, ri, rj, ni, nj, i == j, 1, acc);
 }
 
 void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st) {
   if (n <= 0) return;
-  static bool done[3] = {false, false, false};
-  allow_lds(reinterpret_cast<const void*>(dense_diag_kernel), &done[0]);
-  allow_lds(reinterpret_cast<const void*>(dense_panel_kernel), &done[1]);
-  allow_lds(reinterpret_cast<const void*>(dense_update_kernel), &done[2]);
+  static bool done[2] = {false, false};
+  allow_lds(reinterpret_cast<const void*>(dense_panel_kernel), &done[0]);
+  allow_lds(reinterpret_cast<const void*>(dense_update_kernel), &done[1]);
   const size_t lds = (size_t)2 * kTB * kTLd * sizeof(double);
-  const size_t ldsd = ((size_t)kTB * kNB + kNB * kNB + kNB * 256) * sizeof(double);
   const int nt = (n + kTB - 1) / kTB;
-  hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(kThreads), ldsd, st, A, n, 0, err, bits);
-  for (int p = 0; p + 1 < nt; ++p) {
+  for (int p = 0; p < nt; ++p) {
     const int T = nt - p - 1;
+    hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(64), 0, st, A, n, p, err, bits);
+    if (T == 0) break;
     hipLaunchKernelGGL(dense_panel_kernel, dim3(T), dim3(kThreads), lds, st, A, n, p);
-    hipLaunchKernelGGL(dense_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), lds, st, A, n, p, err, bits);
+    hipLaunchKernelGGL(dense_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), lds, st, A, n, p);
   }
+}
+
+// Solve with a large top, L L^T x = y, in one cooperative launch of G
+// workgroups; row block b (kTB rows) belongs to workgroup b mod G.  Forward,
+// step p: the owner of block p has applied every earlier block to it and
+// forms y_p <- L_pp^{-1} y_p; after a grid barrier every workgroup applies
+// y_p to its blocks below (y_i -= L_ip y_p), the owner of block p + 1 first.
+// Backward from the last block with the transposes (y_i -= L_pi^T x_p for
+// blocks above).  One grid barrier per block and direction; y in global
+// memory.
+__device__ __forceinline__ void blk_apply(const double* Lb, int ld, int nr, int nc, bool trans, const double* x,
+                                          double* y, double* red) {
+  // y[0:nr] -= Lb x (Lb nr x nc at ld) or, trans, y[0:nc] -= Lb^T x[0:nr]:
+  // 256 threads = 64 outputs x 4 partial sums in a fixed order
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int no = trans ? nc : nr, ni = trans ? nr : nc;
+  double s = 0.0;
+  if (o < no)
+    for (int k = g; k < ni; k += 4) s += (trans ? Lb[(size_t)k + (size_t)ld * o] : Lb[(size_t)o + (size_t)ld * k]) * x[k];
+  red[g * 64 + o] = s;
+  __syncthreads();
+  if (threadIdx.x < no) y[threadIdx.x] -= (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kThreads) top_solve_coop_kernel(const double* L, int n, double* y) {
+  __shared__ double xs[kTB], xd[kTB], red[4 * 64];
+  auto grid = cooperative_groups::this_grid();
+  const int nt = (n + kTB - 1) / kTB, G = gridDim.x;
+  const double* Li = L + (size_t)n * n;  // diagonal-block inverses, ld n
+  auto own_diag = [&](int p, bool trans) {
+    // y_p <- L_pp^{-1} y_p (or L_pp^{-T}), by the block's owner
+    const int rp = p * kTB, np = min(kTB, n - rp);
+    if (threadIdx.x < np) xd[threadIdx.x] = y[rp + threadIdx.x];
+    __syncthreads();
+    const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+    double s = 0.0;
+    if (o < np)
+      for (int k = g; k < np; k += 4)
+        s += (trans ? Li[(size_t)(rp + k) + (size_t)n * o] : Li[(size_t)(rp + o) + (size_t)n * k]) * xd[k];
+    red[g * 64 + o] = s;
+    __syncthreads();
+    if (threadIdx.x < np) y[rp + threadIdx.x] = (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
+    __syncthreads();
+  };
+  auto stage = [&](int p) {
+    const int rp = p * kTB, np = min(kTB, n - rp);
+    if (threadIdx.x < np) xs[threadIdx.x] = y[rp + threadIdx.x];
+    __syncthreads();
+    return np;
+  };
+  // forward
+  if (blockIdx.x == 0) own_diag(0, false);
+  grid.sync();
+  for (int p = 0; p < nt; ++p) {
+    const int np = stage(p), rp = p * kTB;
+    for (int b = p + 1; b < nt; ++b) {
+      if (b % G != (int)blockIdx.x) continue;
+      const int rb = b * kTB, nb = min(kTB, n - rb);
+      blk_apply(L + rb + (size_t)n * rp, n, nb, np, false, xs, y + rb, red);
+      if (b == p + 1) own_diag(b, false);  // every earlier block is applied to it now
+    }
+    __syncthreads();
+    grid.sync();
+  }
+  // backward
+  if ((nt - 1) % G == (int)blockIdx.x) own_diag(nt - 1, true);
+  grid.sync();
+  for (int p = nt - 1; p >= 0; --p) {
+    const int np = stage(p), rp = p * kTB;
+    for (int b = p - 1; b >= 0; --b) {
+      if (b % G != (int)blockIdx.x) continue;
+      const int rb = b * kTB;
+      blk_apply(L + rp + (size_t)n * rb, n, np, kTB, true, xs, y + rb, red);
+      if (b == p - 1) own_diag(b, true);
+    }
+    __syncthreads();
+    grid.sync();
+  }
+}
+
+void launch_top_solve_coop(const double* L, int n, double* y, hipStream_t st) {
+  const int nt = (n + kTB - 1) / kTB;
+  const void* fn = reinterpret_cast<const void*>(top_solve_coop_kernel);
+  const int g = coop_grid(fn, 0, nt);
+  void* args[] = {(void*)&L, (void*)&n, (void*)&y};
+  (void)hipLaunchCooperativeKernel(fn, dim3(g), dim3(kThreads), args, 0, st);
 }
 
 // Dense tops of a batch: one workgroup per system.
