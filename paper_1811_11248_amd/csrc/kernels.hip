@@ -2854,7 +2854,7 @@ void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
 // Dense tops larger than one workgroup's Cholesky (kSplitMaxDofs < n <=
 // kTopMaxDofs): right-looking blocked Cholesky over blocks of kTB columns,
 // three launches per block: the diagonal block factored and inverted by one
-// wave in registers; every row tile below it, L_ip = A_ip L_pp^{-T} on MFMA
+// workgroup in LDS; every row tile below it, L_ip = A_ip L_pp^{-T} on MFMA
 // f64 (one workgroup each); every tile of the trailing lower triangle, A_ij
 // -= L_ip L_jp^T on MFMA f64 (one workgroup each).  The buffer holds n x (n
 // + kTB) doubles (ld n): the last kTB columns receive, in the rows of each
@@ -2927,57 +2927,123 @@ __device__ __forceinline__ void store_tile(double* A, size_t ld, int r0, int c0,
       }
 }
 
-// Diagonal block p of a large top in one wave: lane r holds row r of the
-// block (64 registers), column j of the Cholesky factor is formed with the
-// pivot and the multipliers broadcast by readlane; then lane c forms column
-// c of the inverse by forward substitution, the rows of the factor again
-// broadcast by readlane.  Stores L_pp (lower) in place and L_pp^{-1} in the
-// extra columns.  A pivot that is not > 0 is replaced by 1 and reported in
-// the error words (bits == 0) or as the error bit of a batched system.
-// (About 65 us per block: the serial part of the blocked factorization.)
-__global__ void __launch_bounds__(64) dense_diag_kernel(double* A, int n, int p, int32_t* err, int bits) {
-  const int lane = threadIdx.x;
+// Diagonal block p of a large top, one workgroup, in LDS: Cholesky by
+// 16-column panels (the 16 x 16 diagonal part by wave 0 with its rows in
+// registers and readlane broadcasts, the rows below by one thread each, the
+// trailing triangle by all threads), then thread c forms column c of the
+// inverse by forward substitution (four partial sums per entry).  Stores
+// L_pp (lower) in place and L_pp^{-1} in the extra columns.  A pivot that is
+// not > 0 is replaced by 1 and reported in the error words (bits == 0) or as
+// the error bit of a batched system.
+__global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, int p, int32_t* err, int bits) {
+  __shared__ double S[kTB * kTLd];  // the block, row-major (lower part used)
+  __shared__ double rd[kTB];        // 1 / L_jj
+  __shared__ int sbad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int rp = p * kTB, np = min(kTB, n - rp);
-  const bool on = lane < np;
-  double a[kTB];
+  // the block (identity beyond np), eight loads in flight per thread
+  for (int e0 = tid; e0 < kTB * kTB; e0 += kThreads * 8) {
+    double v[8];
 #pragma unroll
-  for (int c = 0; c < kTB; ++c)
-    a[c] = (on && c <= lane && c < np) ? A[(size_t)(rp + lane) + (size_t)n * (rp + c)] : (c == lane ? 1.0 : 0.0);
-  bool bad = false;
-#pragma unroll
-  for (int j = 0; j < kTB; ++j) {
-    double d = readlane_d(a[j], j);
-    if (!(d > 0.0)) {
-      bad = bad || j < np;
-      d = 1.0;
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads, c = e / kTB, r = e - c * kTB;
+      v[u] = (r < np && c < np) ? (r >= c ? A[(size_t)(rp + r) + (size_t)n * (rp + c)] : 0.0) : (r == c ? 1.0 : 0.0);
     }
-    const double piv = sqrt(d);
-    const double rs = 1.0 / piv;
-    a[j] = lane == j ? piv : (lane > j ? a[j] * rs : a[j]);
 #pragma unroll
-    for (int c = j + 1; c < kTB; ++c) {
-      const double lcj = readlane_d(a[j], c);
-      if (lane >= c) a[c] -= a[j] * lcj;
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads, c = e / kTB, r = e - c * kTB;
+      S[r * kTLd + c] = v[u];
     }
   }
-  // column `lane` of L^{-1}: y[r] for r >= lane
-  double y[kTB];
+  if (tid == 0) sbad = 0;
+  __syncthreads();
+  for (int kb = 0; kb < kTB; kb += 16) {
+    if (wv == 0) {
+      double row[16];
 #pragma unroll
-  for (int r = 0; r < kTB; ++r) {
-    double s = r == lane ? 1.0 : 0.0;
+      for (int u = 0; u < 16; ++u) row[u] = (lane < 16 && u <= lane) ? S[(kb + lane) * kTLd + kb + u] : 0.0;
+      bool bad = false;
 #pragma unroll
-    for (int k = 0; k < r; ++k) s -= readlane_d(a[k], r) * y[k];
-    y[r] = r >= lane ? s / readlane_d(a[r], r) : 0.0;
+      for (int u = 0; u < 16; ++u) {
+        double d = readlane_d(row[u], u);
+        if (!(d > 0.0)) {
+          bad = bad || kb + u < np;
+          d = 1.0;
+        }
+        const double piv = sqrt(d), rs = 1.0 / piv;
+        if (lane == u) {
+          row[u] = piv;
+          rd[kb + u] = rs;
+        } else if (lane > u) {
+          row[u] *= rs;
+        }
+#pragma unroll
+        for (int v = u + 1; v < 16; ++v) {
+          const double lvu = readlane_d(row[u], v);
+          if (lane >= v && lane < 16) row[v] -= row[u] * lvu;
+        }
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (u <= lane) S[(kb + lane) * kTLd + kb + u] = row[u];
+      }
+      if (bad && lane == 0) sbad = 1;
+    }
+    __syncthreads();
+    // rows below: x L11^T = a, one thread per row
+    for (int r = kb + 16 + tid; r < kTB; r += kThreads) {
+      double x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = S[r * kTLd + kb + u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        double t = x[u];
+#pragma unroll
+        for (int v = 0; v < u; ++v) t -= x[v] * S[(kb + u) * kTLd + kb + v];
+        x[u] = t * rd[kb + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) S[r * kTLd + kb + u] = x[u];
+    }
+    __syncthreads();
+    // trailing triangle: S[r][c] -= sum_k S[r][kb+k] S[c][kb+k], r >= c >= kb + 16
+    const int rem = kTB - kb - 16;
+    for (int e = tid; e < rem * (rem + 1) / 2; e += kThreads) {
+      int rr = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while ((rr + 1) * (rr + 2) / 2 <= e) ++rr;
+      while (rr * (rr + 1) / 2 > e) --rr;
+      const int cc = e - rr * (rr + 1) / 2;
+      const int r = kb + 16 + rr, c = kb + 16 + cc;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += S[r * kTLd + kb + k] * S[c * kTLd + kb + k];
+      S[r * kTLd + c] -= acc;
+    }
+    __syncthreads();
   }
-  if (on) {
-#pragma unroll
-    for (int c = 0; c < kTB; ++c)
-      if (c <= lane) A[(size_t)(rp + lane) + (size_t)n * (rp + c)] = a[c];
-#pragma unroll
-    for (int r = 0; r < kTB; ++r)
-      if (r < np) A[(size_t)n * n + (size_t)(rp + r) + (size_t)n * lane] = y[r];
+  // the factor to A
+  for (int e = tid; e < np * np; e += kThreads) {
+    const int c = e / np, r = e - c * np;
+    if (r >= c) A[(size_t)(rp + r) + (size_t)n * (rp + c)] = S[r * kTLd + c];
   }
-  if (bad && lane == 0) {
+  // column `tid` of L^{-1}
+  if (tid < kTB) {
+    double x[kTB];
+#pragma unroll
+    for (int r = 0; r < kTB; ++r) {
+      double s4[4] = {r == tid ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < r; ++k) s4[k & 3] -= S[r * kTLd + k] * x[k];
+      x[r] = r >= tid ? ((s4[0] + s4[1]) + (s4[2] + s4[3])) * rd[r] : 0.0;
+    }
+    if (tid < np) {
+#pragma unroll
+      for (int r = 0; r < kTB; ++r)
+        if (r < np) A[(size_t)n * n + (size_t)(rp + r) + (size_t)n * tid] = x[r];
+    }
+  }
+  if (sbad && tid == 0) {
     if (bits) atomicOr(err, 1 << kErrNotSPD);
     else set_error(err, -1, -1, kErrNotSPD);
   }
@@ -3031,7 +3097,7 @@ void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStrea
   const int nt = (n + kTB - 1) / kTB;
   for (int p = 0; p < nt; ++p) {
     const int T = nt - p - 1;
-    hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(64), 0, st, A, n, p, err, bits);
+    hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(kThreads), 0, st, A, n, p, err, bits);
     if (T == 0) break;
     hipLaunchKernelGGL(dense_panel_kernel, dim3(T), dim3(kThreads), lds, st, A, n, p);
     hipLaunchKernelGGL(dense_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), lds, st, A, n, p);
