@@ -34,8 +34,7 @@ METRIC = "time-to-1e-8 residual (factor+PCG) & factor GFLOP/s, plain FP64 vs mix
 HBM_PEAK_GBS = 8000.0
 # the dense top takes over at the first level with at most this many
 # unknowns (Algorithm 1: "small enough"; set by --top-dense)
-TOP_DENSE = 512         # slab workloads: the blocked dense top does not pay below level 1
-TOP_DENSE_LARGE = 4096  # two-component workloads with long chains of coarse colours
+TOP_DENSE = 4096  # "small enough": the dense top takes over at the first level of at most this many unknowns
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -243,10 +242,10 @@ def run_mixed(args):
     b = torch.from_numpy(rhs(pr.n, 0)).cuda()
     out = {"workload": f"{args.mixed_workload}: {pr.grid[0]}x{pr.grid[1]}x{pr.grid[2]}x{pr.grid[3]}, "
                        f"{pr.n} DoF, leaf {pr.leaf}, tol {pr.tol}, PCG to 1e-8",
-           "top_dense_threshold": TOP_DENSE_LARGE}
+           "top_dense_threshold": TOP_DENSE}
     x64 = None
     t0 = time.perf_counter()
-    F0 = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE_LARGE)
+    F0 = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE)
     torch.cuda.synchronize()
     out["first_factor_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
     out["host_analysis_ms"] = round(F0.info()["ms_analysis"], 2)
@@ -259,7 +258,7 @@ def run_mixed(args):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
             e0.record()
-            F = lrsp.Factor(A, tree, pr.tol, gemm_prec=prec, top_dense=TOP_DENSE_LARGE)
+            F = lrsp.Factor(A, tree, pr.tol, gemm_prec=prec, top_dense=TOP_DENSE)
             e1.record()
             _, it, rr = lrsp.pcg(A, F, b, rtol=1e-8, maxit=1000)
             e2.record()
@@ -516,7 +515,7 @@ def run_learned(args):
     A = lrsp.DeviceMatrix.from_problem(pr)
     b = torch.from_numpy(rhs(pr.n, 0)).cuda()
     out["workload"] = f"{args.learned_workload}: {pr.grid[0]}x{pr.grid[1]}x{pr.grid[2]}x{pr.grid[3]}, {pr.n} DoF"
-    out["top_dense_threshold"] = TOP_DENSE_LARGE
+    out["top_dense_threshold"] = TOP_DENSE
     for name, kw in (("plain_f64", {}), ("plain_f32", {"gemm_prec": "f32"}),
                      ("learned_f32", {"mlp": P, "gemm_prec": "f32"}), ("learned_f64", {"mlp": P})):
         tree = lrsp.Tree(pr.grid, pr.leaf)  # fresh tree: nothing reused
@@ -528,7 +527,7 @@ def run_learned(args):
         lrsp.timing_families(["eliminate"])
         lrsp.timing_enable(True)
         t0 = time.perf_counter()
-        F = lrsp.Factor(A, tree, pr.tol, **kw, top_dense=TOP_DENSE_LARGE)
+        F = lrsp.Factor(A, tree, pr.tol, **kw, top_dense=TOP_DENSE)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         lrsp.timing_enable(False)
@@ -559,7 +558,7 @@ def run_learned(args):
                 lrsp.timing_families(["eliminate"])
                 lrsp.timing_enable(True)
                 t0 = time.perf_counter()
-                F = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE_LARGE)
+                F = lrsp.Factor(A, tree, pr.tol, top_dense=TOP_DENSE)
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
                 lrsp.timing_enable(False)
@@ -785,9 +784,7 @@ def main():
                     help="workload of the precision form ('none': skip)")
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--no-changed-values", dest="changed_values", action="store_false")
-    ap.add_argument("--top-dense-large", type=int, default=4096,
-                    help="dense-top threshold of the two-component workloads (precision and learned-rank forms)")
-    ap.add_argument("--top-dense", type=int, default=512,
+    ap.add_argument("--top-dense", type=int, default=4096,
                     help="dense top at the first level with at most this many unknowns (0: only at a "
                          "complete level graph)")
     ap.add_argument("--scaling", default="32,64,128,256",
@@ -804,9 +801,8 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the solver runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
-    global TOP_DENSE, TOP_DENSE_LARGE
+    global TOP_DENSE
     TOP_DENSE = args.top_dense
-    TOP_DENSE_LARGE = args.top_dense_large
     if args.copy_calibration_mib > 0:
         copy_calibration(args.copy_calibration_mib)
     pr, res, timing = run_gpu(args)

@@ -664,9 +664,11 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
     F->top_adj.insert(F->top_adj.end(), adj[x].begin(), adj[x].end());
     F->top_adj_ptr.push_back((int)F->top_adj.size());
   }
-  // n x (n + 64): the blocked Cholesky of large tops forms its diagonal
-  // blocks' inverses in the last 64 columns
-  HIPCHK(dalloc(&F->top, sizeof(double) * std::max<int64_t>(1, (int64_t)ntop * (ntop + 64)), st));
+  // n x (n + 64) (the blocked Cholesky of large tops forms its diagonal
+  // blocks' inverses in the last 64 columns), then for such tops the n x n
+  // inverse of the factor
+  const int64_t top_cols = ntop > kSplitMaxDofs ? 2 * (int64_t)ntop + 64 : (int64_t)ntop + 64;
+  HIPCHK(dalloc(&F->top, sizeof(double) * std::max<int64_t>(1, (int64_t)ntop * top_cols), st));
   double* Tm = at<double>(F->top, 0);
   launch_zero(Tm, (int64_t)ntop * ntop, st);
   if (level == 0) {
@@ -693,7 +695,8 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   HIPCHK(dalloc(&terr, 16, st));
   launch_zero_i32(at<int32_t>(terr, 0), 4, st);
   if (ntop >= 64 && ntop <= kSplitMaxDofs) launch_top_potrf_wg(Tm, ntop, at<int32_t>(terr, 0), st);
-  else if (ntop > kSplitMaxDofs) launch_top_potrf_blocked(Tm, ntop, at<int32_t>(terr, 0), 0, st);
+  else if (ntop > kSplitMaxDofs)  // with the factor's inverse, which the solve applies
+    launch_top_potrf_blocked(Tm, ntop, at<int32_t>(terr, 0), 0, st, Tm + (size_t)ntop * (ntop + 64));
   else launch_top_potrf(Tm, ntop, at<int32_t>(terr, 0), st);
   HIPCHK(hipGetLastError());
   if (g_tm.on) {
@@ -736,7 +739,7 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   inf.top_n = ntop;
   inf.top_clusters = M;
   for (int i = 0; i < 6; ++i) inf.flops[i] = flops[i];
-  double fb = 8.0 * ntop * ntop;
+  double fb = (double)F->top.bytes;
   for (auto& L : F->levels) fb += (double)L->factor_bytes();
   inf.bytes_factor = fb;
   inf.ms_levels = std::chrono::duration<double, std::milli>(t1 - t0).count();

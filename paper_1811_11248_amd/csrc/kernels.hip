@@ -2835,19 +2835,6 @@ __global__ void __launch_bounds__(kThreads) top_solve_kernel(const double* L, in
   for (int i = threadIdx.x; i < n; i += kThreads) yg[i] = y[i];
 }
 
-void launch_top_solve_coop(const double* L, int n, double* y, hipStream_t st);
-
-void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
-  if (n <= 0) return;
-  size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * kBlkLd) * sizeof(double);
-  if (n > kMaxClusterDofs) {
-    launch_top_solve_coop(L, n, y, st);
-    return;
-  }
-  static bool lds_ok = false;
-  allow_lds(reinterpret_cast<const void*>(top_solve_kernel), &lds_ok);
-  hipLaunchKernelGGL(top_solve_kernel, dim3(1), dim3(kThreads), lds, st, L, n, y);
-}
 
 
 // ---------------------------------------------------------------------------
@@ -2876,6 +2863,24 @@ __device__ __forceinline__ void load_tile(const double* A, size_t ld, int r0, in
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * kThreads, c = e / kTB, r = e - c * kTB;
       if (e < kTB * kTB) T[r * kTLd + c] = v[u];
+    }
+  }
+}
+
+// The transpose: T[c * kTLd + r] = X(r0 + r, c0 + c) (rows r < nr, columns
+// c < nc; zeros elsewhere), so that tile_abt multiplies by X itself.
+__device__ __forceinline__ void load_tile_t(const double* X, size_t ld, int r0, int c0, int nr, int nc, double* T) {
+  for (int e0 = threadIdx.x; e0 < kTB * kTB; e0 += kThreads * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads, c = e / kTB, r = e - c * kTB;
+      v[u] = (e < kTB * kTB && r < nr && c < nc) ? X[(size_t)(r0 + r) + ld * (size_t)(c0 + c)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads, c = e / kTB, r = e - c * kTB;
+      if (e < kTB * kTB) T[c * kTLd + r] = v[u];
     }
   }
 }
@@ -3049,15 +3054,36 @@ __global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, 
   }
 }
 
-// Panel launch of step p: workgroup b takes row tile i = p + 1 + b, L_ip =
-// A_ip L_pp^{-T} with the inverse from dense_diag_kernel.
-__global__ void __launch_bounds__(kThreads) dense_panel_kernel(double* A, int n, int p) {
+// Panel launch of step p: workgroup b < T takes row tile i = p + 1 + b, L_ip
+// = A_ip L_pp^{-T} with the inverse from dense_diag_kernel; with the
+// inverse X of the whole factor being formed (X != null), workgroup T + c
+// (c <= p) finishes tile (p, c) of X: X_pp = L_pp^{-1}, X_pc = L_pp^{-1}
+// R_pc, where R_pc = -sum_{q<p} L_pq X_qc has been accumulated in place.
+__global__ void __launch_bounds__(kThreads) dense_panel_kernel(double* A, int n, int p, int T, double* X) {
   extern __shared__ double lds[];
   double* As = lds;
   double* Bs = lds + kTB * kTLd;
+  const int rp = p * kTB, np = min(kTB, n - rp);
+  if ((int)blockIdx.x >= T) {
+    const int c = blockIdx.x - T, rc = c * kTB;
+    if (c == p) {
+      for (int e = threadIdx.x; e < np * np; e += kThreads) {
+        const int cc = e / np, r = e - cc * np;
+        X[(size_t)(rp + r) + (size_t)n * (rp + cc)] = A[(size_t)n * n + (size_t)(rp + r) + (size_t)n * cc];
+      }
+      return;
+    }
+    load_tile(A + (size_t)n * n, n, rp, 0, np, np, As);  // L_pp^{-1}
+    load_tile_t(X, n, rp, rc, np, kTB, Bs);              // R_pc
+    __syncthreads();
+    d4_t acc[2][2];
+    tile_abt(As, Bs, acc);
+    store_tile(X, n, rp, rc, np, kTB, false, 0, acc);
+    return;
+  }
   const int i = p + 1 + blockIdx.x;
-  const int ri = i * kTB, rp = p * kTB;
-  const int ni = min(kTB, n - ri), np = min(kTB, n - rp);
+  const int ri = i * kTB;
+  const int ni = min(kTB, n - ri);
   load_tile(A, n, ri, rp, ni, np, As);                 // A_ip
   load_tile(A + (size_t)n * n, n, rp, 0, np, np, Bs);  // L_pp^{-1}
   __syncthreads();
@@ -3066,12 +3092,28 @@ __global__ void __launch_bounds__(kThreads) dense_panel_kernel(double* A, int n,
   store_tile(A, n, ri, rp, ni, np, false, 0, acc);
 }
 
-// Update launch of step p: workgroup t takes lower tile (i, j), p < j <= i,
-// in row order of the triangle.
-__global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n, int p) {
+// Update launch of step p: workgroup t < T(T+1)/2 takes lower tile (i, j),
+// p < j <= i, in row order of the triangle; with X, the further workgroups
+// take the tiles (i, c), i > p, c <= p, of the inverse's accumulators:
+// R_ic -= L_ip X_pc.
+__global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n, int p, int T, double* X) {
   extern __shared__ double lds[];
   double* As = lds;
   double* Bs = lds + kTB * kTLd;
+  const int ntri = T * (T + 1) / 2;
+  if ((int)blockIdx.x >= ntri) {
+    const int u = blockIdx.x - ntri;
+    const int i = p + 1 + u / (p + 1), c = u % (p + 1);
+    const int ri = i * kTB, rp = p * kTB, rc = c * kTB;
+    const int ni = min(kTB, n - ri), np = min(kTB, n - rp);
+    load_tile(A, n, ri, rp, ni, np, As);    // L_ip
+    load_tile_t(X, n, rp, rc, np, kTB, Bs);  // X_pc
+    __syncthreads();
+    d4_t acc[2][2];
+    tile_abt(As, Bs, acc);
+    store_tile(X, n, ri, rc, ni, kTB, false, 1, acc);
+    return;
+  }
   const int t = blockIdx.x;
   int ii = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
@@ -3088,107 +3130,84 @@ __global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n
   store_tile(A, n, ri, rj, ni, nj, i == j, 1, acc);
 }
 
-void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st) {
+void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st, double* X) {
   if (n <= 0) return;
   static bool done[2] = {false, false};
   allow_lds(reinterpret_cast<const void*>(dense_panel_kernel), &done[0]);
   allow_lds(reinterpret_cast<const void*>(dense_update_kernel), &done[1]);
   const size_t lds = (size_t)2 * kTB * kTLd * sizeof(double);
   const int nt = (n + kTB - 1) / kTB;
+  if (X) launch_zero(X, (int64_t)n * n, st);
   for (int p = 0; p < nt; ++p) {
     const int T = nt - p - 1;
     hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(kThreads), 0, st, A, n, p, err, bits);
-    if (T == 0) break;
-    hipLaunchKernelGGL(dense_panel_kernel, dim3(T), dim3(kThreads), lds, st, A, n, p);
-    hipLaunchKernelGGL(dense_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), lds, st, A, n, p);
+    const int gp = T + (X ? p + 1 : 0);
+    if (gp > 0)
+      hipLaunchKernelGGL(dense_panel_kernel, dim3(gp), dim3(kThreads), lds, st, A, n, p, T, X);
+    const int gu = T * (T + 1) / 2 + (X ? T * (p + 1) : 0);
+    if (gu > 0)
+      hipLaunchKernelGGL(dense_update_kernel, dim3(gu), dim3(kThreads), lds, st, A, n, p, T, X);
   }
 }
 
-// Solve with a large top, L L^T x = y, in one cooperative launch of G
-// workgroups; row block b (kTB rows) belongs to workgroup b mod G.  Forward,
-// step p: the owner of block p has applied every earlier block to it and
-// forms y_p <- L_pp^{-1} y_p; after a grid barrier every workgroup applies
-// y_p to its blocks below (y_i -= L_ip y_p), the owner of block p + 1 first.
-// Backward from the last block with the transposes (y_i -= L_pi^T x_p for
-// blocks above).  One grid barrier per block and direction; y in global
-// memory.
-__device__ __forceinline__ void blk_apply(const double* Lb, int ld, int nr, int nc, bool trans, const double* x,
-                                          double* y, double* red) {
-  // y[0:nr] -= Lb x (Lb nr x nc at ld) or, trans, y[0:nc] -= Lb^T x[0:nr]:
-  // 256 threads = 64 outputs x 4 partial sums in a fixed order
+// y <- X^T X y for the lower inverse X (n x n, ld n) of a large top's
+// factor: z = X y by row blocks, then y = X^T z by column blocks (one
+// workgroup per 64-row block; 64 outputs x 4 partial sums in a fixed order);
+// z in the n doubles at zt.
+__global__ void __launch_bounds__(kThreads) top_inv_lower_kernel(const double* X, int n, const double* y,
+                                                                 double* z) {
+  __shared__ double ys[kTopMaxDofs];
+  __shared__ double red[4 * 64];
   const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int no = trans ? nc : nr, ni = trans ? nr : nc;
+  const int ri = blockIdx.x * kTB, ni = min(kTB, n - ri), kend = min(n, ri + kTB);
+  for (int k = threadIdx.x; k < kend; k += kThreads) ys[k] = y[k];
+  __syncthreads();
   double s = 0.0;
-  if (o < no)
-    for (int k = g; k < ni; k += 4) s += (trans ? Lb[(size_t)k + (size_t)ld * o] : Lb[(size_t)o + (size_t)ld * k]) * x[k];
+  if (o < ni)
+    for (int k = g; k < kend; k += 4) s += X[(size_t)(ri + o) + (size_t)n * k] * ys[k];
   red[g * 64 + o] = s;
   __syncthreads();
-  if (threadIdx.x < no) y[threadIdx.x] -= (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
+  if (threadIdx.x < ni)
+    z[ri + threadIdx.x] = (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(kThreads) top_inv_upper_kernel(const double* X, int n, const double* z,
+                                                                 double* y) {
+  __shared__ double zs[kTopMaxDofs];
+  __shared__ double red[4 * 64];
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int rc = blockIdx.x * kTB, nc = min(kTB, n - rc);
+  for (int r = rc + threadIdx.x; r < n; r += kThreads) zs[r] = z[r];
   __syncthreads();
+  // column rc + o of X from row rc on, rows split in four contiguous parts
+  const int len = n - rc, q = (len + 3) / 4, r0 = rc + g * q, r1 = min(n, r0 + q);
+  double s = 0.0;
+  if (o < nc) {
+    const double* col = X + (size_t)n * (rc + o);
+    for (int r = r0; r < r1; ++r) s += col[r] * zs[r];
+  }
+  red[g * 64 + o] = s;
+  __syncthreads();
+  if (threadIdx.x < nc)
+    y[rc + threadIdx.x] = (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
 }
 
-__global__ void __launch_bounds__(kThreads) top_solve_coop_kernel(const double* L, int n, double* y) {
-  __shared__ double xs[kTB], xd[kTB], red[4 * 64];
-  auto grid = cooperative_groups::this_grid();
-  const int nt = (n + kTB - 1) / kTB, G = gridDim.x;
-  const double* Li = L + (size_t)n * n;  // diagonal-block inverses, ld n
-  auto own_diag = [&](int p, bool trans) {
-    // y_p <- L_pp^{-1} y_p (or L_pp^{-T}), by the block's owner
-    const int rp = p * kTB, np = min(kTB, n - rp);
-    if (threadIdx.x < np) xd[threadIdx.x] = y[rp + threadIdx.x];
-    __syncthreads();
-    const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
-    double s = 0.0;
-    if (o < np)
-      for (int k = g; k < np; k += 4)
-        s += (trans ? Li[(size_t)(rp + k) + (size_t)n * o] : Li[(size_t)(rp + o) + (size_t)n * k]) * xd[k];
-    red[g * 64 + o] = s;
-    __syncthreads();
-    if (threadIdx.x < np) y[rp + threadIdx.x] = (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
-    __syncthreads();
-  };
-  auto stage = [&](int p) {
-    const int rp = p * kTB, np = min(kTB, n - rp);
-    if (threadIdx.x < np) xs[threadIdx.x] = y[rp + threadIdx.x];
-    __syncthreads();
-    return np;
-  };
-  // forward
-  if (blockIdx.x == 0) own_diag(0, false);
-  grid.sync();
-  for (int p = 0; p < nt; ++p) {
-    const int np = stage(p), rp = p * kTB;
-    for (int b = p + 1; b < nt; ++b) {
-      if (b % G != (int)blockIdx.x) continue;
-      const int rb = b * kTB, nb = min(kTB, n - rb);
-      blk_apply(L + rb + (size_t)n * rp, n, nb, np, false, xs, y + rb, red);
-      if (b == p + 1) own_diag(b, false);  // every earlier block is applied to it now
-    }
-    __syncthreads();
-    grid.sync();
+void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
+  if (n <= 0) return;
+  size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * kBlkLd) * sizeof(double);
+  if (n > kSplitMaxDofs) {
+    // the factor's inverse X (formed by the blocked Cholesky) sits after the
+    // n x (n + 64) factor; the 64 extra columns hold z
+    const double* X = L + (size_t)n * (n + 64);
+    double* z = const_cast<double*>(L) + (size_t)n * n;
+    const int nt = (n + kTB - 1) / kTB;
+    hipLaunchKernelGGL(top_inv_lower_kernel, dim3(nt), dim3(kThreads), 0, st, X, n, y, z);
+    hipLaunchKernelGGL(top_inv_upper_kernel, dim3(nt), dim3(kThreads), 0, st, X, n, z, y);
+    return;
   }
-  // backward
-  if ((nt - 1) % G == (int)blockIdx.x) own_diag(nt - 1, true);
-  grid.sync();
-  for (int p = nt - 1; p >= 0; --p) {
-    const int np = stage(p), rp = p * kTB;
-    for (int b = p - 1; b >= 0; --b) {
-      if (b % G != (int)blockIdx.x) continue;
-      const int rb = b * kTB;
-      blk_apply(L + rp + (size_t)n * rb, n, np, kTB, true, xs, y + rb, red);
-      if (b == p - 1) own_diag(b, true);
-    }
-    __syncthreads();
-    grid.sync();
-  }
-}
-
-void launch_top_solve_coop(const double* L, int n, double* y, hipStream_t st) {
-  const int nt = (n + kTB - 1) / kTB;
-  const void* fn = reinterpret_cast<const void*>(top_solve_coop_kernel);
-  const int g = coop_grid(fn, 0, nt);
-  void* args[] = {(void*)&L, (void*)&n, (void*)&y};
-  (void)hipLaunchCooperativeKernel(fn, dim3(g), dim3(kThreads), args, 0, st);
+  static bool lds_ok = false;
+  allow_lds(reinterpret_cast<const void*>(top_solve_kernel), &lds_ok);
+  hipLaunchKernelGGL(top_solve_kernel, dim3(1), dim3(kThreads), lds, st, L, n, y);
 }
 
 // Dense tops of a batch: one workgroup per system.

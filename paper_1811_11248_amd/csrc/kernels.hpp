@@ -90,9 +90,11 @@ void launch_top_potrf_wg(double* A, int n, int32_t* err, hipStream_t st);
 // Dense tops of kSplitMaxDofs < n <= kTopMaxDofs unknowns: blocked Cholesky
 // over several workgroups (A: n x (n + 64) doubles, ld n; the last 64
 // columns are workspace).  A non-positive pivot sets the error words (bits ==
-// 0) or the bit kErrNotSPD of *err (bits != 0, a batched system).
+// 0) or the bit kErrNotSPD of *err (bits != 0, a batched system).  With X
+// (n x n, ld n) the lower inverse of the factor is formed there as well
+// (cleared first); launch_top_solve then applies it when X = A + n (n + 64).
 constexpr int kTopMaxDofs = 4096;
-void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st);
+void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st, double* X = nullptr);
 // The tops of a batch with 64..kSplitMaxDofs unknowns by the same kernel
 // (the others are skipped); max_n: their largest size.
 void launch_top_potrf_wg_batched(const TopD* tops, int ntops, int max_n, hipStream_t st);

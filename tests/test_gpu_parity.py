@@ -351,7 +351,7 @@ def test_factor_store_and_panel_arena(torch, L):
     assert np.linalg.norm(x - xo) <= APPLY_TOL * np.linalg.norm(xo)
     inf = F1.info()
     st = [F1.level_stats(li) for li in range(inf["nlevels"] + 1)]
-    assert inf["bytes_factor"] == sum(q["factor_bytes"] for q in st[:-1]) + 8 * inf["top_n"] ** 2
+    assert inf["bytes_factor"] == sum(q["factor_bytes"] for q in st)  # the levels' stores and the top
     for q in st[:-1]:
         assert 0 < q["factor_bytes"] < q["held_bytes"]
     _say(f"[factor store] {inf['bytes_factor'] / pr.n:.0f} bytes per DoF, peak {inf['peak_bytes'] / pr.n:.0f}")
