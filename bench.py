@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # the dense top takes over at the first level with at most this many
 # unknowns (Algorithm 1: "small enough"; set by --top-dense)
 TOP_DENSE = 4096  # "small enough": the dense top takes over at the first level of at most this many unknowns
+BATCH_TOP_DENSE = 512  # the batching form's tops stay within one workgroup (one launch for all systems)
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -421,7 +422,7 @@ def run_batch(args):
     out = {"systems": len(probs), "dof": int(sum(p.n for p in probs)), "nrhs": 4}
     for prec in ("f64", "f32"):
         t0 = time.perf_counter()
-        B = lrsp.Batch(mats, trees, 1e-2, gemm_prec=prec, autotune=(prec == "f64"), top_dense=TOP_DENSE)
+        B = lrsp.Batch(mats, trees, 1e-2, gemm_prec=prec, autotune=(prec == "f64"), top_dense=BATCH_TOP_DENSE)
         torch.cuda.synchronize()
         first_ms = (time.perf_counter() - t0) * 1e3
         Bt = B.pack(rhs)
@@ -466,7 +467,7 @@ def run_batch(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(len(probs)):
-            F = lrsp.Factor(mats[i], trees[i], 1e-2, top_dense=TOP_DENSE)
+            F = lrsp.Factor(mats[i], trees[i], 1e-2, top_dense=BATCH_TOP_DENSE)
             _, it, _ = lrsp.pcg(mats[i], F, torch.from_numpy(rhs[i]).cuda())
             iters.append(it)
             del F
