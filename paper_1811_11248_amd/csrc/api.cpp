@@ -666,8 +666,9 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   }
   // n x (n + 64) (the blocked Cholesky of large tops forms its diagonal
   // blocks' inverses in the last 64 columns), then for such tops the n x n
-  // inverse of the factor
-  const int64_t top_cols = ntop > kSplitMaxDofs ? 2 * (int64_t)ntop + 64 : (int64_t)ntop + 64;
+  // inverse of the factor and 64 columns of the solve's partial sums (the
+  // solve keeps its other partial sums in the factor's 64 extra columns)
+  const int64_t top_cols = ntop > kSplitMaxDofs ? 2 * (int64_t)ntop + 128 : (int64_t)ntop + 64;
   HIPCHK(dalloc(&F->top, sizeof(double) * std::max<int64_t>(1, (int64_t)ntop * top_cols), st));
   double* Tm = at<double>(F->top, 0);
   launch_zero(Tm, (int64_t)ntop * ntop, st);

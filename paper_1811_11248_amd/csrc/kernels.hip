@@ -3151,41 +3151,82 @@ void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStrea
 }
 
 // y <- X^T X y for the lower inverse X (n x n, ld n) of a large top's
-// factor: z = X y by row blocks, then y = X^T z by column blocks (one
-// workgroup per 64-row block; 64 outputs x 4 partial sums in a fixed order);
-// z in the n doubles at zt.
-__global__ void __launch_bounds__(kThreads) top_inv_lower_kernel(const double* X, int n, const double* y,
-                                                                 double* z) {
-  __shared__ double ys[kTopMaxDofs];
+// factor, over the 64 x 64 tiles (i, c), i >= c, of its lower triangle (one
+// workgroup per tile, T(T+1)/2 of them for T = ceil(n / 64) tile rows) in
+// three launches: P_c(i) = X_ic y_c; then z_i = sum_{c <= i} P_c(i) (every
+// tile of row i forms the same z_i, in the order c = 0..i) and Q_i(c) =
+// X_ic^T z_i; then y_c = sum_{i >= c} Q_i(c) in the order i = c..T-1.  P and
+// Q hold T x n doubles each (P_c at P + c n, Q_i at Q + i n).  Every sum has
+// one fixed order: four interleaved partial sums combined as (0+1)+(2+3).
+__global__ void __launch_bounds__(kThreads) top_inv_part_kernel(const double* X, int n, const double* y,
+                                                                double* P) {
   __shared__ double red[4 * 64];
   const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int ri = blockIdx.x * kTB, ni = min(kTB, n - ri), kend = min(n, ri + kTB);
-  for (int k = threadIdx.x; k < kend; k += kThreads) ys[k] = y[k];
-  __syncthreads();
+  int i, c;
+  tri_index(blockIdx.x, i, c);
+  const int ri = i * kTB, rc = c * kTB, ni = min(kTB, n - ri), nc = min(kTB, n - rc);
+  double xv[16], yv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int col = g * 16 + u;
+    const bool ok = o < ni && col < nc && (i != c || col <= o);
+    xv[u] = ok ? X[(size_t)(ri + o) + (size_t)n * (rc + col)] : 0.0;
+    yv[u] = col < nc ? y[rc + col] : 0.0;
+  }
   double s = 0.0;
-  if (o < ni)
-    for (int k = g; k < kend; k += 4) s += X[(size_t)(ri + o) + (size_t)n * k] * ys[k];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s += xv[u] * yv[u];
   red[g * 64 + o] = s;
   __syncthreads();
   if (threadIdx.x < ni)
-    z[ri + threadIdx.x] = (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
+    P[(size_t)c * n + ri + threadIdx.x] =
+        (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
 }
 
-__global__ void __launch_bounds__(kThreads) top_inv_upper_kernel(const double* X, int n, const double* z,
-                                                                 double* y) {
-  __shared__ double zs[kTopMaxDofs];
+__global__ void __launch_bounds__(kThreads) top_inv_mid_kernel(const double* X, int n, const double* P,
+                                                               double* Q) {
+  __shared__ double S[kTB * kTLd];  // S[col * kTLd + r] = X_ic(r, col)
+  __shared__ double zs[kTB];
   __shared__ double red[4 * 64];
   const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int rc = blockIdx.x * kTB, nc = min(kTB, n - rc);
-  for (int r = rc + threadIdx.x; r < n; r += kThreads) zs[r] = z[r];
-  __syncthreads();
-  // column rc + o of X from row rc on, rows split in four contiguous parts
-  const int len = n - rc, q = (len + 3) / 4, r0 = rc + g * q, r1 = min(n, r0 + q);
-  double s = 0.0;
-  if (o < nc) {
-    const double* col = X + (size_t)n * (rc + o);
-    for (int r = r0; r < r1; ++r) s += col[r] * zs[r];
+  int i, c;
+  tri_index(blockIdx.x, i, c);
+  const int ri = i * kTB, rc = c * kTB, ni = min(kTB, n - ri), nc = min(kTB, n - rc);
+  double xv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int col = g * 16 + u;
+    const bool ok = o < ni && col < nc && (i != c || col <= o);
+    xv[u] = ok ? X[(size_t)(ri + o) + (size_t)n * (rc + col)] : 0.0;
   }
+  double s = 0.0;
+  if (o < ni)
+    for (int cp = g; cp <= i; cp += 4) s += P[(size_t)cp * n + ri + o];
+  red[g * 64 + o] = s;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) S[(g * 16 + u) * kTLd + o] = xv[u];
+  __syncthreads();
+  if (threadIdx.x < kTB)
+    zs[threadIdx.x] = (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
+  __syncthreads();
+  // column o of the tile against z_i, rows g*16 .. g*16 + 15
+  s = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s += S[o * kTLd + g * 16 + u] * zs[g * 16 + u];
+  red[g * 64 + o] = s;
+  __syncthreads();
+  if (threadIdx.x < nc)
+    Q[(size_t)i * n + rc + threadIdx.x] =
+        (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(kThreads) top_inv_sum_kernel(const double* Q, int n, int T, double* y) {
+  __shared__ double red[4 * 64];
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int c = blockIdx.x, rc = c * kTB, nc = min(kTB, n - rc);
+  double s = 0.0;
+  if (o < nc)
+    for (int i = c + g; i < T; i += 4) s += Q[(size_t)i * n + rc + o];
   red[g * 64 + o] = s;
   __syncthreads();
   if (threadIdx.x < nc)
@@ -3197,12 +3238,15 @@ void launch_top_solve(const double* L, int n, double* y, hipStream_t st) {
   size_t lds = ((size_t)((n + 63) / 64) * 64 + 64 * kBlkLd) * sizeof(double);
   if (n > kSplitMaxDofs) {
     // the factor's inverse X (formed by the blocked Cholesky) sits after the
-    // n x (n + 64) factor; the 64 extra columns hold z
+    // n x (n + 64) factor; the 64 columns after the factor hold P, the 64
+    // after X hold Q (T <= 64 tile rows since n <= kTopMaxDofs)
     const double* X = L + (size_t)n * (n + 64);
-    double* z = const_cast<double*>(L) + (size_t)n * n;
-    const int nt = (n + kTB - 1) / kTB;
-    hipLaunchKernelGGL(top_inv_lower_kernel, dim3(nt), dim3(kThreads), 0, st, X, n, y, z);
-    hipLaunchKernelGGL(top_inv_upper_kernel, dim3(nt), dim3(kThreads), 0, st, X, n, z, y);
+    double* P = const_cast<double*>(L) + (size_t)n * n;
+    double* Q = const_cast<double*>(X) + (size_t)n * n;
+    const int nt = (n + kTB - 1) / kTB, ntile = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(top_inv_part_kernel, dim3(ntile), dim3(kThreads), 0, st, X, n, y, P);
+    hipLaunchKernelGGL(top_inv_mid_kernel, dim3(ntile), dim3(kThreads), 0, st, X, n, P, Q);
+    hipLaunchKernelGGL(top_inv_sum_kernel, dim3(nt), dim3(kThreads), 0, st, Q, n, nt, y);
     return;
   }
   static bool lds_ok = false;

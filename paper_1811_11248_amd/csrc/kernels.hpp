@@ -92,7 +92,9 @@ void launch_top_potrf_wg(double* A, int n, int32_t* err, hipStream_t st);
 // columns are workspace).  A non-positive pivot sets the error words (bits ==
 // 0) or the bit kErrNotSPD of *err (bits != 0, a batched system).  With X
 // (n x n, ld n) the lower inverse of the factor is formed there as well
-// (cleared first); launch_top_solve then applies it when X = A + n (n + 64).
+// (cleared first); launch_top_solve then applies it when X = A + n (n + 64),
+// using the 64 columns after the factor and 64 more after X (A then holds
+// n x (2n + 128) doubles) as its workspace.
 constexpr int kTopMaxDofs = 4096;
 void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st, double* X = nullptr);
 // The tops of a batch with 64..kSplitMaxDofs unknowns by the same kernel
