@@ -335,10 +335,12 @@ void launch_top_potrf_wg_batched(const TopD* tops, int ntops, int max_n, hipStre
 //   (readlane broadcasts, reciprocal square roots) and inverts it; the tiles
 //   below are G_ip = A_ip G_pp^{-T} on MFMA; the trailing tiles are updated on
 //   MFMA.
-//   G^{-1}: forward substitution G X = I by tile rows p: X_pp = G_pp^{-1} and
-//   X_pj = G_pp^{-1} acc_pj (one wave per tile), then acc_ij -= G_ip X_pj for
-//   the rows i > p (acc_ij starts at zero, the identity having no entries
-//   below the diagonal).
+//   G^{-1}: forward substitution G X = I by tile rows, in the same steps: at
+//   step p, once G_pp^{-1} is known, X_pp = G_pp^{-1} and X_pj = G_pp^{-1}
+//   acc_pj (j < p, one wave per tile), and with the trailing update the
+//   accumulators of the rows i > p take acc_ij -= G_ip X_pj (j <= p; acc_ip
+//   starts at zero, the identity having no entries below the diagonal) in
+//   the registers of the tiles of G that are final by then.
 // G goes to the diagonal block of the panel (lower triangle), G^{-1} to Gi
 // (lower tiles, zeros above the diagonal inside the diagonal tiles); no
 // thread reads these stores back, so the barriers order LDS only.
@@ -396,7 +398,7 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
   // the wave's tiles, loaded with lane l on row l%16 of columns 4v + l/16 (16
   // consecutive rows of a column per 16 lanes), then turned into the
   // accumulator layout through a 16 x 17 staging tile of the wave in Ar (free
-  // until the inverse)
+  // until the first step's update)
   d4_t T[kInvSlots];
 #pragma unroll
   for (int j = 0; j < kInvSlots; ++j) {
@@ -443,8 +445,7 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
     // wave 0: G_pp (lane r holds row r; reciprocal square roots from
     // v_rsq_f64 refined by one Newton step), then row r of G_pp^{-1} in the
     // same lane by forward substitution across the lanes (readlane
-    // broadcasts), into the columns 16p.. of Xr, where the inverse below
-    // expects it
+    // broadcasts), into the columns 16p.. of Xr (X_pp of the inverse)
     if (w == 0) {
       double row[16], rdl = 1.0;
 #pragma unroll
@@ -523,9 +524,30 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
         if (gr < m && gc <= gr) A[gr + (size_t)m * gc] = x[v];
       }
     }
+    // tile row p of G^{-1}: X_pj = G_pp^{-1} acc_pj (j < p, the accumulators
+    // in Ar) and X_pp = G_pp^{-1}, one tile per wave at a time; X_pj goes to
+    // the columns 16j.. of Xr (only the columns 16p.. are read above)
+    for (int jt = w; jt <= p; jt += NW) {
+      d4_t x = {0.0, 0.0, 0.0, 0.0};
+      if (jt < p) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          x = __builtin_amdgcn_mfma_f64_16x16x4f64(Xr[lc * kInvLdX + 16 * p + 4 * s4 + lr],
+                                                   Ar[(4 * s4 + lr) * kInvLdX + 16 * jt + lc], x, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = Xr[(4 * v + lr) * kInvLdX + 16 * p + lc];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (jt < p) Xr[(4 * v + lr) * kInvLdX + 16 * jt + lc] = x[v];
+        const int gr = 16 * p + 4 * v + lr, gc = 16 * jt + lc;
+        if (gr < m && gc < m) Xg[gr + (size_t)m * gc] = x[v];
+      }
+    }
     lds_barrier();
-    // trailing tiles: T_rc -= G_rp G_cp^T; the tiles of column p + 1, final
-    // now, go to Dd and Pnext for the next step
+    // rows r > p: trailing tiles T_rc -= G_rp G_cp^T (c > p), the tiles of
+    // column p + 1, final now, to Dd and Pnext for the next step
 #pragma unroll
     for (int j = 0; j < kInvSlots; ++j) {
       __builtin_amdgcn_sched_barrier(0);
@@ -545,56 +567,8 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
         for (int v = 0; v < 4; ++v) dst[(4 * v + lr) * kInvLdP + lc] = acc[v];
       }
     }
-    lds_barrier();
-  }
-  if (sbad) {
-    if (tid == 0) item_error(it, ls.err, level, kErrNotSPD);
-    return;
-  }
-  // G_qq^{-1} sits in the columns 16q.. of Xr (formed by the Cholesky); step
-  // p overwrites only the columns 16j.., j <= p, so it stays there until step q
-  for (int p = 0; p < nt; ++p) {
-    int wq = w;
-    asm volatile("" : "+s"(wq));
-    // tile column p of G to Pc; the accumulators of tile row p to Ar
-#pragma unroll
-    for (int j = 0; j < kInvSlots; ++j) {
-      __builtin_amdgcn_sched_barrier(0);
-      int r, c;
-      if (!Map::slot(wq, j, r, c) || r >= nt) continue;
-      if (r > p && c == p) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Pc[(16 * r + 4 * v + lr) * kInvLdP + lc] = T[j][v];
-      } else if (r == p && c < p) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ar[(4 * v + lr) * kInvLdX + 16 * c + lc] = T[j][v];
-      }
-    }
-    lds_barrier();
-    // X_pj = G_pp^{-1} acc_pj (j < p) and X_pp = G_pp^{-1}, one tile per wave
-    // at a time
-    for (int jt = w; jt <= p; jt += NW) {
-      d4_t x = {0.0, 0.0, 0.0, 0.0};
-      if (jt < p) {
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-          x = __builtin_amdgcn_mfma_f64_16x16x4f64(Xr[lc * kInvLdX + 16 * p + 4 * s4 + lr],
-                                                   Ar[(4 * s4 + lr) * kInvLdX + 16 * jt + lc], x, 0, 0, 0);
-      } else {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) x[v] = Xr[(4 * v + lr) * kInvLdX + 16 * p + lc];
-      }
-      // columns 16jt.. of Xr: X_pj goes there for jt < p (no wave reads them
-      // in this phase); for jt == p they already hold X_pp
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (jt < p) Xr[(4 * v + lr) * kInvLdX + 16 * jt + lc] = x[v];
-        const int gr = 16 * p + 4 * v + lr, gc = 16 * jt + lc;
-        if (gr < m && gc < m) Xg[gr + (size_t)m * gc] = x[v];
-      }
-    }
-    lds_barrier();
-    // rows i > p: acc_ij -= G_ip X_pj (j < p); tile (i, p) becomes -G_ip X_pp
+    // and the inverse's accumulators acc_rc -= G_rp X_pc (c <= p; tile (r, p)
+    // held G_rp, which Pcur keeps), those of row p + 1 to Ar for the next step
 #pragma unroll
     for (int j = 0; j < kInvSlots; ++j) {
       __builtin_amdgcn_sched_barrier(0);
@@ -604,13 +578,21 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
       if (c == p) acc = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
-        const double av = Pc[(16 * r + lc) * kInvLdP + 4 * s4 + lr];
+        const double av = Pcur[(16 * r + lc) * kInvLdP + 4 * s4 + lr];
         const double bv = Xr[(4 * s4 + lr) * kInvLdX + 16 * c + lc];
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av, bv, acc, 0, 0, 0);
       }
       T[j] = acc;
+      if (r == p + 1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Ar[(4 * v + lr) * kInvLdX + 16 * c + lc] = acc[v];
+      }
     }
     lds_barrier();
+  }
+  if (sbad) {
+    if (tid == 0) item_error(it, ls.err, level, kErrNotSPD);
+    return;
   }
   if (tid == 0) ls.giok[it.s] = 1;
 }
