@@ -802,8 +802,12 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
           launch_sweep_level(true, L.d_items, L.d_cstart, p.ncolours, p.cstart.back(), L.max_items, L.max_m, L.max_acap, L.ls, V,
                              st, 0, nullptr, L.vbase, L.nvec) != hipSuccess) {
         if (!per_colour) (void)hipGetLastError();
+        // after the split schedule every cluster of kSweepSplitM..kInvMaxDofs
+        // DoFs keeps W (or G^{-1} when it has no reflector)
+        const bool wide = L.split && L.min_m >= kSweepSplitM && L.max_m <= kInvMaxDofs && !F->nodc;
         for (int c = 0; c < p.ncolours; ++c)
-          launch_fwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st);
+          launch_fwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st,
+                     wide);
       }
       if (g_tm.on)
         for (double by : L.sweep_bytes) g_tm.bytes[1] += by;

@@ -1825,11 +1825,13 @@ __device__ __forceinline__ void trsv_lower_t(const double* G, int ld, int m, dou
 // Shapes of the cluster matrix in gemv_blk.
 constexpr int kGemvLower = 0, kGemvFull = 2;
 
-// y <- M y for M (m x m, ld m, m <= 256) lower triangular or full, y in LDS: the 64x64 tiles are spread over the waves, each lane one
+// y <- M y for M (m x m, ld m, m <= 256) lower triangular or full, y in LDS,
+// NT threads: the 64x64 tiles are spread over the waves, each lane one
 // row of a tile with the tile's 64 entries of that row loaded at once; the
 // partial sums of the column blocks are added in order.  With yg, y is first
 // copied from yg (global) into LDS, after the loads of each wave's first tile
 // have been issued, so that the two overlap.  red: 4*256 doubles of LDS.
+template <int NT = kThreads>
 __device__ __forceinline__ void gemv_blk(const double* M, int m, int shape, double* y, double* red,
                                          const double* yg = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1859,10 +1861,10 @@ __device__ __forceinline__ void gemv_blk(const double* M, int m, int shape, doub
   };
   if (wv < ntl) load_tile(wv);
   if (yg) {
-    for (int i = tid; i < m; i += kThreads) y[i] = gload(yg + i);
+    for (int i = tid; i < m; i += NT) y[i] = gload(yg + i);
     lds_barrier();
   }
-  for (int t = wv; t < ntl; t += kWaves) {
+  for (int t = wv; t < ntl; t += NT / 64) {
     if (t != wv) load_tile(t);
     const int i = 64 * ib + lane;
     double s = 0.0;
@@ -1871,7 +1873,7 @@ __device__ __forceinline__ void gemv_blk(const double* M, int m, int shape, doub
     if (i < m) red[jb * 256 + i] = s;
   }
   __syncthreads();
-  for (int i = tid; i < m; i += kThreads) {
+  for (int i = tid; i < m; i += NT) {
     const int ib = i >> 6;
     const int j1 = shape == kGemvLower ? ib + 1 : nb;
     double t = 0.0;
@@ -1882,11 +1884,14 @@ __device__ __forceinline__ void gemv_blk(const double* M, int m, int shape, doub
 }
 
 // y <- M^T y for M (m x m, ld m, m <= 64 R) lower triangular (lower) or full,
-// y in LDS: one wave per column of M, four columns in flight, each column's
-// dot product with y summed across the wave; the results pass through red (m
-// doubles of LDS) so that no wave overwrites y while another still reads it.
-template <int R>
+// y in LDS: one wave per column of M, QC columns in flight (16 for clusters
+// of at most 256 DoFs, else 4), each column's dot product with y summed
+// across the wave; the results pass through red (m doubles of LDS) so that
+// no wave overwrites y while another still reads it.  NT threads; every
+// column's sum has the same order whatever NT and QC.
+template <int R, int NT = kThreads>
 __device__ __forceinline__ void gemv_t(const double* M, int m, bool lower, double* y, double* red) {
+  constexpr int QC = R <= 4 ? 16 : 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double yr[R];
 #pragma unroll
@@ -1894,10 +1899,10 @@ __device__ __forceinline__ void gemv_t(const double* M, int m, bool lower, doubl
     const int i = lane + 64 * t;
     yr[t] = i < m ? y[i] : 0.0;
   }
-  for (int cb = wv * 4; cb < m; cb += kWaves * 4) {
-    double g[4][R];
+  for (int cb = wv * QC; cb < m; cb += (NT / 64) * QC) {
+    double g[QC][R];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QC; ++q) {
       const int c = min(cb + q, m - 1);
       const double* col = M + (size_t)m * c;
 #pragma unroll
@@ -1907,7 +1912,7 @@ __device__ __forceinline__ void gemv_t(const double* M, int m, bool lower, doubl
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QC; ++q) {
       double acc = 0.0;
 #pragma unroll
       for (int t = 0; t < R; ++t) acc += g[q][t] * yr[t];
@@ -1916,7 +1921,7 @@ __device__ __forceinline__ void gemv_t(const double* M, int m, bool lower, doubl
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m; i += kThreads) y[i] = red[i];
+  for (int i = threadIdx.x; i < m; i += NT) y[i] = red[i];
   __syncthreads();
 }
 
@@ -2648,6 +2653,26 @@ __global__ void __launch_bounds__(kThreads) fwd_units_kernel(const ItemD* __rest
   fwd_unit_any(it, blockIdx.x % upi, ls, vec);
 }
 
+// Per-cluster part of the forward sweep of a colour launched as wide (see
+// launch_fwd): y_s <- W y_s (giok 2) or G^{-1} y_s (giok 1), the product of
+// fwd_head with twice its waves, so every row's sum keeps its order.
+__global__ void __launch_bounds__(kWideThreads) fwd_wide_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                                double* vec) {
+  __shared__ double y[kInvMaxDofs];
+  __shared__ double red[4 * 256];
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m;
+  if (m == 0) return;
+  const int gk = ls.giok[it.s];
+  if (m > kInvMaxDofs || (gk != 1 && gk != 2)) {
+    if (threadIdx.x == 0) item_error(it, ls.err, -1, kErrIndex);
+    return;
+  }
+  double* yg = vec + it.voff;
+  gemv_blk<kWideThreads>(it.S, m, gk == 2 ? kGemvFull : kGemvLower, y, red, yg);
+  for (int i = threadIdx.x; i < m; i += kWideThreads) yg[i] = y[i];
+}
+
 __global__ void __launch_bounds__(kThreads) bwd_units_kernel(const ItemD* __restrict__ items, LevelState ls,
                                                              double* vec, int upi) {
   extern __shared__ double lds[];
@@ -2743,12 +2768,15 @@ int sweep_units(bool forward, int max_m, int max_acap) {
 }
 
 void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
-                hipStream_t st) {
+                hipStream_t st, bool wide) {
   if (nitems <= 0) return;
   allow_sweep_lds();
   const int upi = sweep_units(true, max_m, max_acap);
-  hipLaunchKernelGGL(fwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, nitems, ls, vec,
-                     upi > 0 ? 1 : 0);
+  if (wide && upi > 0 && max_m <= kInvMaxDofs && !ls.nodc)
+    hipLaunchKernelGGL(fwd_wide_kernel, dim3(nitems), dim3(kWideThreads), 0, st, items, ls, vec);
+  else
+    hipLaunchKernelGGL(fwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, nitems, ls, vec,
+                       upi > 0 ? 1 : 0);
   if (upi > 0)
     hipLaunchKernelGGL(fwd_units_kernel, dim3(nitems * upi), dim3(kThreads), 0, st, items, ls, vec, upi);
 }

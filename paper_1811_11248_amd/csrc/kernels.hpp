@@ -72,9 +72,14 @@ constexpr int kSweepWaveVix = 64;  // near-field vector indices staged per clust
 constexpr size_t kSweepWaveTableBytes = 64 + 4 * kSweepWaveVix;  // descriptor, indices
 constexpr size_t kSweepWaveTableMax = 96 * 1024;
 int sweep_units(bool forward, int max_m, int max_acap);
-// The items of one colour (one launch, plus one for the units).
+// The items of one colour (one launch, plus one for the units).  wide: every
+// item is a cluster of kSweepSplitM..kInvMaxDofs DoFs whose store holds W
+// (giok 2) or, with no reflector, G^{-1} (giok 1), as after the split
+// schedule on a level of such clusters; its product with W then runs in a
+// workgroup of kWideThreads (same arithmetic, more loads in flight).
+constexpr int kWideThreads = 512;
 void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
-                hipStream_t st);
+                hipStream_t st, bool wide = false);
 void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
                 hipStream_t st);
 // A whole level in one persistent launch; [vlo, vlo + vn) is the level's

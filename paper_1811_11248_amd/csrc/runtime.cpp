@@ -158,7 +158,11 @@ lrsp_status setup_level_a(LevelDev* L, hipStream_t st, int64_t vbase) {
   const int M = p.M;
   plan_layout(&p);
   L->max_m = 0;
-  for (int x = 0; x < M; ++x) L->max_m = std::max(L->max_m, p.m[x]);
+  L->min_m = M > 0 ? p.m[0] : 0;
+  for (int x = 0; x < M; ++x) {
+    L->max_m = std::max(L->max_m, p.m[x]);
+    L->min_m = std::min(L->min_m, p.m[x]);
+  }
   if (L->max_m > kMaxClusterDofs)
     return fail(LRSP_ERR_ARG, "cluster larger than " + std::to_string(kMaxClusterDofs) +
                                   " DoFs; use a smaller leaf size");

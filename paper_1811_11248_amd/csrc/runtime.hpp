@@ -107,7 +107,7 @@ struct LevelDev {
   const uint64_t id = next_level_id();  // unique per workspace
   LevelPlan plan;
   std::vector<int> k, a, b;
-  int max_m = 0;
+  int max_m = 0, min_m = 0;
   DevBuf work, wints;      // D / fine halves; posmaps and column lists
   DevBuf coarse;           // coarse halves (sized by the rank capacities)
   DevBuf fac;              // panels, inverses, tau, norms (doubles): the level's workspace

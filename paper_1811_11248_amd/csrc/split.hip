@@ -521,7 +521,7 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gr = 16 * r + 4 * v + lr, gc = 16 * p + lc;
-        if (gr < m && gc <= gr) A[gr + (size_t)m * gc] = x[v];
+        if (gr < m && gc <= gr) gstore(A + gr + (size_t)m * gc, x[v]);
       }
     }
     // tile row p of G^{-1}: X_pj = G_pp^{-1} acc_pj (j < p, the accumulators
@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
       for (int v = 0; v < 4; ++v) {
         if (jt < p) Xr[(4 * v + lr) * kInvLdX + 16 * jt + lc] = x[v];
         const int gr = 16 * p + 4 * v + lr, gc = 16 * jt + lc;
-        if (gr < m && gc < m) Xg[gr + (size_t)m * gc] = x[v];
+        if (gr < m && gc < m) gstore(Xg + gr + (size_t)m * gc, x[v]);
       }
     }
     lds_barrier();
@@ -641,7 +641,7 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * 512;
         const int c = e / nr, r = e - c * nr;
-        v[u] = (e < n && r < m && c < wc) ? B[r + (size_t)m * c] : 0.0;
+        v[u] = (e < n && r < m && c < wc) ? gload(B + r + (size_t)m * c) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -665,7 +665,7 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
           const int gk = 16 * (k0 + kk) + 4 * s4 + lr;
-          av[kk][s4] = (k0 + kk <= i && gr < m && gk < m && gk <= gr) ? Gi[gr + (size_t)m * gk] : 0.0;
+          av[kk][s4] = (k0 + kk <= i && gr < m && gk < m && gk <= gr) ? gload(Gi + gr + (size_t)m * gk) : 0.0;
         }
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
@@ -684,10 +684,10 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * i + 4 * v + lr;
       if (r < m) {
-        if (lc < wc) B[r + (size_t)m * lc] = acc0[v];
+        if (lc < wc) gstore(B + r + (size_t)m * lc, acc0[v]);
         s0 += acc0[v] * acc0[v];
         if constexpr (NC == 32) {
-          if (16 + lc < wc) B[r + (size_t)m * (16 + lc)] = acc1[v];
+          if (16 + lc < wc) gstore(B + r + (size_t)m * (16 + lc), acc1[v]);
           s1 += acc1[v] * acc1[v];
         }
       }
@@ -705,7 +705,7 @@ __global__ void __launch_bounds__(512) trsm_inv_kernel(const ItemD* __restrict__
   if (tid < wc && c0 + tid >= a) {
     double t = 0.0;
     for (int i = 0; i < nt; ++i) t += red[i * 32 + tid];
-    it.norms[c0 + tid - a] = t;
+    gstore(it.norms + c0 + tid - a, t);
   }
 }
 
@@ -1026,7 +1026,7 @@ __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ i
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const int i = lane + 64 * t;
-          y[q][t] = (c < c1 && i >= i0 && i < m) ? C[(size_t)m * c + i] : 0.0;
+          y[q][t] = (c < c1 && i >= i0 && i < m) ? gload(C + (size_t)m * c + i) : 0.0;
         }
       }
       for (int jj = 0; jj < nj; ++jj) {
@@ -1057,7 +1057,7 @@ __global__ void __launch_bounds__(256) applyq_kernel(const ItemD* __restrict__ i
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const int i = lane + 64 * t;
-          if (i < m) C[(size_t)m * c + i] = y[q][t];
+          if (i < m) gstore(C + (size_t)m * c + i, y[q][t]);
         }
       }
     }
@@ -1120,7 +1120,7 @@ __global__ void __launch_bounds__(256) schur_kernel(const ItemD* __restrict__ it
       const int half = e >> 9, ee = e & 511;
       const int col = ee >> 4, ii = ee & 15;
       const int gi = i0 + ii, gc = (half ? C0 : R0) + col;
-      const double v = (gi < m && gc < a) ? C[(size_t)m * gc + gi] : 0.0;
+      const double v = (gi < m && gc < a) ? gload(C + (size_t)m * gc + gi) : 0.0;
       if (half) Fc[ii][col] = v;
       else Fr[ii][col] = v;
     }
