@@ -94,7 +94,7 @@ struct lrsp_factorization {
   DevBuf top_gidx;        // indices into the last level's vector (or unused)
   std::vector<int> top_sizes, top_adj_ptr, top_adj;
   DevBuf perm;            // level-0 cluster order
-  DevBuf vec;             // all level vectors
+  DevBuf vec;             // all level vectors, then their shadow copy
   int64_t vec_total = 0;
   DevBuf scratch;         // PCG work vectors / scalars
   size_t scratch_n = 0;
@@ -731,8 +731,10 @@ static lrsp_status factor_impl(const lrsp_csr* A, lrsp_tree* T, double tol, cons
   flops[5] = (double)ntop * ntop * ntop / 3.0;
   F->top_vbase = vbase;
   F->vec_total = vbase + ntop;
-  HIPCHK(dalloc(&F->vec, sizeof(double) * std::max<int64_t>(1, F->vec_total), st));
-  launch_zero(at<double>(F->vec, 0), F->vec_total, st);
+  // the level vectors, then a shadow copy laid out the same way (the
+  // forward products of split levels write there)
+  HIPCHK(dalloc(&F->vec, sizeof(double) * std::max<int64_t>(1, 2 * F->vec_total), st));
+  launch_zero(at<double>(F->vec, 0), 2 * F->vec_total, st);
   HIPCHK(hipStreamSynchronize(st));
   const auto t1 = std::chrono::steady_clock::now();
   lrsp_info& inf = F->info;
@@ -807,7 +809,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
         const bool wide = L.split && L.min_m >= kSweepSplitM && L.max_m <= kInvMaxDofs && !F->nodc;
         for (int c = 0; c < p.ncolours; ++c)
           launch_fwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st,
-                     wide);
+                     wide ? V + F->vec_total : nullptr);
       }
       if (g_tm.on)
         for (double by : L.sweep_bytes) g_tm.bytes[1] += by;
@@ -842,8 +844,10 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
           launch_sweep_level(false, L.d_items, L.d_cstart, p.ncolours, p.cstart.back(), L.max_items, L.max_m, L.max_acap, L.ls, V,
                              st, 0, nullptr, L.vbase, L.nvec) != hipSuccess) {
         if (!per_colour) (void)hipGetLastError();
+        const bool wide = L.split && L.min_m >= kSweepSplitM && L.max_m <= kInvMaxDofs && !F->nodc;
         for (int c = p.ncolours - 1; c >= 0; --c)
-          launch_bwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st);
+          launch_bwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st,
+                     wide);
       }
       if (g_tm.on)
         for (double by : L.sweep_bytes) g_tm.bytes[2] += by;

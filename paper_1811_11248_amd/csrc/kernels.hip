@@ -2187,12 +2187,13 @@ __device__ __forceinline__ void fwd_head(const ItemD& it, LevelState ls, double*
 // Forward sweep of a split cluster, unit `part`: y_n -= F^T y_f over columns
 // [part*kSweepCols, (part+1)*kSweepCols) of F, y_s read from the vector.
 template <int R>
-__device__ __forceinline__ void fwd_unit(const ItemD& it, int part, LevelState ls, double* vec) {
+__device__ __forceinline__ void fwd_unit(const ItemD& it, int part, LevelState ls, double* vec,
+                                         const double* ysrc) {
   const int m = it.m;
   const int k = ls.k[it.s], a = ls.a[it.s];
   const int c0 = part * kSweepCols;
   if (m == 0 || c0 >= a) return;
-  fwd_near<R>(it, m, k, c0, min(a, c0 + kSweepCols), vec + it.voff, vec);
+  fwd_near<R>(it, m, k, c0, min(a, c0 + kSweepCols), ysrc + it.voff, vec);
 }
 
 // Backward sweep of a split cluster, unit `part`: x_f -= F x_n for the rows
@@ -2622,8 +2623,9 @@ __device__ __forceinline__ void bwd_any(const ItemD& it, bool split, LevelState 
   }
 }
 
-__device__ __forceinline__ void fwd_unit_any(const ItemD& it, int part, LevelState ls, double* vec) {
-  if (it.m >= kSweepSplitM) LRSP_ROWS_DISPATCH(fwd_unit, it, part, ls, vec);
+__device__ __forceinline__ void fwd_unit_any(const ItemD& it, int part, LevelState ls, double* vec,
+                                             const double* ysrc) {
+  if (it.m >= kSweepSplitM) LRSP_ROWS_DISPATCH(fwd_unit, it, part, ls, vec, ysrc);
 }
 
 // Items of one colour; with split (a level holding clusters of at least
@@ -2648,18 +2650,71 @@ __global__ void __launch_bounds__(kThreads) bwd_kernel(const ItemD* __restrict__
 
 // Units of the split clusters of one colour: upi units per item.
 __global__ void __launch_bounds__(kThreads) fwd_units_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                             double* vec, int upi) {
+                                                             double* vec, int upi, const double* shadow) {
   const ItemD& it = items[blockIdx.x / upi];
-  fwd_unit_any(it, blockIdx.x % upi, ls, vec);
+  const int part = blockIdx.x % upi;
+  // y_s in the shadow vector (rows formed by fwd_rows_kernel): read there,
+  // and copied back by the cluster's first unit
+  fwd_unit_any(it, part, ls, vec, shadow ? shadow : vec);
+  if (shadow && part == 0)
+    for (int i = threadIdx.x; i < it.m; i += kThreads) vec[it.voff + i] = gload(shadow + it.voff + i);
 }
 
-// Per-cluster part of the forward sweep of a colour launched as wide (see
-// launch_fwd): y_s <- W y_s (giok 2) or G^{-1} y_s (giok 1), the product of
-// fwd_head with twice its waves, so every row's sum keeps its order.
-__global__ void __launch_bounds__(kWideThreads) fwd_wide_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                                double* vec) {
+// Per-cluster part of the forward sweep of a wide colour (see launch_fwd):
+// workgroup (i, b) forms rows 64b.. of W y_s (giok 2) or G^{-1} y_s (giok 1)
+// into the shadow vector, wave w the partial sums of column block w.  Every
+// row's sum has the order of gemv_blk (each tile's 64 products in order,
+// then the tiles in order).
+__global__ void __launch_bounds__(kThreads) fwd_rows_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                            const double* vec, double* shadow) {
   __shared__ double y[kInvMaxDofs];
-  __shared__ double red[4 * 256];
+  __shared__ double red[4 * 64];
+  const ItemD& it = items[blockIdx.x];
+  const int m = it.m, ib = blockIdx.y, i0 = 64 * ib;
+  if (i0 >= m) return;
+  const int gk = ls.giok[it.s];
+  if (m > kInvMaxDofs || (gk != 1 && gk != 2)) {
+    if (threadIdx.x == 0) item_error(it, ls.err, -1, kErrIndex);
+    return;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, jb = tid >> 6;
+  const int nb = (m + 63) >> 6;
+  const bool full = gk == 2;
+  const bool on = jb < nb && (full || jb <= ib);
+  const int i = i0 + lane;
+  double g[64];
+  if (on) {
+    const double* Mi = it.S + min(i, m - 1);
+#pragma unroll
+    for (int q = 0; q < 64; ++q) {
+      const int j = 64 * jb + q;
+      g[q] = (i < m && j < m && (full || j <= i)) ? gload(Mi + (size_t)m * j) : 0.0;
+    }
+  }
+  for (int r = tid; r < m; r += kThreads) y[r] = gload(vec + it.voff + r);
+  lds_barrier();
+  if (on) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 64; ++q) s += g[q] * y[min(64 * jb + q, m - 1)];
+    red[jb * 64 + lane] = s;
+  }
+  lds_barrier();
+  if (tid < 64 && i < m) {
+    const int j1 = full ? nb : ib + 1;
+    double t = 0.0;
+    for (int b = 0; b < j1; ++b) t += red[b * 64 + tid];
+    gstore(shadow + it.voff + i, t);
+  }
+}
+
+// Per-cluster part of the backward sweep of a wide colour (see launch_bwd):
+// x_s <- W^T x_s (giok 2) or G^{-T} x_s (giok 1, no reflector), the columns
+// of gemv_t spread over twice the waves (every column's sum keeps its order).
+__global__ void __launch_bounds__(kWideThreads) bwd_wide_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                                double* vec) {
+  __shared__ double x[kInvMaxDofs];
+  __shared__ double red[kInvMaxDofs];
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   if (m == 0) return;
@@ -2668,9 +2723,11 @@ __global__ void __launch_bounds__(kWideThreads) fwd_wide_kernel(const ItemD* __r
     if (threadIdx.x == 0) item_error(it, ls.err, -1, kErrIndex);
     return;
   }
-  double* yg = vec + it.voff;
-  gemv_blk<kWideThreads>(it.S, m, gk == 2 ? kGemvFull : kGemvLower, y, red, yg);
-  for (int i = threadIdx.x; i < m; i += kWideThreads) yg[i] = y[i];
+  double* xg = vec + it.voff;
+  for (int i = threadIdx.x; i < m; i += kWideThreads) x[i] = gload(xg + i);
+  __syncthreads();
+  gemv_t<4, kWideThreads>(it.S, m, gk != 2, x, red);
+  for (int i = threadIdx.x; i < m; i += kWideThreads) gstore(xg + i, x[i]);
 }
 
 __global__ void __launch_bounds__(kThreads) bwd_units_kernel(const ItemD* __restrict__ items, LevelState ls,
@@ -2713,7 +2770,7 @@ __global__ void __launch_bounds__(kThreads) fwd_level_kernel(const ItemD* __rest
       const int n = (cstart[c + 1] - cstart[c]) * upi;
       for (int u = blockIdx.x; u < n; u += gridDim.x) {
         const ItemD& it = items[cstart[c] + u / upi];
-        fwd_unit_any(it, u % upi, ls, vec);
+        fwd_unit_any(it, u % upi, ls, vec, vec);
       }
       level_sync<SW>(bar);
     }
@@ -2768,29 +2825,34 @@ int sweep_units(bool forward, int max_m, int max_acap) {
 }
 
 void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
-                hipStream_t st, bool wide) {
+                hipStream_t st, double* shadow) {
   if (nitems <= 0) return;
   allow_sweep_lds();
   const int upi = sweep_units(true, max_m, max_acap);
-  if (wide && upi > 0 && max_m <= kInvMaxDofs && !ls.nodc)
-    hipLaunchKernelGGL(fwd_wide_kernel, dim3(nitems), dim3(kWideThreads), 0, st, items, ls, vec);
+  if (!(shadow && upi > 0 && max_m <= kInvMaxDofs && !ls.nodc)) shadow = nullptr;
+  if (shadow)
+    hipLaunchKernelGGL(fwd_rows_kernel, dim3(nitems, (max_m + 63) / 64), dim3(kThreads), 0, st, items, ls, vec,
+                       shadow);
   else
     hipLaunchKernelGGL(fwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, nitems, ls, vec,
                        upi > 0 ? 1 : 0);
   if (upi > 0)
-    hipLaunchKernelGGL(fwd_units_kernel, dim3(nitems * upi), dim3(kThreads), 0, st, items, ls, vec, upi);
+    hipLaunchKernelGGL(fwd_units_kernel, dim3(nitems * upi), dim3(kThreads), 0, st, items, ls, vec, upi, shadow);
 }
 
 void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
-                hipStream_t st) {
+                hipStream_t st, bool wide) {
   if (nitems <= 0) return;
   allow_sweep_lds();
   const int upi = sweep_units(false, max_m, max_acap);
   if (upi > 0)
     hipLaunchKernelGGL(bwd_units_kernel, dim3(nitems * upi), dim3(kThreads), (1024 + 256) * sizeof(double), st,
                        items, ls, vec, upi);
-  hipLaunchKernelGGL(bwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, nitems, ls, vec,
-                     upi > 0 ? 1 : 0);
+  if (wide && upi > 0 && max_m <= kInvMaxDofs && !ls.nodc)
+    hipLaunchKernelGGL(bwd_wide_kernel, dim3(nitems), dim3(kWideThreads), 0, st, items, ls, vec);
+  else
+    hipLaunchKernelGGL(bwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, nitems, ls, vec,
+                       upi > 0 ? 1 : 0);
 }
 
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,

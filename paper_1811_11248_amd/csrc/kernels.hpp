@@ -72,16 +72,20 @@ constexpr int kSweepWaveVix = 64;  // near-field vector indices staged per clust
 constexpr size_t kSweepWaveTableBytes = 64 + 4 * kSweepWaveVix;  // descriptor, indices
 constexpr size_t kSweepWaveTableMax = 96 * 1024;
 int sweep_units(bool forward, int max_m, int max_acap);
-// The items of one colour (one launch, plus one for the units).  wide: every
-// item is a cluster of kSweepSplitM..kInvMaxDofs DoFs whose store holds W
-// (giok 2) or, with no reflector, G^{-1} (giok 1), as after the split
-// schedule on a level of such clusters; its product with W then runs in a
-// workgroup of kWideThreads (same arithmetic, more loads in flight).
-constexpr int kWideThreads = 512;
+// The items of one colour (one launch, plus one for the units).  shadow
+// (non-null): every item is a cluster of kSweepSplitM..kInvMaxDofs DoFs
+// whose store holds W (giok 2) or, with no reflector, G^{-1} (giok 1), as
+// after the split schedule on a level of such clusters; the product with W
+// then runs in one workgroup per 64 rows, writing to shadow (a vector laid
+// out like vec), from where the units read it and copy it back (same
+// arithmetic as the product in one workgroup).
 void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
-                hipStream_t st, bool wide = false);
+                hipStream_t st, double* shadow = nullptr);
+// wide: the same clusters as for launch_fwd's shadow; their product with W^T
+// runs in a workgroup of kWideThreads (same arithmetic, more loads in flight).
+constexpr int kWideThreads = 512;
 void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
-                hipStream_t st);
+                hipStream_t st, bool wide = false);
 // A whole level in one persistent launch; [vlo, vlo + vn) is the level's
 // range of the vector buffer (vn = 0: unknown).
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
