@@ -847,7 +847,7 @@ static lrsp_status apply_one(const lrsp_factorization* F, const double* b, doubl
         const bool wide = L.split && L.min_m >= kSweepSplitM && L.max_m <= kInvMaxDofs && !F->nodc;
         for (int c = p.ncolours - 1; c >= 0; --c)
           launch_bwd(L.d_items + p.cstart[c], p.cstart[c + 1] - p.cstart[c], L.max_m, L.max_acap, L.ls, V, st,
-                     wide);
+                     wide ? V + F->vec_total : nullptr);
       }
       if (g_tm.on)
         for (double by : L.sweep_bytes) g_tm.bytes[2] += by;

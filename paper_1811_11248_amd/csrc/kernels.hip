@@ -2201,11 +2201,18 @@ __device__ __forceinline__ void fwd_unit(const ItemD& it, int part, LevelState l
 // 8 column groups (two per wave): every row sums its columns group by group
 // in a fixed order, then the eight group sums in order.  x_n passes through
 // LDS 1024 columns at a time.  lds: 1024 + 256 doubles.
-__device__ __forceinline__ void bwd_unit(const ItemD& it, int part, LevelState ls, double* vec, double* lds) {
+__device__ __forceinline__ void bwd_unit(const ItemD& it, int part, LevelState ls, double* vec, double* lds,
+                                         double* shadow = nullptr) {
   const int m = it.m;
   const int k = ls.k[it.s], a = ls.a[it.s];
   const int r0 = part * kSweepRows;
-  if (m == 0 || a == 0 || r0 >= m || r0 + kSweepRows <= k) return;
+  if (m == 0 || r0 >= m) return;
+  if (a == 0 || r0 + kSweepRows <= k) {
+    // nothing to subtract: the rows go to the shadow vector unchanged
+    if (shadow && threadIdx.x < kSweepRows && r0 + threadIdx.x < m)
+      gstore(shadow + it.voff + r0 + threadIdx.x, gload(vec + it.voff + r0 + threadIdx.x));
+    return;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row = r0 + (lane & 31), g = 2 * wv + (lane >> 5);
   const bool act = row >= k && row < m;
@@ -2237,11 +2244,16 @@ __device__ __forceinline__ void bwd_unit(const ItemD& it, int part, LevelState l
   }
   red[g * 32 + (lane & 31)] = s;
   __syncthreads();
-  if (tid < 32 && r0 + tid >= k && r0 + tid < m) {
-    double t = 0.0;
+  if (tid < 32 && r0 + tid < m) {
+    double v = vec[it.voff + r0 + tid];
+    if (r0 + tid >= k) {
+      double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) t += red[q * 32 + tid];
-    vec[it.voff + r0 + tid] -= t;
+      for (int q = 0; q < 8; ++q) t += red[q * 32 + tid];
+      v -= t;
+      if (!shadow) vec[it.voff + r0 + tid] = v;
+    }
+    if (shadow) gstore(shadow + it.voff + r0 + tid, v);
   }
   __syncthreads();
 }
@@ -2709,32 +2721,56 @@ __global__ void __launch_bounds__(kThreads) fwd_rows_kernel(const ItemD* __restr
 }
 
 // Per-cluster part of the backward sweep of a wide colour (see launch_bwd):
-// x_s <- W^T x_s (giok 2) or G^{-T} x_s (giok 1, no reflector), the columns
-// of gemv_t spread over twice the waves (every column's sum keeps its order).
-__global__ void __launch_bounds__(kWideThreads) bwd_wide_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                                double* vec) {
-  __shared__ double x[kInvMaxDofs];
-  __shared__ double red[kInvMaxDofs];
+// x_s <- W^T x_s (giok 2) or G^{-T} x_s (giok 1, no reflector), x_s read
+// from the shadow vector (written by the units), workgroup (i, b) the
+// entries 64b.. written to the vector; wave w the 16 columns 64b + 16w..,
+// each column's sum formed as in gemv_t (same lanes, same order).
+__global__ void __launch_bounds__(kThreads) bwd_cols_kernel(const ItemD* __restrict__ items, LevelState ls,
+                                                            double* vec, const double* shadow) {
+  constexpr int R = 4, QC = 16;
   const ItemD& it = items[blockIdx.x];
-  const int m = it.m;
-  if (m == 0) return;
+  const int m = it.m, c0 = 64 * blockIdx.y;
+  if (c0 >= m) return;
   const int gk = ls.giok[it.s];
   if (m > kInvMaxDofs || (gk != 1 && gk != 2)) {
     if (threadIdx.x == 0) item_error(it, ls.err, -1, kErrIndex);
     return;
   }
-  double* xg = vec + it.voff;
-  for (int i = threadIdx.x; i < m; i += kWideThreads) x[i] = gload(xg + i);
-  __syncthreads();
-  gemv_t<4, kWideThreads>(it.S, m, gk != 2, x, red);
-  for (int i = threadIdx.x; i < m; i += kWideThreads) gstore(xg + i, x[i]);
+  const bool lower = gk != 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int cb = c0 + QC * wv;
+  const double* M = it.S;
+  double g[QC][R], yr[R];
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    const int c = min(cb + q, m - 1);
+    const double* col = M + (size_t)m * c;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = lane + 64 * t;
+      g[q][t] = (cb + q < m && i < m && (!lower || i >= c)) ? gload(col + i) : 0.0;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int i = lane + 64 * t;
+    yr[t] = i < m ? gload(shadow + it.voff + i) : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) acc += g[q][t] * yr[t];
+    acc = wave_sum(acc);
+    if (lane == q && cb + q < m) gstore(vec + it.voff + cb + q, acc);
+  }
 }
 
 __global__ void __launch_bounds__(kThreads) bwd_units_kernel(const ItemD* __restrict__ items, LevelState ls,
-                                                             double* vec, int upi) {
+                                                             double* vec, int upi, double* shadow) {
   extern __shared__ double lds[];
   const ItemD& it = items[blockIdx.x / upi];
-  if (it.m >= kSweepSplitM) bwd_unit(it, blockIdx.x % upi, ls, vec, lds);
+  if (it.m >= kSweepSplitM) bwd_unit(it, blockIdx.x % upi, ls, vec, lds, shadow);
 }
 
 template <bool SW>
@@ -2841,15 +2877,17 @@ void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelSt
 }
 
 void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
-                hipStream_t st, bool wide) {
+                hipStream_t st, double* shadow) {
   if (nitems <= 0) return;
   allow_sweep_lds();
   const int upi = sweep_units(false, max_m, max_acap);
+  if (!(shadow && upi > 0 && max_m <= kInvMaxDofs && !ls.nodc)) shadow = nullptr;
   if (upi > 0)
     hipLaunchKernelGGL(bwd_units_kernel, dim3(nitems * upi), dim3(kThreads), (1024 + 256) * sizeof(double), st,
-                       items, ls, vec, upi);
-  if (wide && upi > 0 && max_m <= kInvMaxDofs && !ls.nodc)
-    hipLaunchKernelGGL(bwd_wide_kernel, dim3(nitems), dim3(kWideThreads), 0, st, items, ls, vec);
+                       items, ls, vec, upi, shadow);
+  if (shadow)
+    hipLaunchKernelGGL(bwd_cols_kernel, dim3(nitems, (max_m + 63) / 64), dim3(kThreads), 0, st, items, ls, vec,
+                       shadow);
   else
     hipLaunchKernelGGL(bwd_kernel, dim3(nitems), dim3(kThreads), sweep_lds(max_m), st, items, nitems, ls, vec,
                        upi > 0 ? 1 : 0);

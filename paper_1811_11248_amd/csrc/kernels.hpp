@@ -81,11 +81,11 @@ int sweep_units(bool forward, int max_m, int max_acap);
 // arithmetic as the product in one workgroup).
 void launch_fwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
                 hipStream_t st, double* shadow = nullptr);
-// wide: the same clusters as for launch_fwd's shadow; their product with W^T
-// runs in a workgroup of kWideThreads (same arithmetic, more loads in flight).
-constexpr int kWideThreads = 512;
+// shadow (non-null): the same clusters as for launch_fwd; the units write
+// their rows to shadow and the product with W^T, one workgroup per 64
+// entries, reads it there and writes the vector (same arithmetic).
 void launch_bwd(const ItemD* items, int nitems, int max_m, int max_acap, LevelState ls, double* vec,
-                hipStream_t st, bool wide = false);
+                hipStream_t st, double* shadow = nullptr);
 // A whole level in one persistent launch; [vlo, vlo + vn) is the level's
 // range of the vector buffer (vn = 0: unknown).
 hipError_t launch_sweep_level(bool forward, const ItemD* items, const int32_t* cstart, int ncolours,
