@@ -2009,10 +2009,12 @@ __device__ __forceinline__ void apply_reflectors(const double* V, const double* 
 }
 
 // y_n -= F^T y_f over the columns [c0, c1) of F = C[k:m, :] (C = U^T G^{-1}
-// A_sn in the factor store, ld m): one wave per column, four columns in
-// flight.  y (m entries) may be in LDS or global memory.
+// A_sn in the factor store, ld m): one wave per column, QC columns in flight
+// (16 for clusters of at most 256 DoFs, else 4; every column's sum has the
+// same order either way).  y (m entries) may be in LDS or global memory.
 template <int R>
 __device__ __forceinline__ void fwd_near(const ItemD& it, int m, int k, int c0, int c1, const double* y, double* vec) {
+  constexpr int QC = R <= 4 ? 16 : 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double yr[R];
 #pragma unroll
@@ -2021,32 +2023,27 @@ __device__ __forceinline__ void fwd_near(const ItemD& it, int m, int k, int c0, 
     yr[t] = (i >= k && i < m) ? y[i] : 0.0;
   }
   const double* C = it.S + (size_t)m * m;
-  for (int cb = c0 + wv * 4; cb < c1; cb += kWaves * 4) {
-    double g[4][R];
+  for (int cb = c0 + wv * QC; cb < c1; cb += kWaves * QC) {
+    double g[QC][R];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QC; ++q) {
       const double* f = C + (size_t)m * min(cb + q, c1 - 1);
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         const int i = lane + 64 * t;
-        g[q][t] = (cb + q < c1 && i >= k && i < m) ? f[i] : 0.0;
+        g[q][t] = (cb + q < c1 && i >= k && i < m) ? gload(f + i) : 0.0;
       }
     }
-    double s[4];
+    double sv = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QC; ++q) {
       double acc = 0.0;
 #pragma unroll
       for (int t = 0; t < R; ++t) acc += g[q][t] * yr[t];
-      s[q] = wave_sum(acc);
+      acc = wave_sum(acc);
+      if (q == lane) sv = acc;
     }
-    if (lane < 4 && cb + lane < c1) {
-      double sv = s[0];
-#pragma unroll
-      for (int q = 1; q < 4; ++q)
-        if (q == lane) sv = s[q];
-      vec[it.vidx[cb + lane]] -= sv;
-    }
+    if (lane < QC && cb + lane < c1) vec[it.vidx[cb + lane]] -= sv;
   }
 }
 
@@ -3103,7 +3100,12 @@ __global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, 
           bad = bad || kb + u < np;
           d = 1.0;
         }
-        const double piv = sqrt(d), rs = 1.0 / piv;
+        // 1 / sqrt(d) from v_rsq_f64 refined by two Newton steps, sqrt(d)
+        // as d times it (no divide or square-root sequence on the chain)
+        double rs = __builtin_amdgcn_rsq(d);
+        rs = rs + rs * (0.5 - 0.5 * d * rs * rs);
+        rs = rs + rs * (0.5 - 0.5 * d * rs * rs);
+        const double piv = d * rs;
         if (lane == u) {
           row[u] = piv;
           rd[kb + u] = rs;
