@@ -3065,10 +3065,9 @@ __device__ __forceinline__ void store_tile(double* A, size_t ld, int r0, int c0,
 // L_pp (lower) in place and L_pp^{-1} in the extra columns.  A pivot that is
 // not > 0 is replaced by 1 and reported in the error words (bits == 0) or as
 // the error bit of a batched system.
-__global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, int p, int32_t* err, int bits) {
-  __shared__ double S[kTB * kTLd];  // the block, row-major (lower part used)
-  __shared__ double rd[kTB];        // 1 / L_jj
-  __shared__ int sbad;
+// S: kTB x kTLd doubles of LDS, rd: kTB doubles of LDS, sbad: an int of LDS.
+__device__ __forceinline__ void dense_diag_block(double* A, int n, int p, int32_t* err, int bits, double* S,
+                                                 double* rd, int& sbad) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int rp = p * kTB, np = min(kTB, n - rp);
   // the block (identity beyond np), eight loads in flight per thread
@@ -3087,6 +3086,7 @@ __global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, 
   }
   if (tid == 0) sbad = 0;
   __syncthreads();
+#pragma unroll
   for (int kb = 0; kb < kTB; kb += 16) {
     if (wv == 0) {
       double row[16];
@@ -3158,30 +3158,45 @@ __global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, 
     __syncthreads();
   }
   // the factor to A
-  for (int e = tid; e < np * np; e += kThreads) {
-    const int c = e / np, r = e - c * np;
-    if (r >= c) A[(size_t)(rp + r) + (size_t)n * (rp + c)] = S[r * kTLd + c];
+  for (int e = tid; e < kTB * kTB; e += kThreads) {
+    const int c = e / kTB, r = e - c * kTB;
+    if (r < np && c < np && r >= c) A[(size_t)(rp + r) + (size_t)n * (rp + c)] = S[r * kTLd + c];
   }
-  // column `tid` of L^{-1}
-  if (tid < kTB) {
-    double x[kTB];
+  // column c = 16 wv + lane / 4 of L^{-1} by the four lanes q = lane % 4 of
+  // a quad: lane q keeps the entries x_k, k = q mod 4, and sums the terms of
+  // those k of every row (lane 0 starting from the identity's entry); the
+  // quad then adds its four partial sums as (0+1)+(2+3)
+  {
+    const int c = 16 * wv + (lane >> 2), q = lane & 3;
+    double xq[kTB / 4];
 #pragma unroll
     for (int r = 0; r < kTB; ++r) {
-      double s4[4] = {r == tid ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+      double s = (q == 0 && r == c) ? 1.0 : 0.0;
 #pragma unroll
-      for (int k = 0; k < r; ++k) s4[k & 3] -= S[r * kTLd + k] * x[k];
-      x[r] = r >= tid ? ((s4[0] + s4[1]) + (s4[2] + s4[3])) * rd[r] : 0.0;
+      for (int j = 0; 4 * j < r; ++j)
+        if (4 * j + q < r) s -= S[r * kTLd + 4 * j + q] * xq[j];
+      double t = s + dpp_d<kDppXor1>(s);
+      t = t + dpp_d<kDppXor2>(t);
+      const double xr = r >= c ? t * rd[r] : 0.0;
+      if ((r & 3) == q) xq[r >> 2] = xr;
     }
-    if (tid < np) {
+    if (c < np) {
 #pragma unroll
-      for (int r = 0; r < kTB; ++r)
-        if (r < np) A[(size_t)n * n + (size_t)(rp + r) + (size_t)n * tid] = x[r];
+      for (int j = 0; j < kTB / 4; ++j)
+        if (4 * j + q < np) A[(size_t)n * n + (size_t)(rp + 4 * j + q) + (size_t)n * c] = xq[j];
     }
   }
   if (sbad && tid == 0) {
     if (bits) atomicOr(err, 1 << kErrNotSPD);
     else set_error(err, -1, -1, kErrNotSPD);
   }
+}
+
+__global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, int p, int32_t* err, int bits) {
+  __shared__ double S[kTB * kTLd];  // the block, row-major (lower part used)
+  __shared__ double rd[kTB];        // 1 / L_jj
+  __shared__ int sbad;
+  dense_diag_block(A, n, p, err, bits, S, rd, sbad);
 }
 
 // Panel launch of step p: workgroup b < T takes row tile i = p + 1 + b, L_ip
@@ -3225,9 +3240,13 @@ __global__ void __launch_bounds__(kThreads) dense_panel_kernel(double* A, int n,
 // Update launch of step p: workgroup t < T(T+1)/2 takes lower tile (i, j),
 // p < j <= i, in row order of the triangle; with X, the further workgroups
 // take the tiles (i, c), i > p, c <= p, of the inverse's accumulators:
-// R_ic -= L_ip X_pc.
-__global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n, int p, int T, double* X) {
+// R_ic -= L_ip X_pc.  Workgroup 0, whose tile (p+1, p+1) is then final,
+// goes on to factor and invert that diagonal block (the diagonal step of
+// step p + 1, while the other tiles are still being updated).
+__global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n, int p, int T, double* X,
+                                                                int32_t* err, int bits) {
   extern __shared__ double lds[];
+  __shared__ int sbad;
   double* As = lds;
   double* Bs = lds + kTB * kTLd;
   const int ntri = T * (T + 1) / 2;
@@ -3258,6 +3277,14 @@ __global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n
   d4_t acc[2][2];
   tile_abt(As, Bs, acc);
   store_tile(A, n, ri, rj, ni, nj, i == j, 1, acc);
+  if (t == 0) {
+    // the stores above, made visible to the whole workgroup (device-scope
+    // fences on both sides of the barrier, so no stale cached line is read)
+    __threadfence();
+    __syncthreads();
+    __threadfence();
+    dense_diag_block(A, n, p + 1, err, bits, lds, lds + kTB * kTLd, sbad);
+  }
 }
 
 void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st, double* X) {
@@ -3268,15 +3295,17 @@ void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStrea
   const size_t lds = (size_t)2 * kTB * kTLd * sizeof(double);
   const int nt = (n + kTB - 1) / kTB;
   if (X) launch_zero(X, (int64_t)n * n, st);
+  // the diagonal block of step p + 1 is factored by the update launch of
+  // step p (its workgroup 0), the first one by a launch of its own
+  hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(kThreads), 0, st, A, n, 0, err, bits);
   for (int p = 0; p < nt; ++p) {
     const int T = nt - p - 1;
-    hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(kThreads), 0, st, A, n, p, err, bits);
     const int gp = T + (X ? p + 1 : 0);
     if (gp > 0)
       hipLaunchKernelGGL(dense_panel_kernel, dim3(gp), dim3(kThreads), lds, st, A, n, p, T, X);
     const int gu = T * (T + 1) / 2 + (X ? T * (p + 1) : 0);
     if (gu > 0)
-      hipLaunchKernelGGL(dense_update_kernel, dim3(gu), dim3(kThreads), lds, st, A, n, p, T, X);
+      hipLaunchKernelGGL(dense_update_kernel, dim3(gu), dim3(kThreads), lds, st, A, n, p, T, X, err, bits);
   }
 }
 
