@@ -1093,13 +1093,15 @@ __device__ __forceinline__ void schur_put(const ItemD& it, int rr, int cc, doubl
 }
 
 // X -= F^T F for one 32x32 lower tile of the a x a product; four waves own
-// its 16x16 quadrants.  PREC 0: fp64 MFMA; 1: fp32 inputs, fp32 accumulate;
-// 2: bf16 inputs (round to nearest even), fp32 accumulate.
+// its 16x16 quadrants; the rows of F pass through LDS 64 at a time (16 loads
+// in flight per thread).  PREC 0: fp64 MFMA; 1: fp32 inputs, fp32
+// accumulate; 2: bf16 inputs (round to nearest even), fp32 accumulate.
+constexpr int kSchurRows = 64;
 template <int PREC>
 __global__ void __launch_bounds__(256) schur_kernel(const ItemD* __restrict__ items, LevelState ls,
                                                     int level) {
-  __shared__ double Fr[16][33];
-  __shared__ double Fc[16][33];
+  __shared__ double Fr[kSchurRows][33];
+  __shared__ double Fc[kSchurRows][33];
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   const int k = min(ls.k[it.s], it.kcap), a = ls.a[it.s];
@@ -1115,41 +1117,55 @@ __global__ void __launch_bounds__(256) schur_kernel(const ItemD* __restrict__ it
   const double* C = it.P + (size_t)m * m;
   d4_t acc64 = {0.0, 0.0, 0.0, 0.0};
   f4_t acc32 = {0.f, 0.f, 0.f, 0.f};
-  for (int i0 = k; i0 < m; i0 += 16) {
-    for (int e = tid; e < 2 * 16 * 32; e += 256) {
-      const int half = e >> 9, ee = e & 511;
-      const int col = ee >> 4, ii = ee & 15;
+  for (int i0 = k; i0 < m; i0 += kSchurRows) {
+    // 16 loads in flight per thread: column col of the tile pair, rows ii
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u;
+      const int half = e >> 11, ee = e & 2047;
+      const int col = ee >> 6, ii = ee & 63;
       const int gi = i0 + ii, gc = (half ? C0 : R0) + col;
-      const double v = (gi < m && gc < a) ? gload(C + (size_t)m * gc + gi) : 0.0;
-      if (half) Fc[ii][col] = v;
-      else Fr[ii][col] = v;
+      v[u] = (gi < m && gc < a) ? gload(C + (size_t)m * gc + gi) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u;
+      const int half = e >> 11, ee = e & 2047;
+      const int col = ee >> 6, ii = ee & 63;
+      if (half) Fc[ii][col] = v[u];
+      else Fr[ii][col] = v[u];
     }
     __syncthreads();
+    // the row chunks of 16 in order, each as before (same accumulation order)
+    const int nch = min(kSchurRows, ((m - i0 + 15) / 16) * 16);
     if (live) {
       const int ar = 16 * qr + (lane & 15), bc = 16 * qc + (lane & 15);
-      if (PREC == 0) {
+      for (int c16 = 0; c16 < nch; c16 += 16) {
+        if (PREC == 0) {
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const int ka = kk + (lane >> 4);
-          acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(Fr[ka][ar], Fc[ka][bc], acc64, 0, 0, 0);
-        }
-      } else if (PREC == 1) {
+          for (int kk = 0; kk < 16; kk += 4) {
+            const int ka = c16 + kk + (lane >> 4);
+            acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(Fr[ka][ar], Fc[ka][bc], acc64, 0, 0, 0);
+          }
+        } else if (PREC == 1) {
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const int ka = kk + (lane >> 4);
-          acc32 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)Fr[ka][ar], (float)Fc[ka][bc], acc32, 0, 0, 0);
-        }
-      } else {
-        s4_t av, bv;
+          for (int kk = 0; kk < 16; kk += 4) {
+            const int ka = c16 + kk + (lane >> 4);
+            acc32 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)Fr[ka][ar], (float)Fc[ka][bc], acc32, 0, 0, 0);
+          }
+        } else {
+          s4_t av, bv;
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int ka = 4 * (lane >> 4) + jj;
-          const uint32_t ua = __float_as_uint(round_bf16((float)Fr[ka][ar]));
-          const uint32_t ub = __float_as_uint(round_bf16((float)Fc[ka][bc]));
-          av[jj] = (short)(ua >> 16);
-          bv[jj] = (short)(ub >> 16);
+          for (int jj = 0; jj < 4; ++jj) {
+            const int ka = c16 + 4 * (lane >> 4) + jj;
+            const uint32_t ua = __float_as_uint(round_bf16((float)Fr[ka][ar]));
+            const uint32_t ub = __float_as_uint(round_bf16((float)Fc[ka][bc]));
+            av[jj] = (short)(ua >> 16);
+            bv[jj] = (short)(ub >> 16);
+          }
+          acc32 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc32, 0, 0, 0);
         }
-        acc32 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc32, 0, 0, 0);
       }
     }
     __syncthreads();
