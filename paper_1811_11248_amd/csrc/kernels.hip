@@ -3106,16 +3106,14 @@ __device__ __forceinline__ void dense_diag_block(double* A, int n, int p, int32_
         rs = rs + rs * (0.5 - 0.5 * d * rs * rs);
         rs = rs + rs * (0.5 - 0.5 * d * rs * rs);
         const double piv = d * rs;
-        if (lane == u) {
-          row[u] = piv;
-          rd[kb + u] = rs;
-        } else if (lane > u) {
-          row[u] *= rs;
-        }
+        // every lane computes; only the lower part of the panel's diagonal
+        // tile (lane >= the column, lane < 16) is ever read again
+        if (lane == u) rd[kb + u] = rs;
+        row[u] = lane == u ? piv : row[u] * rs;
 #pragma unroll
         for (int v = u + 1; v < 16; ++v) {
           const double lvu = readlane_d(row[u], v);
-          if (lane >= v && lane < 16) row[v] -= row[u] * lvu;
+          row[v] -= row[u] * lvu;
         }
       }
       if (lane < 16) {

@@ -459,16 +459,14 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
         }
         double y = __builtin_amdgcn_rsq(d);
         y = y + y * (0.5 - 0.5 * d * y * y);
-        if (lane == u) {
-          row[u] = d * y;
-          rdl = y;
-        } else if (lane > u) {
-          row[u] = row[u] * y;
-        }
+        // every lane computes; only the lower part of the tile (lane >= the
+        // column, lane < 16) is ever read again, so no lane needs masking
+        if (lane == u) rdl = y;
+        row[u] = lane == u ? d * y : row[u] * y;
 #pragma unroll
         for (int v = u + 1; v < 16; ++v) {
           const double lvu = readlane_d(row[u], v);
-          if (lane >= v && lane < 16) row[v] -= row[u] * lvu;
+          row[v] -= row[u] * lvu;
         }
       }
       double Y[16];
