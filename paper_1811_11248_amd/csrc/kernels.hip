@@ -3065,9 +3065,11 @@ __device__ __forceinline__ void store_tile(double* A, size_t ld, int r0, int c0,
 // L_pp (lower) in place and L_pp^{-1} in the extra columns.  A pivot that is
 // not > 0 is replaced by 1 and reported in the error words (bits == 0) or as
 // the error bit of a batched system.
-// S: kTB x kTLd doubles of LDS, rd: kTB doubles of LDS, sbad: an int of LDS.
+// S: kTB x kTLd doubles of LDS, rd: kTB, Xs: kTB x kTB, sbad: an int of LDS
+// (kTB (kTLd + kTB + 1) doubles in all).
+constexpr int kDiagLds = kTB * (kTLd + kTB + 1);
 __device__ __forceinline__ void dense_diag_block(double* A, int n, int p, int32_t* err, int bits, double* S,
-                                                 double* rd, int& sbad) {
+                                                 double* rd, double* Xs, int& sbad) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int rp = p * kTB, np = min(kTB, n - rp);
   // the block (identity beyond np), eight loads in flight per thread
@@ -3160,28 +3162,49 @@ __device__ __forceinline__ void dense_diag_block(double* A, int n, int p, int32_
     const int c = e / kTB, r = e - c * kTB;
     if (r < np && c < np && r >= c) A[(size_t)(rp + r) + (size_t)n * (rp + c)] = S[r * kTLd + c];
   }
-  // column c = 16 wv + lane / 4 of L^{-1} by the four lanes q = lane % 4 of
-  // a quad: lane q keeps the entries x_k, k = q mod 4, and sums the terms of
-  // those k of every row (lane 0 starting from the identity's entry); the
-  // quad then adds its four partial sums as (0+1)+(2+3)
+  // L_pp^{-1} by 16 x 16 tiles in Xs (64 x 64, ld 64): wave w inverts the
+  // diagonal tile w (lane c < 16 forms column c by forward substitution),
+  // then the tiles below the diagonal follow on MFMA by distance from it,
+  // X_ij = -X_ii (sum_{k=j}^{i-1} L_ik X_kj) for i - j = 1, 2, 3 in turn
   {
-    const int c = 16 * wv + (lane >> 2), q = lane & 3;
-    double xq[kTB / 4];
+    const int w0 = 16 * wv;
+    if (lane < 16) {
+      double x[16];
 #pragma unroll
-    for (int r = 0; r < kTB; ++r) {
-      double s = (q == 0 && r == c) ? 1.0 : 0.0;
+      for (int r = 0; r < 16; ++r) {
+        double s = 0.0;
 #pragma unroll
-      for (int j = 0; 4 * j < r; ++j)
-        if (4 * j + q < r) s -= S[r * kTLd + 4 * j + q] * xq[j];
-      double t = s + dpp_d<kDppXor1>(s);
-      t = t + dpp_d<kDppXor2>(t);
-      const double xr = r >= c ? t * rd[r] : 0.0;
-      if ((r & 3) == q) xq[r >> 2] = xr;
+        for (int q = 0; q < r; ++q) s += S[(w0 + r) * kTLd + w0 + q] * x[q];
+        x[r] = ((r == lane ? 1.0 : 0.0) - s) * rd[w0 + r];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Xs[(w0 + r) * kTB + w0 + lane] = x[r];
     }
-    if (c < np) {
+    __syncthreads();
+    const int lr = lane >> 4, lc = lane & 15;
+    for (int d = 1; d < 4; ++d) {
+      const int ti = wv + d, tj = wv;  // this wave's tile at distance d
+      if (ti < 4) {
+        d4_t t = {0.0, 0.0, 0.0, 0.0};
+        for (int kt = tj; kt < ti; ++kt) {
 #pragma unroll
-      for (int j = 0; j < kTB / 4; ++j)
-        if (4 * j + q < np) A[(size_t)n * n + (size_t)(rp + 4 * j + q) + (size_t)n * c] = xq[j];
+          for (int s4 = 0; s4 < 4; ++s4)
+            t = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(16 * ti + lc) * kTLd + 16 * kt + 4 * s4 + lr],
+                                                     Xs[(16 * kt + 4 * s4 + lr) * kTB + 16 * tj + lc], t, 0, 0, 0);
+        }
+        d4_t x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          x = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[(16 * ti + lc) * kTB + 16 * ti + 4 * s4 + lr], t[s4], x, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xs[(16 * ti + 4 * v + lr) * kTB + 16 * tj + lc] = -x[v];
+      }
+      __syncthreads();
+    }
+    // to the extra columns, zeros above the diagonal
+    for (int e = tid; e < kTB * kTB; e += kThreads) {
+      const int c = e / kTB, r = e - c * kTB;
+      if (r < np && c < np) A[(size_t)n * n + (size_t)(rp + r) + (size_t)n * c] = r >= c ? Xs[r * kTB + c] : 0.0;
     }
   }
   if (sbad && tid == 0) {
@@ -3191,10 +3214,9 @@ __device__ __forceinline__ void dense_diag_block(double* A, int n, int p, int32_
 }
 
 __global__ void __launch_bounds__(kThreads) dense_diag_kernel(double* A, int n, int p, int32_t* err, int bits) {
-  __shared__ double S[kTB * kTLd];  // the block, row-major (lower part used)
-  __shared__ double rd[kTB];        // 1 / L_jj
+  extern __shared__ double lds[];  // the block (row-major, lower part used), 1 / L_jj, the inverse
   __shared__ int sbad;
-  dense_diag_block(A, n, p, err, bits, S, rd, sbad);
+  dense_diag_block(A, n, p, err, bits, lds, lds + kTB * kTLd, lds + kTB * kTLd + kTB, sbad);
 }
 
 // Panel launch of step p: workgroup b < T takes row tile i = p + 1 + b, L_ip
@@ -3281,21 +3303,24 @@ __global__ void __launch_bounds__(kThreads) dense_update_kernel(double* A, int n
     __threadfence();
     __syncthreads();
     __threadfence();
-    dense_diag_block(A, n, p + 1, err, bits, lds, lds + kTB * kTLd, sbad);
+    dense_diag_block(A, n, p + 1, err, bits, lds, lds + kTB * kTLd, lds + kTB * kTLd + kTB, sbad);
   }
 }
 
 void launch_top_potrf_blocked(double* A, int n, int32_t* err, int bits, hipStream_t st, double* X) {
   if (n <= 0) return;
-  static bool done[2] = {false, false};
+  static bool done[3] = {false, false, false};
   allow_lds(reinterpret_cast<const void*>(dense_panel_kernel), &done[0]);
   allow_lds(reinterpret_cast<const void*>(dense_update_kernel), &done[1]);
+  allow_lds(reinterpret_cast<const void*>(dense_diag_kernel), &done[2]);
   const size_t lds = (size_t)2 * kTB * kTLd * sizeof(double);
+  static_assert(kDiagLds <= 2 * kTB * kTLd, "the update launch's LDS holds the diagonal step's");
   const int nt = (n + kTB - 1) / kTB;
   if (X) launch_zero(X, (int64_t)n * n, st);
   // the diagonal block of step p + 1 is factored by the update launch of
   // step p (its workgroup 0), the first one by a launch of its own
-  hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(kThreads), 0, st, A, n, 0, err, bits);
+  hipLaunchKernelGGL(dense_diag_kernel, dim3(1), dim3(kThreads), (size_t)kDiagLds * sizeof(double), st, A, n, 0,
+                     err, bits);
   for (int p = 0; p < nt; ++p) {
     const int T = nt - p - 1;
     const int gp = T + (X ? p + 1 : 0);
