@@ -3095,13 +3095,15 @@ __device__ __forceinline__ void dense_diag_block(double* A, int n, int p, int32_
 #pragma unroll
       for (int u = 0; u < 16; ++u) row[u] = (lane < 16 && u <= lane) ? S[(kb + lane) * kTLd + kb + u] : 0.0;
       bool bad = false;
+      double rdl = 1.0;
+      // one branch-free block: the pivot test and lane u's reciprocal are
+      // selects, so the pivots' dependency chains can be scheduled together
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         double d = readlane_d(row[u], u);
-        if (!(d > 0.0)) {
-          bad = bad || kb + u < np;
-          d = 1.0;
-        }
+        const bool nonpos = !(d > 0.0);
+        bad = bad || (nonpos && kb + u < np);
+        d = nonpos ? 1.0 : d;
         // 1 / sqrt(d) from v_rsq_f64 refined by two Newton steps, sqrt(d)
         // as d times it (no divide or square-root sequence on the chain)
         double rs = __builtin_amdgcn_rsq(d);
@@ -3110,7 +3112,7 @@ __device__ __forceinline__ void dense_diag_block(double* A, int n, int p, int32_
         const double piv = d * rs;
         // every lane computes; only the lower part of the panel's diagonal
         // tile (lane >= the column, lane < 16) is ever read again
-        if (lane == u) rd[kb + u] = rs;
+        rdl = lane == u ? rs : rdl;
         row[u] = lane == u ? piv : row[u] * rs;
 #pragma unroll
         for (int v = u + 1; v < 16; ++v) {
@@ -3119,6 +3121,7 @@ __device__ __forceinline__ void dense_diag_block(double* A, int n, int p, int32_
         }
       }
       if (lane < 16) {
+        rd[kb + lane] = rdl;
 #pragma unroll
         for (int u = 0; u < 16; ++u)
           if (u <= lane) S[(kb + lane) * kTLd + kb + u] = row[u];

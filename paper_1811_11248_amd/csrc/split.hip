@@ -368,6 +368,76 @@ struct InvMap {
   }
 };
 
+// Look-ahead of chol_inv_kernel: from tile step kLookAheadFrom on, wave
+// kLookAheadWave owns no tile below the diagonal step (its tile rows 7 and 8
+// are final), so during the trailing phase of step p it forms the diagonal
+// tile p + 1 as soon as the owner of that tile has updated it, instead of
+// wave 0 after the phase.  The same operations on the same values.
+constexpr bool kLookAhead = true;
+constexpr int kLookAheadFrom = 8;
+constexpr int kLookAheadWave = 7;
+// Polls of the look-ahead wave before it gives up on the tile and reports
+// the block as failed (a bound only: the owner hands the tile over
+// unconditionally).
+constexpr uint32_t kLookAheadSpins = 1u << 22;
+
+// Diagonal tile p of chol_inv_kernel by one wave: G_pp (lane r holds row r;
+// reciprocal square roots from v_rsq_f64 refined by one Newton step) in Dd,
+// and row r of G_pp^{-1} in the same lane by forward substitution across the
+// lanes (readlane broadcasts) into the columns 16p.. of Xr (X_pp of the
+// inverse).  A pivot that is not > 0 is replaced by 1 and sets *sbad.
+__device__ __forceinline__ void inv_diag_tile(double* Dd, double* Xr, int p, int lane, int* sbad) {
+  double row[16], Y[16], rdl = 1.0;
+  bool bad = false;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) row[u] = lane < 16 ? Dd[lane * kInvLdP + u] : 0.0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) Y[c] = 0.0;
+  // pivot u of G_pp, then row u of its inverse, which needs only column u
+  // of G_pp (final after pivot u): the two dependency chains are
+  // interleaved in one branch-free block (selects instead of lane
+  // branches), with the same operations per entry as one after the other
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    double d = readlane_d(row[u], u);
+    const bool nonpos = !(d > 0.0);
+    bad = bad || nonpos;
+    d = nonpos ? 1.0 : d;
+    double y = __builtin_amdgcn_rsq(d);
+    y = y + y * (0.5 - 0.5 * d * y * y);
+    // every lane computes; only the lower part of the tile (lane >= the
+    // column, lane < 16) is ever read again, so no lane needs masking
+    rdl = lane == u ? y : rdl;
+    row[u] = lane == u ? d * y : row[u] * y;
+#pragma unroll
+    for (int v = u + 1; v < 16; ++v) {
+      const double lvu = readlane_d(row[u], v);
+      row[v] -= row[u] * lvu;
+    }
+    // row u of G_pp^{-1}: lane u solves for its entries, the lanes below
+    // take its contribution
+#pragma unroll
+    for (int c = 0; c <= u; ++c) {
+      const double t = ((c == u ? 1.0 : 0.0) - Y[c]) * rdl;
+      Y[c] = lane == u ? t : Y[c];
+    }
+#pragma unroll
+    for (int c = 0; c <= u; ++c) {
+      const double yuc = readlane_d(Y[c], u);
+      const double t = Y[c] + row[u] * yuc;
+      Y[c] = lane > u ? t : Y[c];
+    }
+  }
+  if (bad && lane == 0) *sbad = 1;
+  if (lane < 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      Dd[lane * kInvLdP + u] = u <= lane ? row[u] : 0.0;
+      Xr[lane * kInvLdX + 16 * p + u] = u <= lane ? Y[u] : 0.0;
+    }
+  }
+}
+
 template <int NW>
 __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restrict__ items, LevelState ls,
                                                            int level) {
@@ -381,6 +451,7 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
   double* Xr = Dd + 16 * kInvLdP;    // 16 x kInvLdX: tile row p of X
   double* Ar = Xr + 16 * kInvLdX;    // 16 x kInvLdX: accumulators of tile row p
   __shared__ int sbad;
+  __shared__ int sla;  // last diagonal tile handed to the look-ahead wave
   const ItemD& it = items[blockIdx.x];
   const int m = it.m;
   if (m == 0) return;
@@ -394,7 +465,11 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
   const int nt = (m + 15) >> 4;
   double* A = it.P;
   double* Xg = it.Gi;
-  if (tid == 0) sbad = 0;
+  static_assert(!kLookAhead || (kLookAheadWave & 7) == 7, "the look-ahead wave owns tile rows 7 and 8");
+  if (tid == 0) {
+    sbad = 0;
+    sla = -1;
+  }
   // the wave's tiles, loaded with lane l on row l%16 of columns 4v + l/16 (16
   // consecutive rows of a column per 16 lanes), then turned into the
   // accumulator layout through a 16 x 17 staging tile of the wave in Ar (free
@@ -442,57 +517,12 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
     asm volatile("" : "+s"(wq));
     double* Pcur = (p & 1) ? Pc2 : Pc;   // tile column p
     double* Pnext = (p & 1) ? Pc : Pc2;  // tile column p + 1
-    // wave 0: G_pp (lane r holds row r; reciprocal square roots from
-    // v_rsq_f64 refined by one Newton step), then row r of G_pp^{-1} in the
-    // same lane by forward substitution across the lanes (readlane
-    // broadcasts), into the columns 16p.. of Xr (X_pp of the inverse)
-    if (w == 0) {
-      double row[16], rdl = 1.0;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) row[u] = lane < 16 ? Dd[lane * kInvLdP + u] : 0.0;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        double d = readlane_d(row[u], u);
-        if (!(d > 0.0)) {
-          if (lane == 0) sbad = 1;
-          d = 1.0;
-        }
-        double y = __builtin_amdgcn_rsq(d);
-        y = y + y * (0.5 - 0.5 * d * y * y);
-        // every lane computes; only the lower part of the tile (lane >= the
-        // column, lane < 16) is ever read again, so no lane needs masking
-        if (lane == u) rdl = y;
-        row[u] = lane == u ? d * y : row[u] * y;
-#pragma unroll
-        for (int v = u + 1; v < 16; ++v) {
-          const double lvu = readlane_d(row[u], v);
-          row[v] -= row[u] * lvu;
-        }
-      }
-      double Y[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) Y[c] = 0.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        if (lane == q) {
-#pragma unroll
-          for (int c = 0; c <= q; ++c) Y[c] = ((c == q ? 1.0 : 0.0) - Y[c]) * rdl;
-        }
-#pragma unroll
-        for (int c = 0; c <= q; ++c) {
-          const double yqc = readlane_d(Y[c], q);
-          if (lane > q) Y[c] += row[q] * yqc;
-        }
-      }
-      if (lane < 16) {
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          Dd[lane * kInvLdP + u] = u <= lane ? row[u] : 0.0;
-          Xr[lane * kInvLdX + 16 * p + u] = u <= lane ? Y[u] : 0.0;
-        }
-      }
+    // diagonal tile p by wave 0, unless wave 7 formed it during the
+    // trailing phase of step p - 1
+    if (!(kLookAhead && p > kLookAheadFrom)) {
+      if (w == 0) inv_diag_tile(Dd, Xr, p, lane, &sbad);
+      lds_barrier();
     }
-    lds_barrier();
     // tile column p of G: G_pp from Dd; G_ip = A_ip G_pp^{-T} on MFMA, back to
     // the tile's rows of Pcur for the trailing update
 #pragma unroll
@@ -544,6 +574,39 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
       }
     }
     lds_barrier();
+    // look-ahead: the owner of tile (p + 1, p + 1) updates it first and hands
+    // it over in Dd; the look-ahead wave, idle otherwise, forms G and X of
+    // diagonal tile p + 1 meanwhile
+    const bool la = kLookAhead && p >= kLookAheadFrom && p + 1 < nt;
+    if (la) {
+#pragma unroll
+      for (int j = 0; j < kInvSlots; ++j) {
+        __builtin_amdgcn_sched_barrier(0);
+        int r, c;
+        if (!Map::slot(wq, j, r, c) || r != p + 1 || c != p + 1) continue;
+        d4_t acc = T[j];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const double av = Pcur[(16 * r + lc) * kInvLdP + 4 * s4 + lr];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av, av, acc, 0, 0, 0);
+        }
+        T[j] = acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Dd[(4 * v + lr) * kInvLdP + lc] = acc[v];
+        __hip_atomic_store(&sla, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      if (w == kLookAheadWave) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&sla, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != p + 1) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kLookAheadSpins) {
+            if (lane == 0) sbad = 1;
+            break;
+          }
+        }
+        inv_diag_tile(Dd, Xr, p + 1, lane, &sbad);
+      }
+    }
     // rows r > p: trailing tiles T_rc -= G_rp G_cp^T (c > p), the tiles of
     // column p + 1, final now, to Dd and Pnext for the next step
 #pragma unroll
@@ -551,6 +614,7 @@ __global__ void __launch_bounds__(NW * 64) chol_inv_kernel(const ItemD* __restri
       __builtin_amdgcn_sched_barrier(0);
       int r, c;
       if (!Map::slot(wq, j, r, c) || r >= nt || r <= p || c <= p) continue;
+      if (la && r == p + 1 && c == p + 1) continue;
       d4_t acc = T[j];
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
