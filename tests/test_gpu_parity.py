@@ -59,6 +59,10 @@ CASES = {
     # the precision workload's shape: 2 components x 20 layers, 2x2 columns
     # per leaf = 160 DoFs per cluster
     "vector_m160": (lambda: slab_vector(16, 16, 20, 1e4), 256, 1e-2),
+    # 17 DoFs per column: level-0 clusters of 136, 170, 204 and 255 DoFs, i.e.
+    # 9, 11, 13 and 16 tile rows in the Cholesky-inverse kernel (whose
+    # look-ahead steps depend on the tile count) and a last tile of 15 rows
+    "slab_nt_mix": (lambda: slab_scalar(19, 11, 17, 1e3, lognormal_field((11, 19, 17), seed=11)), 256, 1e-2),
 }
 # kernel schedules: one workgroup per cluster and one launch per colour; the
 # same in one cooperative launch per level; several workgroups per cluster
